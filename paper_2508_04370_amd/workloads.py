@@ -1,0 +1,242 @@
+"""Seeded synthetic inputs for the regularised Newton systems of an LP interior point method.
+
+This module only draws random numbers and lays them out (a sparse constraint matrix in CSC
+form, the diagonal Theta, the right-hand sides and the regularisation scalars).  It holds none
+of the method's arithmetic, so the factorisation library, its tests and the CPU reference
+implementation can all draw from it without sharing computation.
+
+The paper measures on LP collections that are not available here; every workload below is a
+synthetic stand-in with the shape of the systems the paper factorises (Sections 3 and 5):
+
+* ``ne_random``      -- small random LP, normal-equations form (300 x 600, ~1 % density).
+* ``as_staircase``   -- multi-period staircase LP, augmented-system form (40 periods of
+                        500 x 1000, ~5 nonzeros per column, links between consecutive periods).
+* ``ne_grid``        -- LP coupled on a 3-D 7-point grid, normal-equations form.
+* ``as_batch``       -- many independent small random LPs, augmented-system form.
+* ``as_dense_cols``  -- grid-coupled LP with a few dense columns, augmented-system form.
+* ``dense_front``    -- a single dense symmetric front with quasi-definite diagonal signs.
+
+All randomness comes from ``numpy.random.Generator(PCG64(SeedSequence(seed_list)))``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NE = 0
+AS = 1
+
+
+def rng(*seed):
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(s) for s in seed])))
+
+
+def log_uniform(g, lo, hi, size):
+    """Theta_j = 10**U(log10 lo, log10 hi)."""
+    return 10.0 ** g.uniform(np.log10(lo), np.log10(hi), size)
+
+
+class LP(dict):
+    """A sparse matrix A (m x n, CSC with sorted row indices) plus the scalars of one system."""
+
+    __getattr__ = dict.__getitem__
+
+    @property
+    def nnz(self):
+        return int(self["colptr"][-1])
+
+
+def _csc_from_columns(m, cols, g_vals):
+    """cols: list of sorted unique int arrays (row indices of each column)."""
+    n = len(cols)
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    for j, c in enumerate(cols):
+        colptr[j + 1] = colptr[j] + len(c)
+    rowidx = np.concatenate(cols).astype(np.int32) if n else np.zeros(0, np.int32)
+    val = g_vals.standard_normal(int(colptr[-1]))
+    return colptr, rowidx, val
+
+
+def _csc_from_pairs(m, n, rows, cols, g_vals):
+    """Build CSC from (row, col) pairs; duplicates merged; rows sorted within a column."""
+    key = np.unique(cols.astype(np.int64) * m + rows.astype(np.int64))
+    c = (key // m).astype(np.int64)
+    r = (key % m).astype(np.int32)
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(colptr, c + 1, 1)
+    colptr = np.cumsum(colptr)
+    val = g_vals.standard_normal(len(r))
+    return colptr, r, val
+
+
+def random_lp_pattern(g, m, n, density):
+    """Bernoulli(density) pattern plus one forced entry (pi[j mod m], j) per column."""
+    mask = g.random((m, n)) < density
+    pi = g.permutation(m)
+    mask[pi[np.arange(n) % m], np.arange(n)] = True
+    r, c = np.nonzero(mask)
+    return r, c
+
+
+def ne_random(m=300, n=600, density=0.01, seed=1, theta_range=(1e-6, 1e6), rho=0.0,
+              delta=1e-8, nrhs=1):
+    """Small random LP in normal-equations form (one forced nonzero per column)."""
+    g = rng(seed)
+    r, c = random_lp_pattern(g, m, n, density)
+    colptr, rowidx, val = _csc_from_pairs(m, n, r, c, g)
+    theta = log_uniform(g, *theta_range, n)
+    gr = rng(seed, 1)
+    r1 = gr.standard_normal((nrhs, m)).T.copy(order="F")
+    r7 = np.zeros((n, nrhs), order="F")
+    return LP(m=m, n=n, colptr=colptr, rowidx=rowidx, val=val, theta=theta, rho=rho,
+              delta=delta, mode=NE, r1=r1, r7=r7, name=f"ne_random_{m}x{n}")
+
+
+def as_staircase(periods=40, rows=500, cols=1000, per_col=5, link_cols=100, seed=2,
+                 theta_range=(1e-10, 1e10), rho=1e-10, delta=1e-10, nrhs=1):
+    """Multi-period staircase LP (energy-model-like) in augmented-system form.
+
+    Period t owns rows [rows*t, rows*(t+1)) and columns [cols*t, cols*(t+1)); each column
+    has ``per_col`` distinct rows of its own period; the first ``link_cols`` columns of
+    period t also touch one row of period t+1; empty rows get one entry in their period.
+    """
+    g = rng(seed)
+    m, n = periods * rows, periods * cols
+    rr = []
+    cc = []
+    for t in range(periods):
+        base_r, base_c = rows * t, cols * t
+        picks = np.argsort(g.random((cols, rows)), axis=1)[:, :per_col]
+        rr.append((picks + base_r).ravel())
+        cc.append(np.repeat(np.arange(cols) + base_c, per_col))
+        if t < periods - 1:
+            lr = g.integers(0, rows, link_cols) + rows * (t + 1)
+            rr.append(lr)
+            cc.append(np.arange(link_cols) + base_c)
+    rr = np.concatenate(rr)
+    cc = np.concatenate(cc)
+    present = np.zeros(m, bool)
+    present[rr] = True
+    empty = np.nonzero(~present)[0]
+    if len(empty):
+        per = empty // rows
+        ec = g.integers(0, cols, len(empty)) + per * cols
+        rr = np.concatenate([rr, empty])
+        cc = np.concatenate([cc, ec])
+    colptr, rowidx, val = _csc_from_pairs(m, n, rr, cc, g)
+    theta = log_uniform(g, *theta_range, n)
+    gr = rng(seed, 1)
+    r7 = gr.standard_normal((nrhs, n)).T.copy(order="F")
+    r1 = gr.standard_normal((nrhs, m)).T.copy(order="F")
+    return LP(m=m, n=n, colptr=colptr, rowidx=rowidx, val=val, theta=theta, rho=rho,
+              delta=delta, mode=AS, r1=r1, r7=r7, name=f"as_staircase_{periods}x{rows}x{cols}")
+
+
+def _grid_neighbours(nx, ny, nz):
+    """For every node r = x + nx*y + nx*ny*z: array (m, 6) of 6-neighbours, -1 if outside."""
+    m = nx * ny * nz
+    r = np.arange(m)
+    x, y, z = r % nx, (r // nx) % ny, r // (nx * ny)
+    nb = np.full((m, 6), -1, np.int64)
+    nb[:, 0] = np.where(x > 0, r - 1, -1)
+    nb[:, 1] = np.where(x < nx - 1, r + 1, -1)
+    nb[:, 2] = np.where(y > 0, r - nx, -1)
+    nb[:, 3] = np.where(y < ny - 1, r + nx, -1)
+    nb[:, 4] = np.where(z > 0, r - nx * ny, -1)
+    nb[:, 5] = np.where(z < nz - 1, r + nx * ny, -1)
+    return nb
+
+
+def ne_grid(nx=50, ny=50, nz=40, seed=3, theta_range=(1e-6, 1e6), rho=0.0, delta=1e-8,
+            nrhs=8):
+    """LP coupled on a 3-D grid: columns 2r and 2r+1 touch row r and its 6 grid neighbours."""
+    g = rng(seed)
+    m = nx * ny * nz
+    n = 2 * m
+    nb = _grid_neighbours(nx, ny, nz)
+    sup = np.concatenate([np.arange(m)[:, None], nb], axis=1)
+    sup.sort(axis=1)
+    cols = []
+    for r in range(m):
+        s = sup[r][sup[r] >= 0]
+        cols.append(s)
+        cols.append(s)
+    colptr, rowidx, val = _csc_from_columns(m, cols, g)
+    theta = log_uniform(g, *theta_range, n)
+    gr = rng(seed, 1)
+    r1 = gr.standard_normal((nrhs, m)).T.copy(order="F")
+    r7 = np.zeros((n, nrhs), order="F")
+    return LP(m=m, n=n, colptr=colptr, rowidx=rowidx, val=val, theta=theta, rho=rho,
+              delta=delta, mode=NE, r1=r1, r7=r7, grid=(nx, ny, nz),
+              name=f"ne_grid_{nx}x{ny}x{nz}")
+
+
+def as_batch_system(s, seed=4, mrange=(50, 2000), drange=(0.005, 0.02), rho=1e-10,
+                    delta=1e-10):
+    """System s of the batched workload: random LP with m ~ U{mlo..mhi}, n = 2m."""
+    g = rng(seed, s)
+    m = int(g.integers(mrange[0], mrange[1] + 1))
+    n = 2 * m
+    d = float(g.uniform(*drange))
+    r, c = random_lp_pattern(g, m, n, d)
+    colptr, rowidx, val = _csc_from_pairs(m, n, r, c, g)
+    return LP(m=m, n=n, colptr=colptr, rowidx=rowidx, val=val, rho=rho, delta=delta, mode=AS,
+              name=f"as_batch_{s}")
+
+
+def as_batch_theta(lp, s, k, seed=4, theta_range=(1e-8, 1e8)):
+    return log_uniform(rng(seed, s, k), *theta_range, lp["n"])
+
+
+def as_batch_rhs(lp, s, k, j, seed=4):
+    g = rng(seed, s, k, j)
+    return g.standard_normal(lp["n"]), g.standard_normal(lp["m"])
+
+
+def as_dense_cols(nx=80, ny=50, nz=50, ndense=20, dense_p=0.5, seed=5,
+                  theta_range=(1e-10, 1e10), rho=1e-9, delta=1e-9, nrhs=1):
+    """Grid-coupled sparse columns (anchor + 3 grid neighbours) plus a few dense columns."""
+    g = rng(seed)
+    m = nx * ny * nz
+    n = 2 * m
+    nb = _grid_neighbours(nx, ny, nz)
+    cols = []
+    for j in range(n - ndense):
+        a = j % m
+        cand = nb[a][nb[a] >= 0]
+        pick = cand if len(cand) <= 3 else g.choice(cand, 3, replace=False)
+        cols.append(np.unique(np.concatenate([[a], pick])))
+    for _ in range(ndense):
+        cols.append(np.nonzero(g.random(m) < dense_p)[0])
+    colptr, rowidx, val = _csc_from_columns(m, cols, g)
+    theta = log_uniform(g, *theta_range, n)
+    gr = rng(seed, 1)
+    r7 = gr.standard_normal((nrhs, n)).T.copy(order="F")
+    r1 = gr.standard_normal((nrhs, m)).T.copy(order="F")
+    return LP(m=m, n=n, colptr=colptr, rowidx=rowidx, val=val, theta=theta, rho=rho,
+              delta=delta, mode=AS, r1=r1, r7=r7, grid=(nx, ny, nz), ndense=ndense,
+              name=f"as_dense_cols_{nx}x{ny}x{nz}")
+
+
+def dense_front(f, p, seed=0, dmin=1.0, dmax=10.0):
+    """One dense symmetric front (column-major, full) with a quasi-definite sign pattern.
+
+    sigma_i = -1 for a primal row, +1 for a dual row (random); |F_ii| in [dmin, dmax] with
+    sign sigma_i; off-diagonal N(0,1)/sqrt(f).
+    """
+    g = rng(0, f, p, seed)
+    sigma = np.where(g.random(f) < 0.5, -1, 1).astype(np.int8)
+    F = g.standard_normal((f, f)) / np.sqrt(f)
+    F = np.tril(F, -1)
+    F = F + F.T
+    F[np.arange(f), np.arange(f)] = sigma * g.uniform(dmin, dmax, f)
+    return np.asfortranarray(F), sigma
+
+
+def small_config():
+    """The small correctness workload: random 300 x 600 LP, normal equations, FP64."""
+    return ne_random()
+
+
+def main_config():
+    """The 20000 x 40000 staircase LP, augmented system, FP64."""
+    return as_staircase()
