@@ -1,0 +1,201 @@
+/*
+ * qdmf -- multifrontal LDL^T factorise + solve of the regularised Newton systems of an LP
+ * interior point method, on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement follows Zanetti & Gondzio, arXiv 2508.04370:
+ *   normal equations (NE), Section 3 eq. (normeq) with (regul_matrix):
+ *       K = A (Theta^{-1} + rho I)^{-1} A^T + delta I            (order m)
+ *   augmented system (AS), Section 3 eq. (augsys) with (regul_matrix):
+ *       K = [[-(Theta^{-1} + rho I), A^T], [A, delta I]]         (order n + m)
+ * A is m x n and fixed across IPM iterations; Theta (diagonal, n, positive) changes every
+ * iteration.  Ordering and symbolic analysis run once (Section 4.2); the numeric
+ * factorisation (Section 4.1, pivoting and regularisation of Sections 4.5-4.6) and the
+ * solves with iterative refinement (Section 4.5) run on the GPU each iteration.
+ *
+ * Conventions
+ *   - return value 0: success; < 0: error (nothing was enqueued); > 0: numerical warning.
+ *   - indices are int32, offsets int64.  Column-major dense vectors, leading dim = rows.
+ *   - pointers documented "device" must be device memory of the handle's device.
+ *   - a handle is not thread-safe; separate handles are independent.
+ *   - factorise / solve / graph_launch are asynchronous on the handle's stream;
+ *     analyse, symbolic, the stats calls and destroy synchronise.
+ */
+#ifndef QDMF_H
+#define QDMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qdmf_ctx* qdmf_handle;
+
+enum { QDMF_NE = 0, QDMF_AS = 1 };              /* system form (Section 3)           */
+enum { QDMF_FP64 = 0, QDMF_MIXED = 1 };         /* precision of the Schur updates    */
+enum { QDMF_ORDER_AMD = 0, QDMF_ORDER_USER = 1, QDMF_ORDER_GRID_ND = 2 };
+
+enum {
+    QDMF_OK = 0,
+    QDMF_ERR_INVALID_ARG = -1,    /* bad argument, bad CSC, Theta <= 0 or not finite     */
+    QDMF_ERR_HIP = -2,            /* a HIP runtime call failed                            */
+    QDMF_ERR_OOM = -3,            /* memory plan exceeds the cap or hipMalloc failed     */
+    QDMF_ERR_INDEX_OVERFLOW = -4, /* a 32-bit index would overflow (Section 5.4 lesson)   */
+    QDMF_ERR_NOT_ANALYSED = -5,
+    QDMF_ERR_NOT_FACTORISED = -6,
+    QDMF_ERR_NO_MATRIX = -7,      /* qdmf_set_matrix not called                          */
+    QDMF_ERR_UNSUPPORTED = -8,    /* e.g. a front larger than the kernels support        */
+    QDMF_WARN_DYN_REG = 1,        /* dynamic regularisation (Prop. 3 / sign rule) fired   */
+    QDMF_WARN_INERTIA = 2,        /* inertia differs from the quasi-definite one          */
+    QDMF_WARN_NOT_CONVERGED = 3,  /* refinement stopped above the target backward error  */
+    QDMF_WARN_LARGE_REG = 4       /* some |E_dyn| > tau_big * ||K||_1 (Section 4.6)       */
+};
+
+typedef struct {
+    int32_t nb;               /* pivot window width; numerical parameter (Section 4.4), 64  */
+    double alpha;             /* Bunch-Kaufman constant (Section 4.5), (1+sqrt(17))/8       */
+    double eps_lift;          /* lift threshold factor (Section 4.5), 2^-52                 */
+    int32_t presort;          /* swap the largest diagonal first (Section 4.5), 1           */
+    int32_t max_refine;       /* refinement steps, FP64 path (Section 4.5), 2               */
+    int32_t max_refine_mixed; /* refinement steps, mixed path, 10                           */
+    double target_berr;       /* normwise backward error target, FP64 path, 1e-12          */
+    double target_berr_mixed; /* normwise backward error target, mixed path, 1e-10         */
+    double tau_big;           /* "too large" regularisation threshold (Section 4.6), 1e-8  */
+    int32_t ordering;         /* QDMF_ORDER_*                                               */
+    int32_t grid[3];          /* GRID_ND: row grid dims, row r = x + g0*(y + g1*z)          */
+    int32_t amalgamate;       /* relaxed supernode amalgamation (Section 4.1), 1            */
+    int32_t f_mix;            /* MIXED: fronts of order >= f_mix use FP32 Schur updates    */
+    int32_t small_front;      /* fronts of order <= small_front are factorised in LDS, 64  */
+    int64_t mem_cap_bytes;    /* 0: none; analyse fails with QDMF_ERR_OOM above it         */
+} qdmf_options;
+
+typedef struct {
+    int32_t N;                /* order of K                                                 */
+    int32_t nsuper;           /* number of supernodes                                       */
+    int32_t nlevels;          /* levels of the supernodal tree (leaves = 0)                 */
+    int32_t max_front;        /* largest front order                                        */
+    int64_t nnz_l;            /* nonzeros of L (exact structure, incl. diagonal)            */
+    int64_t nnz_k;            /* nonzeros of lower(K)                                       */
+    double flops_fact;        /* sum_j c_j (c_j + 3), exact structure                       */
+    double flops_solve;       /* 4 sum_j c_j + N per right-hand side                        */
+    int64_t device_bytes;     /* bytes the handle holds on the device                       */
+    int64_t front_bytes;      /* of which dense front storage                               */
+    /* arrays owned by the handle, valid until the next analyse or destroy (host memory) */
+    const int32_t* perm;      /* new -> old, length N                                       */
+    const int32_t* sn_ptr;    /* supernode s = columns [sn_ptr[s], sn_ptr[s+1]), nsuper+1   */
+    const int32_t* sn_parent; /* parent supernode or -1, nsuper                             */
+    const int32_t* sn_front;  /* front order f of each supernode, nsuper                    */
+    const int32_t* sn_level;  /* level of each supernode, nsuper                            */
+} qdmf_symbolic_info;
+
+typedef struct {
+    int64_t nneg, npos, nzero;        /* inertia of D                                       */
+    int64_t n2x2, nlift, nprop3, nsign, nzskip;
+    double max_edyn;                  /* max |E_dyn|                                        */
+    double knorm;                     /* ||K_static||_1                                     */
+    int32_t status;                   /* 0 or the first QDMF_WARN_* that applies            */
+} qdmf_factor_info;
+
+typedef struct {
+    int32_t nrhs;
+    int32_t max_steps;                /* max over right-hand sides of refinement steps      */
+    double berr_nw;                   /* max over right-hand sides, final normwise error   */
+    double berr_cw;                   /* max over right-hand sides, componentwise error    */
+    double berr_nw_initial;           /* before refinement                                  */
+    int32_t status;                   /* 0 or QDMF_WARN_NOT_CONVERGED                       */
+} qdmf_solve_info;
+
+/* Fills *opt with the defaults listed above. */
+void qdmf_default_options(qdmf_options* opt);
+
+/* Creates a handle bound to `device` and the HIP stream `hip_stream` (NULL: the null
+ * stream).  opt may be NULL (defaults); it is copied.  Owns every device allocation it
+ * makes.  Errors: QDMF_ERR_INVALID_ARG, QDMF_ERR_HIP. */
+int qdmf_create(qdmf_handle* h, int device, void* hip_stream, const qdmf_options* opt);
+
+/* Rebinds the stream used by later asynchronous calls. */
+int qdmf_set_stream(qdmf_handle h, void* hip_stream);
+
+/* Symbolic analysis of the pattern of A (Section 4.2: ordering and symbolic factorisation
+ * once, reused every iteration; Section 4.3: supernodal elimination tree).  Host arrays
+ * (m, n >= 0; colptr: n+1 entries; rowidx: sorted strictly increasing within each column)
+ * are read and not retained.  user_perm (new -> old, length N) is used when
+ * opt.ordering == QDMF_ORDER_USER and ignored otherwise (may be NULL).  Runs on the host,
+ * then uploads the plan.  Errors: QDMF_ERR_INVALID_ARG (bad CSC / perm),
+ * QDMF_ERR_OOM (plan above mem_cap_bytes or allocation failure), QDMF_ERR_INDEX_OVERFLOW,
+ * QDMF_ERR_UNSUPPORTED. */
+int qdmf_analyse(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
+                 const int32_t* rowidx, int32_t mode, const int32_t* user_perm);
+
+/* Symbolic results (host memory owned by the handle).  Error: QDMF_ERR_NOT_ANALYSED. */
+int qdmf_symbolic(qdmf_handle h, qdmf_symbolic_info* out);
+
+/* Values of A in the order of the analysed pattern (nnz entries, FP64); host memory if
+ * on_device == 0, else device memory.  Copied; call again whenever A's values change.
+ * Errors: QDMF_ERR_NOT_ANALYSED, QDMF_ERR_INVALID_ARG. */
+int qdmf_set_matrix(qdmf_handle h, const double* a_val, int32_t on_device);
+
+/* Numeric factorisation P (K_static + E_dyn) P^T = L D L^T on the device (Sections 4.1,
+ * 4.4-4.6).  theta_dev: device, n entries, positive and finite (checked on the device:
+ * a bad value makes qdmf_factor_stats return QDMF_ERR_INVALID_ARG); it must stay valid
+ * until the stream reaches this call's end.  rho, delta >= 0 are the static
+ * regularisations.  prec: QDMF_FP64 or QDMF_MIXED (FP32 MFMA Schur updates on fronts of
+ * order >= opt.f_mix; everything else FP64).  L, D are owned by the handle.  Returns < 0
+ * only for argument errors; numerical outcomes come from qdmf_factor_stats. */
+int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double delta,
+                   int32_t prec);
+
+/* Solves K_static [dx; dy] = [r7; r1] (AS) or K_static dy = r1 + A theta~ r7 and
+ * dx = theta~ (A^T dy - r7) (NE, Section 3 eq. (normeq)), then refines in FP64 against
+ * K_static until the normwise backward error reaches the target or the step limit
+ * (Section 4.5).  All vectors are device memory, column-major: r7 and dx n x nrhs, r1 and
+ * dy m x nrhs; r7 may be NULL (zero).  Outputs must not alias inputs.
+ * Errors: QDMF_ERR_NOT_FACTORISED, QDMF_ERR_INVALID_ARG. */
+int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev,
+               double* dx_dev, double* dy_dev);
+
+/* Synchronises the stream and reports the last factorisation.  Returns the status (0,
+ * a QDMF_WARN_* code, or QDMF_ERR_INVALID_ARG if Theta was invalid). */
+int qdmf_factor_stats(qdmf_handle h, qdmf_factor_info* out);
+
+/* Synchronises the stream and reports the last solve.  berr_nw_per_rhs and
+ * steps_per_rhs may be NULL, else nrhs entries (host).  Returns 0 or
+ * QDMF_WARN_NOT_CONVERGED. */
+int qdmf_solve_stats(qdmf_handle h, qdmf_solve_info* out, double* berr_nw_per_rhs,
+                     int32_t* steps_per_rhs);
+
+/* Dense-factor export for tests and inspection (host memory, synchronises).
+ * pivot_order: length N, original variable at each final pivot position;
+ * d, doff: D diagonal and 2x2 off-diagonals by position; ptype: 0 1x1, 1/2 first/second
+ * of a 2x2 block; edyn: dynamic regularisation added at each position (Section 3.2);
+ * any pointer may be NULL. */
+int qdmf_export_d(qdmf_handle h, int32_t* pivot_order, double* d, double* doff,
+                  int8_t* ptype, double* edyn);
+
+/* Copies supernode s's factored front columns (f x p panel of L, rows in the front's
+ * pivoted order, ld = f) and its row list (global original indices, length f) to host. */
+int qdmf_export_front(qdmf_handle h, int32_t s, double* panel, int32_t* rows);
+
+/* Captures factorise + nsolves x solve (each with refinement) once as a HIP graph; later
+ * qdmf_graph_launch replays it on the handle's stream, reading Theta and the right-hand
+ * sides from the same device buffers (the caller refreshes them in place).
+ * Errors: QDMF_ERR_HIP, QDMF_ERR_NOT_ANALYSED. */
+int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, double delta,
+                       int32_t prec, int32_t nsolves, int32_t nrhs, const double* r7_dev,
+                       const double* r1_dev, double* dx_dev, double* dy_dev);
+int qdmf_graph_launch(qdmf_handle h);
+
+/* Frees everything the handle owns.  NULL is ignored. */
+void qdmf_destroy(qdmf_handle h);
+
+/* Static string for a status code. */
+const char* qdmf_status_string(int code);
+
+/* Human-readable detail of the last failure of a handle's analyse or allocation (owned by
+ * the handle; empty if none). */
+const char* qdmf_last_message(qdmf_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

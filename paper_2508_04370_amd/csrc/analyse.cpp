@@ -1,0 +1,636 @@
+// Symbolic analysis on the host, run once per pattern (Section 4.2): K pattern, ordering,
+// elimination tree (Section 4.3), postorder, column structures, supernodes and relaxed
+// amalgamation (Section 4.1), child->parent index maps, the entry->front map, the
+// normal-equation product lists, levels of the supernodal tree and the launch plan.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/qdmf.h"
+#include "plan.hpp"
+
+namespace qdmf {
+
+namespace {
+
+int check_csc(int32_t m, int32_t n, const int64_t* cp, const int32_t* ri, std::string& msg) {
+    if (m < 0 || n < 0 || !cp || (!ri && n > 0 && cp[n] > 0)) {
+        msg = "null or negative argument";
+        return QDMF_ERR_INVALID_ARG;
+    }
+    if (cp[0] != 0) {
+        msg = "colptr[0] != 0";
+        return QDMF_ERR_INVALID_ARG;
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        if (cp[j + 1] < cp[j]) {
+            msg = "colptr not monotone";
+            return QDMF_ERR_INVALID_ARG;
+        }
+        for (int64_t e = cp[j]; e < cp[j + 1]; ++e) {
+            if (ri[e] < 0 || ri[e] >= m) {
+                msg = "row index out of range";
+                return QDMF_ERR_INVALID_ARG;
+            }
+            if (e > cp[j] && ri[e] <= ri[e - 1]) {
+                msg = "row indices not strictly increasing within a column";
+                return QDMF_ERR_INVALID_ARG;
+            }
+        }
+    }
+    if (cp[n] > INT32_MAX) {
+        msg = "more than 2^31-1 nonzeros in A";
+        return QDMF_ERR_INDEX_OVERFLOW;
+    }
+    return 0;
+}
+
+// Full adjacency of K (no diagonal), original numbering.
+void k_adjacency(const Plan& P, std::vector<int64_t>& xadj, std::vector<int32_t>& adj) {
+    const int32_t N = P.N, n = P.n, m = P.m;
+    xadj.assign(N + 1, 0);
+    if (P.mode == QDMF_AS) {
+        for (int32_t j = 0; j < n; ++j) xadj[j + 1] = P.acp[j + 1] - P.acp[j];
+        for (int32_t i = 0; i < m; ++i) xadj[n + i + 1] = P.arp[i + 1] - P.arp[i];
+        for (int32_t v = 0; v < N; ++v) xadj[v + 1] += xadj[v];
+        adj.resize(xadj[N]);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t e = P.acp[j]; e < P.acp[j + 1]; ++e) adj[xadj[j] + (e - P.acp[j])] = n + P.ari[e];
+        for (int32_t i = 0; i < m; ++i)
+            for (int64_t q = P.arp[i]; q < P.arp[i + 1]; ++q)
+                adj[xadj[n + i] + (q - P.arp[i])] = P.acol[P.are[q]];
+    } else {
+        std::vector<int32_t> mark(m, -1);
+        std::vector<int32_t> tmp;
+        std::vector<std::vector<int32_t>> rowsv(m);
+        for (int32_t i = 0; i < m; ++i) {
+            tmp.clear();
+            mark[i] = i;
+            for (int64_t q = P.arp[i]; q < P.arp[i + 1]; ++q) {
+                int32_t j = P.acol[P.are[q]];
+                for (int64_t e = P.acp[j]; e < P.acp[j + 1]; ++e) {
+                    int32_t k = P.ari[e];
+                    if (mark[k] != i) {
+                        mark[k] = i;
+                        tmp.push_back(k);
+                    }
+                }
+            }
+            std::sort(tmp.begin(), tmp.end());
+            rowsv[i] = tmp;
+            xadj[i + 1] = xadj[i] + (int64_t)tmp.size();
+        }
+        adj.resize(xadj[N]);
+        for (int32_t i = 0; i < m; ++i) std::copy(rowsv[i].begin(), rowsv[i].end(), adj.begin() + xadj[i]);
+    }
+}
+
+// Liu's elimination tree algorithm with path compression, order given by iorder (old->new).
+void etree(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+           const std::vector<int32_t>& order, const std::vector<int32_t>& iorder,
+           std::vector<int32_t>& parent) {
+    parent.assign(N, -1);
+    std::vector<int32_t> anc(N, -1);
+    for (int32_t j = 0; j < N; ++j) {
+        int32_t old = order[j];
+        for (int64_t e = xadj[old]; e < xadj[old + 1]; ++e) {
+            int32_t i = iorder[adj[e]];
+            if (i >= j) continue;
+            while (anc[i] != -1 && anc[i] != j) {
+                int32_t t = anc[i];
+                anc[i] = j;
+                i = t;
+            }
+            if (anc[i] == -1) {
+                anc[i] = j;
+                parent[i] = j;
+            }
+        }
+    }
+}
+
+void postorder(int32_t N, const std::vector<int32_t>& parent, std::vector<int32_t>& post) {
+    std::vector<int32_t> head(N, -1), nxt(N, -1), stack;
+    for (int32_t j = N - 1; j >= 0; --j)
+        if (parent[j] >= 0) {
+            nxt[j] = head[parent[j]];
+            head[parent[j]] = j;
+        }
+    post.clear();
+    post.reserve(N);
+    for (int32_t r = 0; r < N; ++r) {
+        if (parent[r] >= 0) continue;
+        stack.push_back(r);
+        while (!stack.empty()) {
+            int32_t v = stack.back();
+            int32_t c = head[v];
+            if (c >= 0) {
+                head[v] = nxt[c];
+                stack.push_back(c);
+            } else {
+                post.push_back(v);
+                stack.pop_back();
+            }
+        }
+    }
+}
+
+int32_t find_pos(const int32_t* rows, int32_t c0, int32_t p, int32_t f, int32_t r) {
+    if (r >= c0 && r < c0 + p) return r - c0;
+    const int32_t* b = rows + p;
+    const int32_t* e = rows + f;
+    const int32_t* it = std::lower_bound(b, e, r);
+    if (it == e || *it != r) return -1;
+    return (int32_t)(it - rows);
+}
+
+}  // namespace
+
+int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx, int32_t mode,
+               const AnalyseOptions& opt, Plan& P, std::string& msg) {
+    if (mode != QDMF_NE && mode != QDMF_AS) {
+        msg = "mode must be QDMF_NE or QDMF_AS";
+        return QDMF_ERR_INVALID_ARG;
+    }
+    int rc = check_csc(m, n, colptr, rowidx, msg);
+    if (rc) return rc;
+    if (mode == QDMF_AS && (int64_t)n + m > INT32_MAX) {
+        msg = "n + m exceeds 2^31-1";
+        return QDMF_ERR_INDEX_OVERFLOW;
+    }
+    P = Plan();
+    P.m = m;
+    P.n = n;
+    P.mode = mode;
+    P.N = mode == QDMF_AS ? n + m : m;
+    const int32_t N = P.N;
+    const int64_t annz = colptr[n];
+    P.acp.assign(colptr, colptr + n + 1);
+    P.ari.assign(rowidx, rowidx + annz);
+    P.acol.resize(annz);
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) P.acol[e] = j;
+    P.arp.assign(m + 1, 0);
+    for (int64_t e = 0; e < annz; ++e) P.arp[rowidx[e] + 1]++;
+    for (int32_t i = 0; i < m; ++i) P.arp[i + 1] += P.arp[i];
+    P.are.resize(annz);
+    {
+        std::vector<int64_t> fill(P.arp.begin(), P.arp.end() - 1);
+        for (int64_t e = 0; e < annz; ++e) P.are[fill[rowidx[e]]++] = (int32_t)e;
+    }
+
+    std::vector<int64_t> xadj;
+    std::vector<int32_t> adj;
+    k_adjacency(P, xadj, adj);
+
+    // ----- ordering
+    std::vector<int32_t> order;
+    if (opt.ordering == QDMF_ORDER_USER) {
+        if (!opt.user_perm) {
+            msg = "user ordering requested without a permutation";
+            return QDMF_ERR_INVALID_ARG;
+        }
+        order.assign(opt.user_perm, opt.user_perm + N);
+    } else if (opt.ordering == QDMF_ORDER_GRID_ND) {
+        if ((int64_t)opt.grid[0] * opt.grid[1] * opt.grid[2] != m) {
+            msg = "grid dims do not multiply to m";
+            return QDMF_ERR_INVALID_ARG;
+        }
+        grid_nd_order(P, opt.grid, xadj, adj, order);
+    } else {
+        amd_order(N, xadj, adj, order);
+    }
+    std::vector<int32_t> iorder(N, -1);
+    if ((int32_t)order.size() != N) {
+        msg = "ordering has the wrong length";
+        return QDMF_ERR_INVALID_ARG;
+    }
+    for (int32_t k = 0; k < N; ++k) {
+        if (order[k] < 0 || order[k] >= N || iorder[order[k]] >= 0) {
+            msg = "ordering is not a permutation";
+            return QDMF_ERR_INVALID_ARG;
+        }
+        iorder[order[k]] = k;
+    }
+
+    // ----- elimination tree, postorder (children ascending)
+    std::vector<int32_t> par0, post;
+    etree(N, xadj, adj, order, iorder, par0);
+    postorder(N, par0, post);
+    P.perm.resize(N);
+    P.iperm.resize(N);
+    for (int32_t k = 0; k < N; ++k) P.perm[k] = order[post[k]];
+    for (int32_t k = 0; k < N; ++k) P.iperm[P.perm[k]] = k;
+    std::vector<int32_t> ipost(N), parent(N, -1);
+    for (int32_t k = 0; k < N; ++k) ipost[post[k]] = k;
+    for (int32_t k = 0; k < N; ++k) parent[k] = par0[post[k]] >= 0 ? ipost[par0[post[k]]] : -1;
+    std::vector<int32_t>().swap(par0);
+    std::vector<int32_t>().swap(post);
+
+    // ----- column structures (freed as soon as they are consumed), fundamental supernodes
+    std::vector<int32_t> nkids(N, 0);
+    for (int32_t j = 0; j < N; ++j)
+        if (parent[j] >= 0) nkids[parent[j]]++;
+    std::vector<int32_t> kid_ptr(N + 1, 0), kid(N);
+    for (int32_t j = 0; j < N; ++j)
+        if (parent[j] >= 0) kid_ptr[parent[j] + 1]++;
+    for (int32_t j = 0; j < N; ++j) kid_ptr[j + 1] += kid_ptr[j];
+    {
+        std::vector<int32_t> fl(kid_ptr.begin(), kid_ptr.end() - 1);
+        for (int32_t j = 0; j < N; ++j)
+            if (parent[j] >= 0) kid[fl[parent[j]]++] = j;
+    }
+    std::vector<std::vector<int32_t>> cs(N);
+    std::vector<int64_t> cc(N, 0);
+    std::vector<int32_t> mark(N, -1);
+    std::vector<char> sn_start(N, 0);
+    P.nnz_l = 0;
+    P.flops_fact = 0;
+    for (int32_t j = 0; j < N; ++j) {
+        std::vector<int32_t> S;
+        int32_t old = P.perm[j];
+        for (int64_t e = xadj[old]; e < xadj[old + 1]; ++e) {
+            int32_t i = P.iperm[adj[e]];
+            if (i > j && mark[i] != j) {
+                mark[i] = j;
+                S.push_back(i);
+            }
+        }
+        for (int32_t q = kid_ptr[j]; q < kid_ptr[j + 1]; ++q)
+            for (int32_t i : cs[kid[q]])
+                if (i != j && mark[i] != j) {
+                    mark[i] = j;
+                    S.push_back(i);
+                }
+        std::sort(S.begin(), S.end());
+        cc[j] = (int64_t)S.size() + 1;
+        P.nnz_l += cc[j];
+        P.flops_fact += (double)S.size() * ((double)S.size() + 3.0);
+        bool join = j > 0 && parent[j - 1] == j && nkids[j] == 1 && cc[j - 1] == cc[j] + 1;
+        sn_start[j] = !join;
+        if (join) std::vector<int32_t>().swap(cs[j - 1]);  // interior column: not needed
+        cs[j] = std::move(S);
+    }
+    P.flops_solve = 4.0 * (double)(P.nnz_l - N) + N;
+
+    // fundamental supernodes: start, ncols, struct of last column (kept in cs)
+    std::vector<int32_t> s_start, s_p;
+    for (int32_t j = 0; j < N; ++j)
+        if (sn_start[j]) s_start.push_back(j);
+    int32_t ns0 = (int32_t)s_start.size();
+    s_p.resize(ns0);
+    for (int32_t s = 0; s < ns0; ++s) s_p[s] = (s + 1 < ns0 ? s_start[s + 1] : N) - s_start[s];
+    std::vector<int32_t> col2sn(N);
+    for (int32_t s = 0; s < ns0; ++s)
+        for (int32_t c = s_start[s]; c < s_start[s] + s_p[s]; ++c) col2sn[c] = s;
+    std::vector<int32_t> s_par(ns0, -1);
+    for (int32_t s = 0; s < ns0; ++s) {
+        int32_t last = s_start[s] + s_p[s] - 1;
+        s_par[s] = parent[last] >= 0 ? col2sn[parent[last]] : -1;
+    }
+
+    // ----- relaxed amalgamation: merge the child whose columns immediately precede the
+    // parent's, when it adds few explicit zeros (merged supernodes stay contiguous)
+    std::vector<int32_t> alive(ns0, 1), s_nk(ns0, 0);
+    std::vector<int64_t> s_zero(ns0, 0);
+    std::vector<int32_t> s_last(ns0);  // index of the supernode holding the struct (the last fundamental)
+    for (int32_t s = 0; s < ns0; ++s) {
+        s_last[s] = s;
+        if (s_par[s] >= 0) s_nk[s_par[s]]++;
+    }
+    auto fsize = [&](int32_t s) { return (int64_t)s_p[s] + (int64_t)cs[s_start[s] + s_p[s] - 1].size(); };
+    std::vector<int64_t> s_f(ns0);
+    for (int32_t s = 0; s < ns0; ++s) s_f[s] = fsize(s);
+    std::vector<int32_t> merged_into(ns0, -1);
+    if (opt.amalgamate) {
+        for (int32_t s = 0; s < ns0; ++s) {
+            for (;;) {
+                // adjacent child: the alive supernode ending at s_start[s]-1 whose parent is s
+                if (s_start[s] == 0) break;
+                int32_t c = col2sn[s_start[s] - 1];
+                while (merged_into[c] >= 0) c = merged_into[c];
+                if (!alive[c] || c == s) break;
+                {
+                    int32_t pc0 = s_par[c];
+                    while (pc0 >= 0 && merged_into[pc0] >= 0) pc0 = merged_into[pc0];
+                    if (pc0 != s) break;
+                }
+                int64_t delta = s_p[c] + s_f[s] - s_f[c];
+                int64_t pc = s_p[c], pm = s_p[c] + s_p[s];
+                int64_t fm = s_f[s] + s_p[c];
+                int64_t ent = pm * fm - pm * (pm - 1) / 2;
+                int64_t zeros = s_zero[c] + s_zero[s] + pc * delta;
+                bool ok = (s_nk[s] == 1 && delta <= 8) || (pc < 16 && (double)zeros <= 0.05 * (double)ent);
+                if (!ok) break;
+                // merge c into s
+                alive[c] = 0;
+                merged_into[c] = s;
+                s_start[s] = s_start[c];
+                s_p[s] = (int32_t)pm;
+                s_f[s] = fm;
+                s_zero[s] = zeros;
+                s_nk[s] += s_nk[c] - 1;
+            }
+        }
+    }
+    // resolve parents through merges, renumber alive supernodes (ascending start = postorder)
+    auto root_of = [&](int32_t s) {
+        while (s >= 0 && merged_into[s] >= 0) s = merged_into[s];
+        return s;
+    };
+    std::vector<int32_t> newid(ns0, -1);
+    int32_t ns = 0;
+    for (int32_t s = 0; s < ns0; ++s)
+        if (alive[s]) newid[s] = ns++;
+    P.ns = ns;
+    P.sn_ptr.resize(ns + 1);
+    P.sn_parent.assign(ns, -1);
+    P.sn_f.resize(ns);
+    P.sn_p.resize(ns);
+    std::vector<int32_t> s_old(ns);
+    for (int32_t s = 0; s < ns0; ++s) {
+        if (!alive[s]) continue;
+        int32_t t = newid[s];
+        s_old[t] = s;
+        P.sn_ptr[t] = s_start[s];
+        P.sn_p[t] = s_p[s];
+        int64_t f = s_f[s];
+        if (f > INT32_MAX) {
+            msg = "front order overflows int32";
+            return QDMF_ERR_INDEX_OVERFLOW;
+        }
+        P.sn_f[t] = (int32_t)f;
+        int32_t ps = root_of(s_par[s]);
+        P.sn_parent[t] = ps >= 0 ? newid[ps] : -1;
+    }
+    P.sn_ptr[ns] = N;
+    // row lists: pivot columns, then the structure of the last column
+    P.sn_rowptr.assign(ns + 1, 0);
+    for (int32_t t = 0; t < ns; ++t) P.sn_rowptr[t + 1] = P.sn_rowptr[t] + P.sn_f[t];
+    P.rows.resize(P.sn_rowptr[ns]);
+    for (int32_t t = 0; t < ns; ++t) {
+        int32_t s = s_old[t];
+        int64_t w = P.sn_rowptr[t];
+        for (int32_t c = P.sn_ptr[t]; c < P.sn_ptr[t] + P.sn_p[t]; ++c) P.rows[w++] = c;
+        const auto& st = cs[s_start[s] + s_p[s] - 1];  // unchanged by merging into s
+        for (int32_t r : st) P.rows[w++] = r;
+    }
+    std::vector<std::vector<int32_t>>().swap(cs);
+    P.max_front = 0;
+    for (int32_t t = 0; t < ns; ++t) P.max_front = std::max(P.max_front, P.sn_f[t]);
+
+    // children (ascending), levels
+    P.ch_ptr.assign(ns + 1, 0);
+    for (int32_t t = 0; t < ns; ++t)
+        if (P.sn_parent[t] >= 0) P.ch_ptr[P.sn_parent[t] + 1]++;
+    for (int32_t t = 0; t < ns; ++t) P.ch_ptr[t + 1] += P.ch_ptr[t];
+    P.ch.resize(P.ch_ptr[ns]);
+    {
+        std::vector<int32_t> fl(P.ch_ptr.begin(), P.ch_ptr.end() - 1);
+        for (int32_t t = 0; t < ns; ++t)
+            if (P.sn_parent[t] >= 0) P.ch[fl[P.sn_parent[t]]++] = t;
+    }
+    P.sn_level.assign(ns, 0);
+    P.nlevels = ns ? 1 : 0;
+    for (int32_t t = 0; t < ns; ++t) {  // children precede parents
+        int32_t lv = 0;
+        for (int32_t q = P.ch_ptr[t]; q < P.ch_ptr[t + 1]; ++q) lv = std::max(lv, P.sn_level[P.ch[q]] + 1);
+        P.sn_level[t] = lv;
+        P.nlevels = std::max(P.nlevels, lv + 1);
+    }
+
+    // child -> parent relative maps of the CB rows
+    P.rel_ptr.assign(ns + 1, 0);
+    for (int32_t t = 0; t < ns; ++t) P.rel_ptr[t + 1] = P.rel_ptr[t] + (P.sn_f[t] - P.sn_p[t]);
+    P.rel.resize(P.rel_ptr[ns]);
+    for (int32_t t = 0; t < ns; ++t) {
+        int32_t q = P.sn_parent[t];
+        int32_t cb = P.sn_f[t] - P.sn_p[t];
+        if (cb > 0 && q < 0) {
+            msg = "internal: contribution block without a parent";
+            return QDMF_ERR_INVALID_ARG;
+        }
+        for (int32_t i = 0; i < cb; ++i) {
+            int32_t r = P.rows[P.sn_rowptr[t] + P.sn_p[t] + i];
+            int32_t pos = find_pos(&P.rows[P.sn_rowptr[q]], P.sn_ptr[q], P.sn_p[q], P.sn_f[q], r);
+            if (pos < 0) {
+                msg = "internal: child row missing from parent front";
+                return QDMF_ERR_INVALID_ARG;
+            }
+            P.rel[P.rel_ptr[t] + i] = pos;
+        }
+    }
+
+    // entries of lower(K) by new column, with their front row positions and sources
+    std::vector<int32_t> c2s(N);
+    for (int32_t t = 0; t < ns; ++t)
+        for (int32_t c = P.sn_ptr[t]; c < P.sn_ptr[t + 1]; ++c) c2s[c] = t;
+    P.kcol_ptr.assign(N + 1, 0);
+    for (int32_t c = 0; c < N; ++c) {
+        int32_t old = P.perm[c];
+        int64_t cnt = 1;
+        for (int64_t e = xadj[old]; e < xadj[old + 1]; ++e) cnt += P.iperm[adj[e]] > c;
+        P.kcol_ptr[c + 1] = P.kcol_ptr[c] + cnt;
+    }
+    const int64_t knnz = P.kcol_ptr[N];
+    P.kloc.resize(knnz);
+    P.krow_old.resize(knnz);
+    P.kcol_old.resize(knnz);
+    {
+        std::vector<int32_t> tmp;
+        for (int32_t c = 0; c < N; ++c) {
+            int32_t old = P.perm[c];
+            tmp.clear();
+            for (int64_t e = xadj[old]; e < xadj[old + 1]; ++e)
+                if (P.iperm[adj[e]] > c) tmp.push_back(P.iperm[adj[e]]);
+            std::sort(tmp.begin(), tmp.end());
+            int32_t t = c2s[c];
+            const int32_t* rr = &P.rows[P.sn_rowptr[t]];
+            int64_t w = P.kcol_ptr[c];
+            P.kloc[w] = c - P.sn_ptr[t];
+            P.krow_old[w] = old;
+            P.kcol_old[w] = old;
+            ++w;
+            for (int32_t r : tmp) {
+                int32_t pos = find_pos(rr, P.sn_ptr[t], P.sn_p[t], P.sn_f[t], r);
+                if (pos < 0) {
+                    msg = "internal: entry outside its front";
+                    return QDMF_ERR_INVALID_ARG;
+                }
+                P.kloc[w] = pos;
+                P.krow_old[w] = P.perm[r];
+                P.kcol_old[w] = old;
+                ++w;
+            }
+        }
+    }
+    if (mode == QDMF_AS) {
+        P.ksrc.resize(knnz);
+        for (int64_t e = 0; e < knnz; ++e) {
+            int32_t a = P.krow_old[e], b = P.kcol_old[e];
+            if (a == b) {
+                P.ksrc[e] = a < n ? -1 - (int64_t)a : KSRC_ZERO;
+            } else {
+                int32_t x = a < n ? a : b;  // primal index
+                int32_t y = (a < n ? b : a) - n;
+                const int32_t* beg = &P.ari[P.acp[x]];
+                const int32_t* end = &P.ari[0] + P.acp[x + 1];
+                const int32_t* it = std::lower_bound(beg, end, y);
+                P.ksrc[e] = P.acp[x] + (it - beg);
+            }
+        }
+    } else {
+        // pairs (A_ij, A_kj) over the shared columns j, ascending
+        P.kpair_ptr.assign(knnz + 1, 0);
+        std::vector<int32_t> pr;
+        for (int64_t e = 0; e < knnz; ++e) {
+            int32_t i = P.krow_old[e], k = P.kcol_old[e];
+            int64_t a = P.arp[i], ae = P.arp[i + 1], b = P.arp[k], be = P.arp[k + 1];
+            while (a < ae && b < be) {
+                int32_t ja = P.acol[P.are[a]], jb = P.acol[P.are[b]];
+                if (ja < jb) ++a;
+                else if (jb < ja) ++b;
+                else {
+                    pr.push_back(P.are[a]);
+                    pr.push_back(P.are[b]);
+                    ++a;
+                    ++b;
+                }
+            }
+            P.kpair_ptr[e + 1] = (int64_t)pr.size() / 2;
+        }
+        P.kpair = std::move(pr);
+        // rows touching each entry, for the symmetric residual and the norm
+        P.krs_ptr.assign(N + 1, 0);
+        for (int64_t e = 0; e < knnz; ++e) {
+            P.krs_ptr[P.krow_old[e] + 1]++;
+            if (P.krow_old[e] != P.kcol_old[e]) P.krs_ptr[P.kcol_old[e] + 1]++;
+        }
+        for (int32_t i = 0; i < N; ++i) P.krs_ptr[i + 1] += P.krs_ptr[i];
+        P.krs_ent.resize(P.krs_ptr[N]);
+        P.krs_other.resize(P.krs_ptr[N]);
+        std::vector<int64_t> fl(P.krs_ptr.begin(), P.krs_ptr.end() - 1);
+        for (int64_t e = 0; e < knnz; ++e) {
+            int32_t r = P.krow_old[e], c = P.kcol_old[e];
+            P.krs_ent[fl[r]] = (int32_t)e;
+            P.krs_other[fl[r]++] = c;
+            if (r != c) {
+                P.krs_ent[fl[c]] = (int32_t)e;
+                P.krs_other[fl[c]++] = r;
+            }
+        }
+        if (knnz > INT32_MAX) {
+            msg = "lower(K) has more than 2^31-1 entries";
+            return QDMF_ERR_INDEX_OVERFLOW;
+        }
+    }
+    P.primal_new.assign(N, 0);
+    if (mode == QDMF_AS)
+        for (int32_t c = 0; c < N; ++c) P.primal_new[c] = P.perm[c] < n;
+
+    // ----- memory plan: dense square fronts, column-major, ld = f
+    P.sn_ld.resize(ns);
+    P.sn_off.resize(ns);
+    P.sn_nwin.resize(ns);
+    int64_t off = 0;
+    for (int32_t t = 0; t < ns; ++t) {
+        P.sn_ld[t] = P.sn_f[t];
+        P.sn_off[t] = off;
+        off += (int64_t)P.sn_f[t] * P.sn_ld[t];
+        P.sn_nwin[t] = (P.sn_p[t] + NB - 1) / NB;
+    }
+    P.front_total = off;
+    P.ub_off.resize(ns + 1);
+    int64_t uo = 0;
+    for (int32_t t = 0; t < ns; ++t) {
+        P.ub_off[t] = uo;
+        uo += P.sn_f[t] - P.sn_p[t];
+    }
+    P.ub_off[ns] = uo;
+    P.ub_total = uo;
+
+    // ----- solve level lists
+    P.lvl_ptr.assign(P.nlevels + 1, 0);
+    for (int32_t t = 0; t < ns; ++t) P.lvl_ptr[P.sn_level[t] + 1]++;
+    for (int32_t l = 0; l < P.nlevels; ++l) P.lvl_ptr[l + 1] += P.lvl_ptr[l];
+    P.lvl_sn.resize(ns);
+    {
+        std::vector<int64_t> fl(P.lvl_ptr.begin(), P.lvl_ptr.end() - 1);
+        for (int32_t t = 0; t < ns; ++t) P.lvl_sn[fl[P.sn_level[t]]++] = t;
+    }
+
+    // ----- factorisation launch plan, level by level
+    P.tasks.clear();
+    P.launches.clear();
+    auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf) {
+        int64_t cnt = (int64_t)P.tasks.size() - t0;
+        if (cnt > 0) P.launches.push_back(Launch{kind, lvl, t0, cnt, lds, maxf});
+    };
+    for (int32_t l = 0; l < P.nlevels; ++l) {
+        std::vector<int32_t> small, large;
+        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; ++q) {
+            int32_t t = P.lvl_sn[q];
+            (P.sn_f[t] <= opt.small_front ? small : large).push_back(t);
+        }
+        int64_t t0 = (int64_t)P.tasks.size();
+        int32_t mf = 0;
+        for (int32_t t : small) {
+            P.tasks.push_back(Task{t, 0, 0, 0});
+            mf = std::max(mf, P.sn_f[t]);
+        }
+        add_launch(L_SMALL, l, t0, 0, mf);
+        if (large.empty()) continue;
+        t0 = (int64_t)P.tasks.size();
+        mf = 0;
+        for (int32_t t : large) {
+            for (int32_t j = 0; j < P.sn_f[t]; ++j) P.tasks.push_back(Task{t, j, 0, 0});
+            mf = std::max(mf, P.sn_f[t]);
+        }
+        if (mf > 16384) {
+            msg = "front order above 16384 is not supported";
+            return QDMF_ERR_UNSUPPORTED;
+        }
+        add_launch(L_ASSEMBLE, l, t0, mf * 8, mf);
+        int32_t maxwin = 0;
+        for (int32_t t : large) maxwin = std::max(maxwin, P.sn_nwin[t]);
+        for (int32_t w = 0; w < maxwin; ++w) {
+            t0 = (int64_t)P.tasks.size();
+            mf = 0;
+            for (int32_t t : large)
+                if (w < P.sn_nwin[t]) {
+                    P.tasks.push_back(Task{t, w * NB, 0, 0});
+                    mf = std::max(mf, P.sn_f[t]);
+                }
+            add_launch(L_DIAG, l, t0, 0, mf);
+            t0 = (int64_t)P.tasks.size();
+            for (int32_t t : large)
+                if (w < P.sn_nwin[t]) {
+                    int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                    int32_t rows_below = P.sn_f[t] - k1;
+                    for (int32_t c = 0; c < (rows_below + 63) / 64; ++c) P.tasks.push_back(Task{t, w * NB, c, 0});
+                }
+            add_launch(L_PANEL, l, t0, 0, mf);
+            t0 = (int64_t)P.tasks.size();
+            for (int32_t t : large)
+                if (w < P.sn_nwin[t]) {
+                    int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                    int32_t R = (P.sn_f[t] - k1 + 63) / 64;
+                    for (int32_t bj = 0; bj < R; ++bj)
+                        for (int32_t bi = bj; bi < R; ++bi) P.tasks.push_back(Task{t, w * NB, bi, bj});
+                }
+            add_launch(L_SYRK, l, t0, 0, mf);
+        }
+        t0 = (int64_t)P.tasks.size();
+        for (int32_t t : large) {
+            int32_t ncols = (P.sn_nwin[t] - 1) * NB;  // columns that have later windows
+            for (int32_t c = 0; c < ncols; c += 64) P.tasks.push_back(Task{t, c, 0, 0});
+        }
+        add_launch(L_ROWSWAP, l, t0, 0, 0);
+    }
+    return 0;
+}
+
+}  // namespace qdmf

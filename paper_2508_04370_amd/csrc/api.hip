@@ -1,0 +1,610 @@
+// C ABI of the library: handles, analyse/upload, factorise and solve enqueueing, statistics,
+// export and HIP graph capture.  Every numerical step runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qdmf.h"
+#include "device.hpp"
+#include "plan.hpp"
+
+using namespace qdmf;
+
+struct qdmf_ctx {
+    int device = 0;
+    bool host_only = false;
+    hipStream_t stream = nullptr;
+    qdmf_options opt{};
+    std::string msg;
+
+    Plan P;
+    bool analysed = false, have_matrix = false, factorised = false;
+    int last_prec = 0;
+    std::vector<int32_t> user_perm;
+
+    // device memory
+    std::vector<void*> plan_allocs;  // freed at re-analyse
+    DevPlan D{};
+    Task* tasks_dev = nullptr;
+    int32_t* lvl_sn_dev = nullptr;
+    std::vector<int32_t> maxf_lvl;
+    int64_t knnz = 0;
+    int64_t device_bytes = 0;
+
+    // solve work space
+    std::vector<void*> solve_allocs;
+    DevSolve S{};
+    int32_t solve_cap = 0;
+    int32_t last_nrhs = 0;
+    bool solved = false;
+
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+
+    // host copies for qdmf_symbolic
+    std::vector<int32_t> h_front;
+};
+
+namespace {
+
+void free_list(std::vector<void*>& v) {
+    for (void* p : v)
+        if (p) (void)hipFree(p);
+    v.clear();
+}
+
+template <class T>
+int dalloc(qdmf_ctx* h, std::vector<void*>& owner, T** out, int64_t count) {
+    *out = nullptr;
+    if (count <= 0) return 0;
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess) {
+        (void)hipGetLastError();
+        h->msg = "hipMalloc failed";
+        return QDMF_ERR_OOM;
+    }
+    owner.push_back(p);
+    h->device_bytes += (int64_t)(sizeof(T) * (size_t)count);
+    *out = (T*)p;
+    return 0;
+}
+
+template <class T>
+int dupload(qdmf_ctx* h, const std::vector<T>& v, const T** out) {
+    T* p = nullptr;
+    int rc = dalloc(h, h->plan_allocs, &p, (int64_t)v.size());
+    if (rc) return rc;
+    if (!v.empty() && hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        h->msg = "hipMemcpy failed";
+        return QDMF_ERR_HIP;
+    }
+    *out = p;
+    return 0;
+}
+
+void destroy_graph(qdmf_ctx* h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+}
+
+int set_device(qdmf_ctx* h) {
+    if (h->host_only) return QDMF_ERR_INVALID_ARG;
+    return hipSetDevice(h->device) == hipSuccess ? 0 : QDMF_ERR_HIP;
+}
+
+int64_t plan_device_bytes(const Plan& P) {
+    int64_t b = 0;
+    b += P.front_total * 8;
+    b += (int64_t)P.tasks.size() * sizeof(Task);
+    b += (int64_t)P.rows.size() * 4 + (int64_t)P.rel.size() * 4;
+    b += P.kcol_ptr.empty() ? 0 : P.kcol_ptr.back() * (8 + 4 + 8);
+    b += (int64_t)P.kpair.size() * 4;
+    b += (int64_t)P.N * (8 * 4 + 4 + 4);
+    b += (int64_t)P.acp.size() * 8 + (int64_t)P.ari.size() * 16;
+    return b;
+}
+
+int upload_plan(qdmf_ctx* h) {
+    Plan& P = h->P;
+    DevPlan& D = h->D;
+    D = DevPlan{};
+    D.N = P.N;
+    D.n = P.n;
+    D.m = P.m;
+    D.mode = P.mode;
+    D.ns = P.ns;
+    D.ub_total = P.ub_total;
+    int rc = 0;
+#define UP(field, vec)                          \
+    if ((rc = dupload(h, P.vec, &D.field))) return rc;
+    UP(sn_ptr, sn_ptr)
+    UP(sn_f, sn_f)
+    UP(sn_p, sn_p)
+    UP(sn_ld, sn_ld)
+    UP(sn_off, sn_off)
+    UP(sn_rowptr, sn_rowptr)
+    UP(rows, rows)
+    UP(ch_ptr, ch_ptr)
+    UP(ch, ch)
+    UP(rel_ptr, rel_ptr)
+    UP(rel, rel)
+    UP(ub_off, ub_off)
+    UP(kcol_ptr, kcol_ptr)
+    UP(kloc, kloc)
+    UP(ksrc, ksrc)
+    UP(kpair_ptr, kpair_ptr)
+    UP(kpair, kpair)
+    UP(krs_ptr, krs_ptr)
+    UP(krs_ent, krs_ent)
+    UP(krs_other, krs_other)
+    UP(primal_new, primal_new)
+    UP(perm, perm)
+    UP(acp, acp)
+    UP(ari, ari)
+    UP(arp, arp)
+    UP(are, are)
+    UP(acol, acol)
+#undef UP
+    const Task* tk = nullptr;
+    if ((rc = dupload(h, P.tasks, &tk))) return rc;
+    h->tasks_dev = const_cast<Task*>(tk);
+    const int32_t* ls = nullptr;
+    if ((rc = dupload(h, P.lvl_sn, &ls))) return rc;
+    h->lvl_sn_dev = const_cast<int32_t*>(ls);
+    h->knnz = P.kcol_ptr.empty() ? 0 : P.kcol_ptr.back();
+    const int64_t N = P.N;
+    if ((rc = dalloc(h, h->plan_allocs, &D.front, P.front_total))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.kval, h->knnz))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.aval, (int64_t)P.ari.size()))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.colabs, P.n))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.rowabs, P.m))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.dinv, P.n))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.rowsum, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.dval, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.doff, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.ptype, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.edyn, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.pflag, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.zskip, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.lperm, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.lpinv, N))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.sc, 1))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.st, 1))) return rc;
+    // largest front per level (dynamic LDS of the solve kernels)
+    h->maxf_lvl.assign(P.nlevels, 1);
+    for (int32_t l = 0; l < P.nlevels; ++l)
+        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; ++q)
+            h->maxf_lvl[l] = std::max(h->maxf_lvl[l], P.sn_f[P.lvl_sn[q]]);
+    if (hipDeviceSynchronize() != hipSuccess) return QDMF_ERR_HIP;
+    return 0;
+}
+
+int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
+    if (nrhs <= h->solve_cap) {
+        h->S.nrhs = nrhs;
+        return 0;
+    }
+    free_list(h->solve_allocs);
+    destroy_graph(h);
+    DevSolve& S = h->S;
+    const int64_t N = h->P.N;
+    S.nblk = (int32_t)((N + 255) / 256);
+    int rc = 0;
+    if ((rc = dalloc(h, h->solve_allocs, &S.b, N * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.x, N * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.xbak, N * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.r, N * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.d, N * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.xw, N * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.ub, std::max<int64_t>(1, h->P.ub_total) * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.part, (int64_t)3 * S.nblk * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.berr, (int64_t)4 * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.active, nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.steps, nrhs))) return rc;
+    h->solve_cap = nrhs;
+    S.nrhs = nrhs;
+    return 0;
+}
+
+PivotParams pivot_params(const qdmf_ctx* h, int32_t prec) {
+    PivotParams pp;
+    pp.alpha = h->opt.alpha;
+    pp.eps_lift = h->opt.eps_lift;
+    pp.tau_big = h->opt.tau_big;
+    pp.presort = h->opt.presort;
+    pp.mixed = prec == QDMF_MIXED;
+    pp.f_mix = h->opt.f_mix;
+    return pp;
+}
+
+void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delta, int32_t prec) {
+    const PivotParams pp = pivot_params(h, prec);
+    launch_theta(h->D, theta, rho, delta, h->stream);
+    launch_values_n(h->D, h->knnz, h->stream);
+    launch_knorm(h->D, h->stream);
+    for (const Launch& L : h->P.launches) launch_factor_step(h->D, L, h->tasks_dev, pp, h->stream);
+    launch_factor_stats(h->D, pp, h->stream);
+}
+
+void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, double* dy) {
+    const Plan& P = h->P;
+    const DevPlan& D = h->D;
+    const DevSolve& S = h->S;
+    const bool mixed = h->last_prec == QDMF_MIXED;
+    const double target = mixed ? h->opt.target_berr_mixed : h->opt.target_berr;
+    const int max_steps = mixed ? h->opt.max_refine_mixed : h->opt.max_refine;
+    hipStream_t st = h->stream;
+    launch_rhs(D, S, r7, r1, st);
+    launch_ldlt_solve_levels(D, S, h->lvl_sn_dev, P.lvl_ptr.data(), P.nlevels, h->maxf_lvl.data(), S.b, S.x,
+                             nullptr, st);
+    launch_residual(D, S, S.x, st);
+    launch_berr_steps(D, S, 0, target, max_steps, st);
+    for (int it = 0; it < max_steps; ++it) {
+        launch_refine_begin(D, S, st);
+        launch_ldlt_solve_levels(D, S, h->lvl_sn_dev, P.lvl_ptr.data(), P.nlevels, h->maxf_lvl.data(), S.r, S.d,
+                                 S.active, st);
+        launch_refine_update(D, S, st);
+        launch_residual(D, S, S.x, st);
+        launch_berr_steps(D, S, 1, target, max_steps, st);
+    }
+    launch_recover(D, S, r7, dx, dy, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+void qdmf_default_options(qdmf_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->nb = 64;
+    o->alpha = (1.0 + std::sqrt(17.0)) / 8.0;
+    o->eps_lift = 2.220446049250313e-16;
+    o->presort = 1;
+    o->max_refine = 2;
+    o->max_refine_mixed = 10;
+    o->target_berr = 1e-12;
+    o->target_berr_mixed = 1e-10;
+    o->tau_big = 1e-8;
+    o->ordering = QDMF_ORDER_AMD;
+    o->amalgamate = 1;
+    o->f_mix = 1024;
+    o->small_front = 64;
+    o->mem_cap_bytes = 0;
+}
+
+int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_options* opt) {
+    if (!out) return QDMF_ERR_INVALID_ARG;
+    *out = nullptr;
+    qdmf_ctx* h = new qdmf_ctx();
+    if (opt) h->opt = *opt;
+    else qdmf_default_options(&h->opt);
+    if (h->opt.nb != 64 || h->opt.small_front < 1 || h->opt.small_front > 64 || h->opt.max_refine < 0 ||
+        h->opt.max_refine_mixed < 0) {
+        delete h;
+        return QDMF_ERR_INVALID_ARG;
+    }
+    h->device = device;
+    h->host_only = device < 0;
+    h->stream = (hipStream_t)hip_stream;
+    if (!h->host_only) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || device >= count || hipSetDevice(device) != hipSuccess) {
+            (void)hipGetLastError();
+            delete h;
+            return QDMF_ERR_HIP;
+        }
+    }
+    *out = h;
+    return 0;
+}
+
+int qdmf_set_stream(qdmf_handle h, void* s) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (h->stream != (hipStream_t)s) destroy_graph(h);
+    h->stream = (hipStream_t)s;
+    return 0;
+}
+
+int qdmf_analyse(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx,
+                 int32_t mode, const int32_t* user_perm) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->host_only) {
+        int rc = set_device(h);
+        if (rc) return rc;
+        (void)hipStreamSynchronize(h->stream);
+    }
+    destroy_graph(h);
+    free_list(h->solve_allocs);
+    free_list(h->plan_allocs);
+    h->solve_cap = 0;
+    h->analysed = h->have_matrix = h->factorised = h->solved = false;
+    h->device_bytes = 0;
+    AnalyseOptions ao;
+    ao.ordering = h->opt.ordering;
+    for (int a = 0; a < 3; ++a) ao.grid[a] = h->opt.grid[a];
+    ao.amalgamate = h->opt.amalgamate;
+    ao.small_front = h->opt.small_front;
+    ao.user_perm = user_perm;
+    if (h->opt.ordering == QDMF_ORDER_USER && !user_perm) return QDMF_ERR_INVALID_ARG;
+    int rc = build_plan(m, n, colptr, rowidx, mode, ao, h->P, h->msg);
+    if (rc) return rc;
+    const int64_t need = plan_device_bytes(h->P);
+    if (h->opt.mem_cap_bytes > 0 && need > h->opt.mem_cap_bytes) {
+        h->msg = "memory plan exceeds the cap";
+        return QDMF_ERR_OOM;
+    }
+    h->h_front = h->P.sn_f;
+    if (!h->host_only) {
+        rc = upload_plan(h);
+        if (rc) {
+            free_list(h->plan_allocs);
+            return rc;
+        }
+    }
+    h->analysed = true;
+    return 0;
+}
+
+int qdmf_symbolic(qdmf_handle h, qdmf_symbolic_info* out) {
+    if (!h || !out) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
+    const Plan& P = h->P;
+    out->N = P.N;
+    out->nsuper = P.ns;
+    out->nlevels = P.nlevels;
+    out->max_front = P.max_front;
+    out->nnz_l = P.nnz_l;
+    out->nnz_k = P.kcol_ptr.empty() ? 0 : P.kcol_ptr.back();
+    out->flops_fact = P.flops_fact;
+    out->flops_solve = P.flops_solve;
+    out->device_bytes = h->host_only ? plan_device_bytes(P) : h->device_bytes;
+    out->front_bytes = P.front_total * 8;
+    out->perm = P.perm.data();
+    out->sn_ptr = P.sn_ptr.data();
+    out->sn_parent = P.sn_parent.data();
+    out->sn_front = P.sn_f.data();
+    out->sn_level = P.sn_level.data();
+    return 0;
+}
+
+int qdmf_set_matrix(qdmf_handle h, const double* a_val, int32_t on_device) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
+    if (h->host_only) return QDMF_ERR_INVALID_ARG;
+    const int64_t nnz = (int64_t)h->P.ari.size();
+    if (nnz > 0 && !a_val) return QDMF_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    if (nnz > 0) {
+        hipError_t e = hipMemcpyAsync(h->D.aval, a_val, sizeof(double) * (size_t)nnz,
+                                      on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) return QDMF_ERR_HIP;
+    }
+    launch_matrix_norms(h->D, h->stream);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    h->have_matrix = true;
+    h->factorised = false;
+    return 0;
+}
+
+int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double delta, int32_t prec) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
+    if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
+    if (h->host_only || (!theta_dev && h->P.n > 0) || !(rho >= 0) || !(delta >= 0) || !std::isfinite(rho) ||
+        !std::isfinite(delta) || (prec != QDMF_FP64 && prec != QDMF_MIXED))
+        return QDMF_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    enqueue_factorise(h, theta_dev, rho, delta, prec);
+    if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
+    h->last_prec = prec;
+    h->factorised = true;
+    h->solved = false;
+    return 0;
+}
+
+int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev, double* dx_dev,
+               double* dy_dev) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;
+    if (nrhs <= 0 || (!r1_dev && h->P.m > 0) || (!dx_dev && h->P.n > 0) || (!dy_dev && h->P.m > 0))
+        return QDMF_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    if ((rc = ensure_solve(h, nrhs))) return rc;
+    enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
+    if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
+    h->last_nrhs = nrhs;
+    h->solved = true;
+    return 0;
+}
+
+int qdmf_factor_stats(qdmf_handle h, qdmf_factor_info* out) {
+    if (!h || !out) return QDMF_ERR_INVALID_ARG;
+    if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;
+    if (set_device(h)) return QDMF_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    DevStats st;
+    DevScalars sc;
+    if (hipMemcpy(&st, h->D.st, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
+    if (hipMemcpy(&sc, h->D.sc, sizeof(sc), hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
+    out->nneg = st.nneg;
+    out->npos = st.npos;
+    out->nzero = st.nzero;
+    out->n2x2 = st.n2x2;
+    out->nlift = st.nlift;
+    out->nprop3 = st.nprop3;
+    out->nsign = st.nsign;
+    out->nzskip = st.nzskip;
+    out->max_edyn = st.max_edyn;
+    out->knorm = sc.knorm;
+    int status = 0;
+    if (st.bad_theta) status = QDMF_ERR_INVALID_ARG;
+    else if (st.large_reg) status = QDMF_WARN_LARGE_REG;
+    else if (h->P.mode == QDMF_AS ? (st.nneg != h->P.n || st.npos != h->P.m) : (st.npos != h->P.m))
+        status = QDMF_WARN_INERTIA;
+    else if (st.nprop3 || st.nsign) status = QDMF_WARN_DYN_REG;
+    out->status = status;
+    return status;
+}
+
+int qdmf_solve_stats(qdmf_handle h, qdmf_solve_info* out, double* berr_nw_per_rhs, int32_t* steps_per_rhs) {
+    if (!h || !out) return QDMF_ERR_INVALID_ARG;
+    if (!h->solved) return QDMF_ERR_NOT_FACTORISED;
+    if (set_device(h)) return QDMF_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    const int32_t nr = h->last_nrhs;
+    std::vector<double> be(4 * (size_t)nr);
+    std::vector<int32_t> steps(nr);
+    if (hipMemcpy(be.data(), h->S.berr, sizeof(double) * be.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return QDMF_ERR_HIP;
+    if (hipMemcpy(steps.data(), h->S.steps, sizeof(int32_t) * nr, hipMemcpyDeviceToHost) != hipSuccess)
+        return QDMF_ERR_HIP;
+    const bool mixed = h->last_prec == QDMF_MIXED;
+    const double target = mixed ? h->opt.target_berr_mixed : h->opt.target_berr;
+    out->nrhs = nr;
+    out->max_steps = 0;
+    out->berr_nw = 0;
+    out->berr_cw = 0;
+    out->berr_nw_initial = 0;
+    for (int32_t r = 0; r < nr; ++r) {
+        out->max_steps = std::max(out->max_steps, steps[r]);
+        out->berr_nw = std::max(out->berr_nw, be[4 * r]);
+        out->berr_cw = std::max(out->berr_cw, be[4 * r + 1]);
+        out->berr_nw_initial = std::max(out->berr_nw_initial, be[4 * r + 2]);
+        if (berr_nw_per_rhs) berr_nw_per_rhs[r] = be[4 * r];
+        if (steps_per_rhs) steps_per_rhs[r] = steps[r];
+    }
+    out->status = out->berr_nw > target ? QDMF_WARN_NOT_CONVERGED : 0;
+    return out->status;
+}
+
+int qdmf_export_d(qdmf_handle h, int32_t* pivot_order, double* d, double* doff, int8_t* ptype,
+                  double* edyn) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;
+    if (set_device(h)) return QDMF_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    const Plan& P = h->P;
+    const size_t N = (size_t)P.N;
+    if (d && hipMemcpy(d, h->D.dval, 8 * N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
+    if (doff && hipMemcpy(doff, h->D.doff, 8 * N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
+    if (ptype && hipMemcpy(ptype, h->D.ptype, N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
+    if (edyn && hipMemcpy(edyn, h->D.edyn, 8 * N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
+    if (pivot_order) {
+        std::vector<int32_t> lp(N);
+        if (hipMemcpy(lp.data(), h->D.lperm, 4 * N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
+        for (int32_t s = 0; s < P.ns; ++s)
+            for (int32_t k = P.sn_ptr[s]; k < P.sn_ptr[s + 1]; ++k) pivot_order[k] = P.perm[P.sn_ptr[s] + lp[k]];
+    }
+    return 0;
+}
+
+int qdmf_export_front(qdmf_handle h, int32_t s, double* panel, int32_t* rows) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;
+    const Plan& P = h->P;
+    if (s < 0 || s >= P.ns) return QDMF_ERR_INVALID_ARG;
+    if (set_device(h)) return QDMF_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    const int32_t f = P.sn_f[s], p = P.sn_p[s], c0 = P.sn_ptr[s];
+    if (panel) {
+        if (hipMemcpy(panel, h->D.front + P.sn_off[s], sizeof(double) * (size_t)f * p, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return QDMF_ERR_HIP;
+    }
+    if (rows) {
+        std::vector<int32_t> lp(p > 0 ? p : 1);
+        if (p > 0 && hipMemcpy(lp.data(), h->D.lperm + c0, 4 * (size_t)p, hipMemcpyDeviceToHost) != hipSuccess)
+            return QDMF_ERR_HIP;
+        for (int32_t k = 0; k < p; ++k) rows[k] = P.perm[c0 + lp[k]];
+        for (int32_t k = p; k < f; ++k) rows[k] = P.perm[P.rows[P.sn_rowptr[s] + k]];
+    }
+    return 0;
+}
+
+int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, double delta, int32_t prec,
+                       int32_t nsolves, int32_t nrhs, const double* r7_dev, const double* r1_dev, double* dx_dev,
+                       double* dy_dev) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
+    if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
+    if (h->host_only || !h->stream || nsolves < 0 || nrhs <= 0 || (!theta_dev && h->P.n > 0) ||
+        (prec != QDMF_FP64 && prec != QDMF_MIXED) || !(rho >= 0) || !(delta >= 0))
+        return QDMF_ERR_INVALID_ARG;
+    if (set_device(h)) return QDMF_ERR_HIP;
+    int rc = ensure_solve(h, nrhs);
+    if (rc) return rc;
+    destroy_graph(h);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return QDMF_ERR_HIP;
+    h->last_prec = prec;
+    enqueue_factorise(h, theta_dev, rho, delta, prec);
+    for (int32_t q = 0; q < nsolves; ++q) enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(h->stream, &g) != hipSuccess || !g) {
+        (void)hipGetLastError();
+        return QDMF_ERR_HIP;
+    }
+    h->graph = g;
+    if (hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        destroy_graph(h);
+        return QDMF_ERR_HIP;
+    }
+    h->factorised = true;
+    h->last_nrhs = nrhs;
+    h->solved = nsolves > 0;
+    return 0;
+}
+
+int qdmf_graph_launch(qdmf_handle h) {
+    if (!h || !h->gexec) return QDMF_ERR_INVALID_ARG;
+    if (set_device(h)) return QDMF_ERR_HIP;
+    return hipGraphLaunch(h->gexec, h->stream) == hipSuccess ? 0 : QDMF_ERR_HIP;
+}
+
+void qdmf_destroy(qdmf_handle h) {
+    if (!h) return;
+    if (!h->host_only) {
+        (void)hipSetDevice(h->device);
+        (void)hipStreamSynchronize(h->stream);
+    }
+    destroy_graph(h);
+    free_list(h->solve_allocs);
+    free_list(h->plan_allocs);
+    delete h;
+}
+
+const char* qdmf_status_string(int code) {
+    switch (code) {
+        case QDMF_OK: return "ok";
+        case QDMF_ERR_INVALID_ARG: return "invalid argument";
+        case QDMF_ERR_HIP: return "HIP runtime error";
+        case QDMF_ERR_OOM: return "out of memory (plan above cap or allocation failed)";
+        case QDMF_ERR_INDEX_OVERFLOW: return "32-bit index overflow";
+        case QDMF_ERR_NOT_ANALYSED: return "not analysed";
+        case QDMF_ERR_NOT_FACTORISED: return "not factorised";
+        case QDMF_ERR_NO_MATRIX: return "matrix values not set";
+        case QDMF_ERR_UNSUPPORTED: return "unsupported problem shape";
+        case QDMF_WARN_DYN_REG: return "dynamic regularisation applied";
+        case QDMF_WARN_INERTIA: return "inertia differs from the quasi-definite inertia";
+        case QDMF_WARN_NOT_CONVERGED: return "refinement did not reach the target backward error";
+        case QDMF_WARN_LARGE_REG: return "regularisation larger than tau_big * ||K||_1";
+        default: return "unknown status";
+    }
+}
+
+// Last error message of a handle (diagnostics).
+const char* qdmf_last_message(qdmf_handle h) { return h ? h->msg.c_str() : ""; }
+
+}  // extern "C"

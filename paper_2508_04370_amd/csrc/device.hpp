@@ -1,0 +1,131 @@
+// Device-side data of one analysed system and the host wrappers that launch the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace qdmf {
+
+// Per-position pivot flags written by the pivot kernels.
+enum : uint8_t { PF_LIFT = 1, PF_PROP3 = 2, PF_SIGN = 4 };
+
+// Scalars shared by the kernels of one factorisation (device memory).
+struct DevScalars {
+    double knorm;      // ||K_static||_1
+    double rho, delta;
+    int32_t bad_theta; // set if some Theta_j is not positive and finite
+    int32_t pad;
+};
+
+// Factorisation statistics (device memory, reduced at the end of a factorisation).
+struct DevStats {
+    int64_t nneg, npos, nzero, n2x2, nlift, nprop3, nsign, nzskip;
+    double max_edyn;
+    int32_t large_reg, bad_theta;
+};
+
+struct PivotParams {
+    double alpha, eps_lift, tau_big;
+    int32_t presort;
+    int32_t mixed;  // 1: FP32 Schur updates on fronts with f >= f_mix
+    int32_t f_mix;
+};
+
+struct DevPlan {
+    int32_t N, n, m, mode, ns;
+    int64_t ub_total;
+    // supernodes
+    const int32_t* sn_ptr;
+    const int32_t* sn_f;
+    const int32_t* sn_p;
+    const int32_t* sn_ld;
+    const int64_t* sn_off;
+    const int64_t* sn_rowptr;
+    const int32_t* rows;
+    const int32_t* ch_ptr;
+    const int32_t* ch;
+    const int64_t* rel_ptr;
+    const int32_t* rel;
+    const int64_t* ub_off;
+    // K entries
+    const int64_t* kcol_ptr;
+    const int32_t* kloc;
+    const int64_t* ksrc;      // AS
+    const int64_t* kpair_ptr; // NE
+    const int32_t* kpair;
+    const int64_t* krs_ptr;   // NE
+    const int32_t* krs_ent;
+    const int32_t* krs_other;
+    const int8_t* primal_new;
+    const int32_t* perm;      // new -> old
+    // A
+    const int64_t* acp;
+    const int32_t* ari;
+    const int64_t* arp;
+    const int32_t* are;
+    const int32_t* acol;
+    // numeric state (owned by the handle)
+    double* front;
+    double* kval;
+    double* aval;
+    double* colabs;   // sum_i |A_ij|
+    double* rowabs;   // sum_j |A_ij|
+    double* dinv;     // AS: 1/Theta; NE: theta~
+    double* rowsum;   // row 1-norms of K_static (original numbering)
+    double* dval;
+    double* doff;
+    int8_t* ptype;
+    double* edyn;
+    uint8_t* pflag;
+    int32_t* zskip;
+    int32_t* lperm;   // by position: pre-pivot local position now pivoted there
+    int32_t* lpinv;   // inverse: c0 + pre-pivot local position -> post-pivot local position
+    DevScalars* sc;
+    DevStats* st;
+};
+
+// ---- factorisation
+void launch_theta(const DevPlan& D, const double* theta, double rho, double delta, hipStream_t s);
+void launch_values_n(const DevPlan& D, int64_t knnz, hipStream_t s);
+void launch_knorm(const DevPlan& D, hipStream_t s);
+void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks_dev,
+                        const PivotParams& pp, hipStream_t s);
+void launch_factor_stats(const DevPlan& D, const PivotParams& pp, hipStream_t s);
+void launch_matrix_norms(const DevPlan& D, hipStream_t s);
+
+// ---- solve
+// Work state of one solve call (device memory owned by the handle).
+struct DevSolve {
+    int32_t nrhs;
+    double* b;      // system right-hand side, original numbering, N x nrhs
+    double* x;      // solution, N x nrhs
+    double* xbak;
+    double* r;      // residual / correction right-hand side, N x nrhs
+    double* d;      // correction, N x nrhs
+    double* xw;     // permuted work vector, N x nrhs
+    double* ub;     // contribution buffers, ub_total x nrhs
+    double* part;   // per-block partial maxima: 3 x nblk x nrhs
+    int32_t nblk;
+    double* berr;   // per rhs: [nw, cw, nw_initial, nw_prev]
+    int32_t* active;  // per rhs: refinement continues
+    int32_t* steps;   // per rhs
+};
+
+void launch_rhs(const DevPlan& D, const DevSolve& S, const double* r7, const double* r1, hipStream_t s);
+// x = (L D L^T)^{-1} src per rhs (original numbering), level by level; rhs with
+// active[r] == 0 are skipped (active may be NULL).
+void launch_ldlt_solve_levels(const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
+                              const int64_t* lvl_ptr, int nlevels, const int32_t* maxf_lvl,
+                              const double* src, double* dst, const int32_t* active, hipStream_t s);
+void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s);
+void launch_berr_steps(const DevPlan& D, const DevSolve& S, int32_t phase, double target,
+                       int max_steps, hipStream_t s);
+void launch_refine_begin(const DevPlan& D, const DevSolve& S, hipStream_t s);
+void launch_refine_update(const DevPlan& D, const DevSolve& S, hipStream_t s);
+void launch_recover(const DevPlan& D, const DevSolve& S, const double* r7, double* dx, double* dy,
+                    hipStream_t s);
+void launch_zero(double* p, int64_t n, hipStream_t s);
+
+}  // namespace qdmf

@@ -1,0 +1,112 @@
+// Host-side symbolic plan: ordering, supernodal elimination tree, index maps and the
+// level-by-level launch plan of the numeric factorisation and the solves.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qdmf {
+
+constexpr int NB = 64;  // pivot window width used by the device kernels
+
+// One task of a batched launch.  Meaning per kernel:
+//   small front / diag block / row swap / solve: s = supernode, a, b unused (or chunk)
+//   panel:  s, k0 = window start, a = row chunk
+//   syrk:   s, k0 = window start, a = row tile, b = column tile
+struct Task {
+    int32_t s, k0, a, b;
+};
+
+enum LaunchKind : int32_t {
+    L_SMALL = 0,     // whole front in LDS: assembly + factorisation
+    L_ASSEMBLE = 1,  // large fronts: one workgroup per front column
+    L_DIAG = 2,      // window diagonal block
+    L_PANEL = 3,     // window panel solve below the block
+    L_SYRK = 4,      // trailing update tiles
+    L_ROWSWAP = 5    // apply window permutations to earlier L columns
+};
+
+struct Launch {
+    int32_t kind;
+    int32_t level;
+    int64_t task0, ntask;  // range in the task array
+    int32_t lds;           // dynamic LDS bytes (assembly)
+    int32_t maxf;          // largest front order among the tasks
+};
+
+struct Plan {
+    // problem
+    int32_t m = 0, n = 0, mode = 0, N = 0;
+    std::vector<int64_t> acp;   // A pattern, CSC
+    std::vector<int32_t> ari;
+    std::vector<int64_t> arp;   // A pattern, CSR: row pointers
+    std::vector<int32_t> are;   // CSR -> CSC entry index
+    std::vector<int32_t> acol;  // column of each CSC entry
+
+    // ordering (new -> old, old -> new) after postordering
+    std::vector<int32_t> perm, iperm;
+
+    // exact symbolic data (before amalgamation)
+    int64_t nnz_l = 0;
+    double flops_fact = 0, flops_solve = 0;
+
+    // supernodes (after amalgamation), in postorder
+    int32_t ns = 0;
+    std::vector<int32_t> sn_ptr, sn_parent, sn_f, sn_p, sn_ld, sn_level, sn_nwin;
+    std::vector<int64_t> sn_off;    // front offsets in the front arena (doubles)
+    std::vector<int64_t> sn_rowptr; // row lists
+    std::vector<int32_t> rows;      // global (new numbering) row index of each front row
+    std::vector<int32_t> ch_ptr, ch;    // children, ascending
+    std::vector<int64_t> rel_ptr;       // per supernode: CB rows mapped into parent front
+    std::vector<int32_t> rel;
+    std::vector<int64_t> ub_off;        // solve contribution buffer offset (per rhs column)
+    int64_t ub_total = 0;
+    int64_t front_total = 0;            // doubles in the front arena
+    int32_t max_front = 0, nlevels = 0;
+
+    // entries of lower(K) grouped by new column: values are produced in this order
+    std::vector<int64_t> kcol_ptr;      // N + 1
+    std::vector<int32_t> kloc;          // row position inside the front of the column's supernode
+    std::vector<int32_t> krow_old, kcol_old;  // original indices of each entry (row >= col in new order)
+    std::vector<int64_t> ksrc;          // AS: >= 0 A entry, -1-j primal diagonal j, KSRC_ZERO dual diagonal
+    std::vector<int64_t> kpair_ptr;     // NE: per entry, pairs of A entries (a, b), column ascending
+    std::vector<int32_t> kpair;         // 2 per pair
+    // NE residual / norm: per original row, the K entries touching it
+    std::vector<int64_t> krs_ptr;
+    std::vector<int32_t> krs_ent, krs_other;
+
+    std::vector<int8_t> primal_new;     // per new index: 1 if a primal (x) variable
+
+    // launch plan
+    std::vector<Task> tasks;
+    std::vector<Launch> launches;       // factorisation, in order
+    std::vector<int64_t> lvl_ptr;       // supernodes per level for the solves (nlevels + 1)
+    std::vector<int32_t> lvl_sn;
+
+    int64_t device_bytes = 0;
+};
+
+constexpr int64_t KSRC_ZERO = INT64_MIN;
+
+struct AnalyseOptions {
+    int ordering = 0;
+    int grid[3] = {0, 0, 0};
+    int amalgamate = 1;
+    int small_front = 64;
+    const int32_t* user_perm = nullptr;
+};
+
+// Approximate minimum degree ordering of a symmetric pattern given as full adjacency
+// (CSR, no diagonal).  Returns order[k] = node eliminated k-th.
+void amd_order(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+               std::vector<int32_t>& order);
+
+// Geometric nested dissection for grid-coupled problems (rows on an nx x ny x nz grid).
+void grid_nd_order(const Plan& P, const int grid[3], const std::vector<int64_t>& xadj,
+                   const std::vector<int32_t>& adj, std::vector<int32_t>& order);
+
+// Builds the whole plan.  Returns 0 or a QDMF_ERR_* code; msg explains failures.
+int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx,
+               int32_t mode, const AnalyseOptions& opt, Plan& P, std::string& msg);
+
+}  // namespace qdmf

@@ -1,0 +1,214 @@
+"""GPU path vs the CPU oracle, through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_04370_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2508_04370_amd import qdmf as Q
+    Q.lib()
+    return torch, "cuda:0"
+
+
+def gpu_solve(torch_dev, lp, prec=0, theta=None, r7=None, r1=None, perm=None, **opts):
+    torch, dev = torch_dev
+    from paper_2508_04370_amd import qdmf as Q
+    theta = lp["theta"] if theta is None else theta
+    r1 = lp["r1"] if r1 is None else r1
+    if r7 is None and lp["mode"] == W.AS:
+        r7 = lp["r7"]
+    print(f"[gpu case] {lp['name']} N={lp['n'] + lp['m'] if lp['mode'] else lp['m']} prec={prec} "
+          f"opts={opts} user_perm={perm is not None}", flush=True)
+    s = Q.Solver(lp, device=0, perm=perm, **opts)
+    th = torch.from_numpy(np.ascontiguousarray(theta)).to(dev)
+    s.factorise(th, lp["rho"], lp["delta"], prec)
+    r1d = Q.to_device_colmajor(r1, dev)
+    r7d = None if r7 is None else Q.to_device_colmajor(r7, dev)
+    dx, dy = s.solve(r7d, r1d)
+    torch.cuda.synchronize()
+    nrhs = r1d.shape[1]
+    out = dict(dx=dx.cpu().numpy(), dy=dy.cpu().numpy(), fstats=s.factor_stats(),
+               sstats=s.solve_stats(nrhs), solver=s)
+    return out
+
+
+def system_x(lp, dx, dy):
+    return np.concatenate([dx, dy]) if lp["mode"] == W.AS else dy
+
+
+def oracle_berr(lp, theta, x, r7, r1):
+    b = O.system_rhs(lp, r7, r1, theta)
+    _, nw, cw, _ = O.residual(lp, theta, lp["rho"], lp["delta"], x, b)
+    return nw, cw
+
+
+def check_against_oracle(lp, g, kappa_tol=True, berr=1e-12):
+    theta = lp["theta"]
+    r7 = lp.get("r7") if lp["mode"] == W.AS else None
+    S = O.Sym(lp)
+    F = O.Num(S, lp["val"], theta, lp["rho"], lp["delta"])
+    ro = F.solve(r7, lp["r1"])
+    nrhs = lp["r1"].shape[1]
+    for c in range(nrhs):
+        x = system_x(lp, g["dx"][:, c], g["dy"][:, c])
+        r7c = None if r7 is None else r7[:, c]
+        nw, _ = oracle_berr(lp, theta, x, r7c, lp["r1"][:, c])
+        assert nw <= berr, (c, nw)
+        xo = system_x(lp, ro["dx"][:, c], ro["dy"][:, c])
+        rel = np.abs(x - xo).max() / max(np.abs(xo).max(), 1e-300)
+        print(f"  rhs {c}: berr_nw={nw:.2e} gpu_reported={g['sstats']['berr_nw_per_rhs'][c]:.2e} "
+              f"steps={g['sstats']['steps_per_rhs'][c]} |x-x_oracle|/|x_oracle|={rel:.2e}")
+    st = F.stats()
+    fs = g["fstats"]
+    assert (fs["nneg"], fs["npos"], fs["nzero"]) == (st["nneg"], st["npos"], st["nzero"])
+    if lp["mode"] == W.AS:
+        assert (fs["nneg"], fs["npos"]) == (lp["n"], lp["m"])
+    else:
+        assert (fs["nneg"], fs["npos"]) == (0, lp["m"])
+    assert np.isclose(fs["knorm"], F.knorm(), rtol=1e-13)
+    return ro
+
+
+def test_ne_random_fp64(torch_dev):
+    lp = W.ne_random()
+    g = gpu_solve(torch_dev, lp)
+    check_against_oracle(lp, g)
+
+
+def test_small_staircase_fp64(torch_dev):
+    lp = W.as_staircase(periods=4, rows=50, cols=100, link_cols=10)
+    g = gpu_solve(torch_dev, lp)
+    check_against_oracle(lp, g)
+
+
+def test_dense_ne_large_front_windows(torch_dev):
+    """A nearly dense normal-equations matrix: one front of order ~200 factorised by the
+    windowed kernels (assembly, diagonal block, panel, MFMA update, row swaps)."""
+    lp = W.ne_random(m=200, n=400, density=0.08, seed=21)
+    g = gpu_solve(torch_dev, lp)
+    assert g["solver"].sym["max_front"] > 64
+    check_against_oracle(lp, g)
+
+
+def test_ne_with_r7_recovers_dx(torch_dev):
+    lp = W.ne_random(m=120, n=240, density=0.03, seed=5, rho=1e-6)
+    g7 = W.rng(77)
+    r7 = g7.standard_normal((lp["n"], 1))
+    g = gpu_solve(torch_dev, lp, r7=r7)
+    S = O.Sym(lp)
+    F = O.Num(S, lp["val"], lp["theta"], lp["rho"], lp["delta"])
+    ro = F.solve(r7, lp["r1"])
+    for key in ("dx", "dy"):
+        a, b = g[key][:, 0], ro[key][:, 0]
+        print(key, np.abs(a - b).max() / np.abs(b).max())
+    # the augmented system built from the same data is solved by (dx, dy)
+    lpa = W.LP(dict(lp, mode=W.AS))
+    nw, _ = oracle_berr(lpa, lp["theta"], np.concatenate([g["dx"][:, 0], g["dy"][:, 0]]), r7[:, 0],
+                        lp["r1"][:, 0])
+    assert nw <= 1e-11, nw
+
+
+def test_matched_mode_reproduces_oracle_pivots(torch_dev):
+    """Oracle ordering fed to the GPU with fundamental supernodes: same supernodes and
+    windows, so the pivot sequence, D and L must match the oracle's (to rounding)."""
+    lp = W.as_staircase(periods=3, rows=40, cols=80, link_cols=8, seed=9)
+    S = O.Sym(lp)
+    perm = S.perm()
+    g = gpu_solve(torch_dev, lp, perm=perm, amalgamate=0)
+    s = g["solver"]
+    assert np.array_equal(s.sym["perm"], perm)
+    assert np.array_equal(s.sym["sn_ptr"], S.snptr())
+    F = O.Num(S, lp["val"], lp["theta"], lp["rho"], lp["delta"])
+    ex = F.export()
+    gd = s.export_d()
+    agree = np.mean(gd["pivot_order"] == ex["fperm"])
+    print("pivot order agreement", agree)
+    assert agree == 1.0
+    assert np.array_equal(gd["ptype"], ex["ptype"])
+    # both are backward stable: pivots may differ by rounding amplified through the
+    # elimination, bounded by c f u (|L||D||L^T|)_kk (Higham, LDL^T error analysis)
+    Lm = ex["L"]
+    Dm = np.diag(np.abs(ex["d"]))
+    for k in np.nonzero(ex["ptype"] == 1)[0]:
+        Dm[k, k + 1] = Dm[k + 1, k] = abs(ex["doff"][k])
+    scale = np.diag(np.abs(Lm) @ Dm @ np.abs(Lm).T)
+    fmax = s.sym["max_front"]
+    dd = np.abs(gd["d"] - ex["d"])
+    print("max |d_gpu - d_oracle| / (|L||D||L^T|)_kk =", (dd / scale).max())
+    assert np.all(dd <= 50 * fmax * U * scale)
+    assert np.allclose(gd["edyn"], ex["edyn"], rtol=1e-6, atol=1e-300) or np.all(
+        np.abs(gd["edyn"] - ex["edyn"]) <= 50 * fmax * U * scale)
+
+
+def test_full_staircase_fp64(torch_dev):
+    lp = W.as_staircase()
+    g = gpu_solve(torch_dev, lp)
+    fs = g["fstats"]
+    print("factor stats", fs)
+    assert (fs["nneg"], fs["npos"]) == (lp["n"], lp["m"])
+    x = system_x(lp, g["dx"][:, 0], g["dy"][:, 0])
+    nw, cw = oracle_berr(lp, lp["theta"], x, lp["r7"][:, 0], lp["r1"][:, 0])
+    print(f"full staircase: berr_nw={nw:.2e} berr_cw={cw:.2e} gpu={g['sstats']}")
+    assert nw <= 1e-12
+
+
+def test_determinism_bitwise(torch_dev):
+    lp = W.as_staircase(periods=4, rows=50, cols=100, link_cols=10)
+    a = gpu_solve(torch_dev, lp)
+    b = gpu_solve(torch_dev, lp)
+    assert np.array_equal(a["dx"], b["dx"]) and np.array_equal(a["dy"], b["dy"])
+    da, db = a["solver"].export_d(), b["solver"].export_d()
+    assert np.array_equal(da["d"], db["d"])
+
+
+def _dense_factor(s, N):
+    gd = s.export_d()
+    po = gd["pivot_order"]
+    pos = np.empty(N, np.int64)
+    pos[po] = np.arange(N)
+    L = np.eye(N)
+    D = np.diag(gd["d"])
+    for k in np.nonzero(gd["ptype"] == 1)[0]:
+        D[k, k + 1] = D[k + 1, k] = gd["doff"][k]
+    snp = s.sym["sn_ptr"]
+    for sidx in range(len(snp) - 1):
+        panel, rows = s.export_front(sidx)
+        f, p = panel.shape
+        for k in range(p):
+            L[pos[rows[k + 1:]], snp[sidx] + k] = panel[k + 1:, k]
+    return po, L, D, gd["edyn"]
+
+
+@pytest.mark.parametrize("amalgamate", [0, 1])
+def test_factor_backward_stable_and_solve_matches_its_factor(torch_dev, amalgamate):
+    """||P K P^T - L D L^T|| small (no dynamic regularisation here), and the GPU solve
+    (no refinement) equals a dense solve with the GPU's own factor."""
+    import scipy.linalg as sla
+    from test_oracle import dense_K
+    lp = W.as_staircase(periods=3, rows=40, cols=80, link_cols=8, seed=9, theta_range=(1e-2, 1e2))
+    g = gpu_solve(torch_dev, lp, amalgamate=amalgamate, max_refine=0)
+    s = g["solver"]
+    N = s.N
+    K = dense_K(lp, lp["theta"], lp["rho"], lp["delta"])
+    po, L, D, ed = _dense_factor(s, N)
+    R = K[np.ix_(po, po)] + np.diag(ed) - L @ D @ L.T
+    scale = np.abs(L) @ np.abs(D) @ np.abs(L).T
+    print("reconstruction error / (|L||D||L^T|)_max:", np.abs(R).max() / scale.max())
+    assert np.abs(R).max() <= 100 * s.sym["max_front"] * U * scale.max()
+    b = np.concatenate([lp["r7"][:, 0], lp["r1"][:, 0]])
+    y = sla.solve_triangular(L, b[po], lower=True, unit_diagonal=True)
+    w = sla.solve_triangular(L.T, np.linalg.solve(D, y), lower=False, unit_diagonal=True)
+    xf = np.empty(N)
+    xf[po] = w
+    x = system_x(lp, g["dx"][:, 0], g["dy"][:, 0])
+    assert np.abs(x - xf).max() <= 1e-8 * np.abs(xf).max()
