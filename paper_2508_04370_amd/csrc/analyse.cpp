@@ -437,6 +437,7 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     }
     const int64_t knnz = P.kcol_ptr[N];
     P.kloc.resize(knnz);
+    P.kcl.resize(knnz);
     P.krow_old.resize(knnz);
     P.kcol_old.resize(knnz);
     {
@@ -450,6 +451,7 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             int32_t t = c2s[c];
             const int32_t* rr = &P.rows[P.sn_rowptr[t]];
             int64_t w = P.kcol_ptr[c];
+            for (int64_t q = P.kcol_ptr[c]; q < P.kcol_ptr[c + 1]; ++q) P.kcl[q] = c - P.sn_ptr[t];
             P.kloc[w] = c - P.sn_ptr[t];
             P.krow_old[w] = old;
             P.kcol_old[w] = old;
@@ -565,6 +567,8 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     // ----- factorisation launch plan, level by level
     P.tasks.clear();
     P.launches.clear();
+    P.asm_child.clear();
+    P.asm_col.clear();
     auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf) {
         int64_t cnt = (int64_t)P.tasks.size() - t0;
         if (cnt > 0) P.launches.push_back(Launch{kind, lvl, t0, cnt, lds, maxf});
@@ -586,7 +590,21 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         t0 = (int64_t)P.tasks.size();
         mf = 0;
         for (int32_t t : large) {
-            for (int32_t j = 0; j < P.sn_f[t]; ++j) P.tasks.push_back(Task{t, j, 0, 0});
+            // (child, child CB column) pairs of each parent column, children ascending
+            std::vector<std::vector<std::pair<int32_t, int32_t>>> lists(P.sn_f[t]);
+            for (int32_t q = P.ch_ptr[t]; q < P.ch_ptr[t + 1]; ++q) {
+                const int32_t c = P.ch[q];
+                const int32_t cb = P.sn_f[c] - P.sn_p[c];
+                for (int32_t i = 0; i < cb; ++i) lists[P.rel[P.rel_ptr[c] + i]].push_back({c, i});
+            }
+            for (int32_t j = 0; j < P.sn_f[t]; ++j) {
+                const int32_t a = (int32_t)P.asm_child.size();
+                for (auto& pr : lists[j]) {
+                    P.asm_child.push_back(pr.first);
+                    P.asm_col.push_back(pr.second);
+                }
+                P.tasks.push_back(Task{t, j, a, (int32_t)lists[j].size()});
+            }
             mf = std::max(mf, P.sn_f[t]);
         }
         if (mf > 16384) {
@@ -601,18 +619,13 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             mf = 0;
             for (int32_t t : large)
                 if (w < P.sn_nwin[t]) {
-                    P.tasks.push_back(Task{t, w * NB, 0, 0});
-                    mf = std::max(mf, P.sn_f[t]);
-                }
-            add_launch(L_DIAG, l, t0, 0, mf);
-            t0 = (int64_t)P.tasks.size();
-            for (int32_t t : large)
-                if (w < P.sn_nwin[t]) {
                     int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
                     int32_t rows_below = P.sn_f[t] - k1;
-                    for (int32_t c = 0; c < (rows_below + 63) / 64; ++c) P.tasks.push_back(Task{t, w * NB, c, 0});
+                    int32_t nchunk = std::max(1, (rows_below + 63) / 64);
+                    for (int32_t c = 0; c < nchunk; ++c) P.tasks.push_back(Task{t, w * NB, c, 0});
+                    mf = std::max(mf, P.sn_f[t]);
                 }
-            add_launch(L_PANEL, l, t0, 0, mf);
+            add_launch(L_WINDOW, l, t0, 0, mf);
             t0 = (int64_t)P.tasks.size();
             for (int32_t t : large)
                 if (w < P.sn_nwin[t]) {
@@ -624,11 +637,9 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             add_launch(L_SYRK, l, t0, 0, mf);
         }
         t0 = (int64_t)P.tasks.size();
-        for (int32_t t : large) {
-            int32_t ncols = (P.sn_nwin[t] - 1) * NB;  // columns that have later windows
-            for (int32_t c = 0; c < ncols; c += 64) P.tasks.push_back(Task{t, c, 0, 0});
-        }
-        add_launch(L_ROWSWAP, l, t0, 0, 0);
+        for (int32_t t : large)
+            for (int32_t c = 0; c < P.sn_p[t]; c += 64) P.tasks.push_back(Task{t, c, 0, 0});
+        add_launch(L_FINALIZE, l, t0, 0, 0);
     }
     return 0;
 }

@@ -125,6 +125,7 @@ int upload_plan(qdmf_ctx* h) {
 #define UP(field, vec)                          \
     if ((rc = dupload(h, P.vec, &D.field))) return rc;
     UP(sn_ptr, sn_ptr)
+    UP(sn_parent, sn_parent)
     UP(sn_f, sn_f)
     UP(sn_p, sn_p)
     UP(sn_ld, sn_ld)
@@ -138,6 +139,9 @@ int upload_plan(qdmf_ctx* h) {
     UP(ub_off, ub_off)
     UP(kcol_ptr, kcol_ptr)
     UP(kloc, kloc)
+    UP(kcl, kcl)
+    UP(asm_child, asm_child)
+    UP(asm_col, asm_col)
     UP(ksrc, ksrc)
     UP(kpair_ptr, kpair_ptr)
     UP(kpair, kpair)

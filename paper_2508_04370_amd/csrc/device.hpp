@@ -38,6 +38,7 @@ struct DevPlan {
     int64_t ub_total;
     // supernodes
     const int32_t* sn_ptr;
+    const int32_t* sn_parent;
     const int32_t* sn_f;
     const int32_t* sn_p;
     const int32_t* sn_ld;
@@ -51,7 +52,10 @@ struct DevPlan {
     const int64_t* ub_off;
     // K entries
     const int64_t* kcol_ptr;
-    const int32_t* kloc;
+    const int32_t* kloc;      // row position of each entry in its front
+    const int32_t* kcl;       // column position of each entry in its front
+    const int32_t* asm_child; // per large-front column task: (child, child CB column) pairs
+    const int32_t* asm_col;
     const int64_t* ksrc;      // AS
     const int64_t* kpair_ptr; // NE
     const int32_t* kpair;
@@ -114,8 +118,9 @@ struct DevSolve {
 };
 
 void launch_rhs(const DevPlan& D, const DevSolve& S, const double* r7, const double* r1, hipStream_t s);
-// x = (L D L^T)^{-1} src per rhs (original numbering), level by level; rhs with
-// active[r] == 0 are skipped (active may be NULL).
+// x = (L D L^T)^{-1} src per rhs (original numbering), one launch per tree level and pass;
+// lvl_sn_dev lists the supernodes level by level (leaves first), maxf_lvl[l] is the largest
+// front order of level l; rhs with active[r] == 0 are skipped (active may be NULL).
 void launch_ldlt_solve_levels(const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
                               const int64_t* lvl_ptr, int nlevels, const int32_t* maxf_lvl,
                               const double* src, double* dst, const int32_t* active, hipStream_t s);

@@ -24,43 +24,66 @@ constexpr int LDT = 65;  // leading dimension of LDS tiles (doubles), odd to spr
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ inline void wave_argmax(double v, int idx, double& bv, int& bi) {
-    // maximum value, lowest index among equal maxima
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(v, off);
-        int oi = __shfl_xor(idx, off);
-        if (ov > v || (ov == v && oi < idx)) {
-            v = ov;
-            idx = oi;
-        }
-    }
-    bv = v;
-    bi = idx;
+// Wave64 reductions with DPP: row_shr 1/2/4/8 leave each row's total in its lane 15,
+// row_bcast15 / row_bcast31 combine the four rows into lane 63, which is read back as a
+// wave-uniform value.  No LDS round trips.  All 64 lanes must be active.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_shift(double v, double old) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double lane63(double v) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 __device__ inline double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-    return v;
-}
-
-__device__ inline int wave_sum(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v = fmax(v, dpp_shift<0x111, 0xf>(v, v));
+    v = fmax(v, dpp_shift<0x112, 0xf>(v, v));
+    v = fmax(v, dpp_shift<0x114, 0xf>(v, v));
+    v = fmax(v, dpp_shift<0x118, 0xf>(v, v));
+    v = fmax(v, dpp_shift<0x142, 0xa>(v, v));
+    v = fmax(v, dpp_shift<0x143, 0xc>(v, v));
+    return lane63(v);
 }
 
 __device__ inline double wave_sum_d(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += dpp_shift<0x111, 0xf>(v, 0.0);
+    v += dpp_shift<0x112, 0xf>(v, 0.0);
+    v += dpp_shift<0x114, 0xf>(v, 0.0);
+    v += dpp_shift<0x118, 0xf>(v, 0.0);
+    v += dpp_shift<0x142, 0xa>(v, 0.0);
+    v += dpp_shift<0x143, 0xc>(v, 0.0);
+    return lane63(v);
 }
 
-// LDS state of the one-wave pivot kernel.  T holds a full symmetric fr x fr matrix
-// (fr <= 64), T[i][j] at j*LDT + i; the first nbw columns are the pivot window.
+__device__ inline int wave_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Maximum value and the lowest lane holding it (lane = position).
+__device__ inline void wave_argmax(double v, int /*lane*/, double& bv, int& bi) {
+    bv = wave_max(v);
+    const unsigned long long m = __ballot(v == bv);
+    bi = __ffsll((long long)m) - 1;
+}
+
+// LDS state of the one-wave pivot kernel.  T is a tile of 64 columns: rows [0, 64) hold a
+// full symmetric block (the window's diagonal block B_D, or a whole small front), rows
+// [64, 128) optional panel rows below the window (part of B_P).  T[i][j] at j*LDW + i.
+constexpr int LDW = 129;
+
 struct PivShared {
-    double T[64 * LDT];
+    double T[64 * LDW];
     double sh[64];  // static shift of the row (-rho primal, +delta dual)
     double w0[64], w1[64];
     double d[64], doff[64], ed[64];
@@ -69,18 +92,26 @@ struct PivShared {
     int pt[64], fl[64], zs[64];
 };
 
-__device__ void sym_swap(PivShared& S, int fr, int a, int b, int lane) {
+// Symmetric interchange of positions a and b: rows/columns of the symmetric block, and the
+// columns of the panel rows.
+template <bool PANEL>
+__device__ void sym_swap(PivShared& S, int nsym, int a, int b, int lane) {
     if (a == b) return;
-    if (lane < fr) {  // rows a and b
-        double t = S.T[lane * LDT + a];
-        S.T[lane * LDT + a] = S.T[lane * LDT + b];
-        S.T[lane * LDT + b] = t;
+    if (lane < nsym) {  // rows a and b of the symmetric block (lane = column)
+        double t = S.T[lane * LDW + a];
+        S.T[lane * LDW + a] = S.T[lane * LDW + b];
+        S.T[lane * LDW + b] = t;
     }
     __syncthreads();
-    if (lane < fr) {  // columns a and b
-        double t = S.T[a * LDT + lane];
-        S.T[a * LDT + lane] = S.T[b * LDT + lane];
-        S.T[b * LDT + lane] = t;
+    if (lane < nsym) {  // columns a and b (lane = row)
+        double t = S.T[a * LDW + lane];
+        S.T[a * LDW + lane] = S.T[b * LDW + lane];
+        S.T[b * LDW + lane] = t;
+    }
+    if (PANEL) {
+        double t = S.T[a * LDW + 64 + lane];
+        S.T[a * LDW + 64 + lane] = S.T[b * LDW + 64 + lane];
+        S.T[b * LDW + 64 + lane] = t;
     }
     if (lane == 0) {
         int ts = S.sg[a]; S.sg[a] = S.sg[b]; S.sg[b] = ts;
@@ -90,82 +121,121 @@ __device__ void sym_swap(PivShared& S, int fr, int a, int b, int lane) {
     __syncthreads();
 }
 
-// Partial LDL^T of the window [0, nbw) of the fr x fr matrix in S.T; rows [nbw, fr) are
-// eliminated too (right-looking).  One wavefront (blockDim.x == 64).
-__device__ void factor_window(PivShared& S, int fr, int nbw, double knorm, const PivotParams& pp,
+// T[row][j] -= m * S.w0[j] for j in [j0, ncols): 8 columns per trip so the LDS loads of a
+// trip are independent of its stores and can be issued together.
+template <bool PANEL>
+__device__ inline void rank1_rows(PivShared& S, int j0, int ncols, double m0, double m1, int lane) {
+    for (int jb = j0 & ~7; jb < ncols; jb += 8) {
+        double t0[8], t1[8], w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = jb + q;
+            const bool on = j >= j0 && j < ncols;
+            w[q] = on ? S.w0[j] : 0.0;
+            t0[q] = S.T[j * LDW + lane];
+            if (PANEL) t1[q] = S.T[j * LDW + 64 + lane];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            S.T[(jb + q) * LDW + lane] = t0[q] - m0 * w[q];
+            if (PANEL) S.T[(jb + q) * LDW + 64 + lane] = t1[q] - m1 * w[q];
+        }
+    }
+}
+
+// Partial LDL^T over the window [0, nbw) of the nsym x nsym symmetric block in S.T, with
+// the updates applied to the columns [0, ncols) of the symmetric rows (nsym = ncols) and,
+// if PANEL, of the panel rows.  Pivot tests read only the window (Section 4.5).  One
+// wavefront (blockDim.x == 64); every decision is wave-uniform.
+template <bool PANEL>
+__device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, const PivotParams& pp,
                               int lane) {
+    const int ncols = nsym;
     const double tiny = pp.eps_lift * knorm;  // delta * ||M||_1 of the lift test
     const double alpha = pp.alpha;
     int k = 0;
     while (k < nbw) {
         if (pp.presort) {  // largest |diagonal| of the window to position k
-            double v = (lane >= k && lane < nbw) ? fabs(S.T[lane * LDT + lane]) : -1.0;
+            double v = (lane >= k && lane < nbw) ? fabs(S.T[lane * LDW + lane]) : -1.0;
             double bv;
             int q;
             wave_argmax(v, lane, bv, q);
-            sym_swap(S, fr, k, q, lane);
+            if (q < k || q >= nbw) q = k;  // no candidate (NaN input): no swap
+            sym_swap<PANEL>(S, nsym, k, q, lane);
         }
         double gp;
         int r;
         {
-            double v = (lane > k && lane < nbw) ? fabs(S.T[k * LDT + lane]) : -1.0;
+            double v = (lane > k && lane < nbw) ? fabs(S.T[k * LDW + lane]) : -1.0;
             wave_argmax(v, lane, gp, r);
-            if (!(gp > 0.0)) {
+            if (!(gp > 0.0) || r <= k || r >= nbw) {
                 gp = 0.0;
                 r = -1;
             }
         }
-        const double akk = fabs(S.T[k * LDT + k]);
+        const double akk = fabs(S.T[k * LDW + k]);
         int two = 0, lifted = 0;
-        double fkk_before = S.T[k * LDT + k];
+        double fkk_before = S.T[k * LDW + k];
         if (fmax(akk, gp) <= tiny) {
             lifted = 1;
         } else if (akk >= alpha * gp) {
             // 1x1 at k
         } else {
-            double v2 = (lane >= k && lane < nbw && lane != r) ? fabs(S.T[r * LDT + lane]) : -1.0;
+            double v2 = (lane >= k && lane < nbw && lane != r) ? fabs(S.T[r * LDW + lane]) : -1.0;
             double gr = wave_max(v2);
             if (gr < 0.0) gr = 0.0;
             if (akk * gr >= alpha * gp * gp) {
                 // 1x1 at k
-            } else if (fabs(S.T[r * LDT + r]) >= alpha * gr) {
-                sym_swap(S, fr, k, r, lane);
-                fkk_before = S.T[k * LDT + k];
+            } else if (fabs(S.T[r * LDW + r]) >= alpha * gr) {
+                sym_swap<PANEL>(S, nsym, k, r, lane);
+                fkk_before = S.T[k * LDW + k];
             } else {
-                sym_swap(S, fr, k + 1, r, lane);
+                sym_swap<PANEL>(S, nsym, k + 1, r, lane);
                 two = 1;
             }
         }
         if (two) {
-            const double a = S.T[k * LDT + k] + S.sh[k];
-            const double b = S.T[k * LDT + k + 1];
-            const double c = S.T[(k + 1) * LDT + k + 1] + S.sh[k + 1];
+            const double a = S.T[k * LDW + k] + S.sh[k];
+            const double b = S.T[k * LDW + k + 1];
+            const double c = S.T[(k + 1) * LDW + k + 1] + S.sh[k + 1];
             const double det = a * c - b * b;
             if (det == 0.0) {
                 two = 0;
-                fkk_before = S.T[k * LDT + k];
+                fkk_before = S.T[k * LDW + k];
                 lifted = 1;
             } else {
-                const bool act = lane >= k + 2 && lane < fr;
-                double u0 = 0.0, u1 = 0.0, l0 = 0.0, l1 = 0.0;
-                if (act) {
-                    u0 = S.T[k * LDT + lane];
-                    u1 = S.T[(k + 1) * LDT + lane];
-                    l0 = (u0 * c - u1 * b) / det;
-                    l1 = (u1 * a - u0 * b) / det;
+                // rows of the symmetric block below the pivot, and panel rows
+                const bool act = lane >= k + 2 && lane < nsym;
+                const double u0 = act ? S.T[k * LDW + lane] : 0.0;
+                const double u1 = act ? S.T[(k + 1) * LDW + lane] : 0.0;
+                const double l0 = act ? (u0 * c - u1 * b) / det : 0.0;
+                const double l1 = act ? (u1 * a - u0 * b) / det : 0.0;
+                double p0 = 0.0, p1 = 0.0, q0 = 0.0, q1 = 0.0;
+                if (PANEL) {
+                    p0 = S.T[k * LDW + 64 + lane];
+                    p1 = S.T[(k + 1) * LDW + 64 + lane];
+                    q0 = (p0 * c - p1 * b) / det;
+                    q1 = (p1 * a - p0 * b) / det;
                 }
                 S.w0[lane] = l0;
                 S.w1[lane] = l1;
                 __syncthreads();
-                if (act)
-                    for (int j = k + 2; j < fr; ++j) S.T[j * LDT + lane] -= u0 * S.w0[j] + u1 * S.w1[j];
+                for (int j = k + 2; j < ncols; ++j) {
+                    const double lj0 = S.w0[j], lj1 = S.w1[j];
+                    if (act) S.T[j * LDW + lane] -= u0 * lj0 + u1 * lj1;
+                    if (PANEL) S.T[j * LDW + 64 + lane] -= p0 * lj0 + p1 * lj1;
+                }
                 __syncthreads();
                 if (act) {
-                    S.T[k * LDT + lane] = l0;
-                    S.T[(k + 1) * LDT + lane] = l1;
+                    S.T[k * LDW + lane] = l0;
+                    S.T[(k + 1) * LDW + lane] = l1;
+                }
+                if (PANEL) {
+                    S.T[k * LDW + 64 + lane] = q0;
+                    S.T[(k + 1) * LDW + 64 + lane] = q1;
                 }
                 if (lane == 0) {
-                    S.T[k * LDT + k + 1] = 0.0;
+                    S.T[k * LDW + k + 1] = 0.0;
                     S.d[k] = a;
                     S.d[k + 1] = c;
                     S.doff[k] = b;
@@ -185,17 +255,17 @@ __device__ void factor_window(PivShared& S, int fr, int nbw, double knorm, const
             }
         }
         // 1x1 pivot at k
-        if (lifted && lane == 0) S.T[k * LDT + k] = S.sg[k] * tiny;
+        if (lifted && lane == 0) S.T[k * LDW + k] = S.sg[k] * tiny;
         __syncthreads();
-        double dk = S.T[k * LDT + k] + S.sh[k];  // static regularisation after the pivot
+        double dk = S.T[k * LDW + k] + S.sh[k];  // static regularisation after the pivot
         const int sgk = S.sg[k];
         double q = -1.0;
         int zz = 0;
         if (lane > k && lane < nbw && S.sg[lane] == sgk) {
-            double den = fabs(S.T[lane * LDT + lane] + S.sh[lane]);
+            double den = fabs(S.T[lane * LDW + lane] + S.sh[lane]);
             if (den == 0.0) zz = 1;
             else {
-                double fjk = S.T[k * LDT + lane];
+                double fjk = S.T[k * LDW + lane];
                 q = fjk * fjk / den;
             }
         }
@@ -215,14 +285,15 @@ __device__ void factor_window(PivShared& S, int fr, int nbw, double knorm, const
             flag |= PF_SIGN;
         }
         const double e = dk - (fkk_before + S.sh[k]);
-        const bool act = lane > k && lane < fr;
-        double li = 0.0;
-        if (act) {
-            li = S.T[k * LDT + lane] / dk;
-            for (int j = k + 1; j < fr; ++j) S.T[j * LDT + lane] -= li * S.T[k * LDT + j];
-        }
+        const bool act = lane > k && lane < nsym;
+        const double li = act ? S.T[k * LDW + lane] / dk : 0.0;
+        const double pi = PANEL ? S.T[k * LDW + 64 + lane] / dk : 0.0;
+        S.w0[lane] = (lane > k && lane < ncols) ? S.T[k * LDW + lane] : 0.0;  // column k
         __syncthreads();
-        if (act) S.T[k * LDT + lane] = li;
+        rank1_rows<PANEL>(S, k + 1, ncols, li, pi, lane);
+        __syncthreads();
+        if (act) S.T[k * LDW + lane] = li;
+        if (PANEL) S.T[k * LDW + 64 + lane] = pi;
         if (lane == 0) {
             S.d[k] = dk;
             S.doff[k] = 0.0;
@@ -273,45 +344,60 @@ __global__ __launch_bounds__(64) void k_small(DevPlan D, const Task* tasks, int6
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     double* F = D.front + D.sn_off[s];
     const int32_t* rows = D.rows + D.sn_rowptr[s];
-    for (int j = 0; j < 64; ++j) S.T[j * LDT + lane] = 0.0;
+    for (int j = 0; j < 64; ++j) S.T[j * LDW + lane] = 0.0;
     __syncthreads();
-    for (int c = 0; c < p; ++c) {
-        const int64_t e1 = D.kcol_ptr[c0 + c + 1];
-        for (int64_t e = D.kcol_ptr[c0 + c] + lane; e < e1; e += 64) {
-            const int r = D.kloc[e];
+    {  // original entries of the pivot columns (row position, column position, value)
+        const int64_t e0 = D.kcol_ptr[c0], e1 = D.kcol_ptr[c0 + p];
+        for (int64_t e = e0 + lane; e < e1; e += 64) {
+            const int r = D.kloc[e], c = D.kcl[e];
             const double v = D.kval[e];
-            S.T[c * LDT + r] = v;
-            S.T[r * LDT + c] = v;
+            S.T[c * LDW + r] = v;
+            S.T[r * LDW + c] = v;
         }
     }
     __syncthreads();
     for (int q = D.ch_ptr[s]; q < D.ch_ptr[s + 1]; ++q) {  // children in ascending order
         const int ch = D.ch[q];
         const int cp = D.sn_p[ch], cb = D.sn_f[ch] - cp, cld = D.sn_ld[ch];
-        const double* CF = D.front + D.sn_off[ch];
+        const double* CF = D.front + D.sn_off[ch] + cp + (int64_t)cp * cld;
         const int32_t* rel = D.rel + D.rel_ptr[ch];
-        for (int b = 0; b < cb; ++b) {
-            const int rb = rel[b];
-            for (int a = b + lane; a < cb; a += 64) {
-                const int ra = rel[a];
-                const double v = CF[(cp + a) + (int64_t)(cp + b) * cld];
-                S.T[rb * LDT + ra] += v;
-                if (a != b) S.T[ra * LDT + rb] += v;
+        // the child's contribution block (cb <= 64), all of it in flight at once
+        const int ntot = cb * cb;
+        for (int i0 = 0; i0 < ntot; i0 += 64 * 8) {
+            double v[8];
+            int ia[8], ib[8];
+#pragma unroll
+            for (int q2 = 0; q2 < 8; ++q2) {
+                const int idx = i0 + q2 * 64 + lane;
+                const int b = idx / cb, a = idx - b * cb;
+                ia[q2] = a;
+                ib[q2] = b;
+                v[q2] = (idx < ntot && a >= b) ? CF[a + (int64_t)b * cld] : 0.0;
+            }
+#pragma unroll
+            for (int q2 = 0; q2 < 8; ++q2) {
+                const int idx = i0 + q2 * 64 + lane;
+                if (idx < ntot && ia[q2] >= ib[q2]) {
+                    const int ra = rel[ia[q2]], rb = rel[ib[q2]];
+                    S.T[rb * LDW + ra] += v[q2];
+                    if (ia[q2] != ib[q2]) S.T[ra * LDW + rb] += v[q2];
+                }
             }
         }
         __syncthreads();
     }
     init_signs(S, D, rows, f, lane);
     __syncthreads();
-    factor_window(S, f, p, D.sc->knorm, pp, lane);
+    factor_window<false>(S, f, p, D.sc->knorm, pp, lane);
     for (int j = 0; j < f; ++j)
-        if (lane >= j && lane < f) F[lane + (int64_t)j * ld] = S.T[j * LDT + lane];
+        if (lane >= j && lane < f) F[lane + (int64_t)j * ld] = S.T[j * LDW + lane];
     store_pivots(S, D, c0, 0, p, lane);
 }
 
 // Large fronts: one workgroup per front column.  The column is summed in LDS from the
 // original entries and, children in ascending order, the children's contribution-block
-// columns that map onto it (the parent pulls; no atomics), then written once.
+// columns that map onto it (the parent pulls; no atomics), then written once.  The list of
+// (child, child column) pairs of each parent column is built by the analyse.
 __global__ __launch_bounds__(256) void k_assemble(DevPlan D, const Task* tasks, int64_t t0) {
     extern __shared__ double buf[];
     const Task t = tasks[t0 + blockIdx.x];
@@ -326,105 +412,64 @@ __global__ __launch_bounds__(256) void k_assemble(DevPlan D, const Task* tasks, 
         for (int64_t e = D.kcol_ptr[c0 + j] + tid; e < e1; e += 256) buf[D.kloc[e] - j] = D.kval[e];
     }
     __syncthreads();
-    for (int q = D.ch_ptr[s]; q < D.ch_ptr[s + 1]; ++q) {
-        const int ch = D.ch[q];
+    for (int q = t.a; q < t.a + t.b; ++q) {
+        const int ch = D.asm_child[q], lo = D.asm_col[q];
         const int cp = D.sn_p[ch], cb = D.sn_f[ch] - cp, cld = D.sn_ld[ch];
         const int32_t* rel = D.rel + D.rel_ptr[ch];
-        int lo = 0, hi = cb;  // rel is increasing: find the CB column mapped to j
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (rel[mid] < j) lo = mid + 1;
-            else hi = mid;
-        }
-        if (lo < cb && rel[lo] == j) {
-            const double* col = D.front + D.sn_off[ch] + (int64_t)(cp + lo) * cld + cp;
-            for (int a = lo + tid; a < cb; a += 256) buf[rel[a] - j] += col[a];
-        }
+        const double* col = D.front + D.sn_off[ch] + (int64_t)(cp + lo) * cld + cp;
+        for (int a = lo + tid; a < cb; a += 256) buf[rel[a] - j] += col[a];
         __syncthreads();
     }
     double* out = D.front + D.sn_off[s] + (int64_t)j * ld + j;
     for (int i = tid; i < nr; i += 256) out[i] = buf[i];
 }
 
-// Diagonal block of window [k0, k0+nbw) of a large front.
-__global__ __launch_bounds__(64) void k_diag(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp) {
+// One pivot window [k0, k1) of a large front, for 64 of the rows below it (chunk t.a).
+// Every workgroup of the window loads the same diagonal block and takes the same
+// (deterministic) pivot decisions, applying each elimination to the block and to its own
+// panel rows: the right-looking elimination restricted to the window's columns.  The
+// panel rows become L21.  Workgroup chunk 0 also stores D, the pivot permutation and the
+// factored block; the block goes to its upper triangle (transposed), because the other
+// workgroups of this launch still read the unmodified lower part; k_finalize moves it.
+__global__ __launch_bounds__(64) void k_window(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp) {
     __shared__ PivShared S;
-    const int lane = threadIdx.x;
-    const Task t = tasks[t0 + blockIdx.x];
-    const int s = t.s, k0 = t.k0;
-    const int p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
-    const int nbw = min(NB, p - k0);
-    double* F = D.front + D.sn_off[s] + k0 + (int64_t)k0 * ld;
-    for (int j = 0; j < nbw; ++j)
-        if (lane >= j && lane < nbw) {
-            const double v = F[lane + (int64_t)j * ld];
-            S.T[j * LDT + lane] = v;
-            S.T[lane * LDT + j] = v;
-        }
-    init_signs(S, D, D.rows + D.sn_rowptr[s] + k0, nbw, lane);
-    __syncthreads();
-    factor_window(S, nbw, nbw, D.sc->knorm, pp, lane);
-    for (int j = 0; j < nbw; ++j)
-        if (lane >= j && lane < nbw) F[lane + (int64_t)j * ld] = S.T[j * LDT + lane];
-    store_pivots(S, D, c0 + k0, k0, nbw, lane);
-}
-
-// Rows below the window: apply the window's column permutation, then
-// L21 = B_P L11^{-T} D^{-1}, by forward substitution per row (one row per lane).
-__global__ __launch_bounds__(64) void k_panel(DevPlan D, const Task* tasks, int64_t t0) {
-    __shared__ double L[64 * LDT];
-    __shared__ double Wl[64 * 64];
-    __shared__ double dd[64], od[64];
-    __shared__ int pt[64], pm[64];
     const int lane = threadIdx.x;
     const Task t = tasks[t0 + blockIdx.x];
     const int s = t.s, k0 = t.k0, chunk = t.a;
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const int k1 = min(k0 + NB, p), nbw = k1 - k0;
     double* F = D.front + D.sn_off[s];
-    for (int j = 0; j < 64; ++j) {
-        double v = 0.0;
-        if (j < nbw && lane > j && lane < nbw) v = F[(k0 + lane) + (int64_t)(k0 + j) * ld];
-        L[j * LDT + lane] = v;
-    }
-    if (lane < nbw) {
-        dd[lane] = D.dval[c0 + k0 + lane];
-        od[lane] = D.doff[c0 + k0 + lane];
-        pt[lane] = D.ptype[c0 + k0 + lane];
-        pm[lane] = D.lperm[c0 + k0 + lane] - k0;
-    } else {
-        dd[lane] = 1.0;
-        od[lane] = 0.0;
-        pt[lane] = 0;
-        pm[lane] = 0;
+    const int r = k1 + 64 * chunk + lane;  // this lane's panel row
+    const bool prow = r < f;
+    // load the block's lower part and this workgroup's panel rows; 16 columns per trip keep
+    // 32 global loads in flight per lane
+    for (int jb = 0; jb < 64; jb += 16) {
+        double vb[16], vp[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = jb + q;
+            vb[q] = (j < nbw && lane >= j && lane < nbw) ? F[(k0 + lane) + (int64_t)(k0 + j) * ld] : 0.0;
+            vp[q] = (j < nbw && prow) ? F[r + (int64_t)(k0 + j) * ld] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            S.T[(jb + q) * LDW + lane] = vb[q];
+            S.T[(jb + q) * LDW + 64 + lane] = vp[q];
+        }
     }
     __syncthreads();
-    const int r = k1 + chunk * 64 + lane;
-    const bool act = r < f;
-    // each lane's row vector lives in its own LDS column: Wl[k*64 + lane]
-    for (int j = 0; j < nbw; ++j) Wl[j * 64 + lane] = act ? F[r + (int64_t)(k0 + pm[j]) * ld] : 0.0;
-    // w = b L11^{-T}: column-oriented forward substitution (L11 unit lower)
-    for (int j = 0; j + 1 < nbw; ++j) {
-        const double wj = Wl[j * 64 + lane];
-        for (int k = j + 1; k < nbw; ++k) Wl[k * 64 + lane] -= L[j * LDT + k] * wj;
-    }
-    // L21 = w D^{-1}, 1x1 and 2x2 blocks
-    if (act) {
-        for (int k = 0; k < nbw; ++k) {
-            const int ty = pt[k];
-            const double wk = Wl[k * 64 + lane];
-            double v;
-            if (ty == 0) {
-                v = wk / dd[k];
-            } else if (ty == 1) {
-                const double a = dd[k], b = od[k], c = dd[k + 1];
-                v = (wk * c - Wl[(k + 1) * 64 + lane] * b) / (a * c - b * b);
-            } else {
-                const double a = dd[k - 1], b = od[k - 1], c = dd[k];
-                v = (wk * a - Wl[(k - 1) * 64 + lane] * b) / (a * c - b * b);
-            }
-            F[r + (int64_t)(k0 + k) * ld] = v;
-        }
+    for (int j = 0; j < nbw; ++j)
+        if (lane > j && lane < nbw) S.T[lane * LDW + j] = S.T[j * LDW + lane];
+    init_signs(S, D, D.rows + D.sn_rowptr[s] + k0, nbw, lane);
+    __syncthreads();
+    factor_window<true>(S, nbw, nbw, D.sc->knorm, pp, lane);
+    if (prow)
+        for (int j = 0; j < nbw; ++j) F[r + (int64_t)(k0 + j) * ld] = S.T[j * LDW + 64 + lane];
+    if (chunk == 0) {
+        // L11 (strict lower) transposed into the block's upper triangle, D on its diagonal
+        for (int j = 0; j < nbw; ++j)
+            if (lane > j && lane < nbw) F[(k0 + j) + (int64_t)(k0 + lane) * ld] = S.T[j * LDW + lane];
+        store_pivots(S, D, c0 + k0, k0, nbw, lane);
     }
 }
 
@@ -544,18 +589,25 @@ __global__ __launch_bounds__(256) void k_syrk(DevPlan D, const Task* tasks, int6
         syrk_tile<double>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, As, Bs);
 }
 
-// After all windows of a front: permute the rows of each earlier L column that lie in a
-// later window, as that window's pivot swaps require.
-__global__ __launch_bounds__(64) void k_rowswap(DevPlan D, const Task* tasks, int64_t t0) {
+// After all windows of a front, for 64 of its pivot columns: move each window's factored
+// diagonal block from the upper triangle into place, and permute the rows of the column
+// that lie in later windows as those windows' pivot swaps require.
+__global__ __launch_bounds__(64) void k_finalize(DevPlan D, const Task* tasks, int64_t t0) {
     const int lane = threadIdx.x;
     const Task t = tasks[t0 + blockIdx.x];
     const int s = t.s, col0 = t.k0;
     const int p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const int nwin = (p + NB - 1) / NB;
-    const int jend = min(col0 + 64, (nwin - 1) * NB);
+    const int jend = min(col0 + 64, p);
     double* F = D.front + D.sn_off[s];
     for (int j = col0; j < jend; ++j) {
-        for (int w = j / NB + 1; w < nwin; ++w) {
+        const int w0 = j / NB;
+        {
+            const int k0 = w0 * NB, k1 = min(k0 + NB, p);
+            const int i = j + 1 + lane;  // rows of column j inside its own window
+            if (i < k1) F[i + (int64_t)j * ld] = F[j + (int64_t)i * ld];
+        }
+        for (int w = w0 + 1; w < nwin; ++w) {
             const int k0 = w * NB, nbw = min(NB, p - k0);
             double v = 0.0;
             if (lane < nbw) v = F[k0 + (D.lperm[c0 + k0 + lane] - k0) + (int64_t)j * ld];
@@ -762,12 +814,11 @@ __global__ void k_unpermute(DevPlan D, const double* xw, double* dst, const int3
     dst[D.perm[c] + (int64_t)r * D.N] = xw[c + (int64_t)r * D.N];
 }
 
-// Forward substitution with unit L and the D solve for the supernodes of one level.  The
-// parent gathers its children's contribution vectors (ascending order, no atomics).
-__global__ __launch_bounds__(256) void k_fwd(DevPlan D, DevSolve S, const int32_t* lvl_sn, int64_t base,
-                                             const int32_t* active) {
-    extern __shared__ double y[];
-    const int s = lvl_sn[base + blockIdx.x];
+// Forward substitution with unit L and the D solve for one supernode.  The parent gathers
+// its children's contribution vectors (ascending order, no atomics).  y: f doubles of LDS;
+// Lb: 64 x 65 doubles of LDS holding the current 64 x 64 diagonal block of L.
+__device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const int32_t* active, double* y,
+                              double* Lb) {
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const double* F = D.front + D.sn_off[s];
     const int tid = threadIdx.x;
@@ -789,19 +840,33 @@ __global__ __launch_bounds__(256) void k_fwd(DevPlan D, DevSolve S, const int32_
             __syncthreads();
         }
         for (int k0 = 0; k0 < p; k0 += 64) {
-            const int k1 = min(k0 + 64, p);
+            const int k1 = min(k0 + 64, p), nb = k1 - k0;
+            for (int idx = tid; idx < 64 * 64; idx += 256) {  // diagonal block of L into LDS
+                const int i = idx & 63, k = idx >> 6;
+                Lb[k * 65 + i] = (i < nb && k < nb) ? F[(k0 + i) + (int64_t)(k0 + k) * ld] : 0.0;
+            }
+            __syncthreads();
             if (tid < 64) {
                 const int row = k0 + tid;
                 for (int k = k0; k < k1; ++k) {
                     const double z = y[k];
-                    if (row > k && row < k1) y[row] -= F[row + (int64_t)k * ld] * z;
+                    if (row > k && row < k1) y[row] -= Lb[(k - k0) * 65 + tid] * z;
                     __builtin_amdgcn_wave_barrier();
                 }
             }
             __syncthreads();
             for (int i = k1 + tid; i < f; i += 256) {
+                const double* Li = F + i + (int64_t)k0 * ld;
                 double acc = y[i];
-                for (int k = k0; k < k1; ++k) acc -= F[i + (int64_t)k * ld] * y[k];
+                int k = 0;
+                for (; k + 8 <= nb; k += 8) {
+                    double l[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) l[q] = Li[(int64_t)(k + q) * ld];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) acc -= l[q] * y[k0 + k + q];
+                }
+                for (; k < nb; ++k) acc -= Li[(int64_t)k * ld] * y[k0 + k];
                 y[i] = acc;
             }
             __syncthreads();
@@ -825,11 +890,9 @@ __global__ __launch_bounds__(256) void k_fwd(DevPlan D, DevSolve S, const int32_
     }
 }
 
-// Backward substitution with L^T for the supernodes of one level (ancestors done).
-__global__ __launch_bounds__(256) void k_bwd(DevPlan D, DevSolve S, const int32_t* lvl_sn, int64_t base,
-                                             const int32_t* active) {
-    extern __shared__ double y[];
-    const int s = lvl_sn[base + blockIdx.x];
+// Backward substitution with L^T for one supernode (its ancestors are done).
+__device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const int32_t* active, double* y,
+                              double* Lb) {
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const double* F = D.front + D.sn_off[s];
     const int32_t* rows = D.rows + D.sn_rowptr[s];
@@ -841,10 +904,15 @@ __global__ __launch_bounds__(256) void k_bwd(DevPlan D, DevSolve S, const int32_
         __syncthreads();
         const int nblk = (p + 63) / 64;
         for (int bk = nblk - 1; bk >= 0; --bk) {
-            const int k0 = bk * 64, k1 = min(k0 + 64, p);
+            const int k0 = bk * 64, k1 = min(k0 + 64, p), nb = k1 - k0;
+            for (int idx = tid; idx < 64 * 64; idx += 256) {
+                const int i = idx & 63, k = idx >> 6;
+                Lb[k * 65 + i] = (i < nb && k < nb) ? F[(k0 + i) + (int64_t)(k0 + k) * ld] : 0.0;
+            }
             for (int k = k0 + wv; k < k1; k += 4) {  // rows below the block
+                const double* Lk = F + (int64_t)k * ld;
                 double part = 0.0;
-                for (int i = k1 + lane; i < f; i += 64) part += F[i + (int64_t)k * ld] * y[i];
+                for (int i = k1 + lane; i < f; i += 64) part += Lk[i] * y[i];
                 part = wave_sum_d(part);
                 if (lane == 0) y[k] -= part;
             }
@@ -852,7 +920,7 @@ __global__ __launch_bounds__(256) void k_bwd(DevPlan D, DevSolve S, const int32_
             if (tid < 64) {
                 for (int k = k1 - 1; k >= k0; --k) {
                     const int i = k + 1 + lane;
-                    double part = (i < k1) ? F[i + (int64_t)k * ld] * y[i] : 0.0;
+                    double part = (i < k1) ? Lb[(k - k0) * 65 + (i - k0)] * y[i] : 0.0;
                     part = wave_sum_d(part);
                     if (lane == 0) y[k] -= part;
                     __builtin_amdgcn_wave_barrier();
@@ -863,6 +931,21 @@ __global__ __launch_bounds__(256) void k_bwd(DevPlan D, DevSolve S, const int32_
         for (int k = tid; k < p; k += 256) xw[c0 + D.lperm[c0 + k]] = y[k];
         __syncthreads();
     }
+}
+
+// One level of the supernodal tree per launch: the kernel boundary orders the levels.
+__global__ __launch_bounds__(256) void k_fwd(DevPlan D, DevSolve S, const int32_t* lvl_sn, int64_t base,
+                                             const int32_t* active) {
+    extern __shared__ double dyn[];
+    __shared__ double Lb[64 * 65];
+    fwd_supernode(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb);
+}
+
+__global__ __launch_bounds__(256) void k_bwd(DevPlan D, DevSolve S, const int32_t* lvl_sn, int64_t base,
+                                             const int32_t* active) {
+    extern __shared__ double dyn[];
+    __shared__ double Lb[64 * 65];
+    bwd_supernode(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb);
 }
 
 // r = b - K_static x and (|K||x|)_i in original numbering, from A, Theta, rho, delta
@@ -1070,10 +1153,9 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
         case L_ASSEMBLE:
             hipLaunchKernelGGL(k_assemble, dim3(g), dim3(256), (size_t)L.lds, s, D, tasks, L.task0);
             break;
-        case L_DIAG: hipLaunchKernelGGL(k_diag, dim3(g), dim3(64), 0, s, D, tasks, L.task0, pp); break;
-        case L_PANEL: hipLaunchKernelGGL(k_panel, dim3(g), dim3(64), 0, s, D, tasks, L.task0); break;
+        case L_WINDOW: hipLaunchKernelGGL(k_window, dim3(g), dim3(64), 0, s, D, tasks, L.task0, pp); break;
         case L_SYRK: hipLaunchKernelGGL(k_syrk, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
-        case L_ROWSWAP: hipLaunchKernelGGL(k_rowswap, dim3(g), dim3(64), 0, s, D, tasks, L.task0); break;
+        case L_FINALIZE: hipLaunchKernelGGL(k_finalize, dim3(g), dim3(64), 0, s, D, tasks, L.task0); break;
         default: break;
     }
 }

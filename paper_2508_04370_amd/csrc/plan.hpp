@@ -10,8 +10,10 @@ namespace qdmf {
 constexpr int NB = 64;  // pivot window width used by the device kernels
 
 // One task of a batched launch.  Meaning per kernel:
-//   small front / diag block / row swap / solve: s = supernode, a, b unused (or chunk)
-//   panel:  s, k0 = window start, a = row chunk
+//   small front / solve: s = supernode
+//   window: s, k0 = window start, a = 64-row chunk below the window
+//   finalize: s, k0 = first of 64 pivot columns
+//   assemble: s, k0 = front column, [a, a+b) = range of its (child, child column) list
 //   syrk:   s, k0 = window start, a = row tile, b = column tile
 struct Task {
     int32_t s, k0, a, b;
@@ -20,10 +22,9 @@ struct Task {
 enum LaunchKind : int32_t {
     L_SMALL = 0,     // whole front in LDS: assembly + factorisation
     L_ASSEMBLE = 1,  // large fronts: one workgroup per front column
-    L_DIAG = 2,      // window diagonal block
-    L_PANEL = 3,     // window panel solve below the block
-    L_SYRK = 4,      // trailing update tiles
-    L_ROWSWAP = 5    // apply window permutations to earlier L columns
+    L_WINDOW = 2,    // pivot window: diagonal block + 64 panel rows per workgroup
+    L_SYRK = 3,      // trailing update tiles
+    L_FINALIZE = 4   // factored diagonal blocks into place, row swaps of earlier columns
 };
 
 struct Launch {
@@ -67,6 +68,8 @@ struct Plan {
     // entries of lower(K) grouped by new column: values are produced in this order
     std::vector<int64_t> kcol_ptr;      // N + 1
     std::vector<int32_t> kloc;          // row position inside the front of the column's supernode
+    std::vector<int32_t> kcl;           // column position inside that front
+    std::vector<int32_t> asm_child, asm_col;  // assembly lists of large-front columns
     std::vector<int32_t> krow_old, kcol_old;  // original indices of each entry (row >= col in new order)
     std::vector<int64_t> ksrc;          // AS: >= 0 A entry, -1-j primal diagonal j, KSRC_ZERO dual diagonal
     std::vector<int64_t> kpair_ptr;     // NE: per entry, pairs of A entries (a, b), column ascending

@@ -118,10 +118,14 @@ def test_ne_with_r7_recovers_dx(torch_dev):
     assert nw <= 1e-11, nw
 
 
-def test_matched_mode_reproduces_oracle_pivots(torch_dev):
+@pytest.mark.parametrize("trange,reg", [((1e-10, 1e10), 1e-10), ((1e-1, 1e1), 1e-2)])
+def test_matched_mode_reproduces_oracle_pivots(torch_dev, trange, reg):
     """Oracle ordering fed to the GPU with fundamental supernodes: same supernodes and
-    windows, so the pivot sequence, D and L must match the oracle's (to rounding)."""
-    lp = W.as_staircase(periods=3, rows=40, cols=80, link_cols=8, seed=9)
+    windows, so every pivot decision (order, 1x1/2x2, regularisation flags) must match the
+    oracle exactly.  Pivot values agree to rounding amplified by conditioning: on the
+    well-conditioned case they must agree to 1e-12 relative."""
+    lp = W.as_staircase(periods=3, rows=40, cols=80, link_cols=8, seed=9, theta_range=trange,
+                        rho=reg, delta=reg)
     S = O.Sym(lp)
     perm = S.perm()
     g = gpu_solve(torch_dev, lp, perm=perm, amalgamate=0)
@@ -135,19 +139,14 @@ def test_matched_mode_reproduces_oracle_pivots(torch_dev):
     print("pivot order agreement", agree)
     assert agree == 1.0
     assert np.array_equal(gd["ptype"], ex["ptype"])
-    # both are backward stable: pivots may differ by rounding amplified through the
-    # elimination, bounded by c f u (|L||D||L^T|)_kk (Higham, LDL^T error analysis)
-    Lm = ex["L"]
-    Dm = np.diag(np.abs(ex["d"]))
-    for k in np.nonzero(ex["ptype"] == 1)[0]:
-        Dm[k, k + 1] = Dm[k + 1, k] = abs(ex["doff"][k])
-    scale = np.diag(np.abs(Lm) @ Dm @ np.abs(Lm).T)
-    fmax = s.sym["max_front"]
-    dd = np.abs(gd["d"] - ex["d"])
-    print("max |d_gpu - d_oracle| / (|L||D||L^T|)_kk =", (dd / scale).max())
-    assert np.all(dd <= 50 * fmax * U * scale)
-    assert np.allclose(gd["edyn"], ex["edyn"], rtol=1e-6, atol=1e-300) or np.all(
-        np.abs(gd["edyn"] - ex["edyn"]) <= 50 * fmax * U * scale)
+    assert np.array_equal(gd["edyn"] != 0, ex["edyn"] != 0)
+    rel = np.abs(gd["d"] - ex["d"]) / np.abs(ex["d"])
+    k = int(rel.argmax())
+    print("max relative pivot difference", rel.max(), "at", k, gd["d"][k], ex["d"][k], ex["ptype"][k])
+    if trange[0] >= 1e-1:
+        assert rel.max() <= 1e-12
+    else:
+        assert rel.max() <= 1e-6
 
 
 def test_full_staircase_fp64(torch_dev):
@@ -205,10 +204,85 @@ def test_factor_backward_stable_and_solve_matches_its_factor(torch_dev, amalgama
     scale = np.abs(L) @ np.abs(D) @ np.abs(L).T
     print("reconstruction error / (|L||D||L^T|)_max:", np.abs(R).max() / scale.max())
     assert np.abs(R).max() <= 100 * s.sym["max_front"] * U * scale.max()
-    b = np.concatenate([lp["r7"][:, 0], lp["r1"][:, 0]])
-    y = sla.solve_triangular(L, b[po], lower=True, unit_diagonal=True)
-    w = sla.solve_triangular(L.T, np.linalg.solve(D, y), lower=False, unit_diagonal=True)
-    xf = np.empty(N)
-    xf[po] = w
-    x = system_x(lp, g["dx"][:, 0], g["dy"][:, 0])
-    assert np.abs(x - xf).max() <= 1e-8 * np.abs(xf).max()
+    # the GPU's forward/D/backward solves are backward stable for its own factor:
+    # ||b - L D L^T x||_inf <= c f u (|| |L||D||L^T| ||_inf ||x||_inf + ||b||_inf)
+    b = np.concatenate([lp["r7"][:, 0], lp["r1"][:, 0]])[po]
+    x = system_x(lp, g["dx"][:, 0], g["dy"][:, 0])[po]
+    r = b - L @ (D @ (L.T @ x))
+    bound = np.abs(scale).sum(axis=1).max() * np.abs(x).max() + np.abs(b).max()
+    print("solve backward error vs own factor:", np.abs(r).max() / bound)
+    assert np.abs(r).max() <= 100 * s.sym["max_front"] * U * bound
+
+
+def test_multiple_rhs(torch_dev):
+    lp = W.as_staircase(periods=4, rows=50, cols=100, link_cols=10, nrhs=3)
+    g = gpu_solve(torch_dev, lp)
+    check_against_oracle(lp, g)
+
+
+@pytest.mark.parametrize("lpname", ["dense_ne", "staircase"])
+def test_mixed_precision_refines_to_target(torch_dev, lpname):
+    """FP32 MFMA Schur updates on every large front (f_mix lowered so they apply here);
+    FP64 refinement must bring the normwise backward error to <= 1e-10."""
+    if lpname == "dense_ne":
+        lp = W.ne_random(m=300, n=600, density=0.08, seed=22)
+    else:
+        lp = W.as_staircase(periods=6, rows=120, cols=240, link_cols=30, seed=23)
+    g64 = gpu_solve(torch_dev, lp, prec=0, f_mix=65)
+    gmx = gpu_solve(torch_dev, lp, prec=1, f_mix=65)
+    assert gmx["solver"].sym["max_front"] >= 65
+    ss = gmx["sstats"]
+    print(f"mixed: initial berr {ss['berr_nw_initial']:.2e} final {ss['berr_nw']:.2e} steps {ss['max_steps']}; "
+          f"fp64 initial {g64['sstats']['berr_nw_initial']:.2e}")
+    r7 = lp["r7"][:, 0] if lp["mode"] == W.AS else None
+    x = system_x(lp, gmx["dx"][:, 0], gmx["dy"][:, 0])
+    nw, _ = oracle_berr(lp, lp["theta"], x, r7, lp["r1"][:, 0])
+    assert nw <= 1e-10, nw
+    # the FP32 updates really ran: the unrefined mixed solution is less accurate
+    assert ss["berr_nw_initial"] > g64["sstats"]["berr_nw_initial"]
+    fs = gmx["fstats"]
+    if lp["mode"] == W.AS:
+        assert (fs["nneg"], fs["npos"]) == (lp["n"], lp["m"])
+
+
+def test_graph_replay_matches_eager(torch_dev):
+    """factorise + 2 solves captured once; replays read refreshed Theta and rhs in place
+    and must reproduce the eager results bitwise, every replay."""
+    torch, dev = torch_dev
+    from paper_2508_04370_amd import qdmf as Q
+    lp = W.as_staircase(periods=4, rows=50, cols=100, link_cols=10)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = Q.Solver(lp, device=0, stream=stream.cuda_stream)
+        th = torch.empty(lp["n"], dtype=torch.float64, device=dev)
+        r7 = torch.empty((1, lp["n"]), dtype=torch.float64, device=dev).T
+        r1 = torch.empty((1, lp["m"]), dtype=torch.float64, device=dev).T
+        dx = torch.empty((1, lp["n"]), dtype=torch.float64, device=dev).T
+        dy = torch.empty((1, lp["m"]), dtype=torch.float64, device=dev).T
+
+        def refresh(k):
+            g = W.rng(55, k)
+            th.copy_(torch.from_numpy(W.log_uniform(g, 1e-10, 1e10, lp["n"])))
+            r7.copy_(torch.from_numpy(g.standard_normal((lp["n"], 1))))
+            r1.copy_(torch.from_numpy(g.standard_normal((lp["m"], 1))))
+
+        refresh(0)
+        Q.qdmf_graph_capture(s.h, th, lp["rho"], lp["delta"], 0, 2, 1, r7, r1, dx, dy)
+        for k in range(3):
+            refresh(k)
+            stream.synchronize()
+            Q.qdmf_graph_launch(s.h)
+            stream.synchronize()
+            gx, gy = dx.cpu().numpy().copy(), dy.cpu().numpy().copy()
+            # eager on a fresh handle with the same inputs
+            e = Q.Solver(lp, device=0, stream=stream.cuda_stream)
+            e.factorise(th, lp["rho"], lp["delta"], 0)
+            ex, ey = e.solve(r7, r1)
+            e.solve(r7, r1, ex, ey)
+            stream.synchronize()
+            assert np.array_equal(gx, ex.cpu().numpy()) and np.array_equal(gy, ey.cpu().numpy()), k
+            x = np.concatenate([gx[:, 0], gy[:, 0]])
+            nw, _ = oracle_berr(lp, th.cpu().numpy(), x, r7.cpu().numpy()[:, 0], r1.cpu().numpy()[:, 0])
+            assert nw <= 1e-12
+            e.close()
+        s.close()
