@@ -4,6 +4,10 @@ One step = one IPM-like iteration on the staircase augmented system (20000 x 400
 40 periods): a fresh Theta (already resident in HBM), the numeric factorisation, and the
 predictor and one corrector solve (Section 4.7: 1 + k directions with k >= 1), each refined
 in FP64 to the target backward error.  Prints one JSON line.
+
+The roofline object describes the kernel kind that takes the most time in a step: its
+launches inside the timed region are bracketed with HIP events on the library's stream and
+its algorithmic work per launch comes from the symbolic structure.
 """
 from __future__ import annotations
 
@@ -20,9 +24,12 @@ sys.path.insert(0, ROOT)
 
 from paper_2508_04370_amd import workloads as W  # noqa: E402
 
-PEAK_FP64 = 78.6e12   # MI355X dense FP64 (matrix = vector) FLOP/s
-PEAK_FP32 = 157.3e12
-PEAK_HBM = 8.0e12     # bytes/s
+PEAK_FP64 = 78.6e12   # MI355X dense FP64, matrix and vector (FLOP/s)
+PEAK_FP32 = 157.3e12  # dense FP32 matrix (FLOP/s)
+PEAK_HBM = 8.0e12     # HBM3E (bytes/s)
+
+# which resource bounds each kernel kind ("Kernels and their rooflines")
+KIND_BOUND = {0: "alu", 1: "hbm", 2: "alu", 3: "mfma", 4: "hbm", 5: "hbm", 6: "hbm"}
 
 
 def make_workload(name):
@@ -33,6 +40,12 @@ def make_workload(name):
     if name == "ne_grid":
         lp = W.ne_grid(nrhs=8)
         return lp, dict(ordering=2, grid=lp["grid"])
+    if name == "ne_grid_small":
+        lp = W.ne_grid(24, 24, 20, nrhs=8)
+        return lp, dict(ordering=2, grid=lp["grid"])
+    if name == "as_dense_cols":
+        lp = W.as_dense_cols()
+        return lp, dict(ordering=2, grid=lp["grid"])
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -42,13 +55,15 @@ def thetas(lp, k, seed):
     return W.log_uniform(g, lo, hi, lp["n"])
 
 
-def run_gpu(lp, opts, prec, steps, warmup, nsolves):
+def run_gpu(lp, opts, prec, steps, warmup, nsolves, graph):
     import torch
     from paper_2508_04370_amd import qdmf as Q
     dev = "cuda:0"
-    s = Q.Solver(lp, device=0, **opts)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    s = Q.Solver(lp, device=0, stream=stream.cuda_stream, **opts)
     sym = s.sym
-    nth = warmup + steps
+    nth = warmup + steps + 8
     TH = [torch.from_numpy(thetas(lp, k, 7)).to(dev) for k in range(nth)]
     r1 = Q.to_device_colmajor(lp["r1"], dev)
     r7 = Q.to_device_colmajor(lp["r7"], dev) if lp["mode"] == W.AS else None
@@ -57,19 +72,27 @@ def run_gpu(lp, opts, prec, steps, warmup, nsolves):
     dy = torch.empty((nrhs, lp["m"]), dtype=torch.float64, device=dev).T
 
     def one(k):
-        s.factorise(TH[k], lp["rho"], lp["delta"], prec)
+        s.factorise(TH[k % nth], lp["rho"], lp["delta"], prec)
         for _ in range(nsolves):
             s.solve(r7, r1, dx, dy)
 
     for k in range(warmup):
         one(k)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
+    stream.synchronize()
+    # the dominant kernel kind: one profiled step per kind
+    per_kind = {}
+    for kind in range(7):
+        Q.qdmf_profile_kind(s.h, kind)
+        one(warmup + steps + (kind % 8))
+        per_kind[kind] = Q.qdmf_profile_read(s.h)
+    Q.qdmf_profile_kind(s.h, -1)
+    dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
+    # timed region, the dominant kind bracketed by events
+    Q.qdmf_profile_kind(s.h, dom)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    per = []
-    steps_taken = []
-    berrs = []
+    per, steps_taken, berrs = [], [], []
+    stream.synchronize()
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
         e0.record(stream)
@@ -80,14 +103,33 @@ def run_gpu(lp, opts, prec, steps, warmup, nsolves):
         ss = s.solve_stats(nrhs)
         steps_taken.append(int(ss["max_steps"]))
         berrs.append(float(ss["berr_nw"]))
-    torch.cuda.synchronize()
+    stream.synchronize()
     wall = time.perf_counter() - t0
+    prof = Q.qdmf_profile_read(s.h)
+    Q.qdmf_profile_kind(s.h, -1)
     fs = s.factor_stats()
+    out = dict(ms=per, wall=wall, sym=sym, steps=steps_taken, berr=berrs, fstats=fs, dom=dom, prof=prof,
+               per_kind={Q.KERNEL_KIND_NAMES[k]: round(v["total_ms"], 3) for k, v in per_kind.items()})
+    if graph:  # the same step captured once as a HIP graph and replayed with Theta refreshed
+        th = torch.empty(lp["n"], dtype=torch.float64, device=dev)
+        th.copy_(TH[0])
+        Q.qdmf_graph_capture(s.h, th, lp["rho"], lp["delta"], prec, nsolves, nrhs, r7, r1, dx, dy)
+        gms = []
+        for k in range(warmup + steps):
+            e0.record(stream)
+            th.copy_(TH[k % nth])
+            Q.qdmf_graph_launch(s.h)
+            e1.record(stream)
+            e1.synchronize()
+            if k >= warmup:
+                gms.append(e0.elapsed_time(e1))
+        out["graph_ms"] = gms
+        out["graph_berr"] = float(s.solve_stats(nrhs)["berr_nw"])
     s.close()
-    return dict(ms=per, wall=wall, sym=sym, steps=steps_taken, berr=berrs, fstats=fs)
+    return out
 
 
-def cpu_baseline(lp, budget_s=30.0):
+def cpu_baseline(lp):
     """The oracle (plain C, one thread) on the same workload: factorise + one solve."""
     from oracle import oracle as O
     O.build(force=False)
@@ -96,12 +138,14 @@ def cpu_baseline(lp, budget_s=30.0):
     t0 = time.perf_counter()
     F = O.Num(S, lp["val"], th, lp["rho"], lp["delta"])
     r7 = lp["r7"] if lp["mode"] == W.AS else None
-    F.solve(r7, lp["r1"])
+    res = F.solve(r7, lp["r1"])
     t = time.perf_counter() - t0
-    flops = S.flops + 4.0 * S.nnzL * lp["r1"].shape[1]
-    return dict(value=flops / t / 1e9, unit="GFLOP/s", cores=1, kind="oracle",
-                seconds=t, sample="one factorise + one solve (with refinement) of the full workload; "
-                "ordering/analysis excluded", ms_per_factorise_solve=t * 1e3)
+    nrhs = lp["r1"].shape[1]
+    flops = S.flops + (1 + float(np.mean(res["steps"]))) * nrhs * (4.0 * (S.nnzL - S.N) + S.N)
+    return dict(value=round(flops / t / 1e9, 4), unit="GFLOP/s", cores=1, kind="oracle",
+                sample="one factorise + one solve with refinement of the full workload on one host "
+                       "core (ordering and symbolic analysis excluded)",
+                seconds=round(t, 3), ms_per_factorise_solve=round(t * 1e3, 1))
 
 
 def main():
@@ -112,25 +156,41 @@ def main():
     ap.add_argument("--workload", default="as_staircase")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--nsolves", type=int, default=2)
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: multi-GPU execution is not part of this build "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+              "(DESIGN.md describes how the factorisation would shard)", file=sys.stderr)
         sys.exit(2)
     lp, opts = make_workload(args.workload)
     prec = 1 if args.prec == "mixed" else 0
     print(f"[bench] workload={lp['name']} prec={args.prec} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
-    r = run_gpu(lp, opts, prec, args.steps, args.warmup, args.nsolves)
+    r = run_gpu(lp, opts, prec, args.steps, args.warmup, args.nsolves, not args.no_graph)
     sym = r["sym"]
     ms = float(np.median(r["ms"]))
     nrhs = lp["r1"].shape[1]
     nnz_a = int(lp["colptr"][-1])
-    # algorithmic work of one step: factorisation + every solve pass and residual
+    # algorithmic work of one step (exact structure of L): factorisation, every solve pass
+    # (the first solve and each refinement step) and each residual
     solve_passes = args.nsolves * (1 + float(np.mean(r["steps"])))
     flops = sym["flops_fact"] + solve_passes * nrhs * (sym["flops_solve"] + 4.0 * nnz_a + 2.0 * sym["N"])
     value = flops / (ms * 1e-3) / 1e9
+    from paper_2508_04370_amd import qdmf as Q
+    dom = r["dom"]
+    pr = r["prof"]
+    avg_ms = pr["total_ms"] / max(1, pr["launches"])
+    bound = KIND_BOUND[dom]
+    if bound == "hbm":
+        per_launch = pr["bytes"] / max(1, pr["launches"])
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        peak, unit = PEAK_HBM / 1e9, "GB/s"
+    else:
+        per_launch = pr["flops"] / max(1, pr["launches"])
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        peak = (PEAK_FP32 if (bound == "mfma" and prec == 1) else PEAK_FP64) / 1e12
+        unit = "TFLOP/s"
     out = {
         "metric": "factorise+solve GFLOP/s (ms per IPM iteration alongside)",
         "value": round(value, 3),
@@ -147,12 +207,22 @@ def main():
         "config": {"workload": lp["name"], "m": lp["m"], "n": lp["n"], "mode": "AS" if lp["mode"] else "NE",
                    "nrhs": nrhs, "solves_per_step": args.nsolves, "precision": args.prec,
                    "N": sym["N"], "nsuper": sym["nsuper"], "nlevels": sym["nlevels"],
-                   "max_front": sym["max_front"], "flops_fact": sym["flops_fact"]},
+                   "max_front": sym["max_front"], "flops_fact": sym["flops_fact"],
+                   "nnz_l": sym["nnz_l"]},
+        "roofline": {"bound": bound, "kernel": Q.KERNEL_KIND_NAMES[dom], "achieved": round(achieved, 6),
+                     "peak": peak, "unit": unit, "frac": round(achieved / peak, 6), "traffic": None,
+                     "launches": pr["launches"], "avg_launch_us": round(avg_ms * 1e3, 3),
+                     "work_per_launch": round(per_launch, 1)},
+        "kernel_ms_per_step_by_kind": r["per_kind"],
         "berr_nw_max": max(r["berr"]),
         "refine_steps_mean": float(np.mean(r["steps"])),
         "ms_min": round(min(r["ms"]), 4), "ms_max": round(max(r["ms"]), 4),
         "inertia": [r["fstats"]["nneg"], r["fstats"]["npos"]],
     }
+    if "graph_ms" in r:
+        gms = float(np.median(r["graph_ms"]))
+        out["graph"] = {"ms_per_step": round(gms, 4), "value": round(flops / (gms * 1e-3) / 1e9, 3),
+                        "berr_nw": r["graph_berr"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lp)
     print(json.dumps(out))

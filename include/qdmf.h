@@ -34,6 +34,16 @@ typedef struct qdmf_ctx* qdmf_handle;
 enum { QDMF_NE = 0, QDMF_AS = 1 };              /* system form (Section 3)           */
 enum { QDMF_FP64 = 0, QDMF_MIXED = 1 };         /* precision of the Schur updates    */
 enum { QDMF_ORDER_AMD = 0, QDMF_ORDER_USER = 1, QDMF_ORDER_GRID_ND = 2 };
+/* kernel kinds for qdmf_profile_kind */
+enum {
+    QDMF_K_SMALL = 0,    /* small fronts: assembly + factorisation in LDS        */
+    QDMF_K_ASSEMBLE = 1, /* large fronts: extend-add, one workgroup per column   */
+    QDMF_K_WINDOW = 2,   /* pivot window: diagonal block + panel rows            */
+    QDMF_K_SYRK = 3,     /* trailing Schur update on MFMA                        */
+    QDMF_K_FINALIZE = 4, /* factored blocks into place, row swaps                */
+    QDMF_K_FWD = 5,      /* forward substitution + D, one tree level             */
+    QDMF_K_BWD = 6       /* backward substitution, one tree level                */
+};
 
 enum {
     QDMF_OK = 0,
@@ -184,6 +194,18 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
                        int32_t prec, int32_t nsolves, int32_t nrhs, const double* r7_dev,
                        const double* r1_dev, double* dx_dev, double* dy_dev);
 int qdmf_graph_launch(qdmf_handle h);
+
+/* Measurement hook: while kind >= 0, every later eager launch of that kernel kind (above)
+ * is bracketed by a pair of HIP events recorded on the handle's stream; kind = -1 stops.
+ * Not applied inside qdmf_graph_capture.  Errors: QDMF_ERR_INVALID_ARG. */
+int qdmf_profile_kind(qdmf_handle h, int32_t kind);
+
+/* Synchronises the stream and returns, for the launches timed since the last read: their
+ * number, the sum of their durations (ms, from the events), and their algorithmic flops and
+ * bytes (from the symbolic structure: the work each launch must do, independent of how).
+ * Resets the counters.  Any pointer may be NULL. */
+int qdmf_profile_read(qdmf_handle h, int64_t* launches, double* total_ms, double* flops,
+                      double* bytes);
 
 /* Frees everything the handle owns.  NULL is ignored. */
 void qdmf_destroy(qdmf_handle h);

@@ -564,14 +564,65 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         for (int32_t t = 0; t < ns; ++t) P.lvl_sn[fl[P.sn_level[t]]++] = t;
     }
 
+    // ----- solve work per level (one pass, one rhs): L panel read once, vectors in and out
+    P.lvl_solve_flops.assign(P.nlevels, 0.0);
+    P.lvl_solve_bytes.assign(P.nlevels, 0.0);
+    for (int32_t t = 0; t < ns; ++t) {
+        const double f = P.sn_f[t], p = P.sn_p[t];
+        const double lent = p * f - p * (p - 1) / 2;  // lower trapezoid of the panel
+        P.lvl_solve_flops[P.sn_level[t]] += 2.0 * (lent - p) + p;
+        P.lvl_solve_bytes[P.sn_level[t]] += 8.0 * lent + 8.0 * 3 * f;
+    }
+
     // ----- factorisation launch plan, level by level
     P.tasks.clear();
     P.launches.clear();
     P.asm_child.clear();
     P.asm_col.clear();
+    // algorithmic work per task (front dimensions as the kernels process them)
+    auto task_work = [&](int32_t kind, const Task& tk, double& fl, double& by) {
+        const double f = P.sn_f[tk.s], p = P.sn_p[tk.s];
+        if (kind == L_SMALL) {  // whole partial factorisation of the front + its assembly
+            for (double k = 0; k < p; ++k) fl += (f - k - 1) * (f - k - 1 + 3);
+            by += 8.0 * f * (f + 1) / 2;
+            for (int32_t q = P.ch_ptr[tk.s]; q < P.ch_ptr[tk.s + 1]; ++q) {
+                const double cb = P.sn_f[P.ch[q]] - P.sn_p[P.ch[q]];
+                by += 8.0 * cb * (cb + 1) / 2 + 4.0 * cb;
+            }
+        } else if (kind == L_ASSEMBLE) {  // one front column: children's CB columns in, column out
+            by += 8.0 * (f - tk.k0);
+            for (int32_t q = tk.a; q < tk.a + tk.b; ++q) {
+                const double cb = P.sn_f[P.asm_child[q]] - P.sn_p[P.asm_child[q]];
+                by += 12.0 * (cb - P.asm_col[q]);
+                fl += cb - P.asm_col[q];
+            }
+        } else if (kind == L_WINDOW) {  // eliminations restricted to the window columns
+            const double k0 = tk.k0, k1 = std::min<double>(p, k0 + NB);
+            const double rows = tk.a == 0 ? std::min<double>(64, f - k1) + (k1 - k0) : std::min<double>(64, f - k1 - 64.0 * tk.a);
+            for (double k = k0; k < k1; ++k) {
+                const double below = tk.a == 0 ? (k1 - k - 1) + std::min<double>(64, f - k1) : rows;
+                fl += below * (1 + 2 * (k1 - k - 1));
+            }
+            by += 16.0 * rows * (k1 - k0);
+        } else if (kind == L_SYRK) {  // one 64 x 64 tile of the lower trailing update
+            const double k1 = std::min<double>(p, tk.k0 + NB), nbw = k1 - tk.k0;
+            const double r0 = k1 + 64.0 * tk.a, c0 = k1 + 64.0 * tk.b;
+            const double nr = std::max(0.0, std::min(64.0, f - r0)), nc = std::max(0.0, std::min(64.0, f - c0));
+            double lower = nr * nc;
+            if (tk.a == tk.b) lower = nr * (nr + 1) / 2;
+            fl += 2.0 * nbw * lower;
+            by += 8.0 * (2 * lower + (nr + nc) * nbw);
+        } else if (kind == L_FINALIZE) {
+            by += 16.0 * 64 * std::min<double>(64, p - tk.k0);
+        }
+    };
     auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf) {
         int64_t cnt = (int64_t)P.tasks.size() - t0;
-        if (cnt > 0) P.launches.push_back(Launch{kind, lvl, t0, cnt, lds, maxf});
+        if (cnt > 0) {
+            Launch L{kind, lvl, t0, cnt, lds, maxf};
+            for (int64_t q = t0; q < t0 + cnt; ++q) task_work(kind, P.tasks[q], L.flops, L.bytes);
+            P.launches.push_back(L);
+        }
     };
     for (int32_t l = 0; l < P.nlevels; ++l) {
         std::vector<int32_t> small, large;

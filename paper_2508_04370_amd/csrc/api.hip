@@ -45,6 +45,13 @@ struct qdmf_ctx {
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    bool capturing = false;
+
+    // measurement: event pairs around launches of one kernel kind
+    int32_t prof_kind = -1;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double prof_flops = 0, prof_bytes = 0;
 
     // host copies for qdmf_symbolic
     std::vector<int32_t> h_front;
@@ -86,6 +93,33 @@ int dupload(qdmf_ctx* h, const std::vector<T>& v, const T** out) {
     *out = p;
     return 0;
 }
+
+// Measurement hook: bracket one launch with an event pair when its kind is being timed.
+struct ProfScope {
+    qdmf_ctx* h;
+    bool on;
+    hipEvent_t e1 = nullptr;
+    ProfScope(qdmf_ctx* h_, int32_t kind, double flops, double bytes) : h(h_), on(false) {
+        if (h->capturing || h->prof_kind != kind) return;
+        if (h->ev_used + 2 > h->ev_pool.size()) {
+            for (int q = 0; q < 256; ++q) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                h->ev_pool.push_back(e);
+            }
+        }
+        hipEvent_t e0 = h->ev_pool[h->ev_used];
+        e1 = h->ev_pool[h->ev_used + 1];
+        h->ev_used += 2;
+        (void)hipEventRecord(e0, h->stream);
+        h->prof_flops += flops;
+        h->prof_bytes += bytes;
+        on = true;
+    }
+    ~ProfScope() {
+        if (on) (void)hipEventRecord(e1, h->stream);
+    }
+};
 
 void destroy_graph(qdmf_ctx* h) {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
@@ -233,12 +267,33 @@ void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delt
     launch_theta(h->D, theta, rho, delta, h->stream);
     launch_values_n(h->D, h->knnz, h->stream);
     launch_knorm(h->D, h->stream);
-    for (const Launch& L : h->P.launches) launch_factor_step(h->D, L, h->tasks_dev, pp, h->stream);
+    for (const Launch& L : h->P.launches) {
+        ProfScope ps(h, L.kind, L.flops, L.bytes);
+        launch_factor_step(h->D, L, h->tasks_dev, pp, h->stream);
+    }
     launch_factor_stats(h->D, pp, h->stream);
 }
 
-void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, double* dy) {
+// (L D L^T)^{-1} src -> dst, level by level (forward leaves first, backward roots first).
+void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32_t* active) {
     const Plan& P = h->P;
+    const DevSolve& S = h->S;
+    hipStream_t st = h->stream;
+    launch_permute(h->D, S, src, active, st);
+    for (int32_t l = 0; l < P.nlevels; ++l) {
+        ProfScope ps(h, QDMF_K_FWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
+        launch_solve_level(true, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)(P.lvl_ptr[l + 1] - P.lvl_ptr[l]),
+                           h->maxf_lvl[l], active, st);
+    }
+    for (int32_t l = P.nlevels - 1; l >= 0; --l) {
+        ProfScope ps(h, QDMF_K_BWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
+        launch_solve_level(false, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)(P.lvl_ptr[l + 1] - P.lvl_ptr[l]),
+                           h->maxf_lvl[l], active, st);
+    }
+    launch_unpermute(h->D, S, dst, active, st);
+}
+
+void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, double* dy) {
     const DevPlan& D = h->D;
     const DevSolve& S = h->S;
     const bool mixed = h->last_prec == QDMF_MIXED;
@@ -246,14 +301,12 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
     const int max_steps = mixed ? h->opt.max_refine_mixed : h->opt.max_refine;
     hipStream_t st = h->stream;
     launch_rhs(D, S, r7, r1, st);
-    launch_ldlt_solve_levels(D, S, h->lvl_sn_dev, P.lvl_ptr.data(), P.nlevels, h->maxf_lvl.data(), S.b, S.x,
-                             nullptr, st);
+    enqueue_ldlt_solve(h, S.b, S.x, nullptr);
     launch_residual(D, S, S.x, st);
     launch_berr_steps(D, S, 0, target, max_steps, st);
     for (int it = 0; it < max_steps; ++it) {
         launch_refine_begin(D, S, st);
-        launch_ldlt_solve_levels(D, S, h->lvl_sn_dev, P.lvl_ptr.data(), P.nlevels, h->maxf_lvl.data(), S.r, S.d,
-                                 S.active, st);
+        enqueue_ldlt_solve(h, S.r, S.d, S.active);
         launch_refine_update(D, S, st);
         launch_residual(D, S, S.x, st);
         launch_berr_steps(D, S, 1, target, max_steps, st);
@@ -552,8 +605,10 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return QDMF_ERR_HIP;
     h->last_prec = prec;
+    h->capturing = true;
     enqueue_factorise(h, theta_dev, rho, delta, prec);
     for (int32_t q = 0; q < nsolves; ++q) enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
+    h->capturing = false;
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(h->stream, &g) != hipSuccess || !g) {
         (void)hipGetLastError();
@@ -577,12 +632,40 @@ int qdmf_graph_launch(qdmf_handle h) {
     return hipGraphLaunch(h->gexec, h->stream) == hipSuccess ? 0 : QDMF_ERR_HIP;
 }
 
+int qdmf_profile_kind(qdmf_handle h, int32_t kind) {
+    if (!h || kind < -1 || kind > QDMF_K_BWD) return QDMF_ERR_INVALID_ARG;
+    h->prof_kind = kind;
+    return 0;
+}
+
+int qdmf_profile_read(qdmf_handle h, int64_t* launches, double* total_ms, double* flops, double* bytes) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    double ms = 0.0;
+    if (h->ev_used) {
+        if (set_device(h)) return QDMF_ERR_HIP;
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+        for (size_t q = 0; q + 1 < h->ev_used; q += 2) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, h->ev_pool[q], h->ev_pool[q + 1]) != hipSuccess) return QDMF_ERR_HIP;
+            ms += t;
+        }
+    }
+    if (launches) *launches = (int64_t)(h->ev_used / 2);
+    if (total_ms) *total_ms = ms;
+    if (flops) *flops = h->prof_flops;
+    if (bytes) *bytes = h->prof_bytes;
+    h->ev_used = 0;
+    h->prof_flops = h->prof_bytes = 0;
+    return 0;
+}
+
 void qdmf_destroy(qdmf_handle h) {
     if (!h) return;
     if (!h->host_only) {
         (void)hipSetDevice(h->device);
         (void)hipStreamSynchronize(h->stream);
     }
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     destroy_graph(h);
     free_list(h->solve_allocs);
     free_list(h->plan_allocs);

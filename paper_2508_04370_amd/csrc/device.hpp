@@ -118,12 +118,14 @@ struct DevSolve {
 };
 
 void launch_rhs(const DevPlan& D, const DevSolve& S, const double* r7, const double* r1, hipStream_t s);
-// x = (L D L^T)^{-1} src per rhs (original numbering), one launch per tree level and pass;
-// lvl_sn_dev lists the supernodes level by level (leaves first), maxf_lvl[l] is the largest
-// front order of level l; rhs with active[r] == 0 are skipped (active may be NULL).
-void launch_ldlt_solve_levels(const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
-                              const int64_t* lvl_ptr, int nlevels, const int32_t* maxf_lvl,
-                              const double* src, double* dst, const int32_t* active, hipStream_t s);
+// Solve building blocks: src (original numbering) -> permuted work vector; one tree level of
+// the forward (leaves first) or backward (roots first) pass, one workgroup per supernode;
+// work vector -> dst.  rhs with active[r] == 0 are skipped (active may be NULL).
+void launch_permute(const DevPlan& D, const DevSolve& S, const double* src, const int32_t* active,
+                    hipStream_t s);
+void launch_unpermute(const DevPlan& D, const DevSolve& S, double* dst, const int32_t* active, hipStream_t s);
+void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
+                        int64_t base, unsigned count, int32_t maxf, const int32_t* active, hipStream_t s);
 void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s);
 void launch_berr_steps(const DevPlan& D, const DevSolve& S, int32_t phase, double target,
                        int max_steps, hipStream_t s);

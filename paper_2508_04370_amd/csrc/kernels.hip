@@ -1172,19 +1172,22 @@ void launch_rhs(const DevPlan& D, const DevSolve& S, const double* r7, const dou
     hipLaunchKernelGGL(k_rhs, dim3(nblocks(D.N, 256), S.nrhs), dim3(256), 0, s, D, S, r7, r1);
 }
 
-void launch_ldlt_solve_levels(const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
-                              const int64_t* lvl_ptr, int nlevels, const int32_t* maxf_lvl,
-                              const double* src, double* dst, const int32_t* active, hipStream_t s) {
+void launch_permute(const DevPlan& D, const DevSolve& S, const double* src, const int32_t* active,
+                    hipStream_t s) {
     hipLaunchKernelGGL(k_permute, dim3(nblocks(D.N, 256), S.nrhs), dim3(256), 0, s, D, src, S.xw, active);
-    for (int l = 0; l < nlevels; ++l) {
-        const unsigned g = (unsigned)(lvl_ptr[l + 1] - lvl_ptr[l]);
-        if (g) hipLaunchKernelGGL(k_fwd, dim3(g), dim3(256), (size_t)maxf_lvl[l] * 8, s, D, S, lvl_sn_dev, lvl_ptr[l], active);
-    }
-    for (int l = nlevels - 1; l >= 0; --l) {
-        const unsigned g = (unsigned)(lvl_ptr[l + 1] - lvl_ptr[l]);
-        if (g) hipLaunchKernelGGL(k_bwd, dim3(g), dim3(256), (size_t)maxf_lvl[l] * 8, s, D, S, lvl_sn_dev, lvl_ptr[l], active);
-    }
+}
+
+void launch_unpermute(const DevPlan& D, const DevSolve& S, double* dst, const int32_t* active, hipStream_t s) {
     hipLaunchKernelGGL(k_unpermute, dim3(nblocks(D.N, 256), S.nrhs), dim3(256), 0, s, D, S.xw, dst, active);
+}
+
+void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
+                        int64_t base, unsigned count, int32_t maxf, const int32_t* active, hipStream_t s) {
+    if (!count) return;
+    if (forward)
+        hipLaunchKernelGGL(k_fwd, dim3(count), dim3(256), (size_t)maxf * 8, s, D, S, lvl_sn_dev, base, active);
+    else
+        hipLaunchKernelGGL(k_bwd, dim3(count), dim3(256), (size_t)maxf * 8, s, D, S, lvl_sn_dev, base, active);
 }
 
 void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s) {

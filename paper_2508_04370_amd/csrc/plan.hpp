@@ -33,6 +33,8 @@ struct Launch {
     int64_t task0, ntask;  // range in the task array
     int32_t lds;           // dynamic LDS bytes (assembly)
     int32_t maxf;          // largest front order among the tasks
+    double flops = 0;      // algorithmic work of the launch
+    double bytes = 0;
 };
 
 struct Plan {
@@ -85,6 +87,7 @@ struct Plan {
     std::vector<Launch> launches;       // factorisation, in order
     std::vector<int64_t> lvl_ptr;       // supernodes per level for the solves (nlevels + 1)
     std::vector<int32_t> lvl_sn;
+    std::vector<double> lvl_solve_flops, lvl_solve_bytes;  // per level, one pass, one rhs
 
     int64_t device_bytes = 0;
 };

@@ -34,7 +34,10 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_symbolic", "qdmf_set_matrix", "qdmf_factorise", "qdmf_solve",
             "qdmf_factor_stats", "qdmf_solve_stats", "qdmf_export_d", "qdmf_export_front",
             "qdmf_graph_capture", "qdmf_graph_launch", "qdmf_destroy", "qdmf_status_string",
-            "qdmf_last_message"]
+            "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read"]
+QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD = range(7)
+KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
+                     6: "k_bwd"}
 
 
 class qdmf_options(C.Structure):
@@ -104,6 +107,8 @@ def lib():
         L.qdmf_status_string.restype = C.c_char_p
         L.qdmf_last_message.argtypes = [P]
         L.qdmf_last_message.restype = C.c_char_p
+        L.qdmf_profile_kind.argtypes = [P, I32]
+        L.qdmf_profile_read.argtypes = [P, P, P, P, P]
         for name in EXPORTED:
             getattr(L, name)
         _lib = L
@@ -242,6 +247,19 @@ def qdmf_graph_launch(h):
 def qdmf_destroy(h):
     if h:
         lib().qdmf_destroy(h)
+
+
+def qdmf_profile_kind(h, kind):
+    return _check(lib().qdmf_profile_kind(h, int(kind)), "qdmf_profile_kind", h)
+
+
+def qdmf_profile_read(h):
+    n = C.c_int64()
+    ms = C.c_double()
+    fl = C.c_double()
+    by = C.c_double()
+    _check(lib().qdmf_profile_read(h, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)), "qdmf_profile_read", h)
+    return dict(launches=n.value, total_ms=ms.value, flops=fl.value, bytes=by.value)
 
 
 def qdmf_status_string(code):
