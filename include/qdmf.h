@@ -17,8 +17,9 @@
  *   - indices are int32, offsets int64.  Column-major dense vectors, leading dim = rows.
  *   - pointers documented "device" must be device memory of the handle's device.
  *   - a handle is not thread-safe; separate handles are independent.
- *   - factorise / solve / graph_launch are asynchronous on the handle's stream;
- *     analyse, symbolic, the stats calls and destroy synchronise.
+ *   - factorise / graph_launch are asynchronous on the handle's stream; solve is
+ *     asynchronous up to its refinement decisions (see qdmf_solve); analyse, symbolic,
+ *     the stats calls and destroy synchronise.
  */
 #ifndef QDMF_H
 #define QDMF_H
@@ -33,7 +34,7 @@ typedef struct qdmf_ctx* qdmf_handle;
 
 enum { QDMF_NE = 0, QDMF_AS = 1 };              /* system form (Section 3)           */
 enum { QDMF_FP64 = 0, QDMF_MIXED = 1 };         /* precision of the Schur updates    */
-enum { QDMF_ORDER_AMD = 0, QDMF_ORDER_USER = 1, QDMF_ORDER_GRID_ND = 2 };
+enum { QDMF_ORDER_AMD = 0, QDMF_ORDER_USER = 1, QDMF_ORDER_GRID_ND = 2, QDMF_ORDER_ND = 3, QDMF_ORDER_AUTO = 4 };
 /* kernel kinds for qdmf_profile_kind */
 enum {
     QDMF_K_SMALL = 0,    /* small fronts: assembly + factorisation in LDS        */
@@ -71,7 +72,7 @@ typedef struct {
     double target_berr;       /* normwise backward error target, FP64 path, 1e-12          */
     double target_berr_mixed; /* normwise backward error target, mixed path, 1e-10         */
     double tau_big;           /* "too large" regularisation threshold (Section 4.6), 1e-8  */
-    int32_t ordering;         /* QDMF_ORDER_*                                               */
+    int32_t ordering;         /* QDMF_ORDER_* (default AUTO: the cheaper of AMD and ND)     */
     int32_t grid[3];          /* GRID_ND: row grid dims, row r = x + g0*(y + g1*z)          */
     int32_t amalgamate;       /* relaxed supernode amalgamation (Section 4.1), 1            */
     int32_t f_mix;            /* MIXED: fronts of order >= f_mix use FP32 Schur updates    */
@@ -159,7 +160,11 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
  * dx = theta~ (A^T dy - r7) (NE, Section 3 eq. (normeq)), then refines in FP64 against
  * K_static until the normwise backward error reaches the target or the step limit
  * (Section 4.5).  All vectors are device memory, column-major: r7 and dx n x nrhs, r1 and
- * dy m x nrhs; r7 may be NULL (zero).  Outputs must not alias inputs.
+ * dy m x nrhs; r7 may be NULL (zero).  Outputs must not alias inputs.  Between
+ * refinement steps the call waits for the stream to read the device's stop flags and
+ * launches no further step once every right-hand side meets the target; under graph
+ * capture (qdmf_graph_capture) it waits for nothing and enqueues every step, whose kernels
+ * then return at once for finished right-hand sides.
  * Errors: QDMF_ERR_NOT_FACTORISED, QDMF_ERR_INVALID_ARG. */
 int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev,
                double* dx_dev, double* dy_dev);

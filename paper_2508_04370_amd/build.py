@@ -18,7 +18,7 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,
               "-I", "/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
 
 HIP_SOURCES = ["kernels.hip", "api.hip"]
-HOST_SOURCES = ["analyse.cpp", "amd.cpp", "grid_nd.cpp"]
+HOST_SOURCES = ["analyse.cpp", "amd.cpp", "grid_nd.cpp", "nd.cpp"]
 
 
 def _compile(src):
@@ -37,7 +37,7 @@ def _compile(src):
 
 def build():
     """Compile every source and link libqdmf.so (always rebuilds)."""
-    with cf.ThreadPoolExecutor(max_workers=5) as ex:
+    with cf.ThreadPoolExecutor(max_workers=6) as ex:
         objs = list(ex.map(_compile, HIP_SOURCES + HOST_SOURCES))
     tmp = LIB_PATH + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs

@@ -112,6 +112,64 @@ void etree(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_
     }
 }
 
+}  // namespace
+
+// Column counts of L (entries below the diagonal) and the elimination tree of an ordering,
+// from the row subtrees.
+static void order_counts(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+                         const std::vector<int32_t>& order, std::vector<int64_t>& cnt,
+                         std::vector<int32_t>& parent) {
+    std::vector<int32_t> iorder(N), mark(N, -1);
+    for (int32_t k = 0; k < N; ++k) iorder[order[k]] = k;
+    etree(N, xadj, adj, order, iorder, parent);
+    cnt.assign(N, 0);
+    for (int32_t i = 0; i < N; ++i) {
+        const int32_t old = order[i];
+        mark[i] = i;
+        for (int64_t e = xadj[old]; e < xadj[old + 1]; ++e) {
+            int32_t j = iorder[adj[e]];
+            while (j >= 0 && j < i && mark[j] != i) {
+                mark[j] = i;
+                ++cnt[j];
+                j = parent[j];
+            }
+        }
+    }
+}
+
+// Factorisation flops sum_j c_j (c_j + 3) of an ordering (c_j = entries of column j of L
+// below the diagonal).
+double order_flops(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+                   const std::vector<int32_t>& order) {
+    std::vector<int64_t> cnt;
+    std::vector<int32_t> parent;
+    order_counts(N, xadj, adj, order, cnt, parent);
+    double fl = 0;
+    for (int32_t j = 0; j < N; ++j) fl += (double)cnt[j] * (cnt[j] + 3);
+    return fl;
+}
+
+// Flops plus the height of the elimination tree weighted as 2e6 flops per level: on the
+// device every pivot on the longest path is a sequential step of roughly a microsecond,
+// during which the matrix units could have done that many flops.
+double order_cost(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+                  const std::vector<int32_t>& order) {
+    std::vector<int64_t> cnt;
+    std::vector<int32_t> parent;
+    order_counts(N, xadj, adj, order, cnt, parent);
+    double fl = 0;
+    std::vector<int32_t> h(N, 1);
+    int32_t height = 0;
+    for (int32_t j = 0; j < N; ++j) {
+        fl += (double)cnt[j] * (cnt[j] + 3);
+        height = std::max(height, h[j]);
+        if (parent[j] >= 0) h[parent[j]] = std::max(h[parent[j]], h[j] + 1);
+    }
+    return fl + 2e6 * height;
+}
+
+namespace {
+
 void postorder(int32_t N, const std::vector<int32_t>& parent, std::vector<int32_t>& post) {
     std::vector<int32_t> head(N, -1), nxt(N, -1), stack;
     for (int32_t j = N - 1; j >= 0; --j)
@@ -200,6 +258,13 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             return QDMF_ERR_INVALID_ARG;
         }
         grid_nd_order(P, opt.grid, xadj, adj, order);
+    } else if (opt.ordering == QDMF_ORDER_ND) {
+        nd_order(N, xadj, adj, order);
+    } else if (opt.ordering == QDMF_ORDER_AUTO) {  // the cheaper of the two (order_cost)
+        std::vector<int32_t> nd;
+        amd_order(N, xadj, adj, order);
+        nd_order(N, xadj, adj, nd);
+        if (order_cost(N, xadj, adj, nd) < order_cost(N, xadj, adj, order)) order.swap(nd);
     } else {
         amd_order(N, xadj, adj, order);
     }
@@ -580,7 +645,7 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     P.asm_child.clear();
     P.asm_col.clear();
     // algorithmic work per task (front dimensions as the kernels process them)
-    auto task_work = [&](int32_t kind, const Task& tk, double& fl, double& by) {
+    auto task_work = [&](int32_t kind, int32_t npg, const Task& tk, double& fl, double& by) {
         const double f = P.sn_f[tk.s], p = P.sn_p[tk.s];
         if (kind == L_SMALL) {  // whole partial factorisation of the front + its assembly
             for (double k = 0; k < p; ++k) fl += (f - k - 1) * (f - k - 1 + 3);
@@ -597,10 +662,11 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                 fl += cb - P.asm_col[q];
             }
         } else if (kind == L_WINDOW) {  // eliminations restricted to the window columns
-            const double k0 = tk.k0, k1 = std::min<double>(p, k0 + NB);
-            const double rows = tk.a == 0 ? std::min<double>(64, f - k1) + (k1 - k0) : std::min<double>(64, f - k1 - 64.0 * tk.a);
+            const double k0 = tk.k0, k1 = std::min<double>(p, k0 + NB), ch = 64.0 * npg;
+            const double panel = std::max(0.0, std::min(ch, f - k1 - ch * tk.a));
+            const double rows = panel + (tk.a == 0 ? k1 - k0 : 0.0);
             for (double k = k0; k < k1; ++k) {
-                const double below = tk.a == 0 ? (k1 - k - 1) + std::min<double>(64, f - k1) : rows;
+                const double below = panel + (tk.a == 0 ? k1 - k - 1 : 0.0);
                 fl += below * (1 + 2 * (k1 - k - 1));
             }
             by += 16.0 * rows * (k1 - k0);
@@ -612,15 +678,17 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             if (tk.a == tk.b) lower = nr * (nr + 1) / 2;
             fl += 2.0 * nbw * lower;
             by += 8.0 * (2 * lower + (nr + nc) * nbw);
-        } else if (kind == L_FINALIZE) {
-            by += 16.0 * 64 * std::min<double>(64, p - tk.k0);
+        } else if (kind == L_FINALIZE) {  // one 64-column block of one window: read + write
+            const double nc = std::min<double>(NB, p - tk.k0), nr = std::min<double>(NB, p - (double)tk.a * NB);
+            by += tk.a * NB == tk.k0 ? 16.0 * nc * (nc - 1) / 2 : 16.0 * nc * nr;
         }
     };
-    auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf) {
+    auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf, int32_t npg = 0) {
         int64_t cnt = (int64_t)P.tasks.size() - t0;
         if (cnt > 0) {
             Launch L{kind, lvl, t0, cnt, lds, maxf};
-            for (int64_t q = t0; q < t0 + cnt; ++q) task_work(kind, P.tasks[q], L.flops, L.bytes);
+            L.npg = npg;
+            for (int64_t q = t0; q < t0 + cnt; ++q) task_work(kind, npg, P.tasks[q], L.flops, L.bytes);
             P.launches.push_back(L);
         }
     };
@@ -666,17 +734,24 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         int32_t maxwin = 0;
         for (int32_t t : large) maxwin = std::max(maxwin, P.sn_nwin[t]);
         for (int32_t w = 0; w < maxwin; ++w) {
+            // panel rows per workgroup: 64 * npg, npg <= 3, sized by the largest front
+            int32_t npg = 0;
+            for (int32_t t : large)
+                if (w < P.sn_nwin[t]) {
+                    const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                    npg = std::max(npg, std::min(3, (P.sn_f[t] - k1 + 63) / 64));
+                }
             t0 = (int64_t)P.tasks.size();
             mf = 0;
             for (int32_t t : large)
                 if (w < P.sn_nwin[t]) {
-                    int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
-                    int32_t rows_below = P.sn_f[t] - k1;
-                    int32_t nchunk = std::max(1, (rows_below + 63) / 64);
+                    const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                    const int32_t rows_below = P.sn_f[t] - k1;
+                    const int32_t nchunk = npg ? std::max(1, (rows_below + 64 * npg - 1) / (64 * npg)) : 1;
                     for (int32_t c = 0; c < nchunk; ++c) P.tasks.push_back(Task{t, w * NB, c, 0});
                     mf = std::max(mf, P.sn_f[t]);
                 }
-            add_launch(L_WINDOW, l, t0, 0, mf);
+            add_launch(L_WINDOW, l, t0, 0, mf, npg);
             t0 = (int64_t)P.tasks.size();
             for (int32_t t : large)
                 if (w < P.sn_nwin[t]) {
@@ -689,7 +764,8 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         }
         t0 = (int64_t)P.tasks.size();
         for (int32_t t : large)
-            for (int32_t c = 0; c < P.sn_p[t]; c += 64) P.tasks.push_back(Task{t, c, 0, 0});
+            for (int32_t c = 0; c < P.sn_nwin[t]; ++c)
+                for (int32_t w = c; w < P.sn_nwin[t]; ++w) P.tasks.push_back(Task{t, c * NB, w, 0});
         add_launch(L_FINALIZE, l, t0, 0, 0);
     }
     return 0;

@@ -39,6 +39,7 @@ struct qdmf_ctx {
     std::vector<void*> solve_allocs;
     DevSolve S{};
     int32_t solve_cap = 0;
+    int32_t* act_host = nullptr;  // pinned copy of the refinement flags (eager solves)
     int32_t last_nrhs = 0;
     bool solved = false;
 
@@ -246,6 +247,12 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     if ((rc = dalloc(h, h->solve_allocs, &S.berr, (int64_t)4 * nrhs))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.active, nrhs))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.steps, nrhs))) return rc;
+    if (h->act_host) (void)hipHostFree(h->act_host);
+    h->act_host = nullptr;
+    if (hipHostMalloc((void**)&h->act_host, sizeof(int32_t) * nrhs, hipHostMallocDefault) != hipSuccess) {
+        h->act_host = nullptr;
+        return QDMF_ERR_OOM;
+    }
     h->solve_cap = nrhs;
     S.nrhs = nrhs;
     return 0;
@@ -305,6 +312,18 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
     launch_residual(D, S, S.x, st);
     launch_berr_steps(D, S, 0, target, max_steps, st);
     for (int it = 0; it < max_steps; ++it) {
+        // Eager solves look at the refinement flags and stop launching once every
+        // right-hand side has met the target; a captured graph keeps all passes and the
+        // kernels of a finished right-hand side return at once.
+        if (!h->capturing) {
+            if (hipMemcpyAsync(h->act_host, S.active, sizeof(int32_t) * S.nrhs, hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                break;
+            bool any = false;
+            for (int r = 0; r < S.nrhs; ++r) any = any || h->act_host[r] != 0;
+            if (!any) break;
+        }
         launch_refine_begin(D, S, st);
         enqueue_ldlt_solve(h, S.r, S.d, S.active);
         launch_refine_update(D, S, st);
@@ -330,7 +349,7 @@ void qdmf_default_options(qdmf_options* o) {
     o->target_berr = 1e-12;
     o->target_berr_mixed = 1e-10;
     o->tau_big = 1e-8;
-    o->ordering = QDMF_ORDER_AMD;
+    o->ordering = QDMF_ORDER_AUTO;
     o->amalgamate = 1;
     o->f_mix = 1024;
     o->small_front = 64;
@@ -344,7 +363,7 @@ int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_optio
     if (opt) h->opt = *opt;
     else qdmf_default_options(&h->opt);
     if (h->opt.nb != 64 || h->opt.small_front < 1 || h->opt.small_front > 64 || h->opt.max_refine < 0 ||
-        h->opt.max_refine_mixed < 0) {
+        h->opt.max_refine_mixed < 0 || h->opt.ordering < QDMF_ORDER_AMD || h->opt.ordering > QDMF_ORDER_AUTO) {
         delete h;
         return QDMF_ERR_INVALID_ARG;
     }
@@ -666,6 +685,7 @@ void qdmf_destroy(qdmf_handle h) {
         (void)hipStreamSynchronize(h->stream);
     }
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->act_host) (void)hipHostFree(h->act_host);
     destroy_graph(h);
     free_list(h->solve_allocs);
     free_list(h->plan_allocs);

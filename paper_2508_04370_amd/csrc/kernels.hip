@@ -424,52 +424,342 @@ __global__ __launch_bounds__(256) void k_assemble(DevPlan D, const Task* tasks, 
     for (int i = tid; i < nr; i += 256) out[i] = buf[i];
 }
 
-// One pivot window [k0, k1) of a large front, for 64 of the rows below it (chunk t.a).
-// Every workgroup of the window loads the same diagonal block and takes the same
-// (deterministic) pivot decisions, applying each elimination to the block and to its own
-// panel rows: the right-looking elimination restricted to the window's columns.  The
-// panel rows become L21.  Workgroup chunk 0 also stores D, the pivot permutation and the
-// factored block; the block goes to its upper triangle (transposed), because the other
-// workgroups of this launch still read the unmodified lower part; k_finalize moves it.
-__global__ __launch_bounds__(64) void k_window(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp) {
-    __shared__ PivShared S;
-    const int lane = threadIdx.x;
+// Helpers of the register-tiled window kernel.  readlane with a wave-uniform index.
+__device__ inline double readlane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double shfl_d(double v, int src) {  // value of lane src (ds_bpermute)
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline int shfl_i(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+
+// Register element i (wave-uniform) of a 16-element tile row.  Written as bit masks so that
+// the compiler keeps the tile in registers instead of turning the selection into an indexed
+// access to a stack copy.
+__device__ inline double pick16(const double (&T)[16], int i) {
+    unsigned long long acc = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const unsigned long long m = 0ull - (unsigned long long)(i == q);
+        acc |= (unsigned long long)__double_as_longlong(T[q]) & m;
+    }
+    return __longlong_as_double((long long)acc);
+}
+
+__device__ inline void put16(double (&T)[16], int i, double v) {
+    const unsigned long long bv = (unsigned long long)__double_as_longlong(v);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const unsigned long long m = 0ull - (unsigned long long)(i == q);
+        const unsigned long long bt = (unsigned long long)__double_as_longlong(T[q]);
+        T[q] = __longlong_as_double((long long)((bv & m) | (bt & ~m)));
+    }
+}
+
+// Exchange of the values held by lanes a and b (wave-uniform a, b).
+__device__ inline int xchg_i(int v, int a, int b, int lane) {
+    const int va = __builtin_amdgcn_readlane(v, a), vb = __builtin_amdgcn_readlane(v, b);
+    return lane == a ? vb : (lane == b ? va : v);
+}
+
+__device__ inline double xchg_d(double v, int a, int b, int lane) {
+    const double va = readlane_d(v, a), vb = readlane_d(v, b);
+    return lane == a ? vb : (lane == b ? va : v);
+}
+
+// One pivot window [k0, k1) of a large front plus up to 64*NPG rows of the panel below it
+// (chunk t.a), in one workgroup of four waves, one per SIMD.  Wave w holds window columns
+// 16w .. 16w+15 of every row in registers: row group 0 is the window's own 64 rows, groups
+// 1..NPG are panel rows; lane = row within a group.  Rows and columns never move: the
+// symmetric interchanges of Section 4.5 are tracked as a position -> slot map, and every
+// wave keeps, per position (= lane), the slot, its current diagonal, expected sign and
+// static shift.  A pivot step costs one pivot-column broadcast through LDS (one barrier),
+// wave-local DPP reductions for the tests (every wave takes the same decisions from the
+// same data), and a rank-1 or rank-2 update of the register tile.  Every workgroup of the
+// window repeats the identical decisions; the panel rows become L21.  Workgroup chunk 0
+// also stores D, the pivot permutation and the factored block; the block goes to its upper
+// triangle (transposed), because the other workgroups of this launch still read the
+// unmodified lower part; k_finalize moves it.
+template <int NPG>
+__global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp) {
+    constexpr int RG = NPG + 1, NR = 64 * RG;
+    __shared__ double colA[2][NR], colB[2][NR];
+    __shared__ double Lb[64 * 64];  // L11: Lb[position * 64 + row slot]
+    __shared__ int pinv_s[64];
+    const int tid = threadIdx.x, lane = tid & 63, cq = tid >> 6;
     const Task t = tasks[t0 + blockIdx.x];
     const int s = t.s, k0 = t.k0, chunk = t.a;
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const int k1 = min(k0 + NB, p), nbw = k1 - k0;
     double* F = D.front + D.sn_off[s];
-    const int r = k1 + 64 * chunk + lane;  // this lane's panel row
-    const bool prow = r < f;
-    // load the block's lower part and this workgroup's panel rows; 16 columns per trip keep
-    // 32 global loads in flight per lane
-    for (int jb = 0; jb < 64; jb += 16) {
-        double vb[16], vp[16];
+    const int prow0 = k1 + 64 * NPG * chunk - 64 + lane;  // panel row of group g: prow0 + 64 g
+    double T[RG][16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int c = 16 * cq + q;
+        double v = 0.0;
+        if (lane < nbw && c < nbw)  // lower triangle of the window block, mirrored
+            v = lane >= c ? F[(k0 + lane) + (int64_t)(k0 + c) * ld] : F[(k0 + c) + (int64_t)(k0 + lane) * ld];
+        T[0][q] = v;
+    }
+#pragma unroll
+    for (int g = 1; g < RG; ++g) {
+        const int pr = prow0 + 64 * g;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int j = jb + q;
-            vb[q] = (j < nbw && lane >= j && lane < nbw) ? F[(k0 + lane) + (int64_t)(k0 + j) * ld] : 0.0;
-            vp[q] = (j < nbw && prow) ? F[r + (int64_t)(k0 + j) * ld] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            S.T[(jb + q) * LDW + lane] = vb[q];
-            S.T[(jb + q) * LDW + 64 + lane] = vp[q];
+            const int c = 16 * cq + q;
+            T[g][q] = (pr < f && c < nbw) ? F[pr + (int64_t)(k0 + c) * ld] : 0.0;
         }
     }
+    // per position (= lane; initially position = slot): slot, diagonal, sign, static shift
+    int slotP = lane;
+    double dgP = 0.0, shP = 0.0;
+    int sgP = 1;
+    if (lane < nbw) {
+        dgP = F[(k0 + lane) + (int64_t)(k0 + lane) * ld];
+        const bool pr = D.primal_new[D.rows[D.sn_rowptr[s] + k0 + lane]] != 0;
+        sgP = pr ? -1 : 1;
+        shP = pr ? -D.sc->rho : D.sc->delta;
+    }
+    const double tiny = pp.eps_lift * D.sc->knorm;  // delta * ||M||_1 of the lift test
+    const double alpha = pp.alpha;
+    uint64_t elim = 0;  // eliminated slots
+    double o_d = 0.0, o_off = 0.0, o_ed = 0.0;  // outputs of position = lane
+    int o_pt = 0, o_fl = 0, o_zs = 0;
+    int par = 0;
+    int k = 0;
+    while (k < nbw) {
+        if (pp.presort) {  // largest |diagonal| of the window to position k
+            double bv;
+            int q;
+            wave_argmax((lane >= k && lane < nbw) ? fabs(dgP) : -1.0, lane, bv, q);
+            if (q < k || q >= nbw) q = k;  // no candidate (NaN input): no swap
+            if (q != k) {
+                slotP = xchg_i(slotP, k, q, lane);
+                sgP = xchg_i(sgP, k, q, lane);
+                dgP = xchg_d(dgP, k, q, lane);
+                shP = xchg_d(shP, k, q, lane);
+            }
+        }
+        const int sk = __builtin_amdgcn_readlane(slotP, k);
+        if (cq == (sk >> 4)) {
+#pragma unroll
+            for (int g = 0; g < RG; ++g) colA[par][64 * g + lane] = pick16(T[g], sk & 15);
+        }
+        __syncthreads();
+        // gamma_p (largest |F_ik| below k in the window) and, for a 1x1 pivot on this column,
+        // the Proposition 3 bound over same-sign positions, in one pass
+        const double fkk = readlane_d(dgP, k);
+        const int sgk0 = __builtin_amdgcn_readlane(sgP, k);
+        const double cP = colA[par][slotP];
+        const bool below = lane > k && lane < nbw;
+        double gp, beta;
+        int r, nz;
+        {
+            const double den = fabs(dgP + shP);
+            const bool same = below && sgP == sgk0;
+            const double qv = (same && den != 0.0) ? cP * cP / den : -1.0;
+            wave_argmax(below ? fabs(cP) : -1.0, lane, gp, r);
+            beta = wave_max(qv);
+            nz = __popcll(__ballot(same && den == 0.0));
+            if (!(gp > 0.0) || r <= k || r >= nbw) {
+                gp = 0.0;
+                r = -1;
+            }
+        }
+        const double akk = fabs(fkk);
+        int piv = sk, two = 0, lifted = 0, useB = 0;
+        double fkk_before = fkk;
+        if (fmax(akk, gp) <= tiny) {
+            lifted = 1;
+        } else if (akk >= alpha * gp) {
+            // 1x1 at k
+        } else {
+            const int sr = __builtin_amdgcn_readlane(slotP, r);
+            if (cq == (sr >> 4)) {
+#pragma unroll
+                for (int g = 0; g < RG; ++g) colB[par][64 * g + lane] = pick16(T[g], sr & 15);
+            }
+            __syncthreads();
+            const double cB = colB[par][slotP];
+            double gr = wave_max((lane >= k && lane < nbw && lane != r) ? fabs(cB) : -1.0);
+            if (gr < 0.0) gr = 0.0;
+            const double frr = readlane_d(dgP, r);
+            if (akk * gr >= alpha * gp * gp) {
+                // 1x1 at k
+            } else if (fabs(frr) >= alpha * gr) {
+                slotP = xchg_i(slotP, k, r, lane);
+                sgP = xchg_i(sgP, k, r, lane);
+                dgP = xchg_d(dgP, k, r, lane);
+                shP = xchg_d(shP, k, r, lane);
+                piv = sr;
+                useB = 1;
+                fkk_before = frr;
+                // the Proposition 3 bound of the new pivot column
+                const double cN = colB[par][slotP];
+                const double den = fabs(dgP + shP);
+                const bool same = lane > k && lane < nbw && sgP == __builtin_amdgcn_readlane(sgP, k);
+                beta = wave_max((same && den != 0.0) ? cN * cN / den : -1.0);
+                nz = __popcll(__ballot(same && den == 0.0));
+            } else {
+                slotP = xchg_i(slotP, k + 1, r, lane);
+                sgP = xchg_i(sgP, k + 1, r, lane);
+                dgP = xchg_d(dgP, k + 1, r, lane);
+                shP = xchg_d(shP, k + 1, r, lane);
+                two = 1;
+            }
+        }
+        if (two) {
+            const int sa = sk, sb = __builtin_amdgcn_readlane(slotP, k + 1);
+            const double a = fkk + readlane_d(shP, k);
+            const double b = colA[par][sb];
+            const double c = readlane_d(dgP, k + 1) + readlane_d(shP, k + 1);
+            const double det = a * c - b * b;
+            if (det == 0.0) {
+                two = 0;
+                lifted = 1;
+                piv = sk;
+                fkk_before = fkk;
+                // positions k+1 and r were exchanged: the bound over the new arrangement
+                const double cN = colA[par][slotP];
+                const double den = fabs(dgP + shP);
+                const bool same = lane > k && lane < nbw && sgP == sgk0;
+                beta = wave_max((same && den != 0.0) ? cN * cN / den : -1.0);
+                nz = __popcll(__ballot(same && den == 0.0));
+            } else {
+                elim |= (1ull << sa) | (1ull << sb);
+                // multipliers of the columns (lane = slot), identical in every wave
+                const bool crem = lane < nbw && !((elim >> lane) & 1);
+                const double cu0 = colA[par][lane], cu1 = colB[par][lane];
+                const double cl0 = crem ? (cu0 * c - cu1 * b) / det : 0.0;
+                const double cl1 = crem ? (cu1 * a - cu0 * b) / det : 0.0;
+                double lj0[16], lj1[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    lj0[q] = shfl_d(cl0, 16 * cq + q);
+                    lj1[q] = shfl_d(cl1, 16 * cq + q);
+                }
+#pragma unroll
+                for (int g = 0; g < RG; ++g) {
+                    const bool rem = g > 0 ? prow0 + 64 * g < f : crem;
+                    const double u0 = colA[par][64 * g + lane], u1 = colB[par][64 * g + lane];
+                    const double l0 = rem ? (u0 * c - u1 * b) / det : 0.0;
+                    const double l1 = rem ? (u1 * a - u0 * b) / det : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) T[g][q] -= u0 * lj0[q] + u1 * lj1[q];
+                    if (cq == 0) {
+                        if (g == 0) {
+                            Lb[k * 64 + lane] = l0;
+                            Lb[(k + 1) * 64 + lane] = l1;
+                        } else if (rem) {
+                            F[prow0 + 64 * g + (int64_t)(k0 + k) * ld] = l0;
+                            F[prow0 + 64 * g + (int64_t)(k0 + k + 1) * ld] = l1;
+                        }
+                    }
+                }
+                {  // diagonal of the remaining positions
+                    const double pu0 = colA[par][slotP], pu1 = colB[par][slotP];
+                    if (lane > k + 1 && lane < nbw)
+                        dgP -= pu0 * ((pu0 * c - pu1 * b) / det) + pu1 * ((pu1 * a - pu0 * b) / det);
+                }
+                if (lane == k) {
+                    o_d = a;
+                    o_off = b;
+                    o_pt = 1;
+                    o_ed = 0.0;
+                    o_fl = 0;
+                    o_zs = 0;
+                } else if (lane == k + 1) {
+                    o_d = c;
+                    o_off = 0.0;
+                    o_pt = 2;
+                    o_ed = 0.0;
+                    o_fl = 0;
+                    o_zs = 0;
+                }
+                par ^= 1;
+                k += 2;
+                continue;
+            }
+        }
+        // 1x1 pivot at position k on slot piv
+        const double(*colP) = useB ? colB[par] : colA[par];
+        const int sgk = __builtin_amdgcn_readlane(sgP, k);
+        const double shk = readlane_d(shP, k);
+        const double fk = lifted ? sgk * tiny : fkk_before;
+        double dk = fk + shk;  // static regularisation after the pivot
+        if (beta < 0.0) beta = 0.0;
+        int flag = lifted ? PF_LIFT : 0;
+        if (fabs(dk) < beta) {  // Proposition 3
+            dk = sgk * beta;
+            flag |= PF_PROP3;
+        }
+        if (!((sgk > 0 && dk > 0) || (sgk < 0 && dk < 0))) {  // keep the sign
+            double mag = fabs(dk);
+            if (beta > mag) mag = beta;
+            if (tiny > mag) mag = tiny;
+            dk = sgk * mag;
+            flag |= PF_SIGN;
+        }
+        const double e = dk - (fkk_before + shk);
+        elim |= 1ull << piv;
+        {
+            double wq[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) wq[q] = colP[16 * cq + q];
+            const bool crem = lane < nbw && !((elim >> lane) & 1);
+#pragma unroll
+            for (int g = 0; g < RG; ++g) {
+                const bool rem = g > 0 ? prow0 + 64 * g < f : crem;
+                const double li = rem ? colP[64 * g + lane] / dk : 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) T[g][q] -= li * wq[q];
+                if (cq == 0) {
+                    if (g == 0) Lb[k * 64 + lane] = li;
+                    else if (rem) F[prow0 + 64 * g + (int64_t)(k0 + k) * ld] = li;
+                }
+            }
+        }
+        {  // diagonal of the remaining positions
+            const double cw = colP[slotP];
+            if (lane > k && lane < nbw) dgP -= (cw / dk) * cw;
+        }
+        if (lane == k) {
+            o_d = dk;
+            o_off = 0.0;
+            o_pt = 0;
+            o_ed = e;
+            o_fl = flag;
+            o_zs = nz;
+        }
+        par ^= 1;
+        k += 1;
+    }
+    if (cq == 0 && lane < nbw) pinv_s[slotP] = lane;
     __syncthreads();
-    for (int j = 0; j < nbw; ++j)
-        if (lane > j && lane < nbw) S.T[lane * LDW + j] = S.T[j * LDW + lane];
-    init_signs(S, D, D.rows + D.sn_rowptr[s] + k0, nbw, lane);
-    __syncthreads();
-    factor_window<true>(S, nbw, nbw, D.sc->knorm, pp, lane);
-    if (prow)
-        for (int j = 0; j < nbw; ++j) F[r + (int64_t)(k0 + j) * ld] = S.T[j * LDW + 64 + lane];
     if (chunk == 0) {
-        // L11 (strict lower) transposed into the block's upper triangle, D on its diagonal
-        for (int j = 0; j < nbw; ++j)
-            if (lane > j && lane < nbw) F[(k0 + j) + (int64_t)(k0 + lane) * ld] = S.T[j * LDW + lane];
-        store_pivots(S, D, c0 + k0, k0, nbw, lane);
+        // L11 (strict lower, final order) transposed into the upper triangle: wave v takes
+        // the columns (positions) v, v + 4, ...; lane = row slot
+        const int pr = lane < nbw ? pinv_s[lane] : 0;
+        for (int pc = cq; pc < nbw; pc += 4)
+            if (lane < nbw && pr > pc) F[(k0 + pc) + (int64_t)(k0 + pr) * ld] = Lb[pc * 64 + lane];
+        if (cq == 0 && lane < nbw) {
+            const int g = c0 + k0 + lane;
+            D.dval[g] = o_d;
+            D.doff[g] = o_off;
+            D.ptype[g] = (int8_t)o_pt;
+            D.edyn[g] = o_ed;
+            D.pflag[g] = (uint8_t)o_fl;
+            D.zskip[g] = o_zs;
+            D.lperm[g] = k0 + slotP;
+            D.lpinv[c0 + k0 + slotP] = k0 + lane;
+        }
     }
 }
 
@@ -589,31 +879,42 @@ __global__ __launch_bounds__(256) void k_syrk(DevPlan D, const Task* tasks, int6
         syrk_tile<double>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, As, Bs);
 }
 
-// After all windows of a front, for 64 of its pivot columns: move each window's factored
-// diagonal block from the upper triangle into place, and permute the rows of the column
-// that lie in later windows as those windows' pivot swaps require.
-__global__ __launch_bounds__(64) void k_finalize(DevPlan D, const Task* tasks, int64_t t0) {
-    const int lane = threadIdx.x;
+// After all windows of a front: one task per (pivot window c, window w >= c).  w == c moves
+// the window's factored diagonal block from the upper triangle into place; w > c permutes
+// the rows of window w inside the 64 columns of window c as window w's pivot interchanges
+// require.  Wave v handles columns 16v .. 16v+15, lane = row; each wave loads all of its
+// values before it stores any, so no barrier is needed.
+__global__ __launch_bounds__(256) void k_finalize(DevPlan D, const Task* tasks, int64_t t0) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const Task t = tasks[t0 + blockIdx.x];
-    const int s = t.s, col0 = t.k0;
+    const int s = t.s, kc = t.k0, w = t.a;
     const int p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
-    const int nwin = (p + NB - 1) / NB;
-    const int jend = min(col0 + 64, p);
+    const int ncol = min(NB, p - kc);
     double* F = D.front + D.sn_off[s];
-    for (int j = col0; j < jend; ++j) {
-        const int w0 = j / NB;
-        {
-            const int k0 = w0 * NB, k1 = min(k0 + NB, p);
-            const int i = j + 1 + lane;  // rows of column j inside its own window
-            if (i < k1) F[i + (int64_t)j * ld] = F[j + (int64_t)i * ld];
+    double v[16];
+    if (w * NB == kc) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = 16 * wv + q;
+            v[q] = (j < ncol && lane > j && lane < ncol) ? F[(kc + j) + (int64_t)(kc + lane) * ld] : 0.0;
         }
-        for (int w = w0 + 1; w < nwin; ++w) {
-            const int k0 = w * NB, nbw = min(NB, p - k0);
-            double v = 0.0;
-            if (lane < nbw) v = F[k0 + (D.lperm[c0 + k0 + lane] - k0) + (int64_t)j * ld];
-            __syncthreads();
-            if (lane < nbw) F[k0 + lane + (int64_t)j * ld] = v;
-            __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = 16 * wv + q;
+            if (j < ncol && lane > j && lane < ncol) F[(kc + lane) + (int64_t)(kc + j) * ld] = v[q];
+        }
+    } else {
+        const int k0 = w * NB, nbw = min(NB, p - k0);
+        const int src = lane < nbw ? D.lperm[c0 + k0 + lane] : 0;  // pre-pivot position now at k0 + lane
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = 16 * wv + q;
+            v[q] = (j < ncol && lane < nbw) ? F[src + (int64_t)(kc + j) * ld] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = 16 * wv + q;
+            if (j < ncol && lane < nbw) F[(k0 + lane) + (int64_t)(kc + j) * ld] = v[q];
         }
     }
 }
@@ -1153,9 +1454,16 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
         case L_ASSEMBLE:
             hipLaunchKernelGGL(k_assemble, dim3(g), dim3(256), (size_t)L.lds, s, D, tasks, L.task0);
             break;
-        case L_WINDOW: hipLaunchKernelGGL(k_window, dim3(g), dim3(64), 0, s, D, tasks, L.task0, pp); break;
+        case L_WINDOW:
+            switch (L.npg) {
+                case 0: hipLaunchKernelGGL(k_window<0>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
+                case 1: hipLaunchKernelGGL(k_window<1>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
+                case 2: hipLaunchKernelGGL(k_window<2>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
+                default: hipLaunchKernelGGL(k_window<3>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
+            }
+            break;
         case L_SYRK: hipLaunchKernelGGL(k_syrk, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
-        case L_FINALIZE: hipLaunchKernelGGL(k_finalize, dim3(g), dim3(64), 0, s, D, tasks, L.task0); break;
+        case L_FINALIZE: hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, D, tasks, L.task0); break;
         default: break;
     }
 }

@@ -11,7 +11,7 @@ constexpr int NB = 64;  // pivot window width used by the device kernels
 
 // One task of a batched launch.  Meaning per kernel:
 //   small front / solve: s = supernode
-//   window: s, k0 = window start, a = 64-row chunk below the window
+//   window: s, k0 = window start, a = chunk of 64*npg rows below the window
 //   finalize: s, k0 = first of 64 pivot columns
 //   assemble: s, k0 = front column, [a, a+b) = range of its (child, child column) list
 //   syrk:   s, k0 = window start, a = row tile, b = column tile
@@ -33,6 +33,7 @@ struct Launch {
     int64_t task0, ntask;  // range in the task array
     int32_t lds;           // dynamic LDS bytes (assembly)
     int32_t maxf;          // largest front order among the tasks
+    int32_t npg = 0;       // window: panel row groups of 64 per workgroup (0..3)
     double flops = 0;      // algorithmic work of the launch
     double bytes = 0;
 };
@@ -106,6 +107,17 @@ struct AnalyseOptions {
 // (CSR, no diagonal).  Returns order[k] = node eliminated k-th.
 void amd_order(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
                std::vector<int32_t>& order);
+
+// Factorisation flops sum_j c_j (c_j + 3) of an ordering of a symmetric pattern, and the
+// same plus a charge for the height of its elimination tree (sequential pivot steps).
+double order_flops(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+                   const std::vector<int32_t>& order);
+double order_cost(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+                  const std::vector<int32_t>& order);
+
+// Multilevel graph nested dissection of the same kind of pattern; order[k] = node k-th.
+void nd_order(int32_t N, const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+              std::vector<int32_t>& order);
 
 // Geometric nested dissection for grid-coupled problems (rows on an nx x ny x nz grid).
 void grid_nd_order(const Plan& P, const int grid[3], const std::vector<int64_t>& xadj,

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libqdmf.so")
 
 QDMF_NE, QDMF_AS = 0, 1
 QDMF_FP64, QDMF_MIXED = 0, 1
-QDMF_ORDER_AMD, QDMF_ORDER_USER, QDMF_ORDER_GRID_ND = 0, 1, 2
+QDMF_ORDER_AMD, QDMF_ORDER_USER, QDMF_ORDER_GRID_ND, QDMF_ORDER_ND, QDMF_ORDER_AUTO = 0, 1, 2, 3, 4
 QDMF_ERR_INVALID_ARG = -1
 QDMF_ERR_HIP = -2
 QDMF_ERR_OOM = -3
