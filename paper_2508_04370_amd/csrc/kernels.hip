@@ -22,6 +22,7 @@ namespace {
 constexpr int LDT = 65;  // leading dimension of LDS tiles (doubles), odd to spread banks
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d16 __attribute__((ext_vector_type(16)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Wave64 reductions with DPP: row_shr 1/2/4/8 leave each row's total in its lane 15,
@@ -439,27 +440,31 @@ __device__ inline double shfl_d(double v, int src) {  // value of lane src (ds_b
 
 __device__ inline int shfl_i(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
 
-// Register element i (wave-uniform) of a 16-element tile row.  Written as bit masks so that
-// the compiler keeps the tile in registers instead of turning the selection into an indexed
-// access to a stack copy.
-__device__ inline double pick16(const double (&T)[16], int i) {
-    unsigned long long acc = 0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const unsigned long long m = 0ull - (unsigned long long)(i == q);
-        acc |= (unsigned long long)__double_as_longlong(T[q]) & m;
-    }
-    return __longlong_as_double((long long)acc);
+// Wave maximum of an unsigned 32-bit value (DPP rows then row broadcasts; lanes without a
+// source contribute 0), read back from lane 63.
+__device__ inline unsigned wave_umax(unsigned v) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-__device__ inline void put16(double (&T)[16], int i, double v) {
-    const unsigned long long bv = (unsigned long long)__double_as_longlong(v);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const unsigned long long m = 0ull - (unsigned long long)(i == q);
-        const unsigned long long bt = (unsigned long long)__double_as_longlong(T[q]);
-        T[q] = __longlong_as_double((long long)((bv & m) | (bt & ~m)));
-    }
+// Argmax of x >= 0 over the lanes with ok set (lowest lane on ties).  A non-negative
+// double orders like its bit pattern read as an unsigned integer, so the maximum is taken
+// on 64-bit keys (bits + 1; 0 for lanes without a candidate or with NaN) in two 32-bit
+// passes.  Returns the lane, or -1 when no lane has a candidate.
+__device__ inline int wave_argmax_nn(double x, bool ok) {
+    const bool valid = ok && x == x;
+    const unsigned long long key = valid ? (unsigned long long)__double_as_longlong(x) + 1ull : 0ull;
+    const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+    const unsigned mh = wave_umax(hi);
+    const bool c1 = hi == mh;
+    const unsigned ml = wave_umax(c1 ? lo : 0u);
+    if (mh == 0u && ml == 0u) return -1;
+    return __ffsll((long long)__ballot(c1 && lo == ml)) - 1;
 }
 
 // Exchange of the values held by lanes a and b (wave-uniform a, b).
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
     const int k1 = min(k0 + NB, p), nbw = k1 - k0;
     double* F = D.front + D.sn_off[s];
     const int prow0 = k1 + 64 * NPG * chunk - 64 + lane;  // panel row of group g: prow0 + 64 g
-    double T[RG][16];
+    d16 T[RG];  // vector type: a wave-uniform element index becomes relative register addressing
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int c = 16 * cq + q;
@@ -536,9 +541,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
     int k = 0;
     while (k < nbw) {
         if (pp.presort) {  // largest |diagonal| of the window to position k
-            double bv;
-            int q;
-            wave_argmax((lane >= k && lane < nbw) ? fabs(dgP) : -1.0, lane, bv, q);
+            int q = wave_argmax_nn(fabs(dgP), lane >= k && lane < nbw);
             if (q < k || q >= nbw) q = k;  // no candidate (NaN input): no swap
             if (q != k) {
                 slotP = xchg_i(slotP, k, q, lane);
@@ -550,7 +553,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         const int sk = __builtin_amdgcn_readlane(slotP, k);
         if (cq == (sk >> 4)) {
 #pragma unroll
-            for (int g = 0; g < RG; ++g) colA[par][64 * g + lane] = pick16(T[g], sk & 15);
+            for (int g = 0; g < RG; ++g) colA[par][64 * g + lane] = T[g][sk & 15];
         }
         __syncthreads();
         // gamma_p (largest |F_ik| below k in the window) and, for a 1x1 pivot on this column,
@@ -564,10 +567,12 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         {
             const double den = fabs(dgP + shP);
             const bool same = below && sgP == sgk0;
-            const double qv = (same && den != 0.0) ? cP * cP / den : -1.0;
-            wave_argmax(below ? fabs(cP) : -1.0, lane, gp, r);
-            beta = wave_max(qv);
+            const double qv = (same && den != 0.0) ? cP * cP / den : 0.0;
+            r = wave_argmax_nn(fabs(cP), below);
+            const int bl = wave_argmax_nn(qv, same && den != 0.0);
             nz = __popcll(__ballot(same && den == 0.0));
+            beta = bl >= 0 ? readlane_d(qv, bl) : 0.0;
+            gp = r >= 0 ? fabs(readlane_d(cP, r)) : 0.0;
             if (!(gp > 0.0) || r <= k || r >= nbw) {
                 gp = 0.0;
                 r = -1;
@@ -584,12 +589,12 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
             const int sr = __builtin_amdgcn_readlane(slotP, r);
             if (cq == (sr >> 4)) {
 #pragma unroll
-                for (int g = 0; g < RG; ++g) colB[par][64 * g + lane] = pick16(T[g], sr & 15);
+                for (int g = 0; g < RG; ++g) colB[par][64 * g + lane] = T[g][sr & 15];
             }
             __syncthreads();
             const double cB = colB[par][slotP];
-            double gr = wave_max((lane >= k && lane < nbw && lane != r) ? fabs(cB) : -1.0);
-            if (gr < 0.0) gr = 0.0;
+            const int rl = wave_argmax_nn(fabs(cB), lane >= k && lane < nbw && lane != r);
+            const double gr = rl >= 0 ? fabs(readlane_d(cB, rl)) : 0.0;
             const double frr = readlane_d(dgP, r);
             if (akk * gr >= alpha * gp * gp) {
                 // 1x1 at k
@@ -605,7 +610,9 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
                 const double cN = colB[par][slotP];
                 const double den = fabs(dgP + shP);
                 const bool same = lane > k && lane < nbw && sgP == __builtin_amdgcn_readlane(sgP, k);
-                beta = wave_max((same && den != 0.0) ? cN * cN / den : -1.0);
+                const double qn = (same && den != 0.0) ? cN * cN / den : 0.0;
+                const int bl = wave_argmax_nn(qn, same && den != 0.0);
+                beta = bl >= 0 ? readlane_d(qn, bl) : 0.0;
                 nz = __popcll(__ballot(same && den == 0.0));
             } else {
                 slotP = xchg_i(slotP, k + 1, r, lane);
@@ -630,7 +637,9 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
                 const double cN = colA[par][slotP];
                 const double den = fabs(dgP + shP);
                 const bool same = lane > k && lane < nbw && sgP == sgk0;
-                beta = wave_max((same && den != 0.0) ? cN * cN / den : -1.0);
+                const double qn = (same && den != 0.0) ? cN * cN / den : 0.0;
+                const int bl = wave_argmax_nn(qn, same && den != 0.0);
+                beta = bl >= 0 ? readlane_d(qn, bl) : 0.0;
                 nz = __popcll(__ballot(same && den == 0.0));
             } else {
                 elim |= (1ull << sa) | (1ull << sb);
@@ -694,7 +703,6 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         const double shk = readlane_d(shP, k);
         const double fk = lifted ? sgk * tiny : fkk_before;
         double dk = fk + shk;  // static regularisation after the pivot
-        if (beta < 0.0) beta = 0.0;
         int flag = lifted ? PF_LIFT : 0;
         if (fabs(dk) < beta) {  // Proposition 3
             dk = sgk * beta;
