@@ -31,7 +31,7 @@ struct qdmf_ctx {
     DevPlan D{};
     Task* tasks_dev = nullptr;
     int32_t* lvl_sn_dev = nullptr;
-    std::vector<int32_t> maxf_lvl;
+    std::vector<int32_t> maxf_lvl, maxp_lvl;  // per level: largest front order and pivot count
     int64_t knnz = 0;
     int64_t device_bytes = 0;
 
@@ -216,11 +216,14 @@ int upload_plan(qdmf_ctx* h) {
     if ((rc = dalloc(h, h->plan_allocs, &D.lpinv, N))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.sc, 1))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.st, 1))) return rc;
-    // largest front per level (dynamic LDS of the solve kernels)
+    // largest front (dynamic LDS of the solve kernels) and pivot count (kernel variant) per level
     h->maxf_lvl.assign(P.nlevels, 1);
+    h->maxp_lvl.assign(P.nlevels, 1);
     for (int32_t l = 0; l < P.nlevels; ++l)
-        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; ++q)
+        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; ++q) {
             h->maxf_lvl[l] = std::max(h->maxf_lvl[l], P.sn_f[P.lvl_sn[q]]);
+            h->maxp_lvl[l] = std::max(h->maxp_lvl[l], P.sn_p[P.lvl_sn[q]]);
+        }
     if (hipDeviceSynchronize() != hipSuccess) return QDMF_ERR_HIP;
     return 0;
 }
@@ -290,12 +293,12 @@ void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32
     for (int32_t l = 0; l < P.nlevels; ++l) {
         ProfScope ps(h, QDMF_K_FWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
         launch_solve_level(true, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)(P.lvl_ptr[l + 1] - P.lvl_ptr[l]),
-                           h->maxf_lvl[l], active, st);
+                           h->maxf_lvl[l], h->maxp_lvl[l], active, st);
     }
     for (int32_t l = P.nlevels - 1; l >= 0; --l) {
         ProfScope ps(h, QDMF_K_BWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
         launch_solve_level(false, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)(P.lvl_ptr[l + 1] - P.lvl_ptr[l]),
-                           h->maxf_lvl[l], active, st);
+                           h->maxf_lvl[l], h->maxp_lvl[l], active, st);
     }
     launch_unpermute(h->D, S, dst, active, st);
 }

@@ -125,7 +125,8 @@ void launch_permute(const DevPlan& D, const DevSolve& S, const double* src, cons
                     hipStream_t s);
 void launch_unpermute(const DevPlan& D, const DevSolve& S, double* dst, const int32_t* active, hipStream_t s);
 void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
-                        int64_t base, unsigned count, int32_t maxf, const int32_t* active, hipStream_t s);
+                        int64_t base, unsigned count, int32_t maxf, int32_t maxp, const int32_t* active,
+                        hipStream_t s);
 void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s);
 void launch_berr_steps(const DevPlan& D, const DevSolve& S, int32_t phase, double target,
                        int max_steps, hipStream_t s);

@@ -779,23 +779,35 @@ template <typename T>
 __device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int C0,
                           const double* dd, const double* od, const int* pt, T* As, T* Bs) {
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
-        const int kk = idx >> 6, r = idx & 63;
-        const int row = R0 + r, col = C0 + r;
-        double a = 0.0, b = 0.0;
-        if (kk < nbw) {
-            if (row < f) a = F[row + (int64_t)(k0 + kk) * ld];
-            if (col < f) {
-                const double* cr = F + col + (int64_t)k0 * ld;
-                const int ty = pt[kk];
-                if (ty == 0) b = cr[(int64_t)kk * ld] * dd[kk];
-                else if (ty == 1) b = cr[(int64_t)kk * ld] * dd[kk] + cr[(int64_t)(kk + 1) * ld] * od[kk];
-                else b = cr[(int64_t)(kk - 1) * ld] * od[kk - 1] + cr[(int64_t)kk * ld] * dd[kk];
-            }
-        }
-        As[r * LDT + kk] = (T)a;
-        Bs[r * LDT + kk] = (T)b;
+    // L21 rows of the tile's row block (A) and column block (C), all loads in flight at once
+    double va[16], vc[16];
+    const int r = tid & 63, kq = tid >> 6;  // this thread: row r, columns kq, kq + 4, ...
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int kk = kq + 4 * t;
+        va[t] = (kk < nbw && R0 + r < f) ? F[R0 + r + (int64_t)(k0 + kk) * ld] : 0.0;
+        vc[t] = (kk < nbw && C0 + r < f) ? F[C0 + r + (int64_t)(k0 + kk) * ld] : 0.0;
     }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) As[r * LDT + kq + 4 * t] = (T)va[t];
+    // W = L21 D on the column block: a 1x1 pivot scales its column, a 2x2 block mixes its
+    // two columns (the partner column is read again; 2x2 pivots are rare)
+    double wb[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int kk = kq + 4 * t;
+        double b = 0.0;
+        if (kk < nbw && C0 + r < f) {
+            const int ty = pt[kk];
+            const double* cr = F + C0 + r + (int64_t)k0 * ld;
+            if (ty == 0) b = vc[t] * dd[kk];
+            else if (ty == 1) b = vc[t] * dd[kk] + cr[(int64_t)(kk + 1) * ld] * od[kk];
+            else b = cr[(int64_t)(kk - 1) * ld] * od[kk - 1] + vc[t] * dd[kk];
+        }
+        wb[t] = b;
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) Bs[r * LDT + kq + 4 * t] = (T)wb[t];
     __syncthreads();
     const int wv = tid >> 6, l = tid & 63;
     const int wc = (wv >> 1) * 32, wr = (wv & 1) * 32;
@@ -1123,9 +1135,76 @@ __global__ void k_unpermute(DevPlan D, const double* xw, double* dst, const int3
     dst[D.perm[c] + (int64_t)r * D.N] = xw[c + (int64_t)r * D.N];
 }
 
+// Solve kernels are instantiated per level with NBM >= the largest pivot block of the level
+// (8, 16, 32 or 64), which sizes LDS tiles and register blocks; Lb holds a block with row
+// stride NBM + 1: Lb[k * (NBM + 1) + i] = L(k0 + i, k0 + k), strictly lower, zero elsewhere.
+template <int NBM>
+__device__ inline void stage_block(double* Lb, const double* F, int ld, int k0, int nb, int tid) {
+    constexpr int LS = NBM + 1, NT = (NBM * NBM + 255) / 256;
+    double v[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int idx = tid + 256 * t, i = idx % NBM, k = idx / NBM;
+        v[t] = (idx < NBM * NBM && i < nb && k < nb && i > k) ? F[(k0 + i) + (int64_t)(k0 + k) * ld] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int idx = tid + 256 * t;
+        if (idx < NBM * NBM) Lb[(idx / NBM) * LS + idx % NBM] = v[t];
+    }
+}
+
+// Triangular solves on the staged block in one wavefront with the block in registers: lane
+// i holds row i (forward) or column i (backward) and its y value; each step broadcasts one
+// finished y by readlane.
+template <int NBM>
+__device__ inline double trsv_fwd_wave(const double* Lb, double y, int lane) {
+    constexpr int LS = NBM + 1;
+    double l[NBM];
+#pragma unroll
+    for (int k = 0; k < NBM; ++k) l[k] = lane < NBM ? Lb[k * LS + lane] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NBM - 1; ++k) {
+        const double z = readlane_d(y, k);
+        if (lane > k) y -= l[k] * z;
+    }
+    return y;
+}
+
+template <int NBM>
+__device__ inline double trsv_bwd_wave(const double* Lb, double y, int lane) {
+    constexpr int LS = NBM + 1;
+    double c[NBM];
+#pragma unroll
+    for (int i = 0; i < NBM; ++i) c[i] = lane < NBM ? Lb[lane * LS + i] : 0.0;
+#pragma unroll
+    for (int i = NBM - 1; i > 0; --i) {
+        const double z = readlane_d(y, i);
+        if (lane < i) y -= c[i] * z;
+    }
+    return y;
+}
+
+// y_i -= sum_{k < nb} L(i, k0 + k) y[k0 + k] for one row i below the block, the row's
+// loads in flight together.
+template <int NBM>
+__device__ inline double gemv_row(const double* Li, int ld, int nb, const double* yk) {
+    double l[NBM];
+#pragma unroll
+    for (int k = 0; k < NBM; ++k) l[k] = k < nb ? Li[(int64_t)k * ld] : 0.0;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NBM; k += 2) {
+        if (k < nb) a0 += l[k] * yk[k];
+        if (k + 1 < nb) a1 += l[k + 1] * yk[k + 1];
+    }
+    return a0 + a1;
+}
+
 // Forward substitution with unit L and the D solve for one supernode.  The parent gathers
 // its children's contribution vectors (ascending order, no atomics).  y: f doubles of LDS;
 // Lb: 64 x 65 doubles of LDS holding the current 64 x 64 diagonal block of L.
+template <int NBM>
 __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const int32_t* active, double* y,
                               double* Lb) {
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
@@ -1150,33 +1229,19 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
         }
         for (int k0 = 0; k0 < p; k0 += 64) {
             const int k1 = min(k0 + 64, p), nb = k1 - k0;
-            for (int idx = tid; idx < 64 * 64; idx += 256) {  // diagonal block of L into LDS
-                const int i = idx & 63, k = idx >> 6;
-                Lb[k * 65 + i] = (i < nb && k < nb) ? F[(k0 + i) + (int64_t)(k0 + k) * ld] : 0.0;
-            }
+            stage_block<NBM>(Lb, F, ld, k0, nb, tid);
             __syncthreads();
             if (tid < 64) {
-                const int row = k0 + tid;
-                for (int k = k0; k < k1; ++k) {
-                    const double z = y[k];
-                    if (row > k && row < k1) y[row] -= Lb[(k - k0) * 65 + tid] * z;
-                    __builtin_amdgcn_wave_barrier();
-                }
+                const double y0 = tid < nb ? y[k0 + tid] : 0.0;
+                const double v = trsv_fwd_wave<NBM>(Lb, y0, tid);
+                if (tid < nb) y[k0 + tid] = v;
             }
             __syncthreads();
-            for (int i = k1 + tid; i < f; i += 256) {
+            for (int i = k1 + tid; i < f; i += 256) {  // rows below: a whole row of the block in flight
                 const double* Li = F + i + (int64_t)k0 * ld;
-                double acc = y[i];
-                int k = 0;
-                for (; k + 8 <= nb; k += 8) {
-                    double l[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) l[q] = Li[(int64_t)(k + q) * ld];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) acc -= l[q] * y[k0 + k + q];
-                }
-                for (; k < nb; ++k) acc -= Li[(int64_t)k * ld] * y[k0 + k];
-                y[i] = acc;
+                const double* yk = y + k0;
+                const double dlt = gemv_row<NBM>(Li, ld, nb, yk);
+                y[i] -= dlt;
             }
             __syncthreads();
         }
@@ -1199,9 +1264,11 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
     }
 }
 
-// Backward substitution with L^T for one supernode (its ancestors are done).
+// Backward substitution with L^T for one supernode (its ancestors are done).  part: 4 x 64
+// doubles of LDS for the partial sums of the rows below each block; Lt: a 64 x 65 tile.
+template <int NBM>
 __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const int32_t* active, double* y,
-                              double* Lb) {
+                              double* Lb, double* part, double* Lt) {
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const double* F = D.front + D.sn_off[s];
     const int32_t* rows = D.rows + D.sn_rowptr[s];
@@ -1214,26 +1281,48 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
         const int nblk = (p + 63) / 64;
         for (int bk = nblk - 1; bk >= 0; --bk) {
             const int k0 = bk * 64, k1 = min(k0 + 64, p), nb = k1 - k0;
-            for (int idx = tid; idx < 64 * 64; idx += 256) {
-                const int i = idx & 63, k = idx >> 6;
-                Lb[k * 65 + i] = (i < nb && k < nb) ? F[(k0 + i) + (int64_t)(k0 + k) * ld] : 0.0;
-            }
-            for (int k = k0 + wv; k < k1; k += 4) {  // rows below the block
-                const double* Lk = F + (int64_t)k * ld;
-                double part = 0.0;
-                for (int i = k1 + lane; i < f; i += 64) part += Lk[i] * y[i];
-                part = wave_sum_d(part);
-                if (lane == 0) y[k] -= part;
+            stage_block<NBM>(Lb, F, ld, k0, nb, tid);
+            {  // rows below the block, sum_i L(i, k) y_i: tiles of 64 rows loaded coalesced
+               // (lane = row; the next tile in flight while the current one is summed through
+               // LDS by thread (column = lane, rows wv, wv + 4, ...))
+                constexpr int NT = NBM / 4;
+                double acc = 0.0;
+                double cur[NT], nxt[NT];
+                auto load = [&](int i0, double* v) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const int k = wv + 4 * t, i = i0 + lane;
+                        v[t] = (k < nb && i < f) ? F[i + (int64_t)(k0 + k) * ld] : 0.0;
+                    }
+                };
+                load(k1, cur);
+                for (int i0 = k1; i0 < f; i0 += 64) {
+                    if (i0 + 64 < f) load(i0 + 64, nxt);
+                    const double yi = i0 + lane < f ? y[i0 + lane] : 0.0;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) Lt[(wv + 4 * t) * 65 + lane] = cur[t] * yi;
+                    __syncthreads();
+                    if (lane < NBM) {
+                        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                        for (int t = 0; t < 16; t += 2) {
+                            a0 += Lt[lane * 65 + wv + 4 * t];
+                            a1 += Lt[lane * 65 + wv + 4 * t + 4];
+                        }
+                        acc += a0 + a1;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) cur[t] = nxt[t];
+                }
+                part[wv * 64 + lane] = acc;
             }
             __syncthreads();
             if (tid < 64) {
-                for (int k = k1 - 1; k >= k0; --k) {
-                    const int i = k + 1 + lane;
-                    double part = (i < k1) ? Lb[(k - k0) * 65 + (i - k0)] * y[i] : 0.0;
-                    part = wave_sum_d(part);
-                    if (lane == 0) y[k] -= part;
-                    __builtin_amdgcn_wave_barrier();
-                }
+                double v = 0.0;
+                if (tid < nb) v = y[k0 + tid] - (((part[tid] + part[64 + tid]) + part[128 + tid]) + part[192 + tid]);
+                v = trsv_bwd_wave<NBM>(Lb, v, tid);
+                if (tid < nb) y[k0 + tid] = v;
             }
             __syncthreads();
         }
@@ -1243,18 +1332,24 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
 }
 
 // One level of the supernodal tree per launch: the kernel boundary orders the levels.
+// NBM: a bound on the pivot count of every supernode of the level, capped at 64 (sizes the
+// register blocks, so levels of small supernodes keep many workgroups per CU).
+template <int NBM>
 __global__ __launch_bounds__(256) void k_fwd(DevPlan D, DevSolve S, const int32_t* lvl_sn, int64_t base,
                                              const int32_t* active) {
     extern __shared__ double dyn[];
-    __shared__ double Lb[64 * 65];
-    fwd_supernode(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb);
+    __shared__ double Lb[NBM * (NBM + 1)];
+    fwd_supernode<NBM>(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb);
 }
 
+template <int NBM>
 __global__ __launch_bounds__(256) void k_bwd(DevPlan D, DevSolve S, const int32_t* lvl_sn, int64_t base,
                                              const int32_t* active) {
     extern __shared__ double dyn[];
-    __shared__ double Lb[64 * 65];
-    bwd_supernode(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb);
+    __shared__ double Lb[NBM * (NBM + 1)];
+    __shared__ double part[4 * 64];
+    __shared__ double Lt[NBM * 65];
+    bwd_supernode<NBM>(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb, part, Lt);
 }
 
 // r = b - K_static x and (|K||x|)_i in original numbering, from A, Theta, rho, delta
@@ -1498,12 +1593,24 @@ void launch_unpermute(const DevPlan& D, const DevSolve& S, double* dst, const in
 }
 
 void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
-                        int64_t base, unsigned count, int32_t maxf, const int32_t* active, hipStream_t s) {
+                        int64_t base, unsigned count, int32_t maxf, int32_t maxp, const int32_t* active,
+                        hipStream_t s) {
     if (!count) return;
-    if (forward)
-        hipLaunchKernelGGL(k_fwd, dim3(count), dim3(256), (size_t)maxf * 8, s, D, S, lvl_sn_dev, base, active);
-    else
-        hipLaunchKernelGGL(k_bwd, dim3(count), dim3(256), (size_t)maxf * 8, s, D, S, lvl_sn_dev, base, active);
+    const size_t lds = (size_t)maxf * 8;
+    const int v = maxp <= 8 ? 0 : maxp <= 16 ? 1 : maxp <= 32 ? 2 : 3;
+#define QDMF_SOLVE_LAUNCH(K, NBM) hipLaunchKernelGGL(K<NBM>, dim3(count), dim3(256), lds, s, D, S, lvl_sn_dev, base, active)
+    if (forward) {
+        if (v == 0) QDMF_SOLVE_LAUNCH(k_fwd, 8);
+        else if (v == 1) QDMF_SOLVE_LAUNCH(k_fwd, 16);
+        else if (v == 2) QDMF_SOLVE_LAUNCH(k_fwd, 32);
+        else QDMF_SOLVE_LAUNCH(k_fwd, 64);
+    } else {
+        if (v == 0) QDMF_SOLVE_LAUNCH(k_bwd, 8);
+        else if (v == 1) QDMF_SOLVE_LAUNCH(k_bwd, 16);
+        else if (v == 2) QDMF_SOLVE_LAUNCH(k_bwd, 32);
+        else QDMF_SOLVE_LAUNCH(k_bwd, 64);
+    }
+#undef QDMF_SOLVE_LAUNCH
 }
 
 void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s) {
