@@ -43,6 +43,11 @@ def make_workload(name):
     if name == "ne_grid_small":
         lp = W.ne_grid(24, 24, 20, nrhs=8)
         return lp, dict(ordering=2, grid=lp["grid"])
+    if name in ("as_batch", "as_batch_small"):
+        lps = W.as_batch(512 if name == "as_batch" else 32)
+        cat = W.concat_systems(lps)
+        cat["systems"] = lps
+        return cat, dict(systems=lps, ordering=0)
     if name == "as_dense_cols":
         lp = W.as_dense_cols()
         return lp, dict(ordering=2, grid=lp["grid"])
@@ -50,6 +55,8 @@ def make_workload(name):
 
 
 def thetas(lp, k, seed):
+    if "systems" in lp:  # batch: system s, iteration k draws from seed [4, s, k]
+        return np.concatenate([W.as_batch_theta(q, s, k) for s, q in enumerate(lp["systems"])])
     g = W.rng(seed, 1000 + k)
     lo, hi = (1e-10, 1e10) if lp["mode"] == W.AS else (1e-6, 1e6)
     return W.log_uniform(g, lo, hi, lp["n"])
@@ -65,6 +72,10 @@ def run_gpu(lp, opts, prec, steps, warmup, nsolves, graph):
     sym = s.sym
     nth = warmup + steps + 8
     TH = [torch.from_numpy(thetas(lp, k, 7)).to(dev) for k in range(nth)]
+    if "systems" in lp:  # batch: predictor right-hand sides of iteration 0, seed [4, s, 0, 0]
+        rs = [W.as_batch_rhs(q, s, 0, 0) for s, q in enumerate(lp["systems"])]
+        lp["r7"] = np.concatenate([r[0] for r in rs]).reshape(-1, 1)
+        lp["r1"] = np.concatenate([r[1] for r in rs]).reshape(-1, 1)
     r1 = Q.to_device_colmajor(lp["r1"], dev)
     r7 = Q.to_device_colmajor(lp["r7"], dev) if lp["mode"] == W.AS else None
     nrhs = r1.shape[1]
@@ -116,6 +127,12 @@ def run_gpu(lp, opts, prec, steps, warmup, nsolves, graph):
     per, steps_taken, berrs, _, wall = timed(-1)
     per_p, _, _, prof, _ = timed(dom)
     fs = s.factor_stats()
+    if s.systems is not None:  # the worst system of the batch
+        bs = s.batch_stats(nrhs)
+        fs["systems"] = len(s.systems)
+        fs["worst_system_berr_nw"] = float(bs["berr_nw"].max())
+        fs["inertia_ok_all_systems"] = bool(all(tuple(bs["inertia"][q][:2]) == (sy_["n"], sy_["m"])
+                                               for q, sy_ in enumerate(s.systems)))
     out = dict(ms=per, wall=wall, ms_profiled=per_p, sym=sym, steps=steps_taken, berr=berrs, fstats=fs, dom=dom, prof=prof,
                per_kind={Q.KERNEL_KIND_NAMES[k]: round(v["total_ms"], 3) for k, v in per_kind.items()})
     if graph:  # the same step captured once as a HIP graph and replayed with Theta refreshed
@@ -161,7 +178,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="as_staircase")
+    ap.add_argument("--workload", default="as_staircase",
+                    help="as_staircase | ne_random | ne_grid | ne_grid_small | as_batch | as_batch_small | as_dense_cols")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--nsolves", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")
@@ -228,6 +246,8 @@ def main():
         "ms_median": round(float(np.median(r["ms"])), 4), "ms_min": round(min(r["ms"]), 4),
         "ms_max": round(max(r["ms"]), 4),
         "inertia": [r["fstats"]["nneg"], r["fstats"]["npos"]],
+        "batch": {k: r["fstats"][k] for k in ("systems", "worst_system_berr_nw", "inertia_ok_all_systems")}
+        if "systems" in r["fstats"] else None,
     }
     if "graph_ms" in r:
         gms = float(np.median(r["graph_ms"]))

@@ -169,6 +169,39 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
 int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev,
                double* dx_dev, double* dy_dev);
 
+/* ---- batches of independent systems ---------------------------------------------------
+ * A batch of count independent LPs of one mode is analysed as one block-diagonal pattern:
+ * system q's column j becomes column col_off[q] + j and its row i row row_off[q] + i (offsets
+ * from qdmf_batch_offsets), so every tree-level launch of the factorisation and the solves
+ * covers the fronts of all systems at once (the many-small-fronts case of Section 4.3's tree
+ * parallelism).  Each system keeps its own ||K_static||_1 (lift threshold, Section 4.5), its
+ * own rho and delta, its own backward errors and refinement decisions, and its own inertia.
+ * After qdmf_batch_analyse: qdmf_set_matrix takes the systems' values concatenated in system
+ * order; qdmf_factorise (one rho, delta for all) or qdmf_batch_factorise (per system);
+ * qdmf_solve on concatenated vectors (r7, dx: sum n; r1, dy: sum m); qdmf_solve_stats reports
+ * the worst system per right-hand side and qdmf_batch_stats every system. */
+
+/* m, n, colptr, rowidx: count entries each (host), one CSC pattern per system as for
+ * qdmf_analyse.  Orderings QDMF_ORDER_USER and QDMF_ORDER_GRID_ND are not accepted.
+ * Errors: as qdmf_analyse. */
+int qdmf_batch_analyse(qdmf_handle h, int32_t count, const int32_t* m, const int32_t* n,
+                       const int64_t* const* colptr, const int32_t* const* rowidx, int32_t mode);
+
+/* row_off, col_off: count + 1 entries each (host; either may be NULL).  For a single system
+ * they are {0, m} and {0, n}.  Errors: QDMF_ERR_NOT_ANALYSED. */
+int qdmf_batch_offsets(qdmf_handle h, int64_t* row_off, int64_t* col_off);
+
+/* As qdmf_factorise with rho[q], delta[q] (host, count entries, >= 0) for system q.  The
+ * call waits for the stream before it stages the shifts (graph capture is not supported for
+ * this call; qdmf_graph_capture takes one rho, delta for all systems). */
+int qdmf_batch_factorise(qdmf_handle h, const double* theta_dev, const double* rho,
+                         const double* delta, int32_t prec);
+
+/* Synchronises; any pointer may be NULL.  inertia: 3 x count (negative, positive, zero
+ * pivots of system q at 3q..3q+2); berr_nw, steps: count x nrhs of the last solve, entry
+ * r * count + q for right-hand side r of system q.  Errors: QDMF_ERR_NOT_FACTORISED. */
+int qdmf_batch_stats(qdmf_handle h, int64_t* inertia, double* berr_nw, int32_t* steps);
+
 /* Synchronises the stream and reports the last factorisation.  Returns the status (0,
  * a QDMF_WARN_* code, or QDMF_ERR_INVALID_ARG if Theta was invalid). */
 int qdmf_factor_stats(qdmf_handle h, qdmf_factor_info* out);

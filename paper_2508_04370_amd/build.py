@@ -40,7 +40,7 @@ def build():
     with cf.ThreadPoolExecutor(max_workers=6) as ex:
         objs = list(ex.map(_compile, HIP_SOURCES + HOST_SOURCES))
     tmp = LIB_PATH + ".tmp"
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

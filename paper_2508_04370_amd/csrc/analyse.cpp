@@ -8,6 +8,8 @@
 #include <numeric>
 #include <string>
 #include <vector>
+#include <atomic>
+#include <thread>
 
 #include "../../include/qdmf.h"
 #include "plan.hpp"
@@ -170,6 +172,61 @@ double order_cost(int32_t N, const std::vector<int64_t>& xadj, const std::vector
 
 namespace {
 
+// Fill-reducing order of one subgraph (nodes listed in nodes) by the handle's method.
+void order_one(int32_t ordering, const std::vector<int32_t>& nodes, const std::vector<int64_t>& xadj,
+               const std::vector<int32_t>& adj, std::vector<int32_t>& local, std::vector<int32_t>& out) {
+    const int32_t k = (int32_t)nodes.size();
+    for (int32_t i = 0; i < k; ++i) local[nodes[i]] = i;
+    std::vector<int64_t> sx(k + 1, 0);
+    std::vector<int32_t> sa;
+    for (int32_t i = 0; i < k; ++i) {
+        for (int64_t e = xadj[nodes[i]]; e < xadj[nodes[i] + 1]; ++e)
+            if (local[adj[e]] >= 0) sa.push_back(local[adj[e]]);
+        sx[i + 1] = (int64_t)sa.size();
+    }
+    for (int32_t v : nodes) local[v] = -1;
+    std::vector<int32_t> ord;
+    if (ordering == QDMF_ORDER_ND) {
+        nd_order(k, sx, sa, ord);
+    } else {
+        amd_order(k, sx, sa, ord);
+        if (ordering == QDMF_ORDER_AUTO) {
+            std::vector<int32_t> nd;
+            nd_order(k, sx, sa, nd);
+            if (order_cost(k, sx, sa, nd) < order_cost(k, sx, sa, ord)) ord.swap(nd);
+        }
+    }
+    out.resize(k);
+    for (int32_t i = 0; i < k; ++i) out[i] = nodes[ord[i]];
+}
+
+// Batch: the systems are the diagonal blocks, ordered independently by a pool of threads;
+// the order is the systems' orders concatenated (deterministic).
+void order_systems(int32_t N, int32_t m, int32_t n, int32_t mode, const AnalyseOptions& opt,
+                   const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj, std::vector<int32_t>& order) {
+    const int32_t ns = opt.nsys;
+    std::vector<std::vector<int32_t>> nodes(ns), outs(ns);
+    for (int32_t q = 0; q < ns; ++q) {
+        if (mode == QDMF_AS)
+            for (int64_t j = opt.col_off[q]; j < opt.col_off[q + 1]; ++j) nodes[q].push_back((int32_t)j);
+        for (int64_t i = opt.row_off[q]; i < opt.row_off[q + 1]; ++i)
+            nodes[q].push_back((int32_t)(mode == QDMF_AS ? n + i : i));
+    }
+    (void)m;
+    std::atomic<int32_t> next(0);
+    const int32_t nt = std::max(1, std::min<int32_t>(ns, (int32_t)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int32_t t = 0; t < nt; ++t)
+        pool.emplace_back([&]() {
+            std::vector<int32_t> local(N, -1);
+            for (int32_t q; (q = next++) < ns;) order_one(opt.ordering, nodes[q], xadj, adj, local, outs[q]);
+        });
+    for (auto& th : pool) th.join();
+    order.clear();
+    order.reserve(N);
+    for (int32_t q = 0; q < ns; ++q) order.insert(order.end(), outs[q].begin(), outs[q].end());
+}
+
 void postorder(int32_t N, const std::vector<int32_t>& parent, std::vector<int32_t>& post) {
     std::vector<int32_t> head(N, -1), nxt(N, -1), stack;
     for (int32_t j = N - 1; j >= 0; --j)
@@ -258,6 +315,8 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             return QDMF_ERR_INVALID_ARG;
         }
         grid_nd_order(P, opt.grid, xadj, adj, order);
+    } else if (opt.nsys > 1) {  // a batch: each system ordered on its own, in parallel
+        order_systems(N, m, n, mode, opt, xadj, adj, order);
     } else if (opt.ordering == QDMF_ORDER_ND) {
         nd_order(N, xadj, adj, order);
     } else if (opt.ordering == QDMF_ORDER_AUTO) {  // the cheaper of the two (order_cost)
@@ -388,7 +447,10 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                 int64_t fm = s_f[s] + s_p[c];
                 int64_t ent = pm * fm - pm * (pm - 1) / 2;
                 int64_t zeros = s_zero[c] + s_zero[s] + pc * delta;
-                bool ok = (s_nk[s] == 1 && delta <= 8) || (pc < 16 && (double)zeros <= 0.05 * (double)ent);
+                // (the third rule: large nearly dense fronts, whose separate square storage
+                // and pivot windows would cost more than the few zeros)
+                bool ok = (s_nk[s] == 1 && delta <= 8) || (pc < 16 && (double)zeros <= 0.05 * (double)ent) ||
+                          (fm >= 512 && (double)zeros <= 0.01 * (double)ent);
                 if (!ok) break;
                 // merge c into s
                 alive[c] = 0;
@@ -597,6 +659,47 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     P.primal_new.assign(N, 0);
     if (mode == QDMF_AS)
         for (int32_t c = 0; c < N; ++c) P.primal_new[c] = P.perm[c] < n;
+
+    // ----- systems of a batch (block-diagonal A): per column, per K index, index ranges,
+    // pivot lists
+    P.nsys = std::max(1, opt.nsys);
+    P.sys_col.assign(n, 0);
+    std::vector<int32_t> sys_row(m, 0);
+    if (opt.nsys > 1) {
+        for (int32_t q = 0; q < P.nsys; ++q) {
+            for (int64_t j = opt.col_off[q]; j < opt.col_off[q + 1]; ++j) P.sys_col[j] = q;
+            for (int64_t i = opt.row_off[q]; i < opt.row_off[q + 1]; ++i) sys_row[i] = q;
+        }
+    }
+    P.sys_old.resize(N);
+    for (int32_t v = 0; v < N; ++v)
+        P.sys_old[v] = mode == QDMF_AS ? (v < n ? P.sys_col[v] : sys_row[v - n]) : sys_row[v];
+    P.sys_new.resize(N);
+    for (int32_t k = 0; k < N; ++k) P.sys_new[k] = P.sys_old[P.perm[k]];
+    P.sys_rng.assign(4 * (size_t)P.nsys, 0);
+    for (int32_t q = 0; q < P.nsys; ++q) {
+        const int64_t c0 = opt.nsys > 1 ? opt.col_off[q] : 0, c1 = opt.nsys > 1 ? opt.col_off[q + 1] : n;
+        const int64_t r0 = opt.nsys > 1 ? opt.row_off[q] : 0, r1 = opt.nsys > 1 ? opt.row_off[q + 1] : m;
+        if (mode == QDMF_AS) {
+            P.sys_rng[4 * q] = c0;
+            P.sys_rng[4 * q + 1] = c1;
+            P.sys_rng[4 * q + 2] = n + r0;
+            P.sys_rng[4 * q + 3] = n + r1;
+        } else {
+            P.sys_rng[4 * q] = r0;
+            P.sys_rng[4 * q + 1] = r1;
+            P.sys_rng[4 * q + 2] = r1;
+            P.sys_rng[4 * q + 3] = r1;
+        }
+    }
+    P.sys_piv_ptr.assign(P.nsys + 1, 0);
+    for (int32_t k = 0; k < N; ++k) P.sys_piv_ptr[P.sys_new[k] + 1]++;
+    for (int32_t q = 0; q < P.nsys; ++q) P.sys_piv_ptr[q + 1] += P.sys_piv_ptr[q];
+    P.sys_piv.resize(N);
+    {
+        std::vector<int64_t> fill(P.sys_piv_ptr.begin(), P.sys_piv_ptr.end() - 1);
+        for (int32_t k = 0; k < N; ++k) P.sys_piv[fill[P.sys_new[k]]++] = k;
+    }
 
     // ----- memory plan: dense square fronts, column-major, ld = f
     P.sn_ld.resize(ns);

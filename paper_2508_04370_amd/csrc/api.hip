@@ -40,6 +40,11 @@ struct qdmf_ctx {
     DevSolve S{};
     int32_t solve_cap = 0;
     int32_t* act_host = nullptr;  // pinned copy of the refinement flags (eager solves)
+    double* shift_host = nullptr;  // pinned staging of per-system rho, delta (batch factorise)
+    int32_t shift_cap = 0;
+    double* shift_dev = nullptr;
+    bool batch_shifts = false;     // the last factorisation used per-system shifts
+    std::vector<int64_t> batch_col_off, batch_row_off;  // system offsets of a batch
     int32_t last_nrhs = 0;
     bool solved = false;
 
@@ -190,7 +195,14 @@ int upload_plan(qdmf_ctx* h) {
     UP(arp, arp)
     UP(are, are)
     UP(acol, acol)
+    UP(sys_col, sys_col)
+    UP(sys_old, sys_old)
+    UP(sys_new, sys_new)
+    UP(sys_rng, sys_rng)
+    UP(sys_piv_ptr, sys_piv_ptr)
+    UP(sys_piv, sys_piv)
 #undef UP
+    D.nsys = P.nsys;
     const Task* tk = nullptr;
     if ((rc = dupload(h, P.tasks, &tk))) return rc;
     h->tasks_dev = const_cast<Task*>(tk);
@@ -216,6 +228,11 @@ int upload_plan(qdmf_ctx* h) {
     if ((rc = dalloc(h, h->plan_allocs, &D.lpinv, N))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.sc, 1))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.st, 1))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.knorm_sys, P.nsys))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.rho_sys, P.nsys))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.delta_sys, P.nsys))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.inertia_sys, (int64_t)3 * P.nsys))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &h->shift_dev, (int64_t)2 * P.nsys))) return rc;
     // largest front (dynamic LDS of the solve kernels) and pivot count (kernel variant) per level
     h->maxf_lvl.assign(P.nlevels, 1);
     h->maxp_lvl.assign(P.nlevels, 1);
@@ -247,12 +264,13 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     if ((rc = dalloc(h, h->solve_allocs, &S.xw, N * nrhs))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.ub, std::max<int64_t>(1, h->P.ub_total) * nrhs))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.part, (int64_t)3 * S.nblk * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.berr, (int64_t)4 * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.active, nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.steps, nrhs))) return rc;
+    const int64_t units = (int64_t)nrhs * h->P.nsys;
+    if ((rc = dalloc(h, h->solve_allocs, &S.berr, 4 * units))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.active, units))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.steps, units))) return rc;
     if (h->act_host) (void)hipHostFree(h->act_host);
     h->act_host = nullptr;
-    if (hipHostMalloc((void**)&h->act_host, sizeof(int32_t) * nrhs, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&h->act_host, sizeof(int32_t) * units, hipHostMallocDefault) != hipSuccess) {
         h->act_host = nullptr;
         return QDMF_ERR_OOM;
     }
@@ -272,9 +290,11 @@ PivotParams pivot_params(const qdmf_ctx* h, int32_t prec) {
     return pp;
 }
 
-void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delta, int32_t prec) {
+// shifts_dev: per-system [rho(nsys), delta(nsys)] on the device, or NULL (rho, delta for all)
+void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delta, const double* shifts_dev,
+                       int32_t prec) {
     const PivotParams pp = pivot_params(h, prec);
-    launch_theta(h->D, theta, rho, delta, h->stream);
+    launch_theta(h->D, theta, rho, delta, shifts_dev, shifts_dev ? shifts_dev + h->P.nsys : nullptr, h->stream);
     launch_values_n(h->D, h->knnz, h->stream);
     launch_knorm(h->D, h->stream);
     for (const Launch& L : h->P.launches) {
@@ -289,6 +309,7 @@ void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32
     const Plan& P = h->P;
     const DevSolve& S = h->S;
     hipStream_t st = h->stream;
+    if (P.nsys > 1) active = nullptr;  // flags are per system: solve every system
     launch_permute(h->D, S, src, active, st);
     for (int32_t l = 0; l < P.nlevels; ++l) {
         ProfScope ps(h, QDMF_K_FWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
@@ -319,12 +340,13 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
         // right-hand side has met the target; a captured graph keeps all passes and the
         // kernels of a finished right-hand side return at once.
         if (!h->capturing) {
-            if (hipMemcpyAsync(h->act_host, S.active, sizeof(int32_t) * S.nrhs, hipMemcpyDeviceToHost, st) !=
+            const int64_t units = (int64_t)S.nrhs * h->P.nsys;
+            if (hipMemcpyAsync(h->act_host, S.active, sizeof(int32_t) * units, hipMemcpyDeviceToHost, st) !=
                     hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 break;
             bool any = false;
-            for (int r = 0; r < S.nrhs; ++r) any = any || h->act_host[r] != 0;
+            for (int64_t u = 0; u < units; ++u) any = any || h->act_host[u] != 0;
             if (!any) break;
         }
         launch_refine_begin(D, S, st);
@@ -392,9 +414,10 @@ int qdmf_set_stream(qdmf_handle h, void* s) {
     return 0;
 }
 
-int qdmf_analyse(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx,
-                 int32_t mode, const int32_t* user_perm) {
-    if (!h) return QDMF_ERR_INVALID_ARG;
+namespace {
+
+int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx, int32_t mode,
+                 const int32_t* user_perm, int32_t nsys, const int64_t* col_off, const int64_t* row_off) {
     if (!h->host_only) {
         int rc = set_device(h);
         if (rc) return rc;
@@ -412,6 +435,9 @@ int qdmf_analyse(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     ao.amalgamate = h->opt.amalgamate;
     ao.small_front = h->opt.small_front;
     ao.user_perm = user_perm;
+    ao.nsys = nsys;
+    ao.col_off = col_off;
+    ao.row_off = row_off;
     if (h->opt.ordering == QDMF_ORDER_USER && !user_perm) return QDMF_ERR_INVALID_ARG;
     int rc = build_plan(m, n, colptr, rowidx, mode, ao, h->P, h->msg);
     if (rc) return rc;
@@ -429,6 +455,65 @@ int qdmf_analyse(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
         }
     }
     h->analysed = true;
+    return 0;
+}
+
+}  // namespace
+
+int qdmf_analyse(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx,
+                 int32_t mode, const int32_t* user_perm) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    h->batch_col_off.clear();
+    h->batch_row_off.clear();
+    return analyse_impl(h, m, n, colptr, rowidx, mode, user_perm, 1, nullptr, nullptr);
+}
+
+int qdmf_batch_analyse(qdmf_handle h, int32_t count, const int32_t* m, const int32_t* n,
+                       const int64_t* const* colptr, const int32_t* const* rowidx, int32_t mode) {
+    if (!h || count < 1 || !m || !n || !colptr || !rowidx) return QDMF_ERR_INVALID_ARG;
+    if (h->opt.ordering == QDMF_ORDER_USER || h->opt.ordering == QDMF_ORDER_GRID_ND) return QDMF_ERR_INVALID_ARG;
+    std::vector<int64_t> coff(count + 1, 0), roff(count + 1, 0);
+    int64_t nnz = 0;
+    for (int32_t q = 0; q < count; ++q) {
+        if (m[q] < 0 || n[q] < 0 || !colptr[q] || (n[q] > 0 && !rowidx[q] && colptr[q][n[q]] > 0))
+            return QDMF_ERR_INVALID_ARG;
+        coff[q + 1] = coff[q] + n[q];
+        roff[q + 1] = roff[q] + m[q];
+        nnz += colptr[q][n[q]] - colptr[q][0];
+    }
+    if (coff[count] > INT32_MAX || roff[count] > INT32_MAX) return QDMF_ERR_INDEX_OVERFLOW;
+    // the block-diagonal pattern: system q's column j is column coff[q] + j, its row i row roff[q] + i
+    std::vector<int64_t> cp(coff[count] + 1, 0);
+    std::vector<int32_t> ri;
+    ri.reserve(nnz);
+    for (int32_t q = 0; q < count; ++q)
+        for (int32_t j = 0; j < n[q]; ++j) {
+            for (int64_t e = colptr[q][j]; e < colptr[q][j + 1]; ++e) {
+                const int32_t r = rowidx[q][e];
+                if (r < 0 || r >= m[q]) return QDMF_ERR_INVALID_ARG;
+                ri.push_back((int32_t)(roff[q] + r));
+            }
+            cp[coff[q] + j + 1] = (int64_t)ri.size();
+        }
+    h->batch_col_off = coff;
+    h->batch_row_off = roff;
+    const int rc = analyse_impl(h, (int32_t)roff[count], (int32_t)coff[count], cp.data(), ri.data(), mode, nullptr,
+                                count, coff.data(), roff.data());
+    if (rc) {
+        h->batch_col_off.clear();
+        h->batch_row_off.clear();
+    }
+    return rc;
+}
+
+int qdmf_batch_offsets(qdmf_handle h, int64_t* row_off, int64_t* col_off) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
+    const int32_t ns = h->P.nsys;
+    for (int32_t q = 0; q <= ns; ++q) {
+        if (row_off) row_off[q] = h->batch_row_off.empty() ? (q ? h->P.m : 0) : h->batch_row_off[q];
+        if (col_off) col_off[q] = h->batch_col_off.empty() ? (q ? h->P.n : 0) : h->batch_col_off[q];
+    }
     return 0;
 }
 
@@ -483,11 +568,72 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
         return QDMF_ERR_INVALID_ARG;
     int rc = set_device(h);
     if (rc) return rc;
-    enqueue_factorise(h, theta_dev, rho, delta, prec);
+    enqueue_factorise(h, theta_dev, rho, delta, nullptr, prec);
     if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
     h->last_prec = prec;
     h->factorised = true;
     h->solved = false;
+    return 0;
+}
+
+int qdmf_batch_factorise(qdmf_handle h, const double* theta_dev, const double* rho, const double* delta,
+                         int32_t prec) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
+    if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
+    const int32_t ns = h->P.nsys;
+    if (h->host_only || (!theta_dev && h->P.n > 0) || !rho || !delta || (prec != QDMF_FP64 && prec != QDMF_MIXED))
+        return QDMF_ERR_INVALID_ARG;
+    for (int32_t q = 0; q < ns; ++q)
+        if (!(rho[q] >= 0) || !(delta[q] >= 0) || !std::isfinite(rho[q]) || !std::isfinite(delta[q]))
+            return QDMF_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    // the staging buffer may still feed an earlier copy on the stream: wait for it
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    if (h->shift_cap < ns) {
+        if (h->shift_host) (void)hipHostFree(h->shift_host);
+        h->shift_cap = 0;
+        if (hipHostMalloc((void**)&h->shift_host, sizeof(double) * 2 * ns, hipHostMallocDefault) != hipSuccess) {
+            h->shift_host = nullptr;
+            return QDMF_ERR_OOM;
+        }
+        h->shift_cap = ns;
+    }
+    for (int32_t q = 0; q < ns; ++q) {
+        h->shift_host[q] = rho[q];
+        h->shift_host[ns + q] = delta[q];
+    }
+    if (hipMemcpyAsync(h->shift_dev, h->shift_host, sizeof(double) * 2 * ns, hipMemcpyHostToDevice, h->stream) !=
+        hipSuccess)
+        return QDMF_ERR_HIP;
+    enqueue_factorise(h, theta_dev, rho[0], delta[0], h->shift_dev, prec);
+    if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
+    h->last_prec = prec;
+    h->factorised = true;
+    h->solved = false;
+    return 0;
+}
+
+int qdmf_batch_stats(qdmf_handle h, int64_t* inertia, double* berr_nw, int32_t* steps) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;
+    if (set_device(h)) return QDMF_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    const size_t ns = (size_t)h->P.nsys;
+    if (inertia && hipMemcpy(inertia, h->D.inertia_sys, sizeof(int64_t) * 3 * ns, hipMemcpyDeviceToHost) != hipSuccess)
+        return QDMF_ERR_HIP;
+    if (berr_nw || steps) {
+        if (!h->solved) return QDMF_ERR_NOT_FACTORISED;
+        const size_t units = ns * (size_t)h->last_nrhs;
+        std::vector<double> bu(4 * units);
+        if (hipMemcpy(bu.data(), h->S.berr, sizeof(double) * bu.size(), hipMemcpyDeviceToHost) != hipSuccess)
+            return QDMF_ERR_HIP;
+        if (berr_nw)
+            for (size_t u = 0; u < units; ++u) berr_nw[u] = bu[4 * u];
+        if (steps && hipMemcpy(steps, h->S.steps, sizeof(int32_t) * units, hipMemcpyDeviceToHost) != hipSuccess)
+            return QDMF_ERR_HIP;
+    }
     return 0;
 }
 
@@ -541,13 +687,19 @@ int qdmf_solve_stats(qdmf_handle h, qdmf_solve_info* out, double* berr_nw_per_rh
     if (!h->solved) return QDMF_ERR_NOT_FACTORISED;
     if (set_device(h)) return QDMF_ERR_HIP;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
-    const int32_t nr = h->last_nrhs;
-    std::vector<double> be(4 * (size_t)nr);
-    std::vector<int32_t> steps(nr);
-    if (hipMemcpy(be.data(), h->S.berr, sizeof(double) * be.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    const int32_t nr = h->last_nrhs, ns = h->P.nsys;
+    std::vector<double> bu(4 * (size_t)nr * ns), be(4 * (size_t)nr, 0.0);
+    std::vector<int32_t> su((size_t)nr * ns), steps(nr, 0);
+    if (hipMemcpy(bu.data(), h->S.berr, sizeof(double) * bu.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return QDMF_ERR_HIP;
-    if (hipMemcpy(steps.data(), h->S.steps, sizeof(int32_t) * nr, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(su.data(), h->S.steps, sizeof(int32_t) * su.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return QDMF_ERR_HIP;
+    for (int32_t r = 0; r < nr; ++r)  // worst system per rhs
+        for (int32_t q = 0; q < ns; ++q) {
+            const size_t u = (size_t)r * ns + q;
+            for (int v = 0; v < 3; ++v) be[4 * r + v] = std::max(be[4 * r + v], bu[4 * u + v]);
+            steps[r] = std::max(steps[r], su[u]);
+        }
     const bool mixed = h->last_prec == QDMF_MIXED;
     const double target = mixed ? h->opt.target_berr_mixed : h->opt.target_berr;
     out->nrhs = nr;
@@ -628,7 +780,7 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return QDMF_ERR_HIP;
     h->last_prec = prec;
     h->capturing = true;
-    enqueue_factorise(h, theta_dev, rho, delta, prec);
+    enqueue_factorise(h, theta_dev, rho, delta, nullptr, prec);
     for (int32_t q = 0; q < nsolves; ++q) enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
     h->capturing = false;
     hipGraph_t g = nullptr;
@@ -689,6 +841,7 @@ void qdmf_destroy(qdmf_handle h) {
     }
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->act_host) (void)hipHostFree(h->act_host);
+    if (h->shift_host) (void)hipHostFree(h->shift_host);
     destroy_graph(h);
     free_list(h->solve_allocs);
     free_list(h->plan_allocs);

@@ -88,10 +88,24 @@ struct DevPlan {
     int32_t* lpinv;   // inverse: c0 + pre-pivot local position -> post-pivot local position
     DevScalars* sc;
     DevStats* st;
+    // systems (one unless a batch): per-system ||K_static||_1 and static shifts, and maps
+    int32_t nsys;
+    const int32_t* sys_col;      // per column of A
+    const int32_t* sys_old;      // per K index, original numbering
+    const int32_t* sys_new;      // per K index, elimination order
+    const int64_t* sys_rng;      // per system: [a0, a1), [b0, b1) in original numbering
+    const int64_t* sys_piv_ptr;  // per system: pivot positions
+    const int32_t* sys_piv;
+    double* knorm_sys;
+    double* rho_sys;
+    double* delta_sys;
+    int64_t* inertia_sys;        // per system: negative, positive, zero pivots
 };
 
 // ---- factorisation
-void launch_theta(const DevPlan& D, const double* theta, double rho, double delta, hipStream_t s);
+// rho_sys/delta_sys: per-system shifts (device, nsys each) or NULL to use rho, delta for all
+void launch_theta(const DevPlan& D, const double* theta, double rho, double delta, const double* rho_sys,
+                  const double* delta_sys, hipStream_t s);
 void launch_values_n(const DevPlan& D, int64_t knnz, hipStream_t s);
 void launch_knorm(const DevPlan& D, hipStream_t s);
 void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks_dev,
@@ -112,9 +126,10 @@ struct DevSolve {
     double* ub;     // contribution buffers, ub_total x nrhs
     double* part;   // per-block partial maxima: 3 x nblk x nrhs
     int32_t nblk;
-    double* berr;   // per rhs: [nw, cw, nw_initial, nw_prev]
-    int32_t* active;  // per rhs: refinement continues
-    int32_t* steps;   // per rhs
+    // refinement state per unit u = rhs * nsys + system
+    double* berr;     // per unit: [nw, cw, nw_initial, unused]
+    int32_t* active;  // per unit: refinement continues
+    int32_t* steps;   // per unit
 };
 
 void launch_rhs(const DevPlan& D, const DevSolve& S, const double* r7, const double* r1, hipStream_t s);

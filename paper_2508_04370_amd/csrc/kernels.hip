@@ -308,9 +308,9 @@ __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, con
     }
 }
 
-__device__ inline void init_signs(PivShared& S, const DevPlan& D, const int32_t* rows, int fr,
+__device__ inline void init_signs(PivShared& S, const DevPlan& D, const int32_t* rows, int fr, int sys,
                                   int lane) {
-    const double rho = D.sc->rho, delta = D.sc->delta;
+    const double rho = D.rho_sys[sys], delta = D.delta_sys[sys];
     if (lane < fr) {
         const bool pr = D.primal_new[rows[lane]] != 0;
         S.sg[lane] = pr ? -1 : 1;
@@ -387,9 +387,10 @@ __global__ __launch_bounds__(64) void k_small(DevPlan D, const Task* tasks, int6
         }
         __syncthreads();
     }
-    init_signs(S, D, rows, f, lane);
+    const int sys = D.sys_new[c0];
+    init_signs(S, D, rows, f, sys, lane);
     __syncthreads();
-    factor_window<false>(S, f, p, D.sc->knorm, pp, lane);
+    factor_window<false>(S, f, p, D.knorm_sys[sys], pp, lane);
     for (int j = 0; j < f; ++j)
         if (lane >= j && lane < f) F[lane + (int64_t)j * ld] = S.T[j * LDW + lane];
     store_pivots(S, D, c0, 0, p, lane);
@@ -526,13 +527,14 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
     int slotP = lane;
     double dgP = 0.0, shP = 0.0;
     int sgP = 1;
+    const int sys = D.sys_new[c0];
     if (lane < nbw) {
         dgP = F[(k0 + lane) + (int64_t)(k0 + lane) * ld];
         const bool pr = D.primal_new[D.rows[D.sn_rowptr[s] + k0 + lane]] != 0;
         sgP = pr ? -1 : 1;
-        shP = pr ? -D.sc->rho : D.sc->delta;
+        shP = pr ? -D.rho_sys[sys] : D.delta_sys[sys];
     }
-    const double tiny = pp.eps_lift * D.sc->knorm;  // delta * ||M||_1 of the lift test
+    const double tiny = pp.eps_lift * D.knorm_sys[sys];  // delta * ||M||_1 of the lift test
     const double alpha = pp.alpha;
     uint64_t elim = 0;  // eliminated slots
     double o_d = 0.0, o_off = 0.0, o_ed = 0.0;  // outputs of position = lane
@@ -941,11 +943,19 @@ __global__ __launch_bounds__(256) void k_finalize(DevPlan D, const Task* tasks, 
 
 // ---------------------------------------------------------------- values of K
 
-__global__ void k_init_scalars(DevPlan D, double rho, double delta) {
-    D.sc->rho = rho;
-    D.sc->delta = delta;
-    D.sc->bad_theta = 0;
-    D.sc->knorm = 0.0;
+__global__ void k_init_scalars(DevPlan D, double rho, double delta, const double* rho_a, const double* delta_a) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) {
+        D.sc->rho = rho;
+        D.sc->delta = delta;
+        D.sc->bad_theta = 0;
+        D.sc->knorm = 0.0;
+    }
+    if (q < D.nsys) {
+        D.rho_sys[q] = rho_a ? rho_a[q] : rho;
+        D.delta_sys[q] = delta_a ? delta_a[q] : delta;
+        D.knorm_sys[q] = 0.0;
+    }
 }
 
 // AS: dinv = 1/Theta (diagonal -(Theta^{-1}) of equation (augsys));
@@ -956,7 +966,7 @@ __global__ void k_theta(DevPlan D, const double* theta) {
     const double th = theta[j];
     if (!(th > 0.0) || !isfinite(th)) atomicOr(&D.sc->bad_theta, 1);
     if (D.mode == 1) D.dinv[j] = 1.0 / th;
-    else D.dinv[j] = 1.0 / (1.0 / th + D.sc->rho);
+    else D.dinv[j] = 1.0 / (1.0 / th + D.rho_sys[D.sys_col[j]]);
 }
 
 // Values of lower(K) in analyse order.  NE: K_ik = sum_j (A_ij theta~_j) A_kj over the
@@ -985,7 +995,8 @@ __global__ void k_values(DevPlan D, int64_t knnz) {
 __global__ void k_rowsum(DevPlan D) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= D.N) return;
-    const double rho = D.sc->rho, delta = D.sc->delta;
+    const int sys = D.sys_old[i];
+    const double rho = D.rho_sys[sys], delta = D.delta_sys[sys];
     double s;
     if (D.mode == 1) {
         if (i < D.n) s = (D.dinv[i] + rho) + D.colabs[i];
@@ -1001,17 +1012,25 @@ __global__ void k_rowsum(DevPlan D) {
     D.rowsum[i] = s;
 }
 
+// ||K_static||_1 of each system (one workgroup per system; K is symmetric, so the largest
+// row sum).
 __global__ __launch_bounds__(1024) void k_knorm(DevPlan D) {
     __shared__ double red[1024];
+    const int q = blockIdx.x;
+    const int64_t* rg = D.sys_rng + 4 * q;
     double m = 0.0;
-    for (int i = threadIdx.x; i < D.N; i += 1024) m = fmax(m, D.rowsum[i]);
+    for (int64_t i = rg[0] + threadIdx.x; i < rg[1]; i += 1024) m = fmax(m, D.rowsum[i]);
+    for (int64_t i = rg[2] + threadIdx.x; i < rg[3]; i += 1024) m = fmax(m, D.rowsum[i]);
     red[threadIdx.x] = m;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) D.sc->knorm = red[0];
+    if (threadIdx.x == 0) {
+        D.knorm_sys[q] = red[0];
+        if (D.nsys == 1) D.sc->knorm = red[0];
+    }
 }
 
 // Sum_i |A_ij| per column and sum_j |A_ij| per row (once per matrix).
@@ -1036,8 +1055,8 @@ __global__ __launch_bounds__(1024) void k_factor_stats(DevPlan D, PivotParams pp
     int64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double me = 0.0;
     int big = 0;
-    const double thr = pp.tau_big * D.sc->knorm;
     for (int k = threadIdx.x; k < D.N; k += 1024) {
+        const double thr = pp.tau_big * D.knorm_sys[D.sys_new[k]];
         const int ty = D.ptype[k];
         if (ty == 0) {
             const double d = D.dval[k];
@@ -1090,6 +1109,35 @@ __global__ __launch_bounds__(1024) void k_factor_stats(DevPlan D, PivotParams pp
         st->max_edyn = v < 0 ? -v - 1.0 : v;
         st->bad_theta = D.sc->bad_theta;
     }
+}
+
+// Inertia of each system from its own pivot positions (one workgroup per system).
+__global__ __launch_bounds__(256) void k_sys_inertia(DevPlan D) {
+    __shared__ int64_t red[3][256];
+    const int q = blockIdx.x;
+    int64_t c[3] = {0, 0, 0};
+    for (int64_t t = D.sys_piv_ptr[q] + threadIdx.x; t < D.sys_piv_ptr[q + 1]; t += 256) {
+        const int k = D.sys_piv[t];
+        const int ty = D.ptype[k];
+        if (ty == 0) {
+            const double d = D.dval[k];
+            c[d < 0 ? 0 : (d > 0 ? 1 : 2)]++;
+        } else if (ty == 1) {
+            const double a = D.dval[k], b = D.doff[k], cc = D.dval[k + 1];
+            const double det = a * cc - b * b;
+            if (det < 0) { c[0]++; c[1]++; }
+            else if (a + cc > 0) c[1] += 2;
+            else c[0] += 2;
+        }
+    }
+    for (int v = 0; v < 3; ++v) red[v][threadIdx.x] = c[v];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int v = 0; v < 3; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) D.inertia_sys[3 * q + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // ---------------------------------------------------------------- solve kernels
@@ -1362,7 +1410,8 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const d
     const double* b = S.b + (int64_t)r * D.N;
     double ar = 0.0, ax = 0.0, ab = 0.0;
     if (i < D.N) {
-        const double rho = D.sc->rho, delta = D.sc->delta;
+        const int sys = D.sys_old[i];
+        const double rho = D.rho_sys[sys], delta = D.delta_sys[sys];
         double kx = 0.0, akx = 0.0;
         if (D.mode == 1) {
             if (i < D.n) {
@@ -1417,49 +1466,51 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const d
 // substitution of Arioli, Demmel and Duff) and the refinement decision for each rhs.
 // phase 0: after the first solve; phase 1: after a refinement step.
 __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase, double target, int max_steps) {
-    __shared__ double red[1024];
-    __shared__ double sh_rmax, sh_xmax, sh_bmax;
-    const int r = blockIdx.x;
-    if (phase == 1 && !S.active[r]) return;
-    const double* part = S.part + (int64_t)r * 3 * S.nblk;
-    for (int q = 0; q < 3; ++q) {
-        double m = 0.0;
-        for (int i = threadIdx.x; i < S.nblk; i += 1024) m = fmax(m, part[q * S.nblk + i]);
-        red[threadIdx.x] = m;
-        __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (q == 0) sh_rmax = red[0];
-            else if (q == 1) sh_xmax = red[0];
-            else sh_bmax = red[0];
-        }
-        __syncthreads();
-    }
-    const double xmax = sh_xmax;
-    const double u = 1.1102230246251565e-16;
+    __shared__ double red[4][1024];
+    const int q = blockIdx.x, r = blockIdx.y, u = r * D.nsys + q;  // system q, rhs r
+    if (phase == 1 && !S.active[u]) return;
+    const int64_t* rg = D.sys_rng + 4 * q;
     const double* rr = S.r + (int64_t)r * D.N;
     const double* akx = S.d + (int64_t)r * D.N;
     const double* b = S.b + (int64_t)r * D.N;
-    double cm = 0.0;
-    for (int i = threadIdx.x; i < D.N; i += 1024) {
-        double den = akx[i] + fabs(b[i]);
-        if (den <= 1000.0 * D.N * u * (D.rowsum[i] * xmax + fabs(b[i]))) den = akx[i] + xmax * D.rowsum[i];
-        const double c = den > 0 ? fabs(rr[i]) / den : (rr[i] == 0 ? 0.0 : INFINITY);
-        cm = fmax(cm, c);
-    }
-    red[threadIdx.x] = cm;
+    const double* x = S.x + (int64_t)r * D.N;
+    double mr = 0.0, mx = 0.0, mb = 0.0;
+    for (int part = 0; part < 2; ++part)
+        for (int64_t i = rg[2 * part] + threadIdx.x; i < rg[2 * part + 1]; i += 1024) {
+            mr = fmax(mr, fabs(rr[i]));
+            mx = fmax(mx, fabs(x[i]));
+            mb = fmax(mb, fabs(b[i]));
+        }
+    red[0][threadIdx.x] = mr;
+    red[1][threadIdx.x] = mx;
+    red[2][threadIdx.x] = mb;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        if (threadIdx.x < w)
+            for (int v = 0; v < 3; ++v) red[v][threadIdx.x] = fmax(red[v][threadIdx.x], red[v][threadIdx.x + w]);
         __syncthreads();
     }
-    const double cw = red[0];
-    const double den = D.sc->knorm * xmax + sh_bmax;
-    const double nw = den > 0 ? sh_rmax / den : (sh_rmax == 0 ? 0.0 : INFINITY);
-    double* be = S.berr + 4 * r;
+    const double rmax = red[0][0], xmax = red[1][0], bmax = red[2][0];
+    const double u64 = 1.1102230246251565e-16;
+    double cm = 0.0;
+    for (int part = 0; part < 2; ++part)
+        for (int64_t i = rg[2 * part] + threadIdx.x; i < rg[2 * part + 1]; i += 1024) {
+            double den = akx[i] + fabs(b[i]);
+            if (den <= 1000.0 * D.N * u64 * (D.rowsum[i] * xmax + fabs(b[i]))) den = akx[i] + xmax * D.rowsum[i];
+            const double c = den > 0 ? fabs(rr[i]) / den : (rr[i] == 0 ? 0.0 : INFINITY);
+            cm = fmax(cm, c);
+        }
+    __syncthreads();
+    red[3][threadIdx.x] = cm;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double cw = red[3][0];
+    const double den = D.knorm_sys[q] * xmax + bmax;
+    const double nw = den > 0 ? rmax / den : (rmax == 0 ? 0.0 : INFINITY);
+    double* be = S.berr + 4 * u;
     __shared__ int restore;
     if (threadIdx.x == 0) {
         restore = 0;
@@ -1467,42 +1518,43 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
             be[0] = nw;
             be[1] = cw;
             be[2] = nw;
-            S.steps[r] = 0;
-            S.active[r] = (nw > target && max_steps > 0) ? 1 : 0;
+            S.steps[u] = 0;
+            S.active[u] = (nw > target && max_steps > 0) ? 1 : 0;
         } else {
             const double prev = be[0];
             if (!(nw < prev)) {  // no improvement: keep the previous iterate
                 restore = 1;
-                S.active[r] = 0;
-                S.steps[r] += 1;
+                S.active[u] = 0;
+                S.steps[u] += 1;
             } else {
-                S.steps[r] += 1;
+                S.steps[u] += 1;
                 const bool stagnating = nw > 0.5 * prev;
                 be[0] = nw;
                 be[1] = cw;
-                S.active[r] = (!stagnating && nw > target && S.steps[r] < max_steps) ? 1 : 0;
+                S.active[u] = (!stagnating && nw > target && S.steps[u] < max_steps) ? 1 : 0;
             }
         }
     }
     __syncthreads();
     if (restore) {
-        double* x = S.x + (int64_t)r * D.N;
+        double* xw = S.x + (int64_t)r * D.N;
         const double* xb = S.xbak + (int64_t)r * D.N;
-        for (int i = threadIdx.x; i < D.N; i += 1024) x[i] = xb[i];
+        for (int part = 0; part < 2; ++part)
+            for (int64_t i = rg[2 * part] + threadIdx.x; i < rg[2 * part + 1]; i += 1024) xw[i] = xb[i];
     }
 }
 
 __global__ void k_refine_begin(DevPlan D, DevSolve S) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= D.N || !S.active[r]) return;
+    if (i >= D.N || !S.active[r * D.nsys + D.sys_old[i]]) return;
     S.xbak[i + (int64_t)r * D.N] = S.x[i + (int64_t)r * D.N];
 }
 
 __global__ void k_refine_update(DevPlan D, DevSolve S) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= D.N || !S.active[r]) return;
+    if (i >= D.N || !S.active[r * D.nsys + D.sys_old[i]]) return;
     S.x[i + (int64_t)r * D.N] += S.d[i + (int64_t)r * D.N];
 }
 
@@ -1530,8 +1582,10 @@ inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); 
 
 // ---------------------------------------------------------------- host wrappers
 
-void launch_theta(const DevPlan& D, const double* theta, double rho, double delta, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, D, rho, delta);
+void launch_theta(const DevPlan& D, const double* theta, double rho, double delta, const double* rho_sys,
+                  const double* delta_sys, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_scalars, dim3(nblocks(D.nsys, 256)), dim3(256), 0, s, D, rho, delta, rho_sys,
+                       delta_sys);
     if (D.n > 0) hipLaunchKernelGGL(k_theta, dim3(nblocks(D.n, 256)), dim3(256), 0, s, D, theta);
 }
 
@@ -1541,7 +1595,7 @@ void launch_values_n(const DevPlan& D, int64_t knnz, hipStream_t s) {
 
 void launch_knorm(const DevPlan& D, hipStream_t s) {
     if (D.N > 0) hipLaunchKernelGGL(k_rowsum, dim3(nblocks(D.N, 256)), dim3(256), 0, s, D);
-    hipLaunchKernelGGL(k_knorm, dim3(1), dim3(1024), 0, s, D);
+    hipLaunchKernelGGL(k_knorm, dim3(D.nsys), dim3(1024), 0, s, D);
 }
 
 void launch_matrix_norms(const DevPlan& D, hipStream_t s) {
@@ -1573,6 +1627,7 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
 
 void launch_factor_stats(const DevPlan& D, const PivotParams& pp, hipStream_t s) {
     hipLaunchKernelGGL(k_factor_stats, dim3(1), dim3(1024), 0, s, D, pp);
+    hipLaunchKernelGGL(k_sys_inertia, dim3(D.nsys), dim3(256), 0, s, D);
 }
 
 void launch_zero(double* p, int64_t n, hipStream_t s) {
@@ -1619,7 +1674,7 @@ void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipSt
 
 void launch_berr_steps(const DevPlan& D, const DevSolve& S, int32_t phase, double target, int max_steps,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_berr, dim3(S.nrhs), dim3(1024), 0, s, D, S, phase, target, max_steps);
+    hipLaunchKernelGGL(k_berr, dim3(D.nsys, S.nrhs), dim3(1024), 0, s, D, S, phase, target, max_steps);
 }
 
 void launch_refine_begin(const DevPlan& D, const DevSolve& S, hipStream_t s) {

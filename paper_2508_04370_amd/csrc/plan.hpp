@@ -83,6 +83,16 @@ struct Plan {
 
     std::vector<int8_t> primal_new;     // per new index: 1 if a primal (x) variable
 
+    // independent systems analysed together as one block-diagonal pattern (a batch); one
+    // system otherwise.  K's original numbering: AS columns then rows, NE rows.
+    int32_t nsys = 1;
+    std::vector<int32_t> sys_col;       // per column of A
+    std::vector<int32_t> sys_old;       // per K index, original numbering
+    std::vector<int32_t> sys_new;       // per K index, elimination order
+    std::vector<int64_t> sys_rng;       // per system: index ranges [a0, a1) and [b0, b1)
+    std::vector<int64_t> sys_piv_ptr;   // per system: its pivot positions, ascending
+    std::vector<int32_t> sys_piv;
+
     // launch plan
     std::vector<Task> tasks;
     std::vector<Launch> launches;       // factorisation, in order
@@ -101,6 +111,11 @@ struct AnalyseOptions {
     int amalgamate = 1;
     int small_front = 64;
     const int32_t* user_perm = nullptr;
+    // batch: nsys systems, system s owns columns [col_off[s], col_off[s+1]) and rows
+    // [row_off[s], row_off[s+1]) of the block-diagonal A (nullptr: one system)
+    int32_t nsys = 1;
+    const int64_t* col_off = nullptr;
+    const int64_t* row_off = nullptr;
 };
 
 // Approximate minimum degree ordering of a symmetric pattern given as full adjacency

@@ -34,7 +34,8 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_symbolic", "qdmf_set_matrix", "qdmf_factorise", "qdmf_solve",
             "qdmf_factor_stats", "qdmf_solve_stats", "qdmf_export_d", "qdmf_export_front",
             "qdmf_graph_capture", "qdmf_graph_launch", "qdmf_destroy", "qdmf_status_string",
-            "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read"]
+            "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read", "qdmf_batch_analyse",
+            "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats"]
 QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD = range(7)
 KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
                      6: "k_bwd"}
@@ -109,6 +110,10 @@ def lib():
         L.qdmf_last_message.restype = C.c_char_p
         L.qdmf_profile_kind.argtypes = [P, I32]
         L.qdmf_profile_read.argtypes = [P, P, P, P, P]
+        L.qdmf_batch_analyse.argtypes = [P, I32, P, P, P, P, I32]
+        L.qdmf_batch_offsets.argtypes = [P, P, P]
+        L.qdmf_batch_factorise.argtypes = [P, P, P, P, I32]
+        L.qdmf_batch_stats.argtypes = [P, P, P, P]
         for name in EXPORTED:
             getattr(L, name)
         _lib = L
@@ -262,6 +267,45 @@ def qdmf_profile_read(h):
     return dict(launches=n.value, total_ms=ms.value, flops=fl.value, bytes=by.value)
 
 
+def qdmf_batch_analyse(h, lps, mode):
+    """lps: list of dicts with m, n, colptr, rowidx (one per system)."""
+    cnt = len(lps)
+    m = np.array([lp["m"] for lp in lps], np.int32)
+    n = np.array([lp["n"] for lp in lps], np.int32)
+    cps = [np.ascontiguousarray(lp["colptr"], np.int64) for lp in lps]
+    ris = [np.ascontiguousarray(lp["rowidx"], np.int32) for lp in lps]
+    cpp = (C.c_void_p * cnt)(*[a.ctypes.data for a in cps])
+    rip = (C.c_void_p * cnt)(*[a.ctypes.data if a.size else None for a in ris])
+    return _check(lib().qdmf_batch_analyse(h, cnt, _np(m), _np(n), cpp, rip, int(mode)), "qdmf_batch_analyse", h)
+
+
+def qdmf_batch_offsets(h, count):
+    ro = np.zeros(count + 1, np.int64)
+    co = np.zeros(count + 1, np.int64)
+    _check(lib().qdmf_batch_offsets(h, _np(ro), _np(co)), "qdmf_batch_offsets", h)
+    return ro, co
+
+
+def qdmf_batch_factorise(h, theta_dev, rho, delta, prec=QDMF_FP64):
+    r = np.ascontiguousarray(rho, np.float64)
+    d = np.ascontiguousarray(delta, np.float64)
+    return _check(lib().qdmf_batch_factorise(h, _dev(theta_dev), _np(r), _np(d), int(prec)),
+                  "qdmf_batch_factorise", h)
+
+
+def qdmf_batch_stats(h, count, nrhs=0):
+    inertia = np.zeros(3 * count, np.int64)
+    be = np.zeros(max(1, count * nrhs))
+    st = np.zeros(max(1, count * nrhs), np.int32)
+    _check(lib().qdmf_batch_stats(h, _np(inertia), _np(be) if nrhs else None, _np(st) if nrhs else None),
+           "qdmf_batch_stats", h)
+    out = dict(inertia=inertia.reshape(count, 3))
+    if nrhs:
+        out["berr_nw"] = be.reshape(nrhs, count)
+        out["steps"] = st.reshape(nrhs, count)
+    return out
+
+
 def qdmf_status_string(code):
     return lib().qdmf_status_string(int(code)).decode()
 
@@ -276,9 +320,12 @@ class Solver:
     (analyse and symbolic information only).
     """
 
-    def __init__(self, lp, device=0, stream=None, perm=None, **opts):
+    def __init__(self, lp, device=0, stream=None, perm=None, systems=None, **opts):
+        """systems: the list of independent systems whose block-diagonal concatenation is lp
+        (workloads.concat_systems); they are analysed as a batch."""
         self.lp = lp
         self.device = device
+        self.systems = systems
         self.opt = qdmf_default_options(**opts)
         if perm is not None:
             self.opt.ordering = QDMF_ORDER_USER
@@ -286,7 +333,10 @@ class Solver:
             import torch
             stream = torch.cuda.current_stream(device).cuda_stream
         self.h = qdmf_create(device, stream, self.opt)
-        qdmf_analyse(self.h, lp["m"], lp["n"], lp["colptr"], lp["rowidx"], lp["mode"], perm)
+        if systems is not None:
+            qdmf_batch_analyse(self.h, systems, lp["mode"])
+        else:
+            qdmf_analyse(self.h, lp["m"], lp["n"], lp["colptr"], lp["rowidx"], lp["mode"], perm)
         self.sym = qdmf_symbolic(self.h)
         self.N = self.sym["N"]
         if device >= 0:
@@ -316,6 +366,9 @@ class Solver:
 
     def factor_stats(self):
         return qdmf_factor_stats(self.h)
+
+    def batch_stats(self, nrhs=0):
+        return qdmf_batch_stats(self.h, len(self.systems) if self.systems else 1, nrhs)
 
     def solve_stats(self, nrhs=1):
         return qdmf_solve_stats(self.h, nrhs)

@@ -192,6 +192,30 @@ def as_batch_rhs(lp, s, k, j, seed=4):
     return g.standard_normal(lp["n"]), g.standard_normal(lp["m"])
 
 
+def as_batch(count, seed=4, mrange=(50, 2000), drange=(0.005, 0.02), rho=1e-10, delta=1e-10):
+    """The first count systems of the batched workload (system s from seed [seed, s])."""
+    return [as_batch_system(s, seed, mrange, drange, rho, delta) for s in range(count)]
+
+
+def concat_systems(lps):
+    """Block-diagonal concatenation of several systems (data layout only): system q's column
+    j becomes column col_off[q] + j and its row i row row_off[q] + i; values and per-system
+    vectors are concatenated in system order."""
+    col_off = np.concatenate([[0], np.cumsum([lp["n"] for lp in lps])]).astype(np.int64)
+    row_off = np.concatenate([[0], np.cumsum([lp["m"] for lp in lps])]).astype(np.int64)
+    cps, ris = [np.zeros(1, np.int64)], []
+    base = 0
+    for q, lp in enumerate(lps):
+        cps.append(np.asarray(lp["colptr"][1:], np.int64) - lp["colptr"][0] + base)
+        ris.append(np.asarray(lp["rowidx"], np.int64) + row_off[q])
+        base += int(lp["colptr"][-1] - lp["colptr"][0])
+    val = np.concatenate([np.asarray(lp["val"], np.float64) for lp in lps])
+    return LP(m=int(row_off[-1]), n=int(col_off[-1]), colptr=np.concatenate(cps),
+              rowidx=np.concatenate(ris).astype(np.int32), val=val, mode=lps[0]["mode"],
+              rho=lps[0]["rho"], delta=lps[0]["delta"], col_off=col_off, row_off=row_off,
+              name=f"batch_{len(lps)}")
+
+
 def as_dense_cols(nx=80, ny=50, nz=50, ndense=20, dense_p=0.5, seed=5,
                   theta_range=(1e-10, 1e10), rho=1e-9, delta=1e-9, nrhs=1):
     """Grid-coupled sparse columns (anchor + 3 grid neighbours) plus a few dense columns."""
