@@ -721,6 +721,25 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     }
     P.ub_off[ns] = uo;
     P.ub_total = uo;
+    // forward-solve gather lists: for every front row (indexed like rows[]), the children's
+    // contribution-vector entries that land on it, children ascending
+    P.fg_ptr.assign(P.sn_rowptr[ns] + 1, 0);
+    for (int32_t t = 0; t < ns; ++t)
+        for (int32_t q = P.ch_ptr[t]; q < P.ch_ptr[t + 1]; ++q) {
+            const int32_t c = P.ch[q];
+            for (int64_t a = P.rel_ptr[c]; a < P.rel_ptr[c + 1]; ++a) P.fg_ptr[P.sn_rowptr[t] + P.rel[a] + 1]++;
+        }
+    for (int64_t i = 0; i < P.sn_rowptr[ns]; ++i) P.fg_ptr[i + 1] += P.fg_ptr[i];
+    P.fg_src.resize(P.fg_ptr.back());
+    {
+        std::vector<int64_t> fl(P.fg_ptr.begin(), P.fg_ptr.end() - 1);
+        for (int32_t t = 0; t < ns; ++t)
+            for (int32_t q = P.ch_ptr[t]; q < P.ch_ptr[t + 1]; ++q) {
+                const int32_t c = P.ch[q];
+                for (int64_t a = P.rel_ptr[c]; a < P.rel_ptr[c + 1]; ++a)
+                    P.fg_src[fl[P.sn_rowptr[t] + P.rel[a]]++] = P.ub_off[c] + (a - P.rel_ptr[c]);
+            }
+    }
 
     // ----- solve level lists
     P.lvl_ptr.assign(P.nlevels + 1, 0);

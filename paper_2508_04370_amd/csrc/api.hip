@@ -177,6 +177,8 @@ int upload_plan(qdmf_ctx* h) {
     UP(rel_ptr, rel_ptr)
     UP(rel, rel)
     UP(ub_off, ub_off)
+    UP(fg_ptr, fg_ptr)
+    UP(fg_src, fg_src)
     UP(kcol_ptr, kcol_ptr)
     UP(kloc, kloc)
     UP(kcl, kcl)
@@ -268,6 +270,7 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     if ((rc = dalloc(h, h->solve_allocs, &S.berr, 4 * units))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.active, units))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.steps, units))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.ract, nrhs))) return rc;
     if (h->act_host) (void)hipHostFree(h->act_host);
     h->act_host = nullptr;
     if (hipHostMalloc((void**)&h->act_host, sizeof(int32_t) * units, hipHostMallocDefault) != hipSuccess) {
@@ -309,7 +312,7 @@ void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32
     const Plan& P = h->P;
     const DevSolve& S = h->S;
     hipStream_t st = h->stream;
-    if (P.nsys > 1) active = nullptr;  // flags are per system: solve every system
+    if (P.nsys > 1 && active) active = S.ract;  // flags are per system: any system of the rhs
     launch_permute(h->D, S, src, active, st);
     for (int32_t l = 0; l < P.nlevels; ++l) {
         ProfScope ps(h, QDMF_K_FWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);

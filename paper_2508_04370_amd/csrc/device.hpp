@@ -50,6 +50,8 @@ struct DevPlan {
     const int64_t* rel_ptr;
     const int32_t* rel;
     const int64_t* ub_off;
+    const int64_t* fg_ptr;    // forward-solve gather list per front row
+    const int64_t* fg_src;
     // K entries
     const int64_t* kcol_ptr;
     const int32_t* kloc;      // row position of each entry in its front
@@ -130,6 +132,7 @@ struct DevSolve {
     double* berr;     // per unit: [nw, cw, nw_initial, unused]
     int32_t* active;  // per unit: refinement continues
     int32_t* steps;   // per unit
+    int32_t* ract;    // per rhs: some system of it still refines (gates the solve kernels)
 };
 
 void launch_rhs(const DevPlan& D, const DevSolve& S, const double* r7, const double* r1, hipStream_t s);

@@ -1261,20 +1261,17 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
     for (int r = 0; r < S.nrhs; ++r) {
         if (active && !active[r]) continue;
         double* xw = S.xw + (int64_t)r * D.N;
-        for (int i = tid; i < f; i += 256) y[i] = i < p ? xw[c0 + D.lperm[c0 + i]] : 0.0;
-        __syncthreads();
-        for (int q = D.ch_ptr[s]; q < D.ch_ptr[s + 1]; ++q) {
-            const int ch = D.ch[q];
-            const int cb = D.sn_f[ch] - D.sn_p[ch];
-            const int32_t* rel = D.rel + D.rel_ptr[ch];
-            const double* u = S.ub + D.ub_off[ch] + (int64_t)r * D.ub_total;
-            // the child->parent map addresses pre-pivot rows; pivot rows moved in factorisation
-            for (int a = tid; a < cb; a += 256) {
-                const int t = rel[a];
-                y[t < p ? D.lpinv[c0 + t] : t] += u[a];
+        {  // front row t (pre-pivot numbering): own entry plus the children's contributions
+           // in ascending child order; pivot rows moved in factorisation (lpinv)
+            const int64_t* gp = D.fg_ptr + D.sn_rowptr[s];
+            const double* ub = S.ub + (int64_t)r * D.ub_total;
+            for (int t = tid; t < f; t += 256) {
+                double v = t < p ? xw[c0 + t] : 0.0;
+                for (int64_t q = gp[t]; q < gp[t + 1]; ++q) v += ub[D.fg_src[q]];
+                y[t < p ? D.lpinv[c0 + t] : t] = v;
             }
-            __syncthreads();
         }
+        __syncthreads();
         for (int k0 = 0; k0 < p; k0 += 64) {
             const int k1 = min(k0 + 64, p), nb = k1 - k0;
             stage_block<NBM>(Lb, F, ld, k0, nb, tid);
@@ -1544,6 +1541,15 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
     }
 }
 
+// Per rhs: whether any system still refines (the solve kernels' gate in a batch).
+__global__ void k_any_active(DevPlan D, DevSolve S) {
+    const int r = blockIdx.x;
+    int any = 0;
+    for (int q = threadIdx.x; q < D.nsys; q += blockDim.x) any |= S.active[r * D.nsys + q];
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) S.ract[r] = any;
+}
+
 __global__ void k_refine_begin(DevPlan D, DevSolve S) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
@@ -1675,6 +1681,7 @@ void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipSt
 void launch_berr_steps(const DevPlan& D, const DevSolve& S, int32_t phase, double target, int max_steps,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_berr, dim3(D.nsys, S.nrhs), dim3(1024), 0, s, D, S, phase, target, max_steps);
+    if (D.nsys > 1) hipLaunchKernelGGL(k_any_active, dim3(S.nrhs), dim3(256), 0, s, D, S);
 }
 
 void launch_refine_begin(const DevPlan& D, const DevSolve& S, hipStream_t s) {

@@ -64,6 +64,8 @@ struct Plan {
     std::vector<int64_t> rel_ptr;       // per supernode: CB rows mapped into parent front
     std::vector<int32_t> rel;
     std::vector<int64_t> ub_off;        // solve contribution buffer offset (per rhs column)
+    std::vector<int64_t> fg_ptr;        // per front row (as rows[]): its forward-solve gather list
+    std::vector<int64_t> fg_src;        // entries of the children's contribution buffers
     int64_t ub_total = 0;
     int64_t front_total = 0;            // doubles in the front arena
     int32_t max_front = 0, nlevels = 0;
