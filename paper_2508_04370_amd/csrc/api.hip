@@ -39,6 +39,12 @@ struct qdmf_ctx {
     std::vector<void*> solve_allocs;
     DevSolve S{};
     int32_t solve_cap = 0;
+    // Krylov refinement work space (mixed precision, eager solves), allocated on first use
+    double* gm_V = nullptr;    // (GM_M + 1) blocks of N x nrhs
+    double* gm_T = nullptr;    // N x nrhs
+    double* gm_W = nullptr;    // N x nrhs
+    double* gm_dev = nullptr;  // device scalars: 2 (GM_M + 1) + 1 + GM_M per rhs
+    int32_t gm_cap = 0;
     int32_t* act_host = nullptr;  // pinned copy of the refinement flags (eager solves)
     double* shift_host = nullptr;  // pinned staging of per-system rho, delta (batch factorise)
     int32_t shift_cap = 0;
@@ -254,6 +260,8 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     }
     free_list(h->solve_allocs);
     destroy_graph(h);
+    h->gm_V = h->gm_T = h->gm_W = h->gm_dev = nullptr;
+    h->gm_cap = 0;
     DevSolve& S = h->S;
     const int64_t N = h->P.N;
     S.nblk = (int32_t)((N + 255) / 256);
@@ -327,6 +335,112 @@ void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32
     launch_unpermute(h->D, S, dst, active, st);
 }
 
+// ---- FP64 refinement with a Krylov correction (mixed precision)
+// Each correction d of K_static d = r is computed by GMRES on K_static M, right-preconditioned
+// by the mixed-precision factor M = (L D L^T)^{-1}, so that the FP64 residual ||r - K d||_2
+// itself is minimised (classical Gram-Schmidt applied twice, Givens rotations on the host),
+// instead of d = M r: the correction stays accurate when the FP32 Schur updates leave
+// ||I - K M|| above one, which plain refinement needs below one.
+constexpr int GM_M = 30;         // Krylov dimension of one correction
+constexpr double GM_TOL = 1e-10;  // reduction of the preconditioned residual norm
+
+int ensure_gmres(qdmf_ctx* h) {
+    const int32_t nr = h->S.nrhs;
+    if (h->gm_V && h->gm_cap >= nr) return 0;
+    const int64_t N = h->P.N;
+    const int32_t cap = std::max(nr, h->solve_cap);
+    int rc = 0;
+    if ((rc = dalloc(h, h->solve_allocs, &h->gm_V, (int64_t)(GM_M + 1) * N * cap))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &h->gm_T, N * cap))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &h->gm_W, N * cap))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &h->gm_dev, (int64_t)(3 * GM_M + 4) * cap))) return rc;
+    h->gm_cap = cap;
+    return 0;
+}
+
+// S.d = approximate solution of K_static d = S.r (all right-hand sides).
+int gmres_correction(qdmf_ctx* h) {
+    DevSolve& S = h->S;
+    const int32_t nr = S.nrhs;
+    const int64_t N = h->P.N;
+    hipStream_t st = h->stream;
+    int rc = ensure_gmres(h);
+    if (rc) return rc;
+    auto Vb = [&](int j) { return h->gm_V + (int64_t)j * N * nr; };
+    double* hd1 = h->gm_dev;                       // (GM_M + 1) x nr
+    double* hd2 = hd1 + (int64_t)(GM_M + 1) * nr;  // (GM_M + 1) x nr
+    double* nrm = hd2 + (int64_t)(GM_M + 1) * nr;  // nr
+    double* yd = nrm + nr;                         // GM_M x nr
+    launch_dots(S.r, 1, S.r, nrm, N, nr, st);
+    std::vector<double> beta(nr), g((size_t)(GM_M + 1) * nr, 0.0), cs((size_t)GM_M * nr), sn((size_t)GM_M * nr);
+    std::vector<double> R((size_t)GM_M * GM_M * nr, 0.0);  // R[(i * GM_M + j) * nr + r], upper triangular
+    std::vector<double> h1((size_t)(GM_M + 1) * nr), h2((size_t)(GM_M + 1) * nr), nn(nr);
+    if (hipMemcpyAsync(nn.data(), nrm, sizeof(double) * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return QDMF_ERR_HIP;
+    for (int r = 0; r < nr; ++r) {
+        beta[r] = std::sqrt(nn[r]);
+        g[r] = beta[r];
+    }
+    launch_vscale(S.r, nrm, Vb(0), N, nr, st);
+    int k = 0;
+    for (int j = 0; j < GM_M; ++j) {
+        enqueue_ldlt_solve(h, Vb(j), h->gm_T, nullptr);  // K M v_j
+        launch_matvec(h->D, h->gm_T, h->gm_W, nr, st);
+        launch_dots(h->gm_V, j + 1, h->gm_W, hd1, N, nr, st);
+        launch_vcombine(h->gm_V, j + 1, hd1, h->gm_W, N, nr, true, st);
+        launch_dots(h->gm_V, j + 1, h->gm_W, hd2, N, nr, st);
+        launch_vcombine(h->gm_V, j + 1, hd2, h->gm_W, N, nr, true, st);
+        launch_dots(h->gm_W, 1, h->gm_W, nrm, N, nr, st);
+        launch_vscale(h->gm_W, nrm, Vb(j + 1), N, nr, st);
+        if (hipMemcpyAsync(h1.data(), hd1, sizeof(double) * (j + 1) * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(h2.data(), hd2, sizeof(double) * (j + 1) * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(nn.data(), nrm, sizeof(double) * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return QDMF_ERR_HIP;
+        k = j + 1;
+        bool all = true;
+        for (int r = 0; r < nr; ++r) {
+            std::vector<double> col(j + 2);
+            for (int i = 0; i <= j; ++i) col[i] = h1[(size_t)i * nr + r] + h2[(size_t)i * nr + r];
+            col[j + 1] = std::sqrt(nn[r]);
+            for (int i = 0; i < j; ++i) {  // earlier rotations
+                const double c = cs[(size_t)i * nr + r], s_ = sn[(size_t)i * nr + r];
+                const double a = c * col[i] + s_ * col[i + 1];
+                col[i + 1] = -s_ * col[i] + c * col[i + 1];
+                col[i] = a;
+            }
+            const double a = col[j], b = col[j + 1];
+            const double den = std::hypot(a, b);
+            const double c = den > 0 ? a / den : 1.0, s_ = den > 0 ? b / den : 0.0;
+            cs[(size_t)j * nr + r] = c;
+            sn[(size_t)j * nr + r] = s_;
+            col[j] = den;
+            for (int i = 0; i <= j; ++i) R[((size_t)i * GM_M + j) * nr + r] = col[i];
+            const double gj = g[(size_t)j * nr + r];
+            g[(size_t)j * nr + r] = c * gj;
+            g[(size_t)(j + 1) * nr + r] = -s_ * gj;
+            if (!(std::fabs(g[(size_t)(j + 1) * nr + r]) <= GM_TOL * beta[r])) all = false;
+        }
+        if (all) break;
+    }
+    // y = R^{-1} g (back substitution; a zero pivot from a breakdown contributes nothing)
+    std::vector<double> y((size_t)GM_M * nr, 0.0);
+    for (int r = 0; r < nr; ++r)
+        for (int i = k - 1; i >= 0; --i) {
+            double v = g[(size_t)i * nr + r];
+            for (int jj = i + 1; jj < k; ++jj) v -= R[((size_t)i * GM_M + jj) * nr + r] * y[(size_t)jj * nr + r];
+            const double d = R[((size_t)i * GM_M + i) * nr + r];
+            y[(size_t)i * nr + r] = d != 0.0 ? v / d : 0.0;
+        }
+    if (hipMemcpyAsync(yd, y.data(), sizeof(double) * k * nr, hipMemcpyHostToDevice, st) != hipSuccess)
+        return QDMF_ERR_HIP;
+    launch_vcombine(h->gm_V, k, yd, h->gm_T, N, nr, false, st);
+    enqueue_ldlt_solve(h, h->gm_T, S.d, nullptr);  // d = M V y
+    // the host vector y must outlive the copy
+    return hipStreamSynchronize(st) == hipSuccess ? 0 : QDMF_ERR_HIP;
+}
+
 void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, double* dy) {
     const DevPlan& D = h->D;
     const DevSolve& S = h->S;
@@ -353,7 +467,11 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
             if (!any) break;
         }
         launch_refine_begin(D, S, st);
-        enqueue_ldlt_solve(h, S.r, S.d, S.active);
+        if (mixed && !h->capturing) {
+            if (gmres_correction(h)) break;
+        } else {
+            enqueue_ldlt_solve(h, S.r, S.d, S.active);
+        }
         launch_refine_update(D, S, st);
         launch_residual(D, S, S.x, st);
         launch_berr_steps(D, S, 1, target, max_steps, st);

@@ -154,4 +154,11 @@ void launch_recover(const DevPlan& D, const DevSolve& S, const double* r7, doubl
                     hipStream_t s);
 void launch_zero(double* p, int64_t n, hipStream_t s);
 
+// ---- Krylov refinement building blocks (N x nrhs blocks, original numbering)
+void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, hipStream_t s);
+void launch_dots(const double* V, int nv, const double* w, double* out, int64_t N, int nrhs, hipStream_t s);
+void launch_vcombine(const double* V, int nv, const double* h, double* w, int64_t N, int nrhs, bool subtract,
+                     hipStream_t s);
+void launch_vscale(const double* src, const double* nrm2, double* dst, int64_t N, int nrhs, hipStream_t s);
+
 }  // namespace qdmf

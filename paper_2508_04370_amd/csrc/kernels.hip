@@ -1541,6 +1541,81 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
     }
 }
 
+// ---------------------------------------------------------------- Krylov refinement
+// Vectors are N x nrhs blocks in original numbering; a basis V holds blocks j = 0, 1, ...
+// at V + j * N * nrhs.  Reductions run in a fixed order (one workgroup per output).
+
+// out = K_static v, from A, Theta, rho, delta (AS) or from the K values (NE).
+__global__ __launch_bounds__(256) void k_matvec(DevPlan D, const double* vin, double* out, int nrhs) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= D.N || r >= nrhs) return;
+    const double* v = vin + (int64_t)r * D.N;
+    const int sys = D.sys_old[i];
+    const double rho = D.rho_sys[sys], delta = D.delta_sys[sys];
+    double kx = 0.0;
+    if (D.mode == 1) {
+        if (i < D.n) {
+            kx = -(D.dinv[i] + rho) * v[i];
+            for (int64_t e = D.acp[i]; e < D.acp[i + 1]; ++e) kx += D.aval[e] * v[D.n + D.ari[e]];
+        } else {
+            const int row = i - D.n;
+            for (int64_t q = D.arp[row]; q < D.arp[row + 1]; ++q) {
+                const int32_t e = D.are[q];
+                kx += D.aval[e] * v[D.acol[e]];
+            }
+            kx += delta * v[i];
+        }
+    } else {
+        for (int64_t q = D.krs_ptr[i]; q < D.krs_ptr[i + 1]; ++q) {
+            const int o = D.krs_other[q];
+            double kv = D.kval[D.krs_ent[q]];
+            if (o == i) kv += delta;
+            kx += kv * v[o];
+        }
+    }
+    out[i + (int64_t)r * D.N] = kx;
+}
+
+// out[j * nrhs + r] = <V_j(:, r), w(:, r)> for j < nv.
+__global__ __launch_bounds__(256) void k_dots(const double* V, int nv, const double* w, double* out, int64_t N,
+                                              int nrhs) {
+    __shared__ double red[256];
+    const int j = blockIdx.x, r = blockIdx.y;
+    const double* a = V + ((int64_t)j * nrhs + r) * N;
+    const double* b = w + (int64_t)r * N;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += 256) acc += a[i] * b[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j * nrhs + r] = red[0];
+}
+
+// w(:, r) -= sum_{j < nv} h[j * nrhs + r] V_j(:, r)   (sign = -1), or
+// w(:, r)  = sum_{j < nv} h[j * nrhs + r] V_j(:, r)   (sign = 0).
+__global__ void k_vcombine(const double* V, int nv, const double* h, double* w, int64_t N, int nrhs, int sign) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= N) return;
+    double acc = 0.0;
+    for (int j = 0; j < nv; ++j) acc += h[j * nrhs + r] * V[((int64_t)j * nrhs + r) * N + i];
+    double* wi = w + (int64_t)r * N + i;
+    *wi = sign ? *wi - acc : acc;
+}
+
+// dst(:, r) = src(:, r) / sqrt(nrm2[r])  (0 where the norm is 0).
+__global__ void k_vscale(const double* src, const double* nrm2, double* dst, int64_t N, int nrhs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= N) return;
+    const double nn = sqrt(nrm2[r]);
+    dst[(int64_t)r * N + i] = nn > 0.0 ? src[(int64_t)r * N + i] / nn : 0.0;
+}
+
 // Per rhs: whether any system still refines (the solve kernels' gate in a batch).
 __global__ void k_any_active(DevPlan D, DevSolve S) {
     const int r = blockIdx.x;
@@ -1634,6 +1709,24 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
 void launch_factor_stats(const DevPlan& D, const PivotParams& pp, hipStream_t s) {
     hipLaunchKernelGGL(k_factor_stats, dim3(1), dim3(1024), 0, s, D, pp);
     hipLaunchKernelGGL(k_sys_inertia, dim3(D.nsys), dim3(256), 0, s, D);
+}
+
+void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_matvec, dim3(nblocks(D.N, 256), nrhs), dim3(256), 0, s, D, v, out, nrhs);
+}
+
+void launch_dots(const double* V, int nv, const double* w, double* out, int64_t N, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_dots, dim3(nv, nrhs), dim3(256), 0, s, V, nv, w, out, N, nrhs);
+}
+
+void launch_vcombine(const double* V, int nv, const double* h, double* w, int64_t N, int nrhs, bool subtract,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_vcombine, dim3(nblocks(N, 256), nrhs), dim3(256), 0, s, V, nv, h, w, N, nrhs,
+                       subtract ? 1 : 0);
+}
+
+void launch_vscale(const double* src, const double* nrm2, double* dst, int64_t N, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_vscale, dim3(nblocks(N, 256), nrhs), dim3(256), 0, s, src, nrm2, dst, N, nrhs);
 }
 
 void launch_zero(double* p, int64_t n, hipStream_t s) {
