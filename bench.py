@@ -32,6 +32,42 @@ PEAK_HBM = 8.0e12     # HBM3E (bytes/s)
 KIND_BOUND = {0: "alu", 1: "hbm", 2: "alu", 3: "mfma", 4: "hbm", 5: "hbm", 6: "hbm"}
 
 
+def kernel_source_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2508_04370_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of kernel on workload from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading on a plain copy of
+    known size), or None when there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic: "):
+            rec = json.loads(line[len("traffic: "):])
+    if not rec or rec.get("kernels_sha") != kernel_source_sha():
+        return None
+    return rec["fetch_kib_per_dispatch"] * 1024.0 / rec["copy_fetch_factor"] + \
+        rec["write_kib_per_dispatch"] * 1024.0 / rec["copy_write_factor"]
+
+
+def copy_calibration(nbytes):
+    """One plain device copy of nbytes (reads nbytes, writes nbytes): the reference dispatch
+    for the HBM counters."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "kernels_sha": kernel_source_sha()}))
+
+
 def make_workload(name):
     if name == "as_staircase":
         return W.as_staircase(), dict()
@@ -184,7 +220,12 @@ def main():
     ap.add_argument("--nsolves", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: multi-GPU execution is not part of this build "
               "(DESIGN.md describes how the factorisation would shard)", file=sys.stderr)
@@ -236,7 +277,9 @@ def main():
                    "max_front": sym["max_front"], "flops_fact": sym["flops_fact"],
                    "nnz_l": sym["nnz_l"]},
         "roofline": {"bound": bound, "kernel": Q.KERNEL_KIND_NAMES[dom], "achieved": round(achieved, 6),
-                     "peak": peak, "unit": unit, "frac": round(achieved / peak, 6), "traffic": None,
+                     "peak": peak, "unit": unit, "frac": round(achieved / peak, 6),
+                     "traffic": measured_traffic(Q.KERNEL_KIND_NAMES[dom], args.workload),
+                     "algorithmic_bytes_per_launch": round(pr["bytes"] / max(1, pr["launches"]), 1),
                      "launches": pr["launches"], "avg_launch_us": round(avg_ms * 1e3, 3),
                      "work_per_launch": round(per_launch, 1),
                      "ms_per_step_with_brackets": round(float(np.median(r["ms_profiled"])), 4)},
