@@ -49,6 +49,7 @@ struct qdmf_ctx {
     double* shift_host = nullptr;  // pinned staging of per-system rho, delta (batch factorise)
     int32_t shift_cap = 0;
     double* shift_dev = nullptr;
+    double* stats_part = nullptr;  // per-block partials of the factorisation statistics
     bool batch_shifts = false;     // the last factorisation used per-system shifts
     std::vector<int64_t> batch_col_off, batch_row_off;  // system offsets of a batch
     int32_t last_nrhs = 0;
@@ -241,6 +242,7 @@ int upload_plan(qdmf_ctx* h) {
     if ((rc = dalloc(h, h->plan_allocs, &D.delta_sys, P.nsys))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.inertia_sys, (int64_t)3 * P.nsys))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &h->shift_dev, (int64_t)2 * P.nsys))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &h->stats_part, (int64_t)10 * factor_stats_blocks(P.N)))) return rc;
     // largest front (dynamic LDS of the solve kernels) and pivot count (kernel variant) per level
     h->maxf_lvl.assign(P.nlevels, 1);
     h->maxp_lvl.assign(P.nlevels, 1);
@@ -312,7 +314,7 @@ void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delt
         ProfScope ps(h, L.kind, L.flops, L.bytes);
         launch_factor_step(h->D, L, h->tasks_dev, pp, h->stream);
     }
-    launch_factor_stats(h->D, pp, h->stream);
+    launch_factor_stats(h->D, pp, h->stats_part, h->stream);
 }
 
 // (L D L^T)^{-1} src -> dst, level by level (forward leaves first, backward roots first).

@@ -112,7 +112,9 @@ void launch_values_n(const DevPlan& D, int64_t knnz, hipStream_t s);
 void launch_knorm(const DevPlan& D, hipStream_t s);
 void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks_dev,
                         const PivotParams& pp, hipStream_t s);
-void launch_factor_stats(const DevPlan& D, const PivotParams& pp, hipStream_t s);
+// part: factor_stats_blocks(N) x 10 doubles of device scratch
+int factor_stats_blocks(int64_t N);
+void launch_factor_stats(const DevPlan& D, const PivotParams& pp, double* part, hipStream_t s);
 void launch_matrix_norms(const DevPlan& D, hipStream_t s);
 
 // ---- solve

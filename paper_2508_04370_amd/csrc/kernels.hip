@@ -10,6 +10,7 @@
 // after the decision, Proposition 3 and the sign rule (Section 4.6), 1x1 or 2x2 pivots.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -78,10 +79,9 @@ __device__ inline void wave_argmax(double v, int /*lane*/, double& bv, int& bi) 
     bi = __ffsll((long long)m) - 1;
 }
 
-// LDS state of the one-wave pivot kernel.  T is a tile of 64 columns: rows [0, 64) hold a
-// full symmetric block (the window's diagonal block B_D, or a whole small front), rows
-// [64, 128) optional panel rows below the window (part of B_P).  T[i][j] at j*LDW + i.
-constexpr int LDW = 129;
+// LDS state of the one-wave pivot kernel of small fronts: T holds the whole symmetric front
+// (f <= 64), T[i][j] at j*LDW + i.
+constexpr int LDW = 65;
 
 struct PivShared {
     double T[64 * LDW];
@@ -93,9 +93,7 @@ struct PivShared {
     int pt[64], fl[64], zs[64];
 };
 
-// Symmetric interchange of positions a and b: rows/columns of the symmetric block, and the
-// columns of the panel rows.
-template <bool PANEL>
+// Symmetric interchange of positions a and b: rows and columns of the symmetric block.
 __device__ void sym_swap(PivShared& S, int nsym, int a, int b, int lane) {
     if (a == b) return;
     if (lane < nsym) {  // rows a and b of the symmetric block (lane = column)
@@ -109,11 +107,6 @@ __device__ void sym_swap(PivShared& S, int nsym, int a, int b, int lane) {
         S.T[a * LDW + lane] = S.T[b * LDW + lane];
         S.T[b * LDW + lane] = t;
     }
-    if (PANEL) {
-        double t = S.T[a * LDW + 64 + lane];
-        S.T[a * LDW + 64 + lane] = S.T[b * LDW + 64 + lane];
-        S.T[b * LDW + 64 + lane] = t;
-    }
     if (lane == 0) {
         int ts = S.sg[a]; S.sg[a] = S.sg[b]; S.sg[b] = ts;
         double tz = S.sh[a]; S.sh[a] = S.sh[b]; S.sh[b] = tz;
@@ -124,31 +117,27 @@ __device__ void sym_swap(PivShared& S, int nsym, int a, int b, int lane) {
 
 // T[row][j] -= m * S.w0[j] for j in [j0, ncols): 8 columns per trip so the LDS loads of a
 // trip are independent of its stores and can be issued together.
-template <bool PANEL>
-__device__ inline void rank1_rows(PivShared& S, int j0, int ncols, double m0, double m1, int lane) {
+__device__ inline void rank1_rows(PivShared& S, int j0, int ncols, double m0, int lane) {
     for (int jb = j0 & ~7; jb < ncols; jb += 8) {
-        double t0[8], t1[8], w[8];
+        double t0[8], w[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int j = jb + q;
             const bool on = j >= j0 && j < ncols;
             w[q] = on ? S.w0[j] : 0.0;
             t0[q] = S.T[j * LDW + lane];
-            if (PANEL) t1[q] = S.T[j * LDW + 64 + lane];
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             S.T[(jb + q) * LDW + lane] = t0[q] - m0 * w[q];
-            if (PANEL) S.T[(jb + q) * LDW + 64 + lane] = t1[q] - m1 * w[q];
         }
     }
 }
 
 // Partial LDL^T over the window [0, nbw) of the nsym x nsym symmetric block in S.T, with
-// the updates applied to the columns [0, ncols) of the symmetric rows (nsym = ncols) and,
-// if PANEL, of the panel rows.  Pivot tests read only the window (Section 4.5).  One
-// wavefront (blockDim.x == 64); every decision is wave-uniform.
-template <bool PANEL>
+// the updates applied to the columns [0, ncols) of the symmetric rows (nsym = ncols).  Pivot
+// tests read only the window (Section 4.5).  One wavefront (blockDim.x == 64); every
+// decision is wave-uniform.
 __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, const PivotParams& pp,
                               int lane) {
     const int ncols = nsym;
@@ -162,7 +151,7 @@ __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, con
             int q;
             wave_argmax(v, lane, bv, q);
             if (q < k || q >= nbw) q = k;  // no candidate (NaN input): no swap
-            sym_swap<PANEL>(S, nsym, k, q, lane);
+            sym_swap(S, nsym, k, q, lane);
         }
         double gp;
         int r;
@@ -188,10 +177,10 @@ __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, con
             if (akk * gr >= alpha * gp * gp) {
                 // 1x1 at k
             } else if (fabs(S.T[r * LDW + r]) >= alpha * gr) {
-                sym_swap<PANEL>(S, nsym, k, r, lane);
+                sym_swap(S, nsym, k, r, lane);
                 fkk_before = S.T[k * LDW + k];
             } else {
-                sym_swap<PANEL>(S, nsym, k + 1, r, lane);
+                sym_swap(S, nsym, k + 1, r, lane);
                 two = 1;
             }
         }
@@ -211,29 +200,17 @@ __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, con
                 const double u1 = act ? S.T[(k + 1) * LDW + lane] : 0.0;
                 const double l0 = act ? (u0 * c - u1 * b) / det : 0.0;
                 const double l1 = act ? (u1 * a - u0 * b) / det : 0.0;
-                double p0 = 0.0, p1 = 0.0, q0 = 0.0, q1 = 0.0;
-                if (PANEL) {
-                    p0 = S.T[k * LDW + 64 + lane];
-                    p1 = S.T[(k + 1) * LDW + 64 + lane];
-                    q0 = (p0 * c - p1 * b) / det;
-                    q1 = (p1 * a - p0 * b) / det;
-                }
                 S.w0[lane] = l0;
                 S.w1[lane] = l1;
                 __syncthreads();
                 for (int j = k + 2; j < ncols; ++j) {
                     const double lj0 = S.w0[j], lj1 = S.w1[j];
                     if (act) S.T[j * LDW + lane] -= u0 * lj0 + u1 * lj1;
-                    if (PANEL) S.T[j * LDW + 64 + lane] -= p0 * lj0 + p1 * lj1;
                 }
                 __syncthreads();
                 if (act) {
                     S.T[k * LDW + lane] = l0;
                     S.T[(k + 1) * LDW + lane] = l1;
-                }
-                if (PANEL) {
-                    S.T[k * LDW + 64 + lane] = q0;
-                    S.T[(k + 1) * LDW + 64 + lane] = q1;
                 }
                 if (lane == 0) {
                     S.T[k * LDW + k + 1] = 0.0;
@@ -288,13 +265,11 @@ __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, con
         const double e = dk - (fkk_before + S.sh[k]);
         const bool act = lane > k && lane < nsym;
         const double li = act ? S.T[k * LDW + lane] / dk : 0.0;
-        const double pi = PANEL ? S.T[k * LDW + 64 + lane] / dk : 0.0;
         S.w0[lane] = (lane > k && lane < ncols) ? S.T[k * LDW + lane] : 0.0;  // column k
         __syncthreads();
-        rank1_rows<PANEL>(S, k + 1, ncols, li, pi, lane);
+        rank1_rows(S, k + 1, ncols, li, lane);
         __syncthreads();
         if (act) S.T[k * LDW + lane] = li;
-        if (PANEL) S.T[k * LDW + 64 + lane] = pi;
         if (lane == 0) {
             S.d[k] = dk;
             S.doff[k] = 0.0;
@@ -390,7 +365,7 @@ __global__ __launch_bounds__(64) void k_small(DevPlan D, const Task* tasks, int6
     const int sys = D.sys_new[c0];
     init_signs(S, D, rows, f, sys, lane);
     __syncthreads();
-    factor_window<false>(S, f, p, D.knorm_sys[sys], pp, lane);
+    factor_window(S, f, p, D.knorm_sys[sys], pp, lane);
     for (int j = 0; j < f; ++j)
         if (lane >= j && lane < f) F[lane + (int64_t)j * ld] = S.T[j * LDW + lane];
     store_pivots(S, D, c0, 0, p, lane);
@@ -1019,7 +994,9 @@ __global__ __launch_bounds__(1024) void k_knorm(DevPlan D) {
     const int q = blockIdx.x;
     const int64_t* rg = D.sys_rng + 4 * q;
     double m = 0.0;
+#pragma unroll 8
     for (int64_t i = rg[0] + threadIdx.x; i < rg[1]; i += 1024) m = fmax(m, D.rowsum[i]);
+#pragma unroll 8
     for (int64_t i = rg[2] + threadIdx.x; i < rg[3]; i += 1024) m = fmax(m, D.rowsum[i]);
     red[threadIdx.x] = m;
     __syncthreads();
@@ -1048,26 +1025,31 @@ __global__ void k_matrix_norms(DevPlan D) {
     }
 }
 
-// Inertia and regularisation counts over all pivot positions (fixed-order reduction).
-__global__ __launch_bounds__(1024) void k_factor_stats(DevPlan D, PivotParams pp) {
-    __shared__ int64_t ri[8][1024];
-    __shared__ double rd[1024];
-    int64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double me = 0.0;
-    int big = 0;
-    for (int k = threadIdx.x; k < D.N; k += 1024) {
+// Inertia and regularisation counts over all pivot positions: per-block partials, then a
+// fixed-order sum (k_factor_stats_final).  Partial q of block g: part[g * 10 + q], the eight
+// counts (negative, positive, zero, 2x2, lifts, Proposition 3, sign rule, zero-skips), the
+// largest |E_dyn| and whether some |E_dyn| exceeds tau_big ||K||_1.
+constexpr int FS_PER_BLOCK = 4096;
+
+__global__ __launch_bounds__(256) void k_factor_stats(DevPlan D, PivotParams pp, double* part) {
+    __shared__ double red[10][256];
+    double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double me = 0.0, big = 0.0;
+    const int64_t k0 = (int64_t)blockIdx.x * FS_PER_BLOCK;
+    const int64_t k1 = min((int64_t)D.N, k0 + FS_PER_BLOCK);
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
         const double thr = pp.tau_big * D.knorm_sys[D.sys_new[k]];
         const int ty = D.ptype[k];
         if (ty == 0) {
             const double d = D.dval[k];
-            if (d < 0) c[0]++;
-            else if (d > 0) c[1]++;
-            else c[2]++;
+            if (d < 0) c[0] += 1;
+            else if (d > 0) c[1] += 1;
+            else c[2] += 1;
         } else if (ty == 1) {
-            c[3]++;
+            c[3] += 1;
             const double a = D.dval[k], b = D.doff[k], cc = D.dval[k + 1];
             const double det = a * cc - b * b;
-            if (det < 0) { c[0]++; c[1]++; }
+            if (det < 0) { c[0] += 1; c[1] += 1; }
             else if (a + cc > 0) c[1] += 2;
             else c[0] += 2;
         }
@@ -1078,36 +1060,45 @@ __global__ __launch_bounds__(1024) void k_factor_stats(DevPlan D, PivotParams pp
         c[7] += D.zskip[k];
         const double e = fabs(D.edyn[k]);
         me = fmax(me, e);
-        big |= e > thr;
+        if (e > thr) big = 1.0;
     }
-    for (int q = 0; q < 8; ++q) ri[q][threadIdx.x] = c[q];
-    rd[threadIdx.x] = big ? -fmax(me, 0.0) - 1.0 : me;  // sign carries the flag
+    for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = c[q];
+    red[8][threadIdx.x] = me;
+    red[9][threadIdx.x] = big;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
-            for (int q = 0; q < 8; ++q) ri[q][threadIdx.x] += ri[q][threadIdx.x + w];
-            const double a = rd[threadIdx.x], b = rd[threadIdx.x + w];
-            const bool fa = a < 0, fb = b < 0;
-            const double ma = fa ? -a - 1.0 : a, mb = fb ? -b - 1.0 : b;
-            const double mm = fmax(ma, mb);
-            rd[threadIdx.x] = (fa || fb) ? -mm - 1.0 : mm;
+            for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+            for (int q = 8; q < 10; ++q) red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        DevStats* st = D.st;
-        st->nneg = ri[0][0];
-        st->npos = ri[1][0];
-        st->nzero = ri[2][0];
-        st->n2x2 = ri[3][0];
-        st->nlift = ri[4][0];
-        st->nprop3 = ri[5][0];
-        st->nsign = ri[6][0];
-        st->nzskip = ri[7][0];
-        const double v = rd[0];
-        st->large_reg = v < 0;
-        st->max_edyn = v < 0 ? -v - 1.0 : v;
-        st->bad_theta = D.sc->bad_theta;
+    if (threadIdx.x < 10) part[blockIdx.x * 10 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_factor_stats_final(DevPlan D, const double* part, int nblk) {
+    if (threadIdx.x != 0) return;
+    double t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int g = 0; g < nblk; ++g) {
+        for (int q = 0; q < 8; ++q) t[q] += part[g * 10 + q];
+        for (int q = 8; q < 10; ++q) t[q] = fmax(t[q], part[g * 10 + q]);
+    }
+    DevStats* st = D.st;
+    st->nneg = (int64_t)t[0];
+    st->npos = (int64_t)t[1];
+    st->nzero = (int64_t)t[2];
+    st->n2x2 = (int64_t)t[3];
+    st->nlift = (int64_t)t[4];
+    st->nprop3 = (int64_t)t[5];
+    st->nsign = (int64_t)t[6];
+    st->nzskip = (int64_t)t[7];
+    st->max_edyn = t[8];
+    st->large_reg = t[9] > 0;
+    st->bad_theta = D.sc->bad_theta;
+    if (D.nsys == 1) {  // a single system: its inertia is the total
+        D.inertia_sys[0] = st->nneg;
+        D.inertia_sys[1] = st->npos;
+        D.inertia_sys[2] = st->nzero;
     }
 }
 
@@ -1473,6 +1464,7 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
     const double* x = S.x + (int64_t)r * D.N;
     double mr = 0.0, mx = 0.0, mb = 0.0;
     for (int part = 0; part < 2; ++part)
+#pragma unroll 8
         for (int64_t i = rg[2 * part] + threadIdx.x; i < rg[2 * part + 1]; i += 1024) {
             mr = fmax(mr, fabs(rr[i]));
             mx = fmax(mx, fabs(x[i]));
@@ -1491,6 +1483,7 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
     const double u64 = 1.1102230246251565e-16;
     double cm = 0.0;
     for (int part = 0; part < 2; ++part)
+#pragma unroll 8
         for (int64_t i = rg[2 * part] + threadIdx.x; i < rg[2 * part + 1]; i += 1024) {
             double den = akx[i] + fabs(b[i]);
             if (den <= 1000.0 * D.N * u64 * (D.rowsum[i] * xmax + fabs(b[i]))) den = akx[i] + xmax * D.rowsum[i];
@@ -1706,9 +1699,13 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
     }
 }
 
-void launch_factor_stats(const DevPlan& D, const PivotParams& pp, hipStream_t s) {
-    hipLaunchKernelGGL(k_factor_stats, dim3(1), dim3(1024), 0, s, D, pp);
-    hipLaunchKernelGGL(k_sys_inertia, dim3(D.nsys), dim3(256), 0, s, D);
+int factor_stats_blocks(int64_t N) { return (int)std::max<int64_t>(1, (N + FS_PER_BLOCK - 1) / FS_PER_BLOCK); }
+
+void launch_factor_stats(const DevPlan& D, const PivotParams& pp, double* part, hipStream_t s) {
+    const int g = factor_stats_blocks(D.N);
+    hipLaunchKernelGGL(k_factor_stats, dim3(g), dim3(256), 0, s, D, pp, part);
+    hipLaunchKernelGGL(k_factor_stats_final, dim3(1), dim3(64), 0, s, D, (const double*)part, g);
+    if (D.nsys > 1) hipLaunchKernelGGL(k_sys_inertia, dim3(D.nsys), dim3(256), 0, s, D);
 }
 
 void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, hipStream_t s) {
