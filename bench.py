@@ -79,6 +79,9 @@ def make_workload(name):
     if name == "ne_grid_small":
         lp = W.ne_grid(24, 24, 20, nrhs=8)
         return lp, dict(ordering=2, grid=lp["grid"])
+    if name.startswith("ne_dense_front"):  # ne_dense_front or ne_dense_front_<f>
+        f = int(name.split("_")[-1]) if name[-1].isdigit() else 4096
+        return W.ne_dense_front(f), dict(ordering=0)
     if name in ("as_batch", "as_batch_small"):
         lps = W.as_batch(512 if name == "as_batch" else 32)
         cat = W.concat_systems(lps)
@@ -93,6 +96,8 @@ def make_workload(name):
 def thetas(lp, k, seed):
     if "systems" in lp:  # batch: system s, iteration k draws from seed [4, s, k]
         return np.concatenate([W.as_batch_theta(q, s, k) for s, q in enumerate(lp["systems"])])
+    if lp["name"].startswith("ne_dense_front"):
+        return W.log_uniform(W.rng(seed, 1000 + k), 1e-2, 1e2, lp["n"])
     g = W.rng(seed, 1000 + k)
     lo, hi = (1e-10, 1e10) if lp["mode"] == W.AS else (1e-6, 1e6)
     return W.log_uniform(g, lo, hi, lp["n"])
@@ -215,7 +220,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="as_staircase",
-                    help="as_staircase | ne_random | ne_grid | ne_grid_small | as_batch | as_batch_small | as_dense_cols")
+                    help="as_staircase | ne_random | ne_grid | ne_grid_small | as_batch | as_batch_small | "
+                         "as_dense_cols | ne_dense_front[_<f>]")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--nsolves", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")

@@ -192,6 +192,25 @@ def as_batch_rhs(lp, s, k, j, seed=4):
     return g.standard_normal(lp["n"]), g.standard_normal(lp["m"])
 
 
+def ne_dense_front(f=4096, q=4, seed=0, theta_range=(1e-2, 1e2), delta=1e-8, nrhs=1):
+    """Normal equations whose K is one dense f x f front: A = [I | G] (f x (f + q)), G dense
+    N(0,1)/sqrt(f); K = diag(theta_I) + G diag(theta_G) G^T + delta I, so the single
+    supernode has p = f (the dense-front measurement of the Schur updates)."""
+    g = rng(0, f, q, seed)
+    n = f + q
+    cols = [np.array([j]) for j in range(f)] + [np.arange(f) for _ in range(q)]
+    colptr = np.zeros(n + 1, np.int64)
+    colptr[1:] = np.cumsum([len(c) for c in cols])
+    rowidx = np.concatenate(cols).astype(np.int32)
+    val = np.concatenate([np.ones(f), g.standard_normal(q * f) / np.sqrt(f)])
+    theta = log_uniform(g, *theta_range, n)
+    gr = rng(0, f, q, seed, 1)
+    r1 = gr.standard_normal((nrhs, f)).T.copy(order="F")
+    r7 = np.zeros((n, nrhs), order="F")
+    return LP(m=f, n=n, colptr=colptr, rowidx=rowidx, val=val, theta=theta, rho=0.0, delta=delta, mode=NE,
+              r1=r1, r7=r7, name=f"ne_dense_front_{f}")
+
+
 def as_batch(count, seed=4, mrange=(50, 2000), drange=(0.005, 0.02), rho=1e-10, delta=1e-10):
     """The first count systems of the batched workload (system s from seed [seed, s])."""
     return [as_batch_system(s, seed, mrange, drange, rho, delta) for s in range(count)]
