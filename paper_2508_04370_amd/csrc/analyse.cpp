@@ -741,14 +741,94 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             }
     }
 
-    // ----- solve level lists
+    // ----- solve level lists: per level the supernodes solved one per workgroup first, then
+    // the big ones
     P.lvl_ptr.assign(P.nlevels + 1, 0);
     for (int32_t t = 0; t < ns; ++t) P.lvl_ptr[P.sn_level[t] + 1]++;
     for (int32_t l = 0; l < P.nlevels; ++l) P.lvl_ptr[l + 1] += P.lvl_ptr[l];
     P.lvl_sn.resize(ns);
+    P.lvl_small.assign(P.nlevels, 0);
     {
         std::vector<int64_t> fl(P.lvl_ptr.begin(), P.lvl_ptr.end() - 1);
-        for (int32_t t = 0; t < ns; ++t) P.lvl_sn[fl[P.sn_level[t]]++] = t;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int32_t t = 0; t < ns; ++t)
+                if ((P.sn_f[t] >= opt.split_solve_front) == (pass == 1)) {
+                    P.lvl_sn[fl[P.sn_level[t]]++] = t;
+                    if (pass == 0) P.lvl_small[P.sn_level[t]]++;
+                }
+    }
+    // big supernodes: work-space rows and the launch sequence of each level
+    P.yoff.assign(ns, -1);
+    P.ytotal = 0;
+    P.fwd_ptr.assign(P.nlevels + 1, 0);
+    P.bwd_ptr.assign(P.nlevels + 1, 0);
+    P.ppart_max = 0;
+    auto chunks = [](int64_t rows) { return (int32_t)((rows + 255) / 256); };
+    for (int32_t l = 0; l < P.nlevels; ++l) {
+        std::vector<int32_t> big(P.lvl_sn.begin() + P.lvl_ptr[l] + P.lvl_small[l], P.lvl_sn.begin() + P.lvl_ptr[l + 1]);
+        int32_t nbmax = 0;
+        for (int32_t t : big) {
+            P.yoff[t] = P.ytotal;
+            P.ytotal += P.sn_f[t];
+            nbmax = std::max(nbmax, (P.sn_p[t] + 63) / 64);
+        }
+        auto add = [&](std::vector<SolveLaunch>& plan, int32_t kind, int64_t t0) {
+            const int64_t cnt = (int64_t)P.stasks.size() - t0;
+            if (cnt > 0) plan.push_back(SolveLaunch{kind, t0, cnt});
+        };
+        if (!big.empty()) {
+            int64_t t0 = (int64_t)P.stasks.size();
+            for (int32_t t : big)
+                for (int32_t c = 0; c < chunks(P.sn_f[t]); ++c) P.stasks.push_back(Task{t, c, 0, 0});
+            add(P.fwd_plan, S_GATHER, t0);
+            for (int32_t j = 0; j < nbmax; ++j) {
+                t0 = (int64_t)P.stasks.size();
+                for (int32_t t : big)
+                    if (64 * j < P.sn_p[t]) P.stasks.push_back(Task{t, j, 0, 0});
+                add(P.fwd_plan, S_FDIAG, t0);
+                t0 = (int64_t)P.stasks.size();
+                for (int32_t t : big)
+                    if (64 * j < P.sn_p[t]) {
+                        const int32_t k1 = std::min(P.sn_p[t], 64 * (j + 1));
+                        for (int32_t c = 0; c < chunks(P.sn_f[t] - k1); ++c) P.stasks.push_back(Task{t, j, c, 0});
+                    }
+                add(P.fwd_plan, S_FUPD, t0);
+            }
+            t0 = (int64_t)P.stasks.size();
+            for (int32_t t : big)
+                for (int32_t c = 0; c < chunks(P.sn_f[t]); ++c) P.stasks.push_back(Task{t, c, 0, 0});
+            add(P.fwd_plan, S_FFIN, t0);
+            // backward
+            t0 = (int64_t)P.stasks.size();
+            for (int32_t t : big)
+                for (int32_t c = 0; c < chunks(P.sn_f[t]); ++c) P.stasks.push_back(Task{t, c, 0, 0});
+            add(P.bwd_plan, S_BLOAD, t0);
+            for (int32_t j = nbmax - 1; j >= 0; --j) {
+                t0 = (int64_t)P.stasks.size();
+                std::vector<std::pair<int32_t, int32_t>> range(big.size(), {0, 0});
+                int32_t q = 0;
+                for (size_t bi = 0; bi < big.size(); ++bi) {
+                    const int32_t t = big[bi];
+                    if (64 * j >= P.sn_p[t]) continue;
+                    const int32_t k1 = std::min(P.sn_p[t], 64 * (j + 1));
+                    range[bi].first = q;
+                    for (int32_t c = 0; c < chunks(P.sn_f[t] - k1); ++c) P.stasks.push_back(Task{t, j, c, q++});
+                    range[bi].second = q - range[bi].first;
+                }
+                P.ppart_max = std::max<int64_t>(P.ppart_max, q);
+                add(P.bwd_plan, S_BPART, t0);
+                t0 = (int64_t)P.stasks.size();
+                for (size_t bi = 0; bi < big.size(); ++bi)
+                    if (64 * j < P.sn_p[big[bi]]) P.stasks.push_back(Task{big[bi], j, range[bi].first, range[bi].second});
+                add(P.bwd_plan, S_BDIAG, t0);
+            }
+            t0 = (int64_t)P.stasks.size();
+            for (int32_t t : big)
+                for (int32_t c = 0; c < chunks(P.sn_p[t]); ++c) P.stasks.push_back(Task{t, c, 0, 0});
+            add(P.bwd_plan, S_BSTORE, t0);
+        }
+        P.fwd_ptr[l + 1] = (int64_t)P.fwd_plan.size();
+        P.bwd_ptr[l + 1] = (int64_t)P.bwd_plan.size();
     }
 
     // ----- solve work per level (one pass, one rhs): L panel read once, vectors in and out

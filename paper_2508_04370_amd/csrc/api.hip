@@ -31,6 +31,7 @@ struct qdmf_ctx {
     DevPlan D{};
     Task* tasks_dev = nullptr;
     int32_t* lvl_sn_dev = nullptr;
+    Task* stasks_dev = nullptr;               // tasks of the big-supernode solve launches
     std::vector<int32_t> maxf_lvl, maxp_lvl;  // per level: largest front order and pivot count
     int64_t knnz = 0;
     int64_t device_bytes = 0;
@@ -186,6 +187,7 @@ int upload_plan(qdmf_ctx* h) {
     UP(ub_off, ub_off)
     UP(fg_ptr, fg_ptr)
     UP(fg_src, fg_src)
+    UP(yoff, yoff)
     UP(kcol_ptr, kcol_ptr)
     UP(kloc, kloc)
     UP(kcl, kcl)
@@ -218,6 +220,9 @@ int upload_plan(qdmf_ctx* h) {
     const int32_t* ls = nullptr;
     if ((rc = dupload(h, P.lvl_sn, &ls))) return rc;
     h->lvl_sn_dev = const_cast<int32_t*>(ls);
+    const Task* stk = nullptr;
+    if ((rc = dupload(h, P.stasks, &stk))) return rc;
+    h->stasks_dev = const_cast<Task*>(stk);
     h->knnz = P.kcol_ptr.empty() ? 0 : P.kcol_ptr.back();
     const int64_t N = P.N;
     if ((rc = dalloc(h, h->plan_allocs, &D.front, P.front_total))) return rc;
@@ -243,11 +248,12 @@ int upload_plan(qdmf_ctx* h) {
     if ((rc = dalloc(h, h->plan_allocs, &D.inertia_sys, (int64_t)3 * P.nsys))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &h->shift_dev, (int64_t)2 * P.nsys))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &h->stats_part, (int64_t)10 * factor_stats_blocks(P.N)))) return rc;
-    // largest front (dynamic LDS of the solve kernels) and pivot count (kernel variant) per level
+    // largest front (dynamic LDS of the one-workgroup solve kernels) and pivot count (kernel
+    // variant) per level, over the supernodes those kernels solve
     h->maxf_lvl.assign(P.nlevels, 1);
     h->maxp_lvl.assign(P.nlevels, 1);
     for (int32_t l = 0; l < P.nlevels; ++l)
-        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l + 1]; ++q) {
+        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) {
             h->maxf_lvl[l] = std::max(h->maxf_lvl[l], P.sn_f[P.lvl_sn[q]]);
             h->maxp_lvl[l] = std::max(h->maxp_lvl[l], P.sn_p[P.lvl_sn[q]]);
         }
@@ -281,6 +287,9 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     if ((rc = dalloc(h, h->solve_allocs, &S.active, units))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.steps, units))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.ract, nrhs))) return rc;
+    S.ytot = h->P.ytotal;
+    if ((rc = dalloc(h, h->solve_allocs, &S.Y, std::max<int64_t>(1, h->P.ytotal) * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.P, std::max<int64_t>(1, h->P.ppart_max) * 64 * nrhs))) return rc;
     if (h->act_host) (void)hipHostFree(h->act_host);
     h->act_host = nullptr;
     if (hipHostMalloc((void**)&h->act_host, sizeof(int32_t) * units, hipHostMallocDefault) != hipSuccess) {
@@ -324,15 +333,20 @@ void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32
     hipStream_t st = h->stream;
     if (P.nsys > 1 && active) active = S.ract;  // flags are per system: any system of the rhs
     launch_permute(h->D, S, src, active, st);
+    // per level: the supernodes solved one per workgroup, then the steps of the big ones
     for (int32_t l = 0; l < P.nlevels; ++l) {
         ProfScope ps(h, QDMF_K_FWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
-        launch_solve_level(true, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)(P.lvl_ptr[l + 1] - P.lvl_ptr[l]),
-                           h->maxf_lvl[l], h->maxp_lvl[l], active, st);
+        launch_solve_level(true, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)P.lvl_small[l], h->maxf_lvl[l],
+                           h->maxp_lvl[l], active, st);
+        for (int64_t q = P.fwd_ptr[l]; q < P.fwd_ptr[l + 1]; ++q)
+            launch_big_solve(h->D, S, P.fwd_plan[q], h->stasks_dev, active, st);
     }
     for (int32_t l = P.nlevels - 1; l >= 0; --l) {
         ProfScope ps(h, QDMF_K_BWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
-        launch_solve_level(false, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)(P.lvl_ptr[l + 1] - P.lvl_ptr[l]),
-                           h->maxf_lvl[l], h->maxp_lvl[l], active, st);
+        launch_solve_level(false, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)P.lvl_small[l], h->maxf_lvl[l],
+                           h->maxp_lvl[l], active, st);
+        for (int64_t q = P.bwd_ptr[l]; q < P.bwd_ptr[l + 1]; ++q)
+            launch_big_solve(h->D, S, P.bwd_plan[q], h->stasks_dev, active, st);
     }
     launch_unpermute(h->D, S, dst, active, st);
 }
@@ -502,6 +516,7 @@ void qdmf_default_options(qdmf_options* o) {
     o->f_mix = 1024;
     o->small_front = 64;
     o->mem_cap_bytes = 0;
+    o->split_solve_front = 1024;
 }
 
 int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_options* opt) {
@@ -510,7 +525,8 @@ int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_optio
     qdmf_ctx* h = new qdmf_ctx();
     if (opt) h->opt = *opt;
     else qdmf_default_options(&h->opt);
-    if (h->opt.nb != 64 || h->opt.small_front < 1 || h->opt.small_front > 64 || h->opt.max_refine < 0 ||
+    if (h->opt.nb != 64 || h->opt.small_front < 1 || h->opt.small_front > 64 || h->opt.split_solve_front < 1 ||
+        h->opt.max_refine < 0 ||
         h->opt.max_refine_mixed < 0 || h->opt.ordering < QDMF_ORDER_AMD || h->opt.ordering > QDMF_ORDER_AUTO) {
         delete h;
         return QDMF_ERR_INVALID_ARG;
@@ -557,6 +573,7 @@ int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     for (int a = 0; a < 3; ++a) ao.grid[a] = h->opt.grid[a];
     ao.amalgamate = h->opt.amalgamate;
     ao.small_front = h->opt.small_front;
+    ao.split_solve_front = h->opt.split_solve_front;
     ao.user_perm = user_perm;
     ao.nsys = nsys;
     ao.col_off = col_off;

@@ -50,6 +50,7 @@ struct DevPlan {
     const int64_t* rel_ptr;
     const int32_t* rel;
     const int64_t* ub_off;
+    const int64_t* yoff;      // per supernode: rows in the solve work space (big supernodes)
     const int64_t* fg_ptr;    // forward-solve gather list per front row
     const int64_t* fg_src;
     // K entries
@@ -135,6 +136,9 @@ struct DevSolve {
     int32_t* active;  // per unit: refinement continues
     int32_t* steps;   // per unit
     int32_t* ract;    // per rhs: some system of it still refines (gates the solve kernels)
+    double* Y;        // big-supernode work space, ytot x nrhs
+    int64_t ytot;
+    double* P;        // partial sums of the big backward solves: ppart_max x 64 x nrhs
 };
 
 void launch_rhs(const DevPlan& D, const DevSolve& S, const double* r7, const double* r1, hipStream_t s);
@@ -147,6 +151,9 @@ void launch_unpermute(const DevPlan& D, const DevSolve& S, double* dst, const in
 void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
                         int64_t base, unsigned count, int32_t maxf, int32_t maxp, const int32_t* active,
                         hipStream_t s);
+// One launch of the big-supernode solves (kind: SolveKind).
+void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L, const Task* stasks,
+                      const int32_t* active, hipStream_t s);
 void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s);
 void launch_berr_steps(const DevPlan& D, const DevSolve& S, int32_t phase, double target,
                        int max_steps, hipStream_t s);

@@ -1367,6 +1367,232 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
     }
 }
 
+// ---------------------------------------------------------------- big-supernode solves
+// Supernodes with large fronts are solved by many workgroups, all right-hand sides at once,
+// in the work space Y (rows of supernode s at Y + yoff[s], pivot rows in post-pivot order,
+// right-hand side r at offset r * ytot).  A launch is one step for every big supernode of a
+// tree level: gather, per 64-pivot block a diagonal solve and a row-chunk update, finish;
+// backward: load, per block (last first) row-chunk partial sums and a diagonal solve, store.
+
+__device__ inline bool big_inactive(const DevSolve& S, const int32_t* active) {
+    if (!active) return false;
+    for (int r = 0; r < S.nrhs; ++r)
+        if (active[r]) return false;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_sgather(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
+                                                 const int32_t* active) {
+    if (big_inactive(S, active)) return;
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, i = 256 * t.k0 + threadIdx.x;
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s];
+    if (i >= f) return;
+    const int64_t* gp = D.fg_ptr + D.sn_rowptr[s];
+    const int64_t q0 = gp[i], q1 = gp[i + 1];
+    const int64_t dst = D.yoff[s] + (i < p ? D.lpinv[c0 + i] : i);
+    for (int r = 0; r < S.nrhs; ++r) {
+        if (active && !active[r]) continue;
+        const double* xw = S.xw + (int64_t)r * D.N;
+        const double* ub = S.ub + (int64_t)r * D.ub_total;
+        double v = i < p ? xw[c0 + i] : 0.0;
+        for (int64_t q = q0; q < q1; ++q) v += ub[D.fg_src[q]];
+        S.Y[dst + (int64_t)r * S.ytot] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sfdiag(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
+                                                const int32_t* active) {
+    __shared__ double Lb[64 * 65];
+    if (big_inactive(S, active)) return;
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, k0 = 64 * t.k0;
+    const int p = D.sn_p[s], ld = D.sn_ld[s];
+    const int nb = min(64, p - k0);
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    stage_block<64>(Lb, D.front + D.sn_off[s], ld, k0, nb, tid);
+    __syncthreads();
+    for (int r = wv; r < S.nrhs; r += 4) {
+        if (active && !active[r]) continue;
+        double* y = S.Y + D.yoff[s] + k0 + (int64_t)r * S.ytot;
+        const double v = trsv_fwd_wave<64>(Lb, lane < nb ? y[lane] : 0.0, lane);
+        if (lane < nb) y[lane] = v;
+    }
+}
+
+// rows below block j: y_i -= sum_k L(i, k0 + k) y_{k0 + k}; the row of L stays in registers
+// while the block's y values pass through LDS sixteen right-hand sides at a time
+__global__ __launch_bounds__(256) void k_sfupd(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
+                                               const int32_t* active) {
+    __shared__ double Yb[64 * 16];
+    if (big_inactive(S, active)) return;
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, k0 = 64 * t.k0;
+    const int f = D.sn_f[s], p = D.sn_p[s], ld = D.sn_ld[s];
+    const int k1 = min(k0 + 64, p), nb = k1 - k0;
+    const int tid = threadIdx.x;
+    double* Ys = S.Y + D.yoff[s];
+    const int i = k1 + 256 * t.a + tid;
+    double l[64];
+    {
+        const double* Li = D.front + D.sn_off[s] + min(i, f - 1) + (int64_t)k0 * ld;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) l[k] = k < nb ? Li[(int64_t)k * ld] : 0.0;
+    }
+    for (int rg = 0; rg < S.nrhs; rg += 16) {
+        const int nr = min(16, S.nrhs - rg);
+        __syncthreads();  // the previous group is done with Yb
+        for (int idx = tid; idx < 64 * 16; idx += 256) {
+            const int k = idx & 63, rr = idx >> 6;
+            Yb[idx] = (k < nb && rr < nr) ? Ys[k0 + k + (int64_t)(rg + rr) * S.ytot] : 0.0;
+        }
+        __syncthreads();
+        if (i >= f) continue;
+        for (int rr = 0; rr < nr; ++rr) {
+            if (active && !active[rg + rr]) continue;
+            const double* yb = Yb + 64 * rr;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 64; k += 2) {
+                a0 += l[k] * yb[k];
+                a1 += l[k + 1] * yb[k + 1];
+            }
+            Ys[i + (int64_t)(rg + rr) * S.ytot] -= a0 + a1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sffin(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
+                                               const int32_t* active) {
+    if (big_inactive(S, active)) return;
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, i = 256 * t.k0 + threadIdx.x;
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s];
+    if (i >= f) return;
+    for (int r = 0; r < S.nrhs; ++r) {
+        if (active && !active[r]) continue;
+        const double* y = S.Y + D.yoff[s] + (int64_t)r * S.ytot;
+        if (i >= p) {
+            S.ub[D.ub_off[s] + (i - p) + (int64_t)r * D.ub_total] = y[i];
+            continue;
+        }
+        const int ty = D.ptype[c0 + i];
+        double v;
+        if (ty == 0) v = y[i] / D.dval[c0 + i];
+        else if (ty == 1) {
+            const double a = D.dval[c0 + i], b = D.doff[c0 + i], c = D.dval[c0 + i + 1];
+            v = (c * y[i] - b * y[i + 1]) / (a * c - b * b);
+        } else {
+            const double a = D.dval[c0 + i - 1], b = D.doff[c0 + i - 1], c = D.dval[c0 + i];
+            v = (a * y[i] - b * y[i - 1]) / (a * c - b * b);
+        }
+        S.xw[(int64_t)r * D.N + c0 + D.lperm[c0 + i]] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sbload(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
+                                                const int32_t* active) {
+    if (big_inactive(S, active)) return;
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, i = 256 * t.k0 + threadIdx.x;
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s];
+    if (i >= f) return;
+    const int32_t src = i < p ? c0 + D.lperm[c0 + i] : D.rows[D.sn_rowptr[s] + i];
+    for (int r = 0; r < S.nrhs; ++r)
+        if (!active || active[r]) S.Y[D.yoff[s] + i + (int64_t)r * S.ytot] = S.xw[(int64_t)r * D.N + src];
+}
+
+// partial sums over one 256-row chunk below block j: P[(b * 64 + k) * nrhs + r] =
+// sum_i L(i, k0 + k) y_i[r]; the rows are taken in 64-row tiles loaded coalesced (lane = row)
+// and summed through LDS (lane = column), right-hand sides eight at a time
+__global__ __launch_bounds__(256) void k_sbpart(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
+                                                const int32_t* active) {
+    __shared__ double Lt[64 * 65];
+    __shared__ double Yt[8 * 64];
+    __shared__ double red[4 * 64 * 8];
+    if (big_inactive(S, active)) return;
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, k0 = 64 * t.k0;
+    const int f = D.sn_f[s], p = D.sn_p[s], ld = D.sn_ld[s];
+    const int k1 = min(k0 + 64, p), nb = k1 - k0;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const double* F = D.front + D.sn_off[s];
+    const double* Ys = S.Y + D.yoff[s];
+    const int r0 = k1 + 256 * t.a, r1 = min(f, r0 + 256);
+    for (int rg = 0; rg < S.nrhs; rg += 8) {
+        const int nr = min(8, S.nrhs - rg);
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int i0 = r0; i0 < r1; i0 += 64) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = wv + 4 * q, i = i0 + lane;
+                v[q] = (k < nb && i < r1) ? F[i + (int64_t)(k0 + k) * ld] : 0.0;
+            }
+            __syncthreads();  // the previous tile's sums are done with Lt, Yt
+#pragma unroll
+            for (int q = 0; q < 16; ++q) Lt[(wv + 4 * q) * 65 + lane] = v[q];
+            for (int idx = tid; idx < 8 * 64; idx += 256) {
+                const int i = idx & 63, rr = idx >> 6;
+                Yt[idx] = (rr < nr && i0 + i < r1) ? Ys[i0 + i + (int64_t)(rg + rr) * S.ytot] : 0.0;
+            }
+            __syncthreads();
+            for (int q = 0; q < 16; ++q) {  // rows wv + 4q of the tile, column lane
+                const int i = wv + 4 * q;
+                const double lv = Lt[lane * 65 + i];
+#pragma unroll
+                for (int rr = 0; rr < 8; ++rr) acc[rr] += lv * Yt[rr * 64 + i];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) red[(wv * 64 + lane) * 8 + rr] = acc[rr];
+        __syncthreads();
+        if (wv == 0)
+            for (int rr = 0; rr < nr; ++rr) {
+                const double sum = ((red[(0 * 64 + lane) * 8 + rr] + red[(1 * 64 + lane) * 8 + rr]) +
+                                    red[(2 * 64 + lane) * 8 + rr]) + red[(3 * 64 + lane) * 8 + rr];
+                S.P[((int64_t)t.b * 64 + lane) * S.nrhs + rg + rr] = sum;
+            }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sbdiag(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
+                                                const int32_t* active) {
+    __shared__ double Lb[64 * 65];
+    if (big_inactive(S, active)) return;
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, k0 = 64 * t.k0;
+    const int p = D.sn_p[s], ld = D.sn_ld[s];
+    const int nb = min(64, p - k0);
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    stage_block<64>(Lb, D.front + D.sn_off[s], ld, k0, nb, tid);
+    __syncthreads();
+    for (int r = wv; r < S.nrhs; r += 4) {
+        if (active && !active[r]) continue;
+        double* y = S.Y + D.yoff[s] + k0 + (int64_t)r * S.ytot;
+        double v = 0.0;
+        if (lane < nb) {
+            double sum = 0.0;
+            for (int c = 0; c < t.b; ++c) sum += S.P[((int64_t)(t.a + c) * 64 + lane) * S.nrhs + r];
+            v = y[lane] - sum;
+        }
+        v = trsv_bwd_wave<64>(Lb, v, lane);
+        if (lane < nb) y[lane] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sbstore(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
+                                                 const int32_t* active) {
+    if (big_inactive(S, active)) return;
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, i = 256 * t.k0 + threadIdx.x;
+    const int p = D.sn_p[s], c0 = D.sn_ptr[s];
+    if (i >= p) return;
+    for (int r = 0; r < S.nrhs; ++r)
+        if (!active || active[r]) S.xw[(int64_t)r * D.N + c0 + D.lperm[c0 + i]] = S.Y[D.yoff[s] + i + (int64_t)r * S.ytot];
+}
+
 // One level of the supernodal tree per launch: the kernel boundary orders the levels.
 // NBM: a bound on the pivot count of every supernode of the level, capped at 64 (sizes the
 // register blocks, so levels of small supernodes keep many workgroups per CU).
@@ -1762,6 +1988,22 @@ void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const
         else QDMF_SOLVE_LAUNCH(k_bwd, 64);
     }
 #undef QDMF_SOLVE_LAUNCH
+}
+
+void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L, const Task* stasks,
+                      const int32_t* active, hipStream_t s) {
+    const unsigned g = (unsigned)L.ntask;
+    switch (L.kind) {
+        case S_GATHER: hipLaunchKernelGGL(k_sgather, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_FDIAG: hipLaunchKernelGGL(k_sfdiag, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_FUPD: hipLaunchKernelGGL(k_sfupd, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_FFIN: hipLaunchKernelGGL(k_sffin, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_BLOAD: hipLaunchKernelGGL(k_sbload, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_BPART: hipLaunchKernelGGL(k_sbpart, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_BDIAG: hipLaunchKernelGGL(k_sbdiag, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_BSTORE: hipLaunchKernelGGL(k_sbstore, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        default: break;
+    }
 }
 
 void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s) {

@@ -38,6 +38,19 @@ struct Launch {
     double bytes = 0;
 };
 
+// Solve launches of big supernodes (front order >= the split_solve_front option), spread over
+// many workgroups (all right-hand sides at once).  Task fields per kind:
+//   S_GATHER, S_FFIN, S_BLOAD, S_BSTORE: s, k0 = 256-row chunk of the front
+//   S_FDIAG: s, k0 = pivot block j;  S_BDIAG: s, k0 = j, [a, a + b) = its partial sums
+//   S_FUPD: s, k0 = j, a = 256-row chunk below the block
+//   S_BPART: s, k0 = j, a = 256-row chunk below the block, b = index of its partial sum
+enum SolveKind : int32_t { S_GATHER = 0, S_FDIAG, S_FUPD, S_FFIN, S_BLOAD, S_BPART, S_BDIAG, S_BSTORE };
+
+struct SolveLaunch {
+    int32_t kind;
+    int64_t task0, ntask;
+};
+
 struct Plan {
     // problem
     int32_t m = 0, n = 0, mode = 0, N = 0;
@@ -101,6 +114,13 @@ struct Plan {
     std::vector<int64_t> lvl_ptr;       // supernodes per level for the solves (nlevels + 1)
     std::vector<int32_t> lvl_sn;
     std::vector<double> lvl_solve_flops, lvl_solve_bytes;  // per level, one pass, one rhs
+    std::vector<int32_t> lvl_small;     // per level: supernodes of lvl_sn solved one per workgroup (first)
+    std::vector<Task> stasks;           // tasks of the big-supernode solve launches
+    std::vector<int64_t> fwd_ptr, bwd_ptr;  // per level: its range of fwd_plan / bwd_plan
+    std::vector<SolveLaunch> fwd_plan, bwd_plan;
+    std::vector<int64_t> yoff;          // per supernode: rows in the solve work space (big only)
+    int64_t ytotal = 0;
+    int64_t ppart_max = 0;              // most partial sums of one S_BPART launch
 
     int64_t device_bytes = 0;
 };
@@ -112,6 +132,7 @@ struct AnalyseOptions {
     int grid[3] = {0, 0, 0};
     int amalgamate = 1;
     int small_front = 64;
+    int split_solve_front = 1024;  // fronts at least this big: multi-workgroup solves
     const int32_t* user_perm = nullptr;
     // batch: nsys systems, system s owns columns [col_off[s], col_off[s+1]) and rows
     // [row_off[s], row_off[s+1]) of the block-diagonal A (nullptr: one system)

@@ -203,6 +203,8 @@ def test_invalid_options_rejected():
     _expect(Q.QDMF_ERR_INVALID_ARG, lambda: Q.qdmf_create(-1, None, o))
     o = Q.qdmf_default_options(small_front=65)
     _expect(Q.QDMF_ERR_INVALID_ARG, lambda: Q.qdmf_create(-1, None, o))
+    o = Q.qdmf_default_options(split_solve_front=0)
+    _expect(Q.QDMF_ERR_INVALID_ARG, lambda: Q.qdmf_create(-1, None, o))
 
 
 def test_no_float_atomics_in_kernels():

@@ -188,14 +188,14 @@ def _dense_factor(s, N):
     return po, L, D, gd["edyn"]
 
 
-@pytest.mark.parametrize("amalgamate", [0, 1])
-def test_factor_backward_stable_and_solve_matches_its_factor(torch_dev, amalgamate):
+@pytest.mark.parametrize("amalgamate,split", [(0, 1024), (1, 1024), (1, 1)])
+def test_factor_backward_stable_and_solve_matches_its_factor(torch_dev, amalgamate, split):
     """||P K P^T - L D L^T|| small (no dynamic regularisation here), and the GPU solve
-    (no refinement) equals a dense solve with the GPU's own factor."""
-    import scipy.linalg as sla
+    (no refinement) equals a dense solve with the GPU's own factor; split = 1 sends every
+    supernode through the multi-workgroup solves."""
     from test_oracle import dense_K
     lp = W.as_staircase(periods=3, rows=40, cols=80, link_cols=8, seed=9, theta_range=(1e-2, 1e2))
-    g = gpu_solve(torch_dev, lp, amalgamate=amalgamate, max_refine=0)
+    g = gpu_solve(torch_dev, lp, amalgamate=amalgamate, max_refine=0, split_solve_front=split)
     s = g["solver"]
     N = s.N
     K = dense_K(lp, lp["theta"], lp["rho"], lp["delta"])
@@ -212,6 +212,41 @@ def test_factor_backward_stable_and_solve_matches_its_factor(torch_dev, amalgama
     bound = np.abs(scale).sum(axis=1).max() * np.abs(x).max() + np.abs(b).max()
     print("solve backward error vs own factor:", np.abs(r).max() / bound)
     assert np.abs(r).max() <= 100 * s.sym["max_front"] * U * bound
+
+
+@pytest.mark.parametrize("case", ["dense_ne", "staircase_20rhs"])
+def test_split_solves_match_oracle(torch_dev, case):
+    """Multi-workgroup solves on every supernode (split_solve_front = 1, all right-hand
+    sides per launch, per-rhs refinement flags): same backward-error target, inertia and
+    norm as the oracle.  dense_ne has a front of order ~200 (several 64-pivot blocks and
+    256-row chunks); 20 right-hand sides cross the kernels' groups of 8 and 16."""
+    if case == "dense_ne":
+        lp = W.ne_random(m=200, n=400, density=0.08, seed=21)
+    else:
+        lp = W.as_staircase(periods=4, rows=50, cols=100, link_cols=10, nrhs=20)
+    g = gpu_solve(torch_dev, lp, split_solve_front=1)
+    check_against_oracle(lp, g)
+
+
+def test_split_solves_wide_theta_own_factor(torch_dev):
+    """Theta over [1e-10, 1e10] (2x2 pivots and tiny pivots possible): with no refinement
+    the multi-workgroup solves are backward stable for the GPU's own factor, like the
+    one-workgroup solves."""
+    lp = W.as_staircase(periods=3, rows=40, cols=80, link_cols=8, seed=9, theta_range=(1e-10, 1e10),
+                        rho=1e-10, delta=1e-10)
+    for split in (1024, 1):
+        g = gpu_solve(torch_dev, lp, max_refine=0, split_solve_front=split, amalgamate=0)
+        s = g["solver"]
+        po, L, D, _ = _dense_factor(s, s.N)
+        print(f"split {split}: 2x2 pivots {int((s.export_d()['ptype'] == 1).sum())}")
+        scale = np.abs(L) @ np.abs(D) @ np.abs(L).T
+        b = np.concatenate([lp["r7"][:, 0], lp["r1"][:, 0]])[po]
+        x = system_x(lp, g["dx"][:, 0], g["dy"][:, 0])[po]
+        r = b - L @ (D @ (L.T @ x))
+        bound = np.abs(scale).sum(axis=1).max() * np.abs(x).max() + np.abs(b).max()
+        print("solve backward error vs own factor:", np.abs(r).max() / bound)
+        assert np.abs(r).max() <= 100 * s.sym["max_front"] * U * bound
+        s.close()
 
 
 def test_multiple_rhs(torch_dev):
