@@ -941,7 +941,7 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             for (int32_t t : large)
                 if (w < P.sn_nwin[t]) {
                     const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
-                    npg = std::max(npg, std::min(3, (P.sn_f[t] - k1 + 63) / 64));
+                    npg = std::max(npg, std::min(1, (P.sn_f[t] - k1 + 63) / 64));
                 }
             t0 = (int64_t)P.tasks.size();
             mf = 0;

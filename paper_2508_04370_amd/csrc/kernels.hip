@@ -80,21 +80,24 @@ __device__ inline void wave_argmax(double v, int /*lane*/, double& bv, int& bi) 
 }
 
 // LDS state of the one-wave pivot kernel of small fronts: T holds the whole symmetric front
-// (f <= 64), T[i][j] at j*LDW + i.
-constexpr int LDW = 65;
-
+// (f <= FM <= 64), T[i][j] at j*LDW + i.  Sized per launch (FM = 16, 32 or 64) so that the
+// many tiny fronts of the lowest levels leave room for many workgroups per CU.
+template <int FM>
 struct PivShared {
-    double T[64 * LDW];
-    double sh[64];  // static shift of the row (-rho primal, +delta dual)
-    double w0[64], w1[64];
-    double d[64], doff[64], ed[64];
-    int sg[64];     // expected pivot sign
-    int pm[64];     // original position now at this position
-    int pt[64], fl[64], zs[64];
+    static constexpr int LDW = FM + 1;
+    double T[FM * LDW];
+    double sh[FM];  // static shift of the row (-rho primal, +delta dual)
+    double w0[FM], w1[FM];
+    double d[FM], doff[FM], ed[FM];
+    int sg[FM];     // expected pivot sign
+    int pm[FM];     // original position now at this position
+    int pt[FM], fl[FM], zs[FM];
 };
 
 // Symmetric interchange of positions a and b: rows and columns of the symmetric block.
-__device__ void sym_swap(PivShared& S, int nsym, int a, int b, int lane) {
+template <int FM>
+__device__ void sym_swap(PivShared<FM>& S, int nsym, int a, int b, int lane) {
+    constexpr int LDW = PivShared<FM>::LDW;
     if (a == b) return;
     if (lane < nsym) {  // rows a and b of the symmetric block (lane = column)
         double t = S.T[lane * LDW + a];
@@ -117,7 +120,10 @@ __device__ void sym_swap(PivShared& S, int nsym, int a, int b, int lane) {
 
 // T[row][j] -= m * S.w0[j] for j in [j0, ncols): 8 columns per trip so the LDS loads of a
 // trip are independent of its stores and can be issued together.
-__device__ inline void rank1_rows(PivShared& S, int j0, int ncols, double m0, int lane) {
+template <int FM>
+__device__ inline void rank1_rows(PivShared<FM>& S, int j0, int ncols, double m0, int lane) {
+    constexpr int LDW = PivShared<FM>::LDW;
+    if (lane >= FM) return;
     for (int jb = j0 & ~7; jb < ncols; jb += 8) {
         double t0[8], w[8];
 #pragma unroll
@@ -138,8 +144,10 @@ __device__ inline void rank1_rows(PivShared& S, int j0, int ncols, double m0, in
 // the updates applied to the columns [0, ncols) of the symmetric rows (nsym = ncols).  Pivot
 // tests read only the window (Section 4.5).  One wavefront (blockDim.x == 64); every
 // decision is wave-uniform.
-__device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, const PivotParams& pp,
+template <int FM>
+__device__ void factor_window(PivShared<FM>& S, int nsym, int nbw, double knorm, const PivotParams& pp,
                               int lane) {
+    constexpr int LDW = PivShared<FM>::LDW;
     const int ncols = nsym;
     const double tiny = pp.eps_lift * knorm;  // delta * ||M||_1 of the lift test
     const double alpha = pp.alpha;
@@ -200,8 +208,10 @@ __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, con
                 const double u1 = act ? S.T[(k + 1) * LDW + lane] : 0.0;
                 const double l0 = act ? (u0 * c - u1 * b) / det : 0.0;
                 const double l1 = act ? (u1 * a - u0 * b) / det : 0.0;
-                S.w0[lane] = l0;
-                S.w1[lane] = l1;
+                if (lane < FM) {
+                    S.w0[lane] = l0;
+                    S.w1[lane] = l1;
+                }
                 __syncthreads();
                 for (int j = k + 2; j < ncols; ++j) {
                     const double lj0 = S.w0[j], lj1 = S.w1[j];
@@ -265,7 +275,7 @@ __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, con
         const double e = dk - (fkk_before + S.sh[k]);
         const bool act = lane > k && lane < nsym;
         const double li = act ? S.T[k * LDW + lane] / dk : 0.0;
-        S.w0[lane] = (lane > k && lane < ncols) ? S.T[k * LDW + lane] : 0.0;  // column k
+        if (lane < FM) S.w0[lane] = (lane > k && lane < ncols) ? S.T[k * LDW + lane] : 0.0;  // column k
         __syncthreads();
         rank1_rows(S, k + 1, ncols, li, lane);
         __syncthreads();
@@ -283,7 +293,8 @@ __device__ void factor_window(PivShared& S, int nsym, int nbw, double knorm, con
     }
 }
 
-__device__ inline void init_signs(PivShared& S, const DevPlan& D, const int32_t* rows, int fr, int sys,
+template <int FM>
+__device__ inline void init_signs(PivShared<FM>& S, const DevPlan& D, const int32_t* rows, int fr, int sys,
                                   int lane) {
     const double rho = D.rho_sys[sys], delta = D.delta_sys[sys];
     if (lane < fr) {
@@ -294,7 +305,8 @@ __device__ inline void init_signs(PivShared& S, const DevPlan& D, const int32_t*
     }
 }
 
-__device__ inline void store_pivots(const PivShared& S, const DevPlan& D, int pos0, int k0, int nbw,
+template <int FM>
+__device__ inline void store_pivots(const PivShared<FM>& S, const DevPlan& D, int pos0, int k0, int nbw,
                                     int lane) {
     if (lane < nbw) {
         const int g = pos0 + lane;
@@ -311,16 +323,18 @@ __device__ inline void store_pivots(const PivShared& S, const DevPlan& D, int po
 
 // ---------------------------------------------------------------- factorisation kernels
 
-// Small fronts (f <= 64): assembly of original entries and children's contribution blocks
+// Small fronts (f <= FM <= 64): assembly of original entries and children's contribution blocks
 // straight into LDS, then the whole partial factorisation there.
+template <int FM>
 __global__ __launch_bounds__(64) void k_small(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp) {
-    __shared__ PivShared S;
+    __shared__ PivShared<FM> S;
+    constexpr int LDW = PivShared<FM>::LDW;
     const int lane = threadIdx.x;
     const int s = tasks[t0 + blockIdx.x].s;
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     double* F = D.front + D.sn_off[s];
     const int32_t* rows = D.rows + D.sn_rowptr[s];
-    for (int j = 0; j < 64; ++j) S.T[j * LDW + lane] = 0.0;
+    for (int idx = lane; idx < FM * LDW; idx += 64) S.T[idx] = 0.0;
     __syncthreads();
     {  // original entries of the pivot columns (row position, column position, value)
         const int64_t e0 = D.kcol_ptr[c0], e1 = D.kcol_ptr[c0 + p];
@@ -408,6 +422,13 @@ __device__ inline double readlane_d(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// A value equal in every lane (an LDS read at a wave-uniform address) as a wave-uniform one.
+__device__ inline double readfirst_d(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 __device__ inline double shfl_d(double v, int src) {  // value of lane src (ds_bpermute)
     const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
     const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
@@ -428,19 +449,75 @@ __device__ inline unsigned wave_umax(unsigned v) {
     return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Argmax of x >= 0 over the lanes with ok set (lowest lane on ties).  A non-negative
-// double orders like its bit pattern read as an unsigned integer, so the maximum is taken
-// on 64-bit keys (bits + 1; 0 for lanes without a candidate or with NaN) in two 32-bit
-// passes.  Returns the lane, or -1 when no lane has a candidate.
+// Wave maxima of two unsigned values at once: the two DPP chains are interleaved, so each
+// step of one hides the latency of the other.
+__device__ inline void wave_umax2(unsigned& a, unsigned& b) {
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x111, 0xf, 0xf, false));
+    b = max(b, (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, 0x111, 0xf, 0xf, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x112, 0xf, 0xf, false));
+    b = max(b, (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, 0x112, 0xf, 0xf, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x114, 0xf, 0xf, false));
+    b = max(b, (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, 0x114, 0xf, 0xf, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x118, 0xf, 0xf, false));
+    b = max(b, (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, 0x118, 0xf, 0xf, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x142, 0xa, 0xf, false));
+    b = max(b, (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, 0x142, 0xa, 0xf, false));
+    a = max(a, (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, 0x143, 0xc, 0xf, false));
+    b = max(b, (unsigned)__builtin_amdgcn_update_dpp(0, (int)b, 0x143, 0xc, 0xf, false));
+    a = (unsigned)__builtin_amdgcn_readlane((int)a, 63);
+    b = (unsigned)__builtin_amdgcn_readlane((int)b, 63);
+}
+
+// Lanes where p holds, as a 64-bit mask (the builtin keeps it in scalar registers).
+__device__ inline unsigned long long ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Ordering key of x >= 0 on the lanes with ok set: a non-negative double orders like its bit
+// pattern read as an unsigned integer; bits + 1, so that 0 marks a lane without a candidate
+// (or with NaN).
+__device__ inline unsigned long long nn_key(double x, bool ok) {
+    return (ok && x == x) ? (unsigned long long)__double_as_longlong(x) + 1ull : 0ull;
+}
+
+// Argmax of x >= 0 over the lanes with ok set (lowest lane on ties); -1 when no lane has a
+// candidate.  The maximum of the 64-bit keys is taken on the upper halves first; the lower
+// halves are compared only when several lanes share the largest upper half.
 __device__ inline int wave_argmax_nn(double x, bool ok) {
-    const bool valid = ok && x == x;
-    const unsigned long long key = valid ? (unsigned long long)__double_as_longlong(x) + 1ull : 0ull;
+    const unsigned long long key = nn_key(x, ok);
     const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
     const unsigned mh = wave_umax(hi);
-    const bool c1 = hi == mh;
-    const unsigned ml = wave_umax(c1 ? lo : 0u);
-    if (mh == 0u && ml == 0u) return -1;
-    return __ffsll((long long)__ballot(c1 && lo == ml)) - 1;
+    const unsigned long long m1 = ballot64(key != 0ull && hi == mh);
+    if (m1 == 0ull) return -1;
+    if ((m1 & (m1 - 1ull)) == 0ull) return __ffsll((long long)m1) - 1;
+    const unsigned ml = wave_umax(hi == mh ? lo : 0u);
+    return __ffsll((long long)ballot64(key != 0ull && hi == mh && lo == ml)) - 1;
+}
+
+// In one interleaved pass: the argmax r of x >= 0 over the okx lanes (lowest lane on ties,
+// -1 if none) with its value xm, and the maximum ym of y >= 0 over the oky lanes (0 if none).
+__device__ inline void wave_argmax_max_nn(double x, bool okx, double y, bool oky, int& r, double& xm,
+                                          double& ym) {
+    const unsigned long long kx = nn_key(x, okx), ky = nn_key(y, oky);
+    unsigned hx = (unsigned)(kx >> 32), hy = (unsigned)(ky >> 32);
+    wave_umax2(hx, hy);
+    unsigned lx = (unsigned)(kx >> 32) == hx ? (unsigned)kx : 0u;
+    unsigned ly = (unsigned)(ky >> 32) == hy ? (unsigned)ky : 0u;
+    wave_umax2(lx, ly);
+    const unsigned long long mx = ((unsigned long long)hx << 32) | lx, my = ((unsigned long long)hy << 32) | ly;
+    r = mx ? __ffsll((long long)ballot64(kx == mx)) - 1 : -1;
+    xm = mx ? __longlong_as_double((long long)(mx - 1ull)) : 0.0;
+    ym = my ? __longlong_as_double((long long)(my - 1ull)) : 0.0;
+}
+
+// 1 / d to within about one unit in the last place: the hardware estimate refined by two
+// Newton steps (fewer dependent operations than a correctly rounded division).  Where 1 / d
+// overflows (|d| below about 2^-1024) the estimate's infinity is returned as it is.
+__device__ inline double recip(double d) {
+    const double r0 = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r0, 1.0);
+    double r = fma(r0, e, r0);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    return __builtin_isinf(r0) ? r0 : r;
 }
 
 // Exchange of the values held by lanes a and b (wave-uniform a, b).
@@ -499,17 +576,27 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         }
     }
     // per position (= lane; initially position = slot): slot, diagonal, sign, static shift
-    int slotP = lane;
-    double dgP = 0.0, shP = 0.0;
-    int sgP = 1;
+    // The slot word packs the slot (bits 0-5) and whether its row is primal (bit 6), which
+    // fixes the expected sign and the static shift; only the word and the diagonal move in an
+    // interchange.
+    int slotW = lane;
+    double dgP = 0.0;
     const int sys = D.sys_new[c0];
+    const double shPr = readfirst_d(-D.rho_sys[sys]), shDu = readfirst_d(D.delta_sys[sys]);
     if (lane < nbw) {
         dgP = F[(k0 + lane) + (int64_t)(k0 + lane) * ld];
-        const bool pr = D.primal_new[D.rows[D.sn_rowptr[s] + k0 + lane]] != 0;
-        sgP = pr ? -1 : 1;
-        shP = pr ? -D.rho_sys[sys] : D.delta_sys[sys];
+        if (D.primal_new[D.rows[D.sn_rowptr[s] + k0 + lane]] != 0) slotW |= 64;
     }
-    const double tiny = pp.eps_lift * D.knorm_sys[sys];  // delta * ||M||_1 of the lift test
+    int slotP = slotW & 63, sgP = (slotW & 64) ? -1 : 1;
+    double shP = (slotW & 64) ? shPr : shDu;
+    auto derive = [&]() {
+        slotP = slotW & 63;
+        sgP = (slotW & 64) ? -1 : 1;
+        shP = (slotW & 64) ? shPr : shDu;
+    };
+    // delta * ||M||_1 of the lift test; wave-uniform, so that every decision below, and the
+    // pivot counter, stay scalar
+    const double tiny = readfirst_d(pp.eps_lift * D.knorm_sys[sys]);
     const double alpha = pp.alpha;
     uint64_t elim = 0;  // eliminated slots
     double o_d = 0.0, o_off = 0.0, o_ed = 0.0;  // outputs of position = lane
@@ -519,13 +606,11 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
     while (k < nbw) {
         if (pp.presort) {  // largest |diagonal| of the window to position k
             int q = wave_argmax_nn(fabs(dgP), lane >= k && lane < nbw);
-            if (q < k || q >= nbw) q = k;  // no candidate (NaN input): no swap
-            if (q != k) {
-                slotP = xchg_i(slotP, k, q, lane);
-                sgP = xchg_i(sgP, k, q, lane);
-                dgP = xchg_d(dgP, k, q, lane);
-                shP = xchg_d(shP, k, q, lane);
-            }
+            q = (q < k || q >= nbw) ? k : q;  // no candidate (NaN input): no swap
+            // exchanging position k with itself changes nothing: no branch needed
+            slotW = xchg_i(slotW, k, q, lane);
+            dgP = xchg_d(dgP, k, q, lane);
+            derive();
         }
         const int sk = __builtin_amdgcn_readlane(slotP, k);
         if (cq == (sk >> 4)) {
@@ -544,25 +629,21 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         {
             const double den = fabs(dgP + shP);
             const bool same = below && sgP == sgk0;
-            const double qv = (same && den != 0.0) ? cP * cP / den : 0.0;
-            r = wave_argmax_nn(fabs(cP), below);
-            const int bl = wave_argmax_nn(qv, same && den != 0.0);
-            nz = __popcll(__ballot(same && den == 0.0));
-            beta = bl >= 0 ? readlane_d(qv, bl) : 0.0;
-            gp = r >= 0 ? fabs(readlane_d(cP, r)) : 0.0;
-            if (!(gp > 0.0) || r <= k || r >= nbw) {
+            const double qv = (same && den != 0.0) ? cP * cP * recip(den) : 0.0;
+            wave_argmax_max_nn(fabs(cP), below, qv, same && den != 0.0, r, gp, beta);
+            nz = __popcll(ballot64(same && den == 0.0));
+            if (!(gp > 0.0)) {
                 gp = 0.0;
                 r = -1;
             }
         }
         const double akk = fabs(fkk);
-        int piv = sk, two = 0, lifted = 0, useB = 0;
+        // the common outcomes (a lifted or an accepted 1x1 pivot at k) in one test
+        const bool lift0 = fmax(akk, gp) <= tiny;
+        const bool easy = lift0 | (akk >= alpha * gp);
+        int piv = sk, two = 0, lifted = lift0, useB = 0;
         double fkk_before = fkk;
-        if (fmax(akk, gp) <= tiny) {
-            lifted = 1;
-        } else if (akk >= alpha * gp) {
-            // 1x1 at k
-        } else {
+        if (!easy) {
             const int sr = __builtin_amdgcn_readlane(slotP, r);
             if (cq == (sr >> 4)) {
 #pragma unroll
@@ -576,10 +657,9 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
             if (akk * gr >= alpha * gp * gp) {
                 // 1x1 at k
             } else if (fabs(frr) >= alpha * gr) {
-                slotP = xchg_i(slotP, k, r, lane);
-                sgP = xchg_i(sgP, k, r, lane);
+                slotW = xchg_i(slotW, k, r, lane);
                 dgP = xchg_d(dgP, k, r, lane);
-                shP = xchg_d(shP, k, r, lane);
+                derive();
                 piv = sr;
                 useB = 1;
                 fkk_before = frr;
@@ -587,22 +667,21 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
                 const double cN = colB[par][slotP];
                 const double den = fabs(dgP + shP);
                 const bool same = lane > k && lane < nbw && sgP == __builtin_amdgcn_readlane(sgP, k);
-                const double qn = (same && den != 0.0) ? cN * cN / den : 0.0;
+                const double qn = (same && den != 0.0) ? cN * cN * recip(den) : 0.0;
                 const int bl = wave_argmax_nn(qn, same && den != 0.0);
                 beta = bl >= 0 ? readlane_d(qn, bl) : 0.0;
-                nz = __popcll(__ballot(same && den == 0.0));
+                nz = __popcll(ballot64(same && den == 0.0));
             } else {
-                slotP = xchg_i(slotP, k + 1, r, lane);
-                sgP = xchg_i(sgP, k + 1, r, lane);
+                slotW = xchg_i(slotW, k + 1, r, lane);
                 dgP = xchg_d(dgP, k + 1, r, lane);
-                shP = xchg_d(shP, k + 1, r, lane);
+                derive();
                 two = 1;
             }
         }
         if (two) {
             const int sa = sk, sb = __builtin_amdgcn_readlane(slotP, k + 1);
             const double a = fkk + readlane_d(shP, k);
-            const double b = colA[par][sb];
+            const double b = readfirst_d(colA[par][sb]);  // same in every lane: keeps k wave-uniform
             const double c = readlane_d(dgP, k + 1) + readlane_d(shP, k + 1);
             const double det = a * c - b * b;
             if (det == 0.0) {
@@ -614,10 +693,10 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
                 const double cN = colA[par][slotP];
                 const double den = fabs(dgP + shP);
                 const bool same = lane > k && lane < nbw && sgP == sgk0;
-                const double qn = (same && den != 0.0) ? cN * cN / den : 0.0;
+                const double qn = (same && den != 0.0) ? cN * cN * recip(den) : 0.0;
                 const int bl = wave_argmax_nn(qn, same && den != 0.0);
                 beta = bl >= 0 ? readlane_d(qn, bl) : 0.0;
-                nz = __popcll(__ballot(same && den == 0.0));
+                nz = __popcll(ballot64(same && den == 0.0));
             } else {
                 elim |= (1ull << sa) | (1ull << sb);
                 // multipliers of the columns (lane = slot), identical in every wave
@@ -678,22 +757,20 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         const double(*colP) = useB ? colB[par] : colA[par];
         const int sgk = __builtin_amdgcn_readlane(sgP, k);
         const double shk = readlane_d(shP, k);
+        // selects rather than branches: the values are wave-uniform
         const double fk = lifted ? sgk * tiny : fkk_before;
         double dk = fk + shk;  // static regularisation after the pivot
-        int flag = lifted ? PF_LIFT : 0;
-        if (fabs(dk) < beta) {  // Proposition 3
-            dk = sgk * beta;
-            flag |= PF_PROP3;
-        }
-        if (!((sgk > 0 && dk > 0) || (sgk < 0 && dk < 0))) {  // keep the sign
-            double mag = fabs(dk);
-            if (beta > mag) mag = beta;
-            if (tiny > mag) mag = tiny;
-            dk = sgk * mag;
-            flag |= PF_SIGN;
-        }
+        const bool p3 = fabs(dk) < beta;  // Proposition 3
+        dk = p3 ? sgk * beta : dk;
+        const bool bad = !((sgk > 0 && dk > 0) || (sgk < 0 && dk < 0));  // keep the sign
+        double mag = fabs(dk);
+        mag = beta > mag ? beta : mag;
+        mag = tiny > mag ? tiny : mag;
+        dk = bad ? sgk * mag : dk;
+        const int flag = (lifted ? PF_LIFT : 0) | (p3 ? PF_PROP3 : 0) | (bad ? PF_SIGN : 0);
         const double e = dk - (fkk_before + shk);
         elim |= 1ull << piv;
+        const double rdk = recip(dk);
         {
             double wq[16];
 #pragma unroll
@@ -702,7 +779,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
 #pragma unroll
             for (int g = 0; g < RG; ++g) {
                 const bool rem = g > 0 ? prow0 + 64 * g < f : crem;
-                const double li = rem ? colP[64 * g + lane] / dk : 0.0;
+                const double li = rem ? colP[64 * g + lane] * rdk : 0.0;
 #pragma unroll
                 for (int q = 0; q < 16; ++q) T[g][q] -= li * wq[q];
                 if (cq == 0) {
@@ -713,7 +790,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         }
         {  // diagonal of the remaining positions
             const double cw = colP[slotP];
-            if (lane > k && lane < nbw) dgP -= (cw / dk) * cw;
+            if (lane > k && lane < nbw) dgP -= (cw * rdk) * cw;
         }
         if (lane == k) {
             o_d = dk;
@@ -1178,19 +1255,35 @@ __global__ void k_unpermute(DevPlan D, const double* xw, double* dst, const int3
 // (8, 16, 32 or 64), which sizes LDS tiles and register blocks; Lb holds a block with row
 // stride NBM + 1: Lb[k * (NBM + 1) + i] = L(k0 + i, k0 + k), strictly lower, zero elsewhere.
 template <int NBM>
-__device__ inline void stage_block(double* Lb, const double* F, int ld, int k0, int nb, int tid) {
-    constexpr int LS = NBM + 1, NT = (NBM * NBM + 255) / 256;
-    double v[NT];
+struct BlockRegs {
+    double v[(NBM * NBM + 255) / 256];
+};
+
+template <int NBM>
+__device__ inline void load_block(BlockRegs<NBM>& b, const double* F, int ld, int k0, int nb, int tid) {
+    constexpr int NT = (NBM * NBM + 255) / 256;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int idx = tid + 256 * t, i = idx % NBM, k = idx / NBM;
-        v[t] = (idx < NBM * NBM && i < nb && k < nb && i > k) ? F[(k0 + i) + (int64_t)(k0 + k) * ld] : 0.0;
+        b.v[t] = (idx < NBM * NBM && i < nb && k < nb && i > k) ? F[(k0 + i) + (int64_t)(k0 + k) * ld] : 0.0;
     }
+}
+
+template <int NBM>
+__device__ inline void store_block(double* Lb, const BlockRegs<NBM>& b, int tid) {
+    constexpr int LS = NBM + 1, NT = (NBM * NBM + 255) / 256;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int idx = tid + 256 * t;
-        if (idx < NBM * NBM) Lb[(idx / NBM) * LS + idx % NBM] = v[t];
+        if (idx < NBM * NBM) Lb[(idx / NBM) * LS + idx % NBM] = b.v[t];
     }
+}
+
+template <int NBM>
+__device__ inline void stage_block(double* Lb, const double* F, int ld, int k0, int nb, int tid) {
+    BlockRegs<NBM> b;
+    load_block<NBM>(b, F, ld, k0, nb, tid);
+    store_block<NBM>(Lb, b, tid);
 }
 
 // Triangular solves on the staged block in one wavefront with the block in registers: lane
@@ -1252,32 +1345,93 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
     for (int r = 0; r < S.nrhs; ++r) {
         if (active && !active[r]) continue;
         double* xw = S.xw + (int64_t)r * D.N;
+        BlockRegs<NBM> b0;  // the first diagonal block, loaded along with the gather
+        load_block<NBM>(b0, F, ld, 0, min(64, p), tid);
         {  // front row t (pre-pivot numbering): own entry plus the children's contributions
-           // in ascending child order; pivot rows moved in factorisation (lpinv)
+           // in ascending child order; pivot rows moved in factorisation (lpinv).  Four rows
+           // per thread and trip, so that their loads are in flight together.
             const int64_t* gp = D.fg_ptr + D.sn_rowptr[s];
             const double* ub = S.ub + (int64_t)r * D.ub_total;
-            for (int t = tid; t < f; t += 256) {
-                double v = t < p ? xw[c0 + t] : 0.0;
-                for (int64_t q = gp[t]; q < gp[t + 1]; ++q) v += ub[D.fg_src[q]];
-                y[t < p ? D.lpinv[c0 + t] : t] = v;
+            for (int tb = 0; tb < f; tb += 1024) {
+                int64_t qa[4], qe[4];
+                double v[4];
+                int dst[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int t = tb + tid + 256 * u;
+                    const bool on = t < f;
+                    qa[u] = on ? gp[t] : 0;
+                    qe[u] = on ? gp[t + 1] : 0;
+                    v[u] = (on && t < p) ? xw[c0 + t] : 0.0;
+                    dst[u] = on ? (t < p ? D.lpinv[c0 + t] : t) : -1;
+                }
+                bool more = true;
+                while (more) {
+                    int64_t src[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) src[u] = qa[u] < qe[u] ? D.fg_src[qa[u]] : -1;
+                    more = false;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (src[u] >= 0) {
+                            v[u] += ub[src[u]];
+                            ++qa[u];
+                        }
+                        more |= qa[u] < qe[u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (dst[u] >= 0) y[dst[u]] = v[u];
             }
         }
+        store_block<NBM>(Lb, b0, tid);
         __syncthreads();
         for (int k0 = 0; k0 < p; k0 += 64) {
             const int k1 = min(k0 + 64, p), nb = k1 - k0;
-            stage_block<NBM>(Lb, F, ld, k0, nb, tid);
-            __syncthreads();
+            if (k0 > 0) {
+                stage_block<NBM>(Lb, F, ld, k0, nb, tid);
+                __syncthreads();
+            }
             if (tid < 64) {
                 const double y0 = tid < nb ? y[k0 + tid] : 0.0;
                 const double v = trsv_fwd_wave<NBM>(Lb, y0, tid);
                 if (tid < nb) y[k0 + tid] = v;
             }
             __syncthreads();
-            for (int i = k1 + tid; i < f; i += 256) {  // rows below: a whole row of the block in flight
-                const double* Li = F + i + (int64_t)k0 * ld;
-                const double* yk = y + k0;
-                const double dlt = gemv_row<NBM>(Li, ld, nb, yk);
-                y[i] -= dlt;
+            if constexpr (NBM <= 32) {  // rows below, two per thread and trip: both rows in flight
+                for (int i = k1 + tid; i < f; i += 512) {
+                    const double* Li = F + i + (int64_t)k0 * ld;
+                    const bool two = i + 256 < f;
+                    double la[NBM], lc[NBM];
+#pragma unroll
+                    for (int k = 0; k < NBM; ++k) {
+                        la[k] = k < nb ? Li[(int64_t)k * ld] : 0.0;
+                        lc[k] = (two && k < nb) ? Li[256 + (int64_t)k * ld] : 0.0;
+                    }
+                    double a0 = 0.0, a1 = 0.0, c0s = 0.0, c1s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NBM; k += 2) {
+                        const double y0 = k < nb ? y[k0 + k] : 0.0, y1 = k + 1 < nb ? y[k0 + k + 1] : 0.0;
+                        if (k < nb) {
+                            a0 += la[k] * y0;
+                            c0s += lc[k] * y0;
+                        }
+                        if (k + 1 < nb) {
+                            a1 += la[k + 1] * y1;
+                            c1s += lc[k + 1] * y1;
+                        }
+                    }
+                    y[i] -= a0 + a1;
+                    if (two) y[i + 256] -= c0s + c1s;
+                }
+            } else {
+                for (int i = k1 + tid; i < f; i += 256) {  // rows below: a whole row of the block in flight
+                    const double* Li = F + i + (int64_t)k0 * ld;
+                    const double* yk = y + k0;
+                    const double dlt = gemv_row<NBM>(Li, ld, nb, yk);
+                    y[i] -= dlt;
+                }
             }
             __syncthreads();
         }
@@ -1312,12 +1466,28 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
     for (int r = 0; r < S.nrhs; ++r) {
         if (active && !active[r]) continue;
         double* xw = S.xw + (int64_t)r * D.N;
-        for (int i = tid; i < f; i += 256) y[i] = i < p ? xw[c0 + D.lperm[c0 + i]] : xw[rows[i]];
-        __syncthreads();
         const int nblk = (p + 63) / 64;
+        BlockRegs<NBM> bl;  // the last diagonal block, loaded along with y
+        load_block<NBM>(bl, F, ld, (nblk - 1) * 64, p - (nblk - 1) * 64, tid);
+        for (int ib = 0; ib < f; ib += 1024) {  // four rows per thread and trip
+            int src[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = ib + tid + 256 * u;
+                src[u] = i < p ? c0 + D.lperm[c0 + i] : (i < f ? rows[i] : -1);
+            }
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = src[u] >= 0 ? xw[src[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (src[u] >= 0) y[ib + tid + 256 * u] = v[u];
+        }
+        store_block<NBM>(Lb, bl, tid);
+        __syncthreads();
         for (int bk = nblk - 1; bk >= 0; --bk) {
             const int k0 = bk * 64, k1 = min(k0 + 64, p), nb = k1 - k0;
-            stage_block<NBM>(Lb, F, ld, k0, nb, tid);
+            if (bk < nblk - 1) stage_block<NBM>(Lb, F, ld, k0, nb, tid);
             {  // rows below the block, sum_i L(i, k) y_i: tiles of 64 rows loaded coalesced
                // (lane = row; the next tile in flight while the current one is summed through
                // LDS by thread (column = lane, rows wv, wv + 4, ...))
@@ -1614,6 +1784,104 @@ __global__ __launch_bounds__(256) void k_bwd(DevPlan D, DevSolve S, const int32_
     bwd_supernode<NBM>(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb, part, Lt);
 }
 
+// Levels whose fronts all have f <= 64: one wavefront per supernode, four per workgroup.
+// Lane i holds y_i (pivot rows in post-pivot order).  Forward: lane i gathers pre-pivot row
+// lperm(i) directly, so no permutation step is needed; each pivot k broadcasts y_k by readlane.
+template <int PM>
+__global__ __launch_bounds__(256) void k_fwd_wave(DevPlan D, DevSolve S, const int32_t* lvl_sn, int64_t base,
+                                                  int count, const int32_t* active) {
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (w >= count) return;
+    const int s = __builtin_amdgcn_readfirstlane(lvl_sn[base + w]);
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
+    const double* F = D.front + D.sn_off[s];
+    const bool on = lane < f;
+    const int t = lane < p ? D.lperm[c0 + lane] : lane;  // pre-pivot row at position lane
+    double l[PM];
+#pragma unroll
+    for (int k = 0; k < PM; ++k) l[k] = (k < p && on && lane > k) ? F[lane + (int64_t)k * ld] : 0.0;
+    int ty = 0;
+    double da = 1.0, db = 0.0, dc = 1.0;
+    if (lane < p) {
+        ty = D.ptype[c0 + lane];
+        const int k2 = ty == 2 ? lane - 1 : lane;
+        da = D.dval[c0 + k2];
+        db = ty ? D.doff[c0 + k2] : 0.0;
+        dc = ty ? D.dval[c0 + k2 + 1] : 1.0;
+    }
+    const int64_t* gp = D.fg_ptr + D.sn_rowptr[s];
+    const int64_t q0 = on ? gp[t] : 0, q1 = on ? gp[t + 1] : 0;
+    for (int r = 0; r < S.nrhs; ++r) {
+        if (active && !active[r]) continue;
+        double* xw = S.xw + (int64_t)r * D.N;
+        double* ub = S.ub + (int64_t)r * D.ub_total;
+        double y = (on && lane < p) ? xw[c0 + t] : 0.0;
+        for (int64_t q = q0; q < q1; ++q) y += ub[D.fg_src[q]];
+#pragma unroll
+        for (int k = 0; k < PM; ++k) {  // every pivot, the last one too: rows below are lanes >= p
+            if (k < p) {
+                const double yk = readlane_d(y, k);
+                if (lane > k) y -= l[k] * yk;
+            }
+        }
+        const double yn = shfl_d(y, min(lane + 1, 63)), yp = shfl_d(y, max(lane - 1, 0));
+        if (on && lane >= p) ub[D.ub_off[s] + lane - p] = y;
+        if (lane < p) {
+            double x;
+            if (ty == 0) x = y / da;
+            else if (ty == 1) x = (dc * y - db * yn) / (da * dc - db * db);
+            else x = (da * y - db * yp) / (da * dc - db * db);
+            xw[c0 + t] = x;
+        }
+    }
+}
+
+// Backward solve, one wavefront per supernode: lane j < p accumulates sum_i L(i, j) y_i,
+// first over the rows below the pivot block (its own column of L, eight rows per trip),
+// then over the pivot block from the last pivot up, one readlane per pivot.
+template <int PM>
+__global__ __launch_bounds__(256) void k_bwd_wave(DevPlan D, DevSolve S, const int32_t* lvl_sn, int64_t base,
+                                                  int count, const int32_t* active) {
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (w >= count) return;
+    const int s = __builtin_amdgcn_readfirstlane(lvl_sn[base + w]);
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
+    const double* F = D.front + D.sn_off[s];
+    const double* Fj = F + (int64_t)min(lane, p - 1) * ld;  // column lane of L (lanes < p)
+    const bool on = lane < f;
+    const int src = lane < p ? c0 + D.lperm[c0 + lane] : (on ? D.rows[D.sn_rowptr[s] + lane] : 0);
+    double c[PM];  // c[k] = L(k, lane): row k of the pivot block, column lane
+#pragma unroll
+    for (int k = 0; k < PM; ++k) c[k] = (k < p && lane < k) ? Fj[k] : 0.0;
+    for (int r = 0; r < S.nrhs; ++r) {
+        if (active && !active[r]) continue;
+        double* xw = S.xw + (int64_t)r * D.N;
+        double y = on ? xw[src] : 0.0;
+        double a0 = 0.0, a1 = 0.0;
+        for (int i0 = p; i0 < f; i0 += 8) {
+            double lv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) lv[u] = (lane < p && i0 + u < f) ? Fj[i0 + u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                if (i0 + u < f) a0 += lv[u] * readlane_d(y, i0 + u);
+                if (i0 + u + 1 < f) a1 += lv[u + 1] * readlane_d(y, i0 + u + 1);
+            }
+        }
+        double acc = a0 + a1;
+#pragma unroll
+        for (int k = PM - 1; k >= 0; --k) {
+            if (k >= p) continue;
+            if (lane == k) y -= acc;
+            const double yk = readlane_d(y, k);
+            acc += c[k] * yk;  // c[k] = 0 for lanes >= k
+        }
+        if (lane < p) xw[src] = y;
+    }
+}
+
 // r = b - K_static x and (|K||x|)_i in original numbering, from A, Theta, rho, delta
 // (AS) or from the K values (NE); per-block maxima of |r|, |x|, |b|.
 __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const double* xin) {
@@ -1907,7 +2175,11 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
                         hipStream_t s) {
     const unsigned g = (unsigned)L.ntask;
     switch (L.kind) {
-        case L_SMALL: hipLaunchKernelGGL(k_small, dim3(g), dim3(64), 0, s, D, tasks, L.task0, pp); break;
+        case L_SMALL:
+            if (L.maxf <= 16) hipLaunchKernelGGL(k_small<16>, dim3(g), dim3(64), 0, s, D, tasks, L.task0, pp);
+            else if (L.maxf <= 32) hipLaunchKernelGGL(k_small<32>, dim3(g), dim3(64), 0, s, D, tasks, L.task0, pp);
+            else hipLaunchKernelGGL(k_small<64>, dim3(g), dim3(64), 0, s, D, tasks, L.task0, pp);
+            break;
         case L_ASSEMBLE:
             hipLaunchKernelGGL(k_assemble, dim3(g), dim3(256), (size_t)L.lds, s, D, tasks, L.task0);
             break;
@@ -1973,6 +2245,24 @@ void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const
                         int64_t base, unsigned count, int32_t maxf, int32_t maxp, const int32_t* active,
                         hipStream_t s) {
     if (!count) return;
+    if (maxf <= 64) {  // one wavefront per supernode
+        const dim3 g((count + 3) / 4);
+        const int c = (int)count;
+#define QDMF_WAVE_LAUNCH(K, PM) hipLaunchKernelGGL(K<PM>, g, dim3(256), 0, s, D, S, lvl_sn_dev, base, c, active)
+        if (forward) {
+            if (maxp <= 8) QDMF_WAVE_LAUNCH(k_fwd_wave, 8);
+            else if (maxp <= 16) QDMF_WAVE_LAUNCH(k_fwd_wave, 16);
+            else if (maxp <= 32) QDMF_WAVE_LAUNCH(k_fwd_wave, 32);
+            else QDMF_WAVE_LAUNCH(k_fwd_wave, 64);
+        } else {
+            if (maxp <= 8) QDMF_WAVE_LAUNCH(k_bwd_wave, 8);
+            else if (maxp <= 16) QDMF_WAVE_LAUNCH(k_bwd_wave, 16);
+            else if (maxp <= 32) QDMF_WAVE_LAUNCH(k_bwd_wave, 32);
+            else QDMF_WAVE_LAUNCH(k_bwd_wave, 64);
+        }
+#undef QDMF_WAVE_LAUNCH
+        return;
+    }
     const size_t lds = (size_t)maxf * 8;
     const int v = maxp <= 8 ? 0 : maxp <= 16 ? 1 : maxp <= 32 ? 2 : 3;
 #define QDMF_SOLVE_LAUNCH(K, NBM) hipLaunchKernelGGL(K<NBM>, dim3(count), dim3(256), lds, s, D, S, lvl_sn_dev, base, active)
