@@ -862,17 +862,32 @@ __device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int
     }
 #pragma unroll
     for (int t = 0; t < 16; ++t) Bs[r * LDT + kq + 4 * t] = (T)wb[t];
-    __syncthreads();
     const int wv = tid >> 6, l = tid & 63;
     const int wc = (wv >> 1) * 32, wr = (wv & 1) * 32;
     const int li = l & 15, lk = l >> 4;
+    // this thread's 16 elements of the tile, loaded before the products so that their
+    // latency overlaps them; element (i, j, v) at column C0 + wc + 16 i + cofs(v), row
+    // R0 + wr + 16 j + li
+    double cv[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = C0 + wc + i * 16 + (sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v);
+                const int row = R0 + wr + j * 16 + li;
+                cv[i][j][v] = (row < f && col < f && row >= col) ? F[row + (int64_t)col * ld] : 0.0;
+            }
+    const int kmax = (nbw + 3) & ~3;  // columns beyond the window are zero
+    __syncthreads();
     if constexpr (sizeof(T) == 8) {
         d4 acc[2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-        for (int kk = 0; kk < 64; kk += 4) {
+        for (int kk = 0; kk < kmax; kk += 4) {
             double a0 = Bs[(wc + li) * LDT + kk + lk];
             double a1 = Bs[(wc + 16 + li) * LDT + kk + lk];
             double b0 = As[(wr + li) * LDT + kk + lk];
@@ -891,7 +906,7 @@ __device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int
                     // f64 16x16x4 output: element (lk + 4v, li) of the 16 x 16 block
                     const int col = C0 + wc + i * 16 + lk + 4 * v;
                     const int row = R0 + wr + j * 16 + li;
-                    if (row < f && col < f && row >= col) F[row + (int64_t)col * ld] -= acc[i][j][v];
+                    if (row < f && col < f && row >= col) F[row + (int64_t)col * ld] = cv[i][j][v] - acc[i][j][v];
                 }
     } else {
         f4 acc[2][2];
@@ -899,7 +914,7 @@ __device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        for (int kk = 0; kk < 64; kk += 4) {
+        for (int kk = 0; kk < kmax; kk += 4) {
             float a0 = Bs[(wc + li) * LDT + kk + lk];
             float a1 = Bs[(wc + 16 + li) * LDT + kk + lk];
             float b0 = As[(wr + li) * LDT + kk + lk];
@@ -918,7 +933,7 @@ __device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int
                     // f32 16x16x4 output: element (4 lk + v, li) of the 16 x 16 block
                     const int col = C0 + wc + i * 16 + 4 * lk + v;
                     const int row = R0 + wr + j * 16 + li;
-                    if (row < f && col < f && row >= col) F[row + (int64_t)col * ld] -= (double)acc[i][j][v];
+                    if (row < f && col < f && row >= col) F[row + (int64_t)col * ld] = cv[i][j][v] - (double)acc[i][j][v];
                 }
     }
 }
