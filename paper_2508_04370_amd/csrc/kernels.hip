@@ -415,6 +415,51 @@ __global__ __launch_bounds__(256) void k_assemble(DevPlan D, const Task* tasks, 
     for (int i = tid; i < nr; i += 256) out[i] = buf[i];
 }
 
+// The same assembly with one wavefront per front column (four columns per workgroup), for
+// levels whose fronts are at most 512 rows: many more columns in flight at once.  Each wave
+// sums its column in its own LDS buffer; LDS operations of one wave complete in order, so
+// the children's contributions are added in ascending child order without barriers.
+__global__ __launch_bounds__(256) void k_assemble_w(DevPlan D, const Task* tasks, int64_t t0, int64_t ntask,
+                                                    int maxf) {
+    extern __shared__ double wbuf[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t ti = (int64_t)blockIdx.x * 4 + wv;
+    if (ti >= ntask) return;
+    double* buf = wbuf + (int64_t)wv * maxf;
+    const Task t = tasks[t0 + ti];
+    const int s = t.s, j = t.k0;
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
+    const int nr = f - j;
+    for (int i = lane; i < nr; i += 64) buf[i] = 0.0;
+    if (j < p) {
+        const int64_t e1 = D.kcol_ptr[c0 + j + 1];
+        for (int64_t e = D.kcol_ptr[c0 + j] + lane; e < e1; e += 64) buf[D.kloc[e] - j] = D.kval[e];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    for (int q = t.a; q < t.a + t.b; ++q) {
+        const int ch = D.asm_child[q], lo = D.asm_col[q];
+        const int cp = D.sn_p[ch], cb = D.sn_f[ch] - cp, cld = D.sn_ld[ch];
+        const int32_t* rel = D.rel + D.rel_ptr[ch];
+        const double* col = D.front + D.sn_off[ch] + (int64_t)(cp + lo) * cld + cp;
+        for (int a0 = lo; a0 < cb; a0 += 256) {  // four rows per lane and trip, loads in flight together
+            int ra[4];
+            double va[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int a = a0 + 64 * u + lane;
+                ra[u] = a < cb ? rel[a] - j : -1;
+                va[u] = a < cb ? col[a] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (ra[u] >= 0) buf[ra[u]] += va[u];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    double* out = D.front + D.sn_off[s] + (int64_t)j * ld + j;
+    for (int i = lane; i < nr; i += 64) out[i] = buf[i];
+}
+
 // Helpers of the register-tiled window kernel.  readlane with a wave-uniform index.
 __device__ inline double readlane_d(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -2196,7 +2241,11 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
             else hipLaunchKernelGGL(k_small<64>, dim3(g), dim3(64), 0, s, D, tasks, L.task0, pp);
             break;
         case L_ASSEMBLE:
-            hipLaunchKernelGGL(k_assemble, dim3(g), dim3(256), (size_t)L.lds, s, D, tasks, L.task0);
+            if (L.maxf <= 512)
+                hipLaunchKernelGGL(k_assemble_w, dim3((unsigned)((L.ntask + 3) / 4)), dim3(256), (size_t)4 * L.maxf * 8,
+                                   s, D, tasks, L.task0, L.ntask, L.maxf);
+            else
+                hipLaunchKernelGGL(k_assemble, dim3(g), dim3(256), (size_t)L.lds, s, D, tasks, L.task0);
             break;
         case L_WINDOW:
             switch (L.npg) {
