@@ -32,6 +32,7 @@ struct qdmf_ctx {
     Task* tasks_dev = nullptr;
     int32_t* lvl_sn_dev = nullptr;
     Task* stasks_dev = nullptr;               // tasks of the big-supernode solve launches
+    Task* inv_tasks_dev = nullptr;            // diagonal blocks whose inverse the solves use
     std::vector<int32_t> maxf_lvl, maxp_lvl;  // per level: largest front order and pivot count
     int64_t knnz = 0;
     int64_t device_bytes = 0;
@@ -150,6 +151,7 @@ int set_device(qdmf_ctx* h) {
 int64_t plan_device_bytes(const Plan& P) {
     int64_t b = 0;
     b += P.front_total * 8;
+    b += P.inv_total * 8 + (int64_t)P.inv_tasks.size() * sizeof(Task);
     b += (int64_t)P.tasks.size() * sizeof(Task);
     b += (int64_t)P.rows.size() * 4 + (int64_t)P.rel.size() * 4;
     b += P.kcol_ptr.empty() ? 0 : P.kcol_ptr.back() * (8 + 4 + 8);
@@ -188,6 +190,7 @@ int upload_plan(qdmf_ctx* h) {
     UP(fg_ptr, fg_ptr)
     UP(fg_src, fg_src)
     UP(yoff, yoff)
+    UP(inv_off, inv_off)
     UP(kcol_ptr, kcol_ptr)
     UP(kloc, kloc)
     UP(kcl, kcl)
@@ -223,10 +226,14 @@ int upload_plan(qdmf_ctx* h) {
     const Task* stk = nullptr;
     if ((rc = dupload(h, P.stasks, &stk))) return rc;
     h->stasks_dev = const_cast<Task*>(stk);
+    const Task* itk = nullptr;
+    if ((rc = dupload(h, P.inv_tasks, &itk))) return rc;
+    h->inv_tasks_dev = const_cast<Task*>(itk);
     h->knnz = P.kcol_ptr.empty() ? 0 : P.kcol_ptr.back();
     const int64_t N = P.N;
     if ((rc = dalloc(h, h->plan_allocs, &D.front, P.front_total))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.kval, h->knnz))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.linv, P.inv_total))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.aval, (int64_t)P.ari.size()))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.colabs, P.n))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.rowabs, P.m))) return rc;
@@ -323,6 +330,7 @@ void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delt
         ProfScope ps(h, L.kind, L.flops, L.bytes);
         launch_factor_step(h->D, L, h->tasks_dev, pp, h->stream);
     }
+    launch_inv(h->D, h->inv_tasks_dev, (int64_t)h->P.inv_tasks.size(), h->stream);
     launch_factor_stats(h->D, pp, h->stats_part, h->stream);
 }
 

@@ -51,6 +51,8 @@ struct DevPlan {
     const int32_t* rel;
     const int64_t* ub_off;
     const int64_t* yoff;      // per supernode: rows in the solve work space (big supernodes)
+    const int64_t* inv_off;   // per supernode: inverses of its diagonal blocks in linv, or -1
+    double* linv;
     const int64_t* fg_ptr;    // forward-solve gather list per front row
     const int64_t* fg_src;
     // K entries
@@ -151,6 +153,8 @@ void launch_unpermute(const DevPlan& D, const DevSolve& S, double* dst, const in
 void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const int32_t* lvl_sn_dev,
                         int64_t base, unsigned count, int32_t maxf, int32_t maxp, const int32_t* active,
                         hipStream_t s);
+// Inverses of the diagonal blocks used by the one-workgroup solves (after the factorisation).
+void launch_inv(const DevPlan& D, const Task* tasks, int64_t ntask, hipStream_t s);
 // One launch of the big-supernode solves (kind: SolveKind).
 void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L, const Task* stasks,
                       const int32_t* active, hipStream_t s);

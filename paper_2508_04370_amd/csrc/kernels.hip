@@ -1346,6 +1346,46 @@ __device__ inline void stage_block(double* Lb, const double* F, int ld, int k0, 
     store_block<NBM>(Lb, b, tid);
 }
 
+// The inverse of a unit lower diagonal block (nb x nb, column-major, unit diagonal stored)
+// into the same LDS layout as stage_block: Lb[k * (NBM + 1) + i] = Linv(i, k).
+template <int NBM>
+__device__ inline void load_inv(BlockRegs<NBM>& b, const double* Li, int nb, int tid) {
+    constexpr int NT = (NBM * NBM + 255) / 256;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int idx = tid + 256 * t, i = idx % NBM, k = idx / NBM;
+        b.v[t] = (idx < NBM * NBM && i < nb && k < nb && i >= k) ? Li[i + (int64_t)k * nb] : 0.0;
+    }
+}
+
+// y[0..nb) <- Linv y (forward) or Linv^T y (backward) with the inverse staged in Lb: every
+// thread sums a fixed slice of k, the slices are added in a fixed order.  part: 256 doubles
+// of LDS.  Ends with a barrier.
+template <int NBM, bool TRANS>
+__device__ inline void block_inv_apply(const double* Lb, double* y, int nb, double* part, int tid) {
+    constexpr int LS = NBM + 1;
+    constexpr int KC = NBM * NBM >= 256 ? NBM * NBM / 256 : 1, NP = NBM / KC;
+    const int i = tid % NBM, q = tid / NBM;
+    if (q < NP) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int u = 0; u < KC; u += 2) {
+            const int k = q * KC + u;
+            if (k < nb) a0 += (TRANS ? Lb[i * LS + k] : Lb[k * LS + i]) * y[k];
+            if (u + 1 < KC && k + 1 < nb) a1 += (TRANS ? Lb[i * LS + k + 1] : Lb[(k + 1) * LS + i]) * y[k + 1];
+        }
+        part[q * NBM + i] = a0 + a1;
+    }
+    __syncthreads();
+    if (tid < nb) {
+        double v = 0.0;
+#pragma unroll
+        for (int qq = 0; qq < NP; ++qq) v += part[qq * NBM + tid];
+        y[tid] = v;
+    }
+    __syncthreads();
+}
+
 // Triangular solves on the staged block in one wavefront with the block in registers: lane
 // i holds row i (forward) or column i (backward) and its y value; each step broadcasts one
 // finished y by readlane.
@@ -1398,15 +1438,16 @@ __device__ inline double gemv_row(const double* Li, int ld, int nb, const double
 // Lb: 64 x 65 doubles of LDS holding the current 64 x 64 diagonal block of L.
 template <int NBM>
 __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const int32_t* active, double* y,
-                              double* Lb) {
+                              double* Lb, double* part) {
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const double* F = D.front + D.sn_off[s];
     const int tid = threadIdx.x;
     for (int r = 0; r < S.nrhs; ++r) {
         if (active && !active[r]) continue;
         double* xw = S.xw + (int64_t)r * D.N;
-        BlockRegs<NBM> b0;  // the first diagonal block, loaded along with the gather
-        load_block<NBM>(b0, F, ld, 0, min(64, p), tid);
+        const double* Linv = D.linv + D.inv_off[s];
+        BlockRegs<NBM> b0;  // the first diagonal block's inverse, loaded along with the gather
+        load_inv<NBM>(b0, Linv, min(64, p), tid);
         {  // front row t (pre-pivot numbering): own entry plus the children's contributions
            // in ascending child order; pivot rows moved in factorisation (lpinv).  Four rows
            // per thread and trip, so that their loads are in flight together.
@@ -1450,15 +1491,12 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
         for (int k0 = 0; k0 < p; k0 += 64) {
             const int k1 = min(k0 + 64, p), nb = k1 - k0;
             if (k0 > 0) {
-                stage_block<NBM>(Lb, F, ld, k0, nb, tid);
+                BlockRegs<NBM> bk;
+                load_inv<NBM>(bk, Linv + 4096 * (k0 / 64), nb, tid);
+                store_block<NBM>(Lb, bk, tid);
                 __syncthreads();
             }
-            if (tid < 64) {
-                const double y0 = tid < nb ? y[k0 + tid] : 0.0;
-                const double v = trsv_fwd_wave<NBM>(Lb, y0, tid);
-                if (tid < nb) y[k0 + tid] = v;
-            }
-            __syncthreads();
+            block_inv_apply<NBM, false>(Lb, y + k0, nb, part, tid);  // y_b <- Linv y_b
             if constexpr (NBM <= 32) {  // rows below, two per thread and trip: both rows in flight
                 for (int i = k1 + tid; i < f; i += 512) {
                     const double* Li = F + i + (int64_t)k0 * ld;
@@ -1527,8 +1565,9 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
         if (active && !active[r]) continue;
         double* xw = S.xw + (int64_t)r * D.N;
         const int nblk = (p + 63) / 64;
-        BlockRegs<NBM> bl;  // the last diagonal block, loaded along with y
-        load_block<NBM>(bl, F, ld, (nblk - 1) * 64, p - (nblk - 1) * 64, tid);
+        const double* Linv = D.linv + D.inv_off[s];
+        BlockRegs<NBM> bl;  // the last diagonal block's inverse, loaded along with y
+        load_inv<NBM>(bl, Linv + 4096 * (nblk - 1), p - (nblk - 1) * 64, tid);
         for (int ib = 0; ib < f; ib += 1024) {  // four rows per thread and trip
             int src[4];
 #pragma unroll
@@ -1547,7 +1586,11 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
         __syncthreads();
         for (int bk = nblk - 1; bk >= 0; --bk) {
             const int k0 = bk * 64, k1 = min(k0 + 64, p), nb = k1 - k0;
-            if (bk < nblk - 1) stage_block<NBM>(Lb, F, ld, k0, nb, tid);
+            if (bk < nblk - 1) {
+                BlockRegs<NBM> bb;
+                load_inv<NBM>(bb, Linv + 4096 * bk, nb, tid);
+                store_block<NBM>(Lb, bb, tid);  // read only after the barriers below
+            }
             {  // rows below the block, sum_i L(i, k) y_i: tiles of 64 rows loaded coalesced
                // (lane = row; the next tile in flight while the current one is summed through
                // LDS by thread (column = lane, rows wv, wv + 4, ...))
@@ -1584,13 +1627,9 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
                 part[wv * 64 + lane] = acc;
             }
             __syncthreads();
-            if (tid < 64) {
-                double v = 0.0;
-                if (tid < nb) v = y[k0 + tid] - (((part[tid] + part[64 + tid]) + part[128 + tid]) + part[192 + tid]);
-                v = trsv_bwd_wave<NBM>(Lb, v, tid);
-                if (tid < nb) y[k0 + tid] = v;
-            }
+            if (tid < nb) y[k0 + tid] -= ((part[tid] + part[64 + tid]) + part[128 + tid]) + part[192 + tid];
             __syncthreads();
+            block_inv_apply<NBM, true>(Lb, y + k0, nb, part, tid);  // y_b <- Linv^T y_b
         }
         for (int k = tid; k < p; k += 256) xw[c0 + D.lperm[c0 + k]] = y[k];
         __syncthreads();
@@ -1831,7 +1870,8 @@ __global__ __launch_bounds__(256) void k_fwd(DevPlan D, DevSolve S, const int32_
                                              const int32_t* active) {
     extern __shared__ double dyn[];
     __shared__ double Lb[NBM * (NBM + 1)];
-    fwd_supernode<NBM>(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb);
+    __shared__ double part[256];
+    fwd_supernode<NBM>(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb, part);
 }
 
 template <int NBM>
@@ -1842,6 +1882,53 @@ __global__ __launch_bounds__(256) void k_bwd(DevPlan D, DevSolve S, const int32_
     __shared__ double part[4 * 64];
     __shared__ double Lt[NBM * 65];
     bwd_supernode<NBM>(D, S, lvl_sn[base + blockIdx.x], active, dyn, Lb, part, Lt);
+}
+
+// Inverse of one unit lower diagonal block (64 pivots) of L, for the one-workgroup solves:
+// one wavefront, lane c computes column c of the inverse by forward substitution with the
+// block in LDS (every lane reads the same entry: broadcast), four partial sums per row.
+__global__ __launch_bounds__(64) void k_inv(DevPlan D, const Task* tasks) {
+    __shared__ double Ls[64 * 65];  // Ls[k * 65 + j] = L(k, j), strictly lower, zero elsewhere
+    const Task t = tasks[blockIdx.x];
+    const int s = t.s, k0 = 64 * t.k0, lane = threadIdx.x;
+    const int p = D.sn_p[s], ld = D.sn_ld[s];
+    const int nb = min(64, p - k0);
+    const double* F = D.front + D.sn_off[s] + k0 + (int64_t)k0 * ld;
+    for (int j0 = 0; j0 < 64; j0 += 8) {  // column j of the block, lane = row; eight in flight
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u;
+            v[u] = (lane < nb && j < nb && lane > j) ? F[lane + (int64_t)j * ld] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Ls[lane * 65 + j0 + u] = v[u];
+    }
+    __syncthreads();
+    const int c = lane;
+    double x[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+        double a0 = k == c ? 1.0 : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (k < nb) {
+#pragma unroll
+            for (int j = 0; j + 3 < k; j += 4) {
+                a0 -= Ls[k * 65 + j] * x[j];
+                a1 -= Ls[k * 65 + j + 1] * x[j + 1];
+                a2 -= Ls[k * 65 + j + 2] * x[j + 2];
+                a3 -= Ls[k * 65 + j + 3] * x[j + 3];
+            }
+#pragma unroll
+            for (int j = k & ~3; j < k; ++j) a0 -= Ls[k * 65 + j] * x[j];
+        }
+        x[k] = (a0 + a1) + (a2 + a3);
+    }
+    double* out = D.linv + D.inv_off[s] + 4096 * (int64_t)t.k0;
+    if (c < nb) {
+#pragma unroll
+        for (int k = 0; k < 64; ++k)
+            if (k < nb) out[k + (int64_t)c * nb] = k >= c ? x[k] : 0.0;
+    }
 }
 
 // Levels whose fronts all have f <= 64: one wavefront per supernode, four per workgroup.
@@ -2342,6 +2429,10 @@ void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const
         else QDMF_SOLVE_LAUNCH(k_bwd, 64);
     }
 #undef QDMF_SOLVE_LAUNCH
+}
+
+void launch_inv(const DevPlan& D, const Task* tasks, int64_t ntask, hipStream_t s) {
+    if (ntask > 0) hipLaunchKernelGGL(k_inv, dim3((unsigned)ntask), dim3(64), 0, s, D, tasks);
 }
 
 void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L, const Task* stasks,

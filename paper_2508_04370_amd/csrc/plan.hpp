@@ -119,6 +119,13 @@ struct Plan {
     std::vector<int64_t> fwd_ptr, bwd_ptr;  // per level: its range of fwd_plan / bwd_plan
     std::vector<SolveLaunch> fwd_plan, bwd_plan;
     std::vector<int64_t> yoff;          // per supernode: rows in the solve work space (big only)
+    // Inverses of the unit lower diagonal blocks (64 pivots each) of the supernodes that the
+    // one-workgroup solve kernels handle: block j of supernode s is nb x nb, column-major, at
+    // inv_off[s] + 4096 j (nb = 64 but for the last block); -1 where none.  One task
+    // {s, j} per block.
+    std::vector<int64_t> inv_off;
+    int64_t inv_total = 0;
+    std::vector<Task> inv_tasks;
     int64_t ytotal = 0;
     int64_t ppart_max = 0;              // most partial sums of one S_BPART launch
 
