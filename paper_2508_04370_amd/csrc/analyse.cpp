@@ -832,13 +832,17 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     }
 
     // ----- inverses of the diagonal blocks for the levels solved by the one-workgroup kernels
-    // (levels whose fronts are all at most 64 rows use one wavefront per supernode instead)
+    // with blocks of more than 8 pivots (levels whose fronts are all at most 64 rows use one
+    // wavefront per supernode instead, and blocks of up to 8 pivots a short serial sweep)
     P.inv_off.assign(ns, -1);
     P.inv_total = 0;
     for (int32_t l = 0; l < P.nlevels; ++l) {
-        int32_t mf = 0;
-        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) mf = std::max(mf, P.sn_f[P.lvl_sn[q]]);
-        if (mf <= 64) continue;
+        int32_t mf = 0, mp = 0;
+        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) {
+            mf = std::max(mf, P.sn_f[P.lvl_sn[q]]);
+            mp = std::max(mp, P.sn_p[P.lvl_sn[q]]);
+        }
+        if (mf <= 64 || mp <= 8) continue;
         for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) {
             const int32_t t = P.lvl_sn[q], p = P.sn_p[t], nblk = (p + 63) / 64, nbl = p - 64 * (nblk - 1);
             P.inv_off[t] = P.inv_total;

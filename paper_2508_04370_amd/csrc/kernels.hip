@@ -1445,9 +1445,13 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
     for (int r = 0; r < S.nrhs; ++r) {
         if (active && !active[r]) continue;
         double* xw = S.xw + (int64_t)r * D.N;
-        const double* Linv = D.linv + D.inv_off[s];
-        BlockRegs<NBM> b0;  // the first diagonal block's inverse, loaded along with the gather
-        load_inv<NBM>(b0, Linv, min(64, p), tid);
+        // blocks of more than 8 pivots are solved with their precomputed inverse, smaller ones
+        // by a serial sweep in one wavefront
+        constexpr bool INV = NBM > 8;
+        const double* Linv = INV ? D.linv + D.inv_off[s] : nullptr;
+        BlockRegs<NBM> b0;  // the first diagonal block (or its inverse), loaded along with the gather
+        if constexpr (INV) load_inv<NBM>(b0, Linv, min(64, p), tid);
+        else load_block<NBM>(b0, F, ld, 0, min(64, p), tid);
         {  // front row t (pre-pivot numbering): own entry plus the children's contributions
            // in ascending child order; pivot rows moved in factorisation (lpinv).  Four rows
            // per thread and trip, so that their loads are in flight together.
@@ -1492,11 +1496,21 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
             const int k1 = min(k0 + 64, p), nb = k1 - k0;
             if (k0 > 0) {
                 BlockRegs<NBM> bk;
-                load_inv<NBM>(bk, Linv + 4096 * (k0 / 64), nb, tid);
+                if constexpr (INV) load_inv<NBM>(bk, Linv + 4096 * (k0 / 64), nb, tid);
+                else load_block<NBM>(bk, F, ld, k0, nb, tid);
                 store_block<NBM>(Lb, bk, tid);
                 __syncthreads();
             }
-            block_inv_apply<NBM, false>(Lb, y + k0, nb, part, tid);  // y_b <- Linv y_b
+            if constexpr (INV) {
+                block_inv_apply<NBM, false>(Lb, y + k0, nb, part, tid);  // y_b <- Linv y_b
+            } else {
+                if (tid < 64) {
+                    const double y0 = tid < nb ? y[k0 + tid] : 0.0;
+                    const double v = trsv_fwd_wave<NBM>(Lb, y0, tid);
+                    if (tid < nb) y[k0 + tid] = v;
+                }
+                __syncthreads();
+            }
             if constexpr (NBM <= 32) {  // rows below, two per thread and trip: both rows in flight
                 for (int i = k1 + tid; i < f; i += 512) {
                     const double* Li = F + i + (int64_t)k0 * ld;
@@ -1565,9 +1579,11 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
         if (active && !active[r]) continue;
         double* xw = S.xw + (int64_t)r * D.N;
         const int nblk = (p + 63) / 64;
-        const double* Linv = D.linv + D.inv_off[s];
-        BlockRegs<NBM> bl;  // the last diagonal block's inverse, loaded along with y
-        load_inv<NBM>(bl, Linv + 4096 * (nblk - 1), p - (nblk - 1) * 64, tid);
+        constexpr bool INV = NBM > 8;
+        const double* Linv = INV ? D.linv + D.inv_off[s] : nullptr;
+        BlockRegs<NBM> bl;  // the last diagonal block (or its inverse), loaded along with y
+        if constexpr (INV) load_inv<NBM>(bl, Linv + 4096 * (nblk - 1), p - (nblk - 1) * 64, tid);
+        else load_block<NBM>(bl, F, ld, (nblk - 1) * 64, p - (nblk - 1) * 64, tid);
         for (int ib = 0; ib < f; ib += 1024) {  // four rows per thread and trip
             int src[4];
 #pragma unroll
@@ -1588,7 +1604,8 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
             const int k0 = bk * 64, k1 = min(k0 + 64, p), nb = k1 - k0;
             if (bk < nblk - 1) {
                 BlockRegs<NBM> bb;
-                load_inv<NBM>(bb, Linv + 4096 * bk, nb, tid);
+                if constexpr (INV) load_inv<NBM>(bb, Linv + 4096 * bk, nb, tid);
+                else load_block<NBM>(bb, F, ld, k0, nb, tid);
                 store_block<NBM>(Lb, bb, tid);  // read only after the barriers below
             }
             {  // rows below the block, sum_i L(i, k) y_i: tiles of 64 rows loaded coalesced
@@ -1627,9 +1644,19 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
                 part[wv * 64 + lane] = acc;
             }
             __syncthreads();
-            if (tid < nb) y[k0 + tid] -= ((part[tid] + part[64 + tid]) + part[128 + tid]) + part[192 + tid];
-            __syncthreads();
-            block_inv_apply<NBM, true>(Lb, y + k0, nb, part, tid);  // y_b <- Linv^T y_b
+            if constexpr (INV) {
+                if (tid < nb) y[k0 + tid] -= ((part[tid] + part[64 + tid]) + part[128 + tid]) + part[192 + tid];
+                __syncthreads();
+                block_inv_apply<NBM, true>(Lb, y + k0, nb, part, tid);  // y_b <- Linv^T y_b
+            } else {
+                if (tid < 64) {
+                    double v = 0.0;
+                    if (tid < nb) v = y[k0 + tid] - (((part[tid] + part[64 + tid]) + part[128 + tid]) + part[192 + tid]);
+                    v = trsv_bwd_wave<NBM>(Lb, v, tid);
+                    if (tid < nb) y[k0 + tid] = v;
+                }
+                __syncthreads();
+            }
         }
         for (int k = tid; k < p; k += 256) xw[c0 + D.lperm[c0 + k]] = y[k];
         __syncthreads();
