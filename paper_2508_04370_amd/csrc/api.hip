@@ -288,7 +288,7 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     if ((rc = dalloc(h, h->solve_allocs, &S.d, N * nrhs))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.xw, N * nrhs))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.ub, std::max<int64_t>(1, h->P.ub_total) * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.part, (int64_t)3 * S.nblk * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.part, (int64_t)4 * S.nblk * nrhs))) return rc;
     const int64_t units = (int64_t)nrhs * h->P.nsys;
     if ((rc = dalloc(h, h->solve_allocs, &S.berr, 4 * units))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.active, units))) return rc;

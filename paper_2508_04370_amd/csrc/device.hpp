@@ -131,7 +131,7 @@ struct DevSolve {
     double* d;      // correction, N x nrhs
     double* xw;     // permuted work vector, N x nrhs
     double* ub;     // contribution buffers, ub_total x nrhs
-    double* part;   // per-block partial maxima: 3 x nblk x nrhs
+    double* part;   // per-block partial maxima: |r|, |x|, |b| (3 x nblk x nrhs), then componentwise ratios (nblk x nrhs)
     int32_t nblk;
     // refinement state per unit u = rhs * nsys + system
     double* berr;     // per unit: [nw, cw, nw_initial, unused]

@@ -2118,6 +2118,33 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const d
     if (threadIdx.x < 3) S.part[(int64_t)r * 3 * S.nblk + threadIdx.x * S.nblk + blockIdx.x] = red[threadIdx.x][0];
 }
 
+// The refinement decision of unit u (system, rhs) from its new backward errors: record them,
+// count the step, and keep refining while the target is not met, the error still halves and
+// steps remain; a step that does not improve is undone (returns 1: restore the previous x).
+__device__ inline int berr_decide(DevSolve& S, int u, int phase, double nw, double cw, double target,
+                                  int max_steps) {
+    double* be = S.berr + 4 * u;
+    if (phase == 0) {
+        be[0] = nw;
+        be[1] = cw;
+        be[2] = nw;
+        S.steps[u] = 0;
+        S.active[u] = (nw > target && max_steps > 0) ? 1 : 0;
+        return 0;
+    }
+    const double prev = be[0];
+    S.steps[u] += 1;
+    if (!(nw < prev)) {  // no improvement: keep the previous iterate
+        S.active[u] = 0;
+        return 1;
+    }
+    const bool stagnating = nw > 0.5 * prev;
+    be[0] = nw;
+    be[1] = cw;
+    S.active[u] = (!stagnating && nw > target && S.steps[u] < max_steps) ? 1 : 0;
+    return 0;
+}
+
 // Backward errors (normwise in the infinity norm; componentwise with the small-denominator
 // substitution of Arioli, Demmel and Duff) and the refinement decision for each rhs.
 // phase 0: after the first solve; phase 1: after a refinement step.
@@ -2168,37 +2195,78 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
     const double cw = red[3][0];
     const double den = D.knorm_sys[q] * xmax + bmax;
     const double nw = den > 0 ? rmax / den : (rmax == 0 ? 0.0 : INFINITY);
-    double* be = S.berr + 4 * u;
     __shared__ int restore;
-    if (threadIdx.x == 0) {
-        restore = 0;
-        if (phase == 0) {
-            be[0] = nw;
-            be[1] = cw;
-            be[2] = nw;
-            S.steps[u] = 0;
-            S.active[u] = (nw > target && max_steps > 0) ? 1 : 0;
-        } else {
-            const double prev = be[0];
-            if (!(nw < prev)) {  // no improvement: keep the previous iterate
-                restore = 1;
-                S.active[u] = 0;
-                S.steps[u] += 1;
-            } else {
-                S.steps[u] += 1;
-                const bool stagnating = nw > 0.5 * prev;
-                be[0] = nw;
-                be[1] = cw;
-                S.active[u] = (!stagnating && nw > target && S.steps[u] < max_steps) ? 1 : 0;
-            }
-        }
-    }
+    if (threadIdx.x == 0) restore = berr_decide(S, u, phase, nw, cw, target, max_steps);
     __syncthreads();
     if (restore) {
         double* xw = S.x + (int64_t)r * D.N;
         const double* xb = S.xbak + (int64_t)r * D.N;
         for (int part = 0; part < 2; ++part)
             for (int64_t i = rg[2 * part] + threadIdx.x; i < rg[2 * part + 1]; i += 1024) xw[i] = xb[i];
+    }
+}
+
+// One system (nsys == 1) over many workgroups: the maxima of |r|, |x| and |b| come from the
+// residual kernel's per-block partials; each workgroup takes the componentwise ratio over its
+// 256 rows (section 3 of the partials), and one workgroup per rhs combines and decides.
+__device__ inline double block_max256(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double m = red[0];
+    __syncthreads();
+    return m;
+}
+
+__global__ __launch_bounds__(256) void k_berr_cw(DevPlan D, DevSolve S, int phase) {
+    __shared__ double red[256];
+    const int r = blockIdx.y;
+    if (phase == 1 && !S.active[r]) return;
+    const double* px = S.part + (int64_t)r * 3 * S.nblk + S.nblk;  // per-block max |x|
+    double m = 0.0;
+    for (int j = threadIdx.x; j < S.nblk; j += 256) m = fmax(m, px[j]);
+    const double xmax = block_max256(m, red);
+    const double u64 = 1.1102230246251565e-16;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double c = 0.0;
+    if (i < D.N) {
+        const double rr = S.r[i + (int64_t)r * D.N], bi = fabs(S.b[i + (int64_t)r * D.N]);
+        const double akx = S.d[i + (int64_t)r * D.N];
+        double den = akx + bi;
+        if (den <= 1000.0 * D.N * u64 * (D.rowsum[i] * xmax + bi)) den = akx + xmax * D.rowsum[i];
+        c = den > 0 ? fabs(rr) / den : (rr == 0 ? 0.0 : INFINITY);
+    }
+    const double cm = block_max256(c, red);
+    if (threadIdx.x == 0) S.part[(int64_t)3 * S.nblk * S.nrhs + (int64_t)r * S.nblk + blockIdx.x] = cm;
+}
+
+__global__ __launch_bounds__(256) void k_berr_fin(DevPlan D, DevSolve S, int phase, double target, int max_steps) {
+    __shared__ double red[256];
+    __shared__ int restore;
+    const int r = blockIdx.x;
+    if (phase == 1 && !S.active[r]) return;
+    const double* pr = S.part + (int64_t)r * 3 * S.nblk;
+    const double* pc = S.part + (int64_t)3 * S.nblk * S.nrhs + (int64_t)r * S.nblk;
+    double mr = 0.0, mx = 0.0, mb = 0.0, mc = 0.0;
+    for (int j = threadIdx.x; j < S.nblk; j += 256) {
+        mr = fmax(mr, pr[j]);
+        mx = fmax(mx, pr[S.nblk + j]);
+        mb = fmax(mb, pr[2 * S.nblk + j]);
+        mc = fmax(mc, pc[j]);
+    }
+    const double rmax = block_max256(mr, red), xmax = block_max256(mx, red);
+    const double bmax = block_max256(mb, red), cw = block_max256(mc, red);
+    const double den = D.knorm_sys[0] * xmax + bmax;
+    const double nw = den > 0 ? rmax / den : (rmax == 0 ? 0.0 : INFINITY);
+    if (threadIdx.x == 0) restore = berr_decide(S, r, phase, nw, cw, target, max_steps);
+    __syncthreads();
+    if (restore) {
+        double* xw = S.x + (int64_t)r * D.N;
+        const double* xb = S.xbak + (int64_t)r * D.N;
+        for (int64_t i = threadIdx.x; i < D.N; i += 256) xw[i] = xb[i];
     }
 }
 
@@ -2484,8 +2552,13 @@ void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipSt
 
 void launch_berr_steps(const DevPlan& D, const DevSolve& S, int32_t phase, double target, int max_steps,
                        hipStream_t s) {
+    if (D.nsys == 1) {
+        hipLaunchKernelGGL(k_berr_cw, dim3(S.nblk, S.nrhs), dim3(256), 0, s, D, S, phase);
+        hipLaunchKernelGGL(k_berr_fin, dim3(S.nrhs), dim3(256), 0, s, D, S, phase, target, max_steps);
+        return;
+    }
     hipLaunchKernelGGL(k_berr, dim3(D.nsys, S.nrhs), dim3(1024), 0, s, D, S, phase, target, max_steps);
-    if (D.nsys > 1) hipLaunchKernelGGL(k_any_active, dim3(S.nrhs), dim3(256), 0, s, D, S);
+    hipLaunchKernelGGL(k_any_active, dim3(S.nrhs), dim3(256), 0, s, D, S);
 }
 
 void launch_refine_begin(const DevPlan& D, const DevSolve& S, hipStream_t s) {
