@@ -988,7 +988,17 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         for (int32_t t : large)
             for (int32_t c = 0; c < P.sn_nwin[t]; ++c)
                 for (int32_t w = c; w < P.sn_nwin[t]; ++w) P.tasks.push_back(Task{t, c * NB, w, 0});
-        add_launch(L_FINALIZE, l, t0, 0, 0);
+        // The level's last trailing update touches only rows and columns past every pivot of
+        // its fronts, and the finalize tasks only pivot rows and columns: both run in one
+        // launch when there is such an update.
+        if (!P.launches.empty() && P.launches.back().kind == L_SYRK && P.launches.back().level == l) {
+            Launch& L = P.launches.back();
+            L.fin0 = t0;
+            L.nfin = (int64_t)P.tasks.size() - t0;
+            for (int64_t q = t0; q < t0 + L.nfin; ++q) task_work(L_FINALIZE, 0, P.tasks[q], L.flops, L.bytes);
+        } else {
+            add_launch(L_FINALIZE, l, t0, 0, 0);
+        }
     }
     return 0;
 }

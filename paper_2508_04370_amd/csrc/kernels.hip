@@ -983,44 +983,13 @@ __device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int
     }
 }
 
-__global__ __launch_bounds__(256) void k_syrk(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp) {
-    __shared__ double As[64 * LDT];
-    __shared__ double Bs[64 * LDT];
-    __shared__ double dd[64], od[64];
-    __shared__ int pt[64];
-    const Task t = tasks[t0 + blockIdx.x];
-    const int s = t.s, k0 = t.k0;
-    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
-    const int k1 = min(k0 + NB, p), nbw = k1 - k0;
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        if (tid < nbw) {
-            dd[tid] = D.dval[c0 + k0 + tid];
-            od[tid] = D.doff[c0 + k0 + tid];
-            pt[tid] = D.ptype[c0 + k0 + tid];
-        } else {
-            dd[tid] = 0.0;
-            od[tid] = 0.0;
-            pt[tid] = 0;
-        }
-    }
-    __syncthreads();
-    double* F = D.front + D.sn_off[s];
-    const int R0 = k1 + 64 * t.a, C0 = k1 + 64 * t.b;
-    if (pp.mixed && f >= pp.f_mix)
-        syrk_tile<float>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, (float*)As, (float*)Bs);
-    else
-        syrk_tile<double>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, As, Bs);
-}
-
 // After all windows of a front: one task per (pivot window c, window w >= c).  w == c moves
 // the window's factored diagonal block from the upper triangle into place; w > c permutes
 // the rows of window w inside the 64 columns of window c as window w's pivot interchanges
 // require.  Wave v handles columns 16v .. 16v+15, lane = row; each wave loads all of its
 // values before it stores any, so no barrier is needed.
-__global__ __launch_bounds__(256) void k_finalize(DevPlan D, const Task* tasks, int64_t t0) {
+__device__ inline void finalize_task(const DevPlan& D, const Task t) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const Task t = tasks[t0 + blockIdx.x];
     const int s = t.s, kc = t.k0, w = t.a;
     const int p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const int ncol = min(NB, p - kc);
@@ -1051,6 +1020,48 @@ __global__ __launch_bounds__(256) void k_finalize(DevPlan D, const Task* tasks, 
             if (j < ncol && lane < nbw) F[(k0 + lane) + (int64_t)(kc + j) * ld] = v[q];
         }
     }
+}
+
+// Tiles of the trailing update; workgroups past the first nsy take the level's finalize tasks
+// from fin0 on (a launch may hold both: they touch disjoint parts of the fronts).
+__global__ __launch_bounds__(256) void k_syrk(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp,
+                                              int64_t nsy, int64_t fin0) {
+    if ((int64_t)blockIdx.x >= nsy) {
+        finalize_task(D, tasks[fin0 + (int64_t)blockIdx.x - nsy]);
+        return;
+    }
+    __shared__ double As[64 * LDT];
+    __shared__ double Bs[64 * LDT];
+    __shared__ double dd[64], od[64];
+    __shared__ int pt[64];
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, k0 = t.k0;
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
+    const int k1 = min(k0 + NB, p), nbw = k1 - k0;
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        if (tid < nbw) {
+            dd[tid] = D.dval[c0 + k0 + tid];
+            od[tid] = D.doff[c0 + k0 + tid];
+            pt[tid] = D.ptype[c0 + k0 + tid];
+        } else {
+            dd[tid] = 0.0;
+            od[tid] = 0.0;
+            pt[tid] = 0;
+        }
+    }
+    __syncthreads();
+    double* F = D.front + D.sn_off[s];
+    const int R0 = k1 + 64 * t.a, C0 = k1 + 64 * t.b;
+    if (pp.mixed && f >= pp.f_mix)
+        syrk_tile<float>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, (float*)As, (float*)Bs);
+    else
+        syrk_tile<double>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, As, Bs);
+}
+
+
+__global__ __launch_bounds__(256) void k_finalize(DevPlan D, const Task* tasks, int64_t t0) {
+    finalize_task(D, tasks[t0 + blockIdx.x]);
 }
 
 // ---------------------------------------------------------------- values of K
@@ -1166,7 +1177,7 @@ __global__ void k_matrix_norms(DevPlan D) {
 // fixed-order sum (k_factor_stats_final).  Partial q of block g: part[g * 10 + q], the eight
 // counts (negative, positive, zero, 2x2, lifts, Proposition 3, sign rule, zero-skips), the
 // largest |E_dyn| and whether some |E_dyn| exceeds tau_big ||K||_1.
-constexpr int FS_PER_BLOCK = 4096;
+constexpr int FS_PER_BLOCK = 512;
 
 __global__ __launch_bounds__(256) void k_factor_stats(DevPlan D, PivotParams pp, double* part) {
     __shared__ double red[10][256];
@@ -1213,12 +1224,22 @@ __global__ __launch_bounds__(256) void k_factor_stats(DevPlan D, PivotParams pp,
     if (threadIdx.x < 10) part[blockIdx.x * 10 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Combines the per-block partials: counts are integers held exactly in doubles and the others
+// are maxima, so the result does not depend on the order of combination.
 __global__ __launch_bounds__(64) void k_factor_stats_final(DevPlan D, const double* part, int nblk) {
-    if (threadIdx.x != 0) return;
+    __shared__ double red[10][64];
     double t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int g = 0; g < nblk; ++g) {
+    for (int g = threadIdx.x; g < nblk; g += 64) {
         for (int q = 0; q < 8; ++q) t[q] += part[g * 10 + q];
         for (int q = 8; q < 10; ++q) t[q] = fmax(t[q], part[g * 10 + q]);
+    }
+    for (int q = 0; q < 10; ++q) red[q][threadIdx.x] = t[q];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int q = 0; q < 10; ++q) t[q] = red[q][0];
+    for (int g = 1; g < 64; ++g) {
+        for (int q = 0; q < 8; ++q) t[q] += red[q][g];
+        for (int q = 8; q < 10; ++q) t[q] = fmax(t[q], red[q][g]);
     }
     DevStats* st = D.st;
     st->nneg = (int64_t)t[0];
@@ -2437,7 +2458,10 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
                 default: hipLaunchKernelGGL(k_window<3>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
             }
             break;
-        case L_SYRK: hipLaunchKernelGGL(k_syrk, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
+        case L_SYRK:
+            hipLaunchKernelGGL(k_syrk, dim3((unsigned)(L.ntask + L.nfin)), dim3(256), 0, s, D, tasks, L.task0, pp,
+                               L.ntask, L.fin0);
+            break;
         case L_FINALIZE: hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, D, tasks, L.task0); break;
         default: break;
     }
