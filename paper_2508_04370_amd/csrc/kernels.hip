@@ -1463,6 +1463,31 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const double* F = D.front + D.sn_off[s];
     const int tid = threadIdx.x;
+    // Values that do not depend on the right-hand side, loaded before anything waits: the first
+    // trip of rows below the first block (RT rows per thread), and D of pivot tid.
+    // (with NBM = 64 the prefetched rows would not fit in registers beside the rest)
+    constexpr int RT = NBM <= 32 ? 2 : 1;
+    constexpr bool PF = NBM <= 32;
+    const int k1f = min(64, p), nbf = k1f;
+    double lr[RT][PF ? NBM : 1];
+    if constexpr (PF) {
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+            const int i = k1f + tid + 256 * u;
+#pragma unroll
+            for (int k = 0; k < NBM; ++k) lr[u][k] = (i < f && k < nbf) ? F[i + (int64_t)k * ld] : 0.0;
+        }
+    }
+    int d_ty = 0, d_perm = 0;
+    double d_a = 1.0, d_b = 0.0, d_c = 1.0;
+    if (tid < p) {
+        d_ty = D.ptype[c0 + tid];
+        d_perm = D.lperm[c0 + tid];
+        const int k2 = d_ty == 2 ? tid - 1 : tid;
+        d_a = D.dval[c0 + k2];
+        d_b = d_ty ? D.doff[c0 + k2] : 0.0;
+        d_c = d_ty ? D.dval[c0 + k2 + 1] : 1.0;
+    }
     for (int r = 0; r < S.nrhs; ++r) {
         if (active && !active[r]) continue;
         double* xw = S.xw + (int64_t)r * D.N;
@@ -1532,56 +1557,62 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
                 }
                 __syncthreads();
             }
-            if constexpr (NBM <= 32) {  // rows below, two per thread and trip: both rows in flight
-                for (int i = k1 + tid; i < f; i += 512) {
-                    const double* Li = F + i + (int64_t)k0 * ld;
-                    const bool two = i + 256 < f;
-                    double la[NBM], lc[NBM];
+            // rows below: RT rows per thread and trip, their loads in flight together; the
+            // first block's first trip uses the rows loaded at the start
+            for (int i = k1 + tid; i < f; i += 256 * RT) {
+                double la[RT][NBM];
+                if (PF && k0 == 0 && i == k1 + tid) {
 #pragma unroll
-                    for (int k = 0; k < NBM; ++k) {
-                        la[k] = k < nb ? Li[(int64_t)k * ld] : 0.0;
-                        lc[k] = (two && k < nb) ? Li[256 + (int64_t)k * ld] : 0.0;
-                    }
-                    double a0 = 0.0, a1 = 0.0, c0s = 0.0, c1s = 0.0;
+                    for (int u = 0; u < RT; ++u)
 #pragma unroll
-                    for (int k = 0; k < NBM; k += 2) {
-                        const double y0 = k < nb ? y[k0 + k] : 0.0, y1 = k + 1 < nb ? y[k0 + k + 1] : 0.0;
-                        if (k < nb) {
-                            a0 += la[k] * y0;
-                            c0s += lc[k] * y0;
-                        }
-                        if (k + 1 < nb) {
-                            a1 += la[k + 1] * y1;
-                            c1s += lc[k + 1] * y1;
-                        }
+                        for (int k = 0; k < NBM; ++k) la[u][k] = lr[u][PF ? k : 0];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < RT; ++u) {
+                        const double* Li = F + i + 256 * u + (int64_t)k0 * ld;
+                        const bool on = i + 256 * u < f;
+#pragma unroll
+                        for (int k = 0; k < NBM; ++k) la[u][k] = (on && k < nb) ? Li[(int64_t)k * ld] : 0.0;
                     }
-                    y[i] -= a0 + a1;
-                    if (two) y[i + 256] -= c0s + c1s;
                 }
-            } else {
-                for (int i = k1 + tid; i < f; i += 256) {  // rows below: a whole row of the block in flight
-                    const double* Li = F + i + (int64_t)k0 * ld;
-                    const double* yk = y + k0;
-                    const double dlt = gemv_row<NBM>(Li, ld, nb, yk);
-                    y[i] -= dlt;
+                double a0[RT], a1[RT];
+#pragma unroll
+                for (int u = 0; u < RT; ++u) a0[u] = a1[u] = 0.0;
+#pragma unroll
+                for (int k = 0; k < NBM; k += 2) {
+                    const double y0 = k < nb ? y[k0 + k] : 0.0, y1 = k + 1 < nb ? y[k0 + k + 1] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < RT; ++u) {
+                        if (k < nb) a0[u] += la[u][k] * y0;
+                        if (k + 1 < nb) a1[u] += la[u][k + 1] * y1;
+                    }
                 }
+#pragma unroll
+                for (int u = 0; u < RT; ++u)
+                    if (i + 256 * u < f) y[i + 256 * u] -= a0[u] + a1[u];
             }
             __syncthreads();
         }
         double* u = S.ub + D.ub_off[s] + (int64_t)r * D.ub_total;
         for (int i = p + tid; i < f; i += 256) u[i - p] = y[i];
         for (int k = tid; k < p; k += 256) {  // block-diagonal D
-            const int ty = D.ptype[c0 + k];
-            double v;
-            if (ty == 0) v = y[k] / D.dval[c0 + k];
-            else if (ty == 1) {
-                const double a = D.dval[c0 + k], b = D.doff[c0 + k], c = D.dval[c0 + k + 1];
-                v = (c * y[k] - b * y[k + 1]) / (a * c - b * b);
+            int ty, perm;
+            double a, b, c;
+            if (k == tid) {
+                ty = d_ty, perm = d_perm, a = d_a, b = d_b, c = d_c;
             } else {
-                const double a = D.dval[c0 + k - 1], b = D.doff[c0 + k - 1], c = D.dval[c0 + k];
-                v = (a * y[k] - b * y[k - 1]) / (a * c - b * b);
+                ty = D.ptype[c0 + k];
+                perm = D.lperm[c0 + k];
+                const int k2 = ty == 2 ? k - 1 : k;
+                a = D.dval[c0 + k2];
+                b = ty ? D.doff[c0 + k2] : 0.0;
+                c = ty ? D.dval[c0 + k2 + 1] : 1.0;
             }
-            xw[c0 + D.lperm[c0 + k]] = v;
+            double v;
+            if (ty == 0) v = y[k] / a;
+            else if (ty == 1) v = (c * y[k] - b * y[k + 1]) / (a * c - b * b);
+            else v = (a * y[k] - b * y[k - 1]) / (a * c - b * b);
+            xw[c0 + perm] = v;
         }
         __syncthreads();
     }
