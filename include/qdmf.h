@@ -248,6 +248,28 @@ int qdmf_profile_kind(qdmf_handle h, int32_t kind);
 int qdmf_profile_read(qdmf_handle h, int64_t* launches, double* total_ms, double* flops,
                       double* bytes);
 
+/* Choice between the normal equations and the augmented system for the pattern of A
+ * (Section 4.2: both can be analysed and the better taken, the augmented system first, and
+ * the normal equations given up as soon as forming their pattern would hold more entries than
+ * the augmented system's factor; Section 1: dense columns rule the normal equations out).
+ * A column is dense when it holds at least max(64, ceil(m / 10)) entries.  When the normal
+ * equations survive, both are analysed with the handle's options and the one with fewer
+ * predicted factorisation flops is chosen (ties: NE).  Host only; the handle's own analysis
+ * is not changed.  Inputs as for qdmf_analyse.  Errors: QDMF_ERR_INVALID_ARG,
+ * QDMF_ERR_INDEX_OVERFLOW, QDMF_ERR_UNSUPPORTED. */
+typedef struct {
+    int32_t mode;             /* QDMF_NE or QDMF_AS                                          */
+    int32_t ndense;           /* dense columns of A                                          */
+    int32_t ne_abandoned;     /* 1: the normal equations were given up before their analysis  */
+    int64_t nnz_l_as;         /* nnz(L) of the augmented system                              */
+    int64_t nnz_ne_pattern;   /* lower entries (with the diagonal) of the pattern of A A^T,
+                                 counted up to the point where it was given up               */
+    int64_t nnz_l_ne;         /* nnz(L) of the normal equations, -1 if not analysed           */
+    double flops_as, flops_ne; /* predicted factorisation flops; flops_ne -1 if not analysed */
+} qdmf_mode_choice;
+int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
+                     const int32_t* rowidx, qdmf_mode_choice* out);
+
 /* Frees everything the handle owns.  NULL is ignored. */
 void qdmf_destroy(qdmf_handle h);
 

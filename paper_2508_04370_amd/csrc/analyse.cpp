@@ -264,6 +264,38 @@ int32_t find_pos(const int32_t* rows, int32_t c0, int32_t p, int32_t f, int32_t 
 
 }  // namespace
 
+int64_t ne_pattern_count(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx, int64_t limit) {
+    // rows of A as lists of columns
+    std::vector<int64_t> rp(m + 1, 0);
+    for (int64_t e = 0; e < colptr[n]; ++e) rp[rowidx[e] + 1]++;
+    for (int32_t i = 0; i < m; ++i) rp[i + 1] += rp[i];
+    std::vector<int32_t> rc(colptr[n]);
+    {
+        std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) rc[fill[rowidx[e]]++] = j;
+    }
+    std::vector<int32_t> mark(m, -1);
+    int64_t count = 0;
+    for (int32_t i = 0; i < m; ++i) {  // row i of the lower triangle: rows k <= i sharing a column
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+            const int32_t j = rc[q];
+            for (int64_t e = colptr[j]; e < colptr[j + 1] && rowidx[e] <= i; ++e) {
+                const int32_t k = rowidx[e];
+                if (mark[k] != i) {
+                    mark[k] = i;
+                    if (++count > limit) return count;
+                }
+            }
+        }
+        if (mark[i] != i) {  // the diagonal (delta > 0) even for an empty row
+            mark[i] = i;
+            if (++count > limit) return count;
+        }
+    }
+    return count;
+}
+
 int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx, int32_t mode,
                const AnalyseOptions& opt, Plan& P, std::string& msg) {
     if (mode != QDMF_NE && mode != QDMF_AS) {

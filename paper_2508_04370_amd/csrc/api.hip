@@ -981,6 +981,52 @@ int qdmf_profile_read(qdmf_handle h, int64_t* launches, double* total_ms, double
     return 0;
 }
 
+int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx,
+                     qdmf_mode_choice* out) {
+    if (!h || !out) return QDMF_ERR_INVALID_ARG;
+    if (h->opt.ordering == QDMF_ORDER_USER || h->opt.ordering == QDMF_ORDER_GRID_ND) {
+        h->msg = "qdmf_choose_mode needs an ordering computed from the pattern (AMD, ND or AUTO)";
+        return QDMF_ERR_INVALID_ARG;
+    }
+    qdmf_mode_choice c{};
+    c.nnz_ne_pattern = -1;
+    c.nnz_l_ne = -1;
+    c.flops_ne = -1.0;
+    AnalyseOptions ao;
+    ao.ordering = h->opt.ordering;
+    ao.amalgamate = h->opt.amalgamate;
+    ao.small_front = h->opt.small_front;
+    ao.split_solve_front = h->opt.split_solve_front;
+    {  // the augmented system first
+        Plan Pa;
+        const int rc = build_plan(m, n, colptr, rowidx, QDMF_AS, ao, Pa, h->msg);
+        if (rc) return rc;
+        c.nnz_l_as = Pa.nnz_l;
+        c.flops_as = Pa.flops_fact;
+    }
+    const int64_t dense_min = std::max<int64_t>(64, ((int64_t)m + 9) / 10);
+    for (int32_t j = 0; j < n; ++j)
+        if (colptr[j + 1] - colptr[j] >= dense_min) ++c.ndense;
+    c.mode = QDMF_AS;
+    if (c.ndense > 0) {
+        c.ne_abandoned = 1;
+    } else {
+        c.nnz_ne_pattern = ne_pattern_count(m, n, colptr, rowidx, c.nnz_l_as);
+        if (c.nnz_ne_pattern > c.nnz_l_as) {
+            c.ne_abandoned = 1;
+        } else {
+            Plan Pn;
+            const int rc = build_plan(m, n, colptr, rowidx, QDMF_NE, ao, Pn, h->msg);
+            if (rc) return rc;
+            c.nnz_l_ne = Pn.nnz_l;
+            c.flops_ne = Pn.flops_fact;
+            if (c.flops_ne <= c.flops_as) c.mode = QDMF_NE;
+        }
+    }
+    *out = c;
+    return 0;
+}
+
 void qdmf_destroy(qdmf_handle h) {
     if (!h) return;
     if (!h->host_only) {

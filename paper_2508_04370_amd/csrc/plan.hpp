@@ -170,6 +170,10 @@ void grid_nd_order(const Plan& P, const int grid[3], const std::vector<int64_t>&
                    const std::vector<int32_t>& adj, std::vector<int32_t>& order);
 
 // Builds the whole plan.  Returns 0 or a QDMF_ERR_* code; msg explains failures.
+// Lower entries (with the diagonal) of the pattern of A A^T, counted row by row; stops and
+// returns a value above `limit` as soon as the count exceeds it.
+int64_t ne_pattern_count(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx, int64_t limit);
+
 int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx,
                int32_t mode, const AnalyseOptions& opt, Plan& P, std::string& msg);
 

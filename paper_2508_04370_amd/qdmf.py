@@ -35,7 +35,7 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_factor_stats", "qdmf_solve_stats", "qdmf_export_d", "qdmf_export_front",
             "qdmf_graph_capture", "qdmf_graph_launch", "qdmf_destroy", "qdmf_status_string",
             "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read", "qdmf_batch_analyse",
-            "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats"]
+            "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats", "qdmf_choose_mode"]
 QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD = range(7)
 KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
                      6: "k_bwd"}
@@ -48,6 +48,12 @@ class qdmf_options(C.Structure):
                 ("tau_big", C.c_double), ("ordering", C.c_int32), ("grid", C.c_int32 * 3),
                 ("amalgamate", C.c_int32), ("f_mix", C.c_int32), ("small_front", C.c_int32),
                 ("mem_cap_bytes", C.c_int64), ("split_solve_front", C.c_int32)]
+
+
+class qdmf_mode_choice(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("ndense", C.c_int32), ("ne_abandoned", C.c_int32),
+                ("nnz_l_as", C.c_int64), ("nnz_ne_pattern", C.c_int64), ("nnz_l_ne", C.c_int64),
+                ("flops_as", C.c_double), ("flops_ne", C.c_double)]
 
 
 class qdmf_symbolic_info(C.Structure):
@@ -92,6 +98,7 @@ def lib():
         L.qdmf_create.argtypes = [C.POINTER(P), C.c_int, P, C.POINTER(qdmf_options)]
         L.qdmf_set_stream.argtypes = [P, P]
         L.qdmf_analyse.argtypes = [P, I32, I32, P, P, I32, P]
+        L.qdmf_choose_mode.argtypes = [P, I32, I32, P, P, C.POINTER(qdmf_mode_choice)]
         L.qdmf_symbolic.argtypes = [P, C.POINTER(qdmf_symbolic_info)]
         L.qdmf_set_matrix.argtypes = [P, P, I32]
         L.qdmf_factorise.argtypes = [P, P, D, D, I32]
@@ -172,6 +179,15 @@ def qdmf_analyse(h, m, n, colptr, rowidx, mode, user_perm=None):
     up = None if user_perm is None else np.ascontiguousarray(user_perm, np.int32)
     return _check(lib().qdmf_analyse(h, int(m), int(n), _np(cp), _np(ri), int(mode), _np(up)),
                   "qdmf_analyse", h)
+
+
+def qdmf_choose_mode(h, m, n, colptr, rowidx):
+    """NE or AS for the pattern of A, with the counts the choice rests on (a dict)."""
+    cp = np.ascontiguousarray(colptr, np.int64)
+    ri = np.ascontiguousarray(rowidx, np.int32)
+    c = qdmf_mode_choice()
+    _check(lib().qdmf_choose_mode(h, int(m), int(n), _np(cp), _np(ri), C.byref(c)), "qdmf_choose_mode", h)
+    return {k: getattr(c, k) for k, _ in qdmf_mode_choice._fields_}
 
 
 def qdmf_symbolic(h):
