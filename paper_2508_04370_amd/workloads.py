@@ -275,6 +275,36 @@ def dense_front(f, p, seed=0, dmin=1.0, dmax=10.0):
     return np.asfortranarray(F), sigma
 
 
+def feasible_lp(lp, seed=7):
+    """An LP min c^T x, A x = b, x >= 0 on the pattern and values of `lp`, primal and dual
+    feasible by construction (so with a finite optimum): b = A x0 and c = A^T y0 + z0 for
+    x0, z0 uniform in [0.5, 1.5] and y0 standard normal.  Returns (A as a LP dict with mode AS,
+    b, c)."""
+    g = rng(seed, 71)
+    m, n = lp["m"], lp["n"]
+    x0 = g.uniform(0.5, 1.5, n)
+    z0 = g.uniform(0.5, 1.5, n)
+    y0 = g.standard_normal(m)
+    cp, ri, v = lp["colptr"], lp["rowidx"], lp["val"]
+    b = np.zeros(m)
+    c = z0.copy()
+    for j in range(n):
+        rows, vals = ri[cp[j]:cp[j + 1]], v[cp[j]:cp[j + 1]]
+        b[rows] += vals * x0[j]
+        c[j] += float(vals @ y0[rows])
+    out = LP(dict(lp, mode=AS))
+    return out, b, c
+
+
+def lp_dense(lp):
+    """A of an LP dict as a dense array."""
+    A = np.zeros((lp["m"], lp["n"]))
+    cp, ri, v = lp["colptr"], lp["rowidx"], lp["val"]
+    for j in range(lp["n"]):
+        A[ri[cp[j]:cp[j + 1]], j] = v[cp[j]:cp[j + 1]]
+    return A
+
+
 def small_config():
     """The small correctness workload: random 300 x 600 LP, normal equations, FP64."""
     return ne_random()
