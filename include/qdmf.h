@@ -270,6 +270,44 @@ typedef struct {
 int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
                      const int32_t* rowidx, qdmf_mode_choice* out);
 
+/* Interior point driver around the factorise and solve calls (Section 3: Newton system
+ * reduced to the augmented system, predictor with sigma = 0, centrality correctors from the
+ * complementarity products at the trial point, steps to the boundary, the termination test of
+ * Section 3.1; Section 4.7: the number of correctors).  LP: min c^T x subject to A x = b and
+ * x >= 0, the paper's formulation with every lower bound at zero and no upper bounds; A is the
+ * matrix of the handle, which must be analysed in QDMF_AS mode with qdmf_set_matrix called.
+ * Start: x = z = 1, y = 0.  b (m), c (n) and x, z (n), y (m) are caller-owned device buffers;
+ * x, y, z receive the last iterate.  Runs on the handle's stream and synchronises it several
+ * times per iteration.  Errors: QDMF_ERR_INVALID_ARG, QDMF_ERR_NOT_ANALYSED (or not AS),
+ * QDMF_ERR_NO_MATRIX, QDMF_ERR_HIP, QDMF_ERR_OOM, and the codes of qdmf_factorise / qdmf_solve. */
+typedef struct {
+    double tau;               /* feasibility and optimality tolerance (Section 3.1), 1e-8     */
+    double rho, delta;        /* static regularisation of every factorisation (Section 3.2),
+                                 1e-10 and 1e-10                                              */
+    int32_t max_iter;         /* 100                                                         */
+    int32_t correctors;       /* 0: Section 4.7's estimate; > 0: this many per iteration     */
+    int32_t kmax;             /* most correctors from the estimate, 6                        */
+    double alpha_f;           /* factorisation-efficiency factor of that estimate, 0.025     */
+    int32_t prec;             /* QDMF_FP64 or QDMF_MIXED for every factorisation             */
+} qdmf_ipm_options;
+
+typedef struct {
+    int32_t status;           /* 0: optimal; QDMF_WARN_NOT_CONVERGED: iteration limit         */
+    int32_t iters;            /* iterations taken (factorisations)                           */
+    int32_t correctors;       /* correctors allowed per iteration                            */
+    double primal_obj, dual_obj;
+    double pinf, dinf;        /* ||b - A x||_inf and ||c - A^T y - z||_inf at the last iterate */
+    double mu;                /* x^T z / n at the last iterate                               */
+    double ms;                /* wall time of the iterations                                 */
+} qdmf_ipm_info;
+
+void qdmf_ipm_default_options(qdmf_ipm_options* opt);
+
+/* history: NULL or room for 4 * max_iter doubles; per iteration it receives mu, alpha_p,
+ * alpha_d and the number of correctors used. */
+int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, double* x_dev, double* y_dev,
+                   double* z_dev, const qdmf_ipm_options* opt, qdmf_ipm_info* info, double* history);
+
 /* Frees everything the handle owns.  NULL is ignored. */
 void qdmf_destroy(qdmf_handle h);
 

@@ -2,6 +2,8 @@
 // export and HIP graph capture.  Every numerical step runs in the kernels of kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -979,6 +981,160 @@ int qdmf_profile_read(qdmf_handle h, int64_t* launches, double* total_ms, double
     h->ev_used = 0;
     h->prof_flops = h->prof_bytes = 0;
     return 0;
+}
+
+void qdmf_ipm_default_options(qdmf_ipm_options* o) {
+    if (!o) return;
+    o->tau = 1e-8;
+    o->rho = 1e-10;
+    o->delta = 1e-10;
+    o->max_iter = 100;
+    o->correctors = 0;
+    o->kmax = 6;
+    o->alpha_f = 0.025;
+    o->prec = QDMF_FP64;
+}
+
+int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, double* x_dev, double* y_dev,
+                   double* z_dev, const qdmf_ipm_options* opt_in, qdmf_ipm_info* info, double* history) {
+    // readings shared with the reference implementation the tests compare against
+    constexpr double STEP_FACTOR = 0.995, ALPHA_PLUS = 0.1, BETA_MIN = 0.1, BETA_MAX = 10.0, ACCEPT_GAIN = 0.01;
+    if (!h || !info || !b_dev || !c_dev || !x_dev || !y_dev || !z_dev || h->host_only) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed || h->P.mode != QDMF_AS || h->P.nsys != 1) return QDMF_ERR_NOT_ANALYSED;
+    if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
+    qdmf_ipm_options opt;
+    if (opt_in) opt = *opt_in;
+    else qdmf_ipm_default_options(&opt);
+    if (opt.max_iter < 0 || opt.correctors < 0 || opt.kmax < 1 || !(opt.tau > 0) || opt.rho < 0 || opt.delta < 0)
+        return QDMF_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    const int n = h->P.n, m = h->P.m;
+    hipStream_t st = h->stream;
+    // Section 4.7: (1 + k)(1 + f/2) E_s ~ E_f alpha_F, E_s = 2 nnz(L), E_f = factorisation flops
+    int k = opt.correctors;
+    if (k == 0) {
+        const double es = 2.0 * (double)h->P.nnz_l, f = h->opt.max_refine;
+        k = (int)std::floor(opt.alpha_f * h->P.flops_fact / ((1.0 + f / 2.0) * es) - 1.0);
+        k = std::max(1, std::min(opt.kmax, k));
+    }
+    // work space
+    std::vector<void*> mem;
+    auto alloc = [&](double** p, int64_t len) {
+        *p = nullptr;
+        if (hipMalloc((void**)p, sizeof(double) * (size_t)std::max<int64_t>(1, len)) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        mem.push_back(*p);
+        return true;
+    };
+    double *theta, *r1, *r4, *r5, *r7, *zm, *ax, *ay, *az, *bx, *by, *bz, *cx, *cy, *cz, *part, *out;
+    const int64_t nparts = 8 * (int64_t)ipm_blocks(std::max(n, m));
+    bool ok = alloc(&theta, n) && alloc(&r1, m) && alloc(&r4, n) && alloc(&r5, n) && alloc(&r7, n) &&
+              alloc(&zm, m) && alloc(&ax, n) && alloc(&ay, m) && alloc(&az, n) && alloc(&bx, n) && alloc(&by, m) &&
+              alloc(&bz, n) && alloc(&cx, n) && alloc(&cy, m) && alloc(&cz, n) && alloc(&part, nparts) &&
+              alloc(&out, 8);
+    auto release = [&]() {
+        for (void* p : mem) (void)hipFree(p);
+    };
+    if (!ok) {
+        release();
+        return QDMF_ERR_OOM;
+    }
+    double sc[8];
+    auto read = [&](int cnt) {
+        return hipMemcpyAsync(sc, out, sizeof(double) * cnt, hipMemcpyDeviceToHost, st) == hipSuccess &&
+               hipStreamSynchronize(st) == hipSuccess;
+    };
+    const auto t0 = std::chrono::steady_clock::now();
+    ipm_fill(x_dev, 1.0, n, st);
+    ipm_fill(z_dev, 1.0, n, st);
+    ipm_fill(y_dev, 0.0, m, st);
+    ipm_fill(zm, 0.0, m, st);
+    qdmf_ipm_info res{};
+    res.status = QDMF_WARN_NOT_CONVERGED;
+    res.correctors = k;
+    int it = 0;
+    rc = 0;
+    for (;; ++it) {
+        ipm_resid(h->D, x_dev, y_dev, z_dev, b_dev, c_dev, r1, r4, part, out, st);
+        if (!read(7)) {
+            rc = QDMF_ERR_HIP;
+            break;
+        }
+        const double pinf = sc[0], dinf = sc[1], fp = sc[2], fd = sc[3], xz = sc[4], bmax = sc[5], cmax = sc[6];
+        res.pinf = pinf;
+        res.dinf = dinf;
+        res.primal_obj = fp;
+        res.dual_obj = fd;
+        res.mu = n ? xz / n : 0.0;
+        // Section 3.1, without scaling
+        if (pinf <= opt.tau * (1.0 + bmax) && dinf <= opt.tau * (1.0 + cmax) &&
+            std::fabs(fp - fd) <= opt.tau * (1.0 + 0.5 * std::fabs(fp + fd))) {
+            res.status = 0;
+            break;
+        }
+        if (it >= opt.max_iter) break;
+        const double mu = res.mu;
+        ipm_theta(x_dev, z_dev, theta, n, st);
+        if ((rc = qdmf_factorise(h, theta, opt.rho, opt.delta, opt.prec)) < 0) break;
+        // predictor (sigma = 0)
+        ipm_r5r7(0, x_dev, z_dev, r4, nullptr, nullptr, 0.0, 0.0, 0.0, 0.0, 0.0, r5, r7, n, st);
+        if ((rc = qdmf_solve(h, 1, r7, r1, ax, ay)) < 0) break;
+        ipm_dz(x_dev, z_dev, r5, ax, az, n, st);
+        ipm_step(x_dev, ax, z_dev, az, part, out, n, st);
+        if (!read(2)) {
+            rc = QDMF_ERR_HIP;
+            break;
+        }
+        double ap = -sc[0], ad = -sc[1];
+        ipm_comp(x_dev, ax, z_dev, az, ap, ad, part, out, n, st);
+        if (!read(1)) {
+            rc = QDMF_ERR_HIP;
+            break;
+        }
+        const double mu_aff = sc[0] / n, sigma = (mu_aff / mu) * (mu_aff / mu) * (mu_aff / mu), smu = sigma * mu;
+        // correctors: r1 = r4 = 0, r5 moves the products at the trial point into the band
+        double *dx = ax, *dy = ay, *dz = az, *nx = bx, *ny = by, *nz = bz;
+        int used = 0;
+        for (int j = 0; j < k; ++j) {
+            const double tp = std::min(1.0, ap + ALPHA_PLUS), td = std::min(1.0, ad + ALPHA_PLUS);
+            ipm_r5r7(1, x_dev, z_dev, nullptr, dx, dz, smu, tp, td, BETA_MIN, BETA_MAX, r5, r7, n, st);
+            if ((rc = qdmf_solve(h, 1, r7, zm, cx, cy)) < 0) break;
+            ipm_dz(x_dev, z_dev, r5, cx, cz, n, st);
+            ipm_add(dx, cx, nx, n, st);
+            ipm_add(dy, cy, ny, m, st);
+            ipm_add(dz, cz, nz, n, st);
+            ipm_step(x_dev, nx, z_dev, nz, part, out, n, st);
+            if (!read(2)) {
+                rc = QDMF_ERR_HIP;
+                break;
+            }
+            const double nap = -sc[0], nad = -sc[1];
+            if (j > 0 && nap + nad < (1.0 + ACCEPT_GAIN) * (ap + ad)) break;
+            std::swap(dx, nx);  // the accepted direction; the old one's buffers become the spares
+            std::swap(dy, ny);
+            std::swap(dz, nz);
+            ap = nap;
+            ad = nad;
+            ++used;
+        }
+        if (rc < 0) break;
+        if (history && it < opt.max_iter) {
+            history[4 * it] = mu;
+            history[4 * it + 1] = ap;
+            history[4 * it + 2] = ad;
+            history[4 * it + 3] = used;
+        }
+        ipm_update(x_dev, y_dev, z_dev, dx, dy, dz, STEP_FACTOR * ap, STEP_FACTOR * ad, n, m, st);
+    }
+    if (hipStreamSynchronize(st) != hipSuccess && rc == 0) rc = QDMF_ERR_HIP;
+    res.iters = it;
+    res.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    release();
+    *info = res;
+    return rc < 0 ? rc : res.status;
 }
 
 int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx,

@@ -155,6 +155,24 @@ void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const
                         hipStream_t s);
 // Inverses of the diagonal blocks used by the one-workgroup solves (after the factorisation).
 void launch_inv(const DevPlan& D, const Task* tasks, int64_t ntask, hipStream_t s);
+// Interior point driver kernels (ipm.hip).  out: device scalars; part: 8 x ipm_blocks(len)
+// doubles of partials.
+int ipm_blocks(int64_t len);
+void ipm_resid(const DevPlan& D, const double* x, const double* y, const double* z, const double* b,
+               const double* c, double* r1, double* r4, double* part, double* out, hipStream_t s);
+void ipm_theta(const double* x, const double* z, double* theta, int n, hipStream_t s);
+void ipm_r5r7(int mode, const double* x, const double* z, const double* r4, const double* dx, const double* dz,
+              double smu, double tp, double td, double bmin, double bmax, double* r5, double* r7, int n,
+              hipStream_t s);
+void ipm_dz(const double* x, const double* z, const double* r5, const double* dx, double* dz, int n, hipStream_t s);
+void ipm_add(const double* a, const double* b, double* out, int len, hipStream_t s);
+void ipm_step(const double* x, const double* dx, const double* z, const double* dz, double* part, double* out,
+              int n, hipStream_t s);
+void ipm_comp(const double* x, const double* dx, const double* z, const double* dz, double ap, double ad,
+              double* part, double* out, int n, hipStream_t s);
+void ipm_update(double* x, double* y, double* z, const double* dx, const double* dy, const double* dz, double sp,
+                double sd, int n, int m, hipStream_t s);
+void ipm_fill(double* v, double a, int len, hipStream_t s);
 // One launch of the big-supernode solves (kind: SolveKind).
 void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L, const Task* stasks,
                       const int32_t* active, hipStream_t s);

@@ -35,7 +35,8 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_factor_stats", "qdmf_solve_stats", "qdmf_export_d", "qdmf_export_front",
             "qdmf_graph_capture", "qdmf_graph_launch", "qdmf_destroy", "qdmf_status_string",
             "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read", "qdmf_batch_analyse",
-            "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats", "qdmf_choose_mode"]
+            "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats", "qdmf_choose_mode",
+            "qdmf_ipm_default_options", "qdmf_ipm_solve"]
 QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD = range(7)
 KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
                      6: "k_bwd"}
@@ -54,6 +55,17 @@ class qdmf_mode_choice(C.Structure):
     _fields_ = [("mode", C.c_int32), ("ndense", C.c_int32), ("ne_abandoned", C.c_int32),
                 ("nnz_l_as", C.c_int64), ("nnz_ne_pattern", C.c_int64), ("nnz_l_ne", C.c_int64),
                 ("flops_as", C.c_double), ("flops_ne", C.c_double)]
+
+
+class qdmf_ipm_options(C.Structure):
+    _fields_ = [("tau", C.c_double), ("rho", C.c_double), ("delta", C.c_double), ("max_iter", C.c_int32),
+                ("correctors", C.c_int32), ("kmax", C.c_int32), ("alpha_f", C.c_double), ("prec", C.c_int32)]
+
+
+class qdmf_ipm_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("correctors", C.c_int32),
+                ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("pinf", C.c_double),
+                ("dinf", C.c_double), ("mu", C.c_double), ("ms", C.c_double)]
 
 
 class qdmf_symbolic_info(C.Structure):
@@ -99,6 +111,9 @@ def lib():
         L.qdmf_set_stream.argtypes = [P, P]
         L.qdmf_analyse.argtypes = [P, I32, I32, P, P, I32, P]
         L.qdmf_choose_mode.argtypes = [P, I32, I32, P, P, C.POINTER(qdmf_mode_choice)]
+        L.qdmf_ipm_default_options.argtypes = [C.POINTER(qdmf_ipm_options)]
+        L.qdmf_ipm_default_options.restype = None
+        L.qdmf_ipm_solve.argtypes = [P, P, P, P, P, P, C.POINTER(qdmf_ipm_options), C.POINTER(qdmf_ipm_info), P]
         L.qdmf_symbolic.argtypes = [P, C.POINTER(qdmf_symbolic_info)]
         L.qdmf_set_matrix.argtypes = [P, P, I32]
         L.qdmf_factorise.argtypes = [P, P, D, D, I32]
@@ -179,6 +194,28 @@ def qdmf_analyse(h, m, n, colptr, rowidx, mode, user_perm=None):
     up = None if user_perm is None else np.ascontiguousarray(user_perm, np.int32)
     return _check(lib().qdmf_analyse(h, int(m), int(n), _np(cp), _np(ri), int(mode), _np(up)),
                   "qdmf_analyse", h)
+
+
+def qdmf_ipm_default_options(**overrides):
+    o = qdmf_ipm_options()
+    lib().qdmf_ipm_default_options(C.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def qdmf_ipm_solve(h, b, c, x, y, z, opt=None):
+    """Interior point driver on device tensors b (m), c (n), x, z (n), y (m) (contiguous
+    float64).  Returns (info dict, history array of shape (iters, 4): mu, alpha_p, alpha_d,
+    correctors used).  A positive status (iteration limit) is returned in the dict."""
+    opt = opt if opt is not None else qdmf_ipm_default_options()
+    info = qdmf_ipm_info()
+    hist = np.zeros(4 * max(1, opt.max_iter))
+    rc = lib().qdmf_ipm_solve(h, _dev(b), _dev(c), _dev(x), _dev(y), _dev(z), C.byref(opt), C.byref(info), _np(hist))
+    if rc < 0:
+        _check(rc, "qdmf_ipm_solve", h)
+    out = {k: getattr(info, k) for k, _ in qdmf_ipm_info._fields_}
+    return out, hist[:4 * info.iters].reshape(-1, 4)
 
 
 def qdmf_choose_mode(h, m, n, colptr, rowidx):
