@@ -214,6 +214,42 @@ def cpu_baseline(lp):
                 seconds=round(t, 3), ms_per_factorise_solve=round(t * 1e3, 1))
 
 
+def run_ipm(lp, opts, prec, args):
+    """The interior point driver (qdmf_ipm_solve) on the LP min c^T x, A x = b, x >= 0 with the
+    workload's A and b, c from workloads.feasible_lp; one untimed run (warm-up), then the timed
+    runs; value = milliseconds per IPM iteration."""
+    import torch
+    from paper_2508_04370_amd import qdmf as Q
+    lpf, b, c = W.feasible_lp(lp, seed=7)
+    dev = "cuda:0"
+    s = Q.Solver(lpf, device=0, **{k: v for k, v in opts.items() if k in ("ordering", "grid")})
+    bd, cd = torch.from_numpy(b).to(dev), torch.from_numpy(c).to(dev)
+    x = torch.empty(lpf["n"], dtype=torch.float64, device=dev)
+    z = torch.empty(lpf["n"], dtype=torch.float64, device=dev)
+    y = torch.empty(lpf["m"], dtype=torch.float64, device=dev)
+    opt = Q.qdmf_ipm_default_options(prec=prec)
+    runs = []
+    for k in range(args.warmup + args.steps):
+        info, hist = Q.qdmf_ipm_solve(s.h, bd, cd, x, y, z, opt)
+        print(f"[bench] ipm run {k}: status {info['status']} iters {info['iters']} {info['ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+        if k >= args.warmup:
+            runs.append(info)
+    ms_it = [r["ms"] / max(1, r["iters"]) for r in runs]
+    last = runs[-1]
+    out = {"metric": "interior point iteration time (factorise, predictor, correctors, vector work)",
+           "value": round(float(np.median(ms_it)), 4), "unit": "ms/iteration", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if prec == 0 else "f64+f32", "data": "synthetic",
+           "config": {"workload": lp["name"] + "_feasible_lp", "m": lpf["m"], "n": lpf["n"], "mode": "AS",
+                      "precision": args.prec},
+           "ipm": {"status": last["status"], "iterations": last["iters"], "correctors": last["correctors"],
+                   "primal_obj": last["primal_obj"], "dual_obj": last["dual_obj"], "pinf": last["pinf"],
+                   "dinf": last["dinf"], "ms_total": round(last["ms"], 3)}}
+    s.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +262,9 @@ def main():
     ap.add_argument("--nsolves", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ipm", action="store_true",
+                    help="instead: the interior point driver on a feasible LP over the workload's A "
+                         "(one JSON line, ms per IPM iteration)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -238,6 +277,9 @@ def main():
         sys.exit(2)
     lp, opts = make_workload(args.workload)
     prec = 1 if args.prec == "mixed" else 0
+    if args.ipm:
+        run_ipm(lp, opts, prec, args)
+        return
     print(f"[bench] workload={lp['name']} prec={args.prec} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
     r = run_gpu(lp, opts, prec, args.steps, args.warmup, args.nsolves, not args.no_graph)
