@@ -988,7 +988,8 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         int32_t maxwin = 0;
         for (int32_t t : large) maxwin = std::max(maxwin, P.sn_nwin[t]);
         for (int32_t w = 0; w < maxwin; ++w) {
-            // panel rows per workgroup: 64 * npg, npg <= 3, sized by the largest front
+            // panel rows per workgroup: 64 * npg with npg <= 1 (more rows per workgroup make
+            // every pivot step of the window longer; more workgroups repeat the decisions)
             int32_t npg = 0;
             for (int32_t t : large)
                 if (w < P.sn_nwin[t]) {

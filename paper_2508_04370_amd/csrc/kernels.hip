@@ -2485,8 +2485,7 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
             switch (L.npg) {
                 case 0: hipLaunchKernelGGL(k_window<0>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
                 case 1: hipLaunchKernelGGL(k_window<1>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
-                case 2: hipLaunchKernelGGL(k_window<2>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
-                default: hipLaunchKernelGGL(k_window<3>, dim3(g), dim3(256), 0, s, D, tasks, L.task0, pp); break;
+                default: break;  // the plan uses at most one panel group per workgroup
             }
             break;
         case L_SYRK:

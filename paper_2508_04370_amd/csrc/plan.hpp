@@ -33,7 +33,7 @@ struct Launch {
     int64_t task0, ntask;  // range in the task array
     int32_t lds;           // dynamic LDS bytes (assembly)
     int32_t maxf;          // largest front order among the tasks
-    int32_t npg = 0;       // window: panel row groups of 64 per workgroup (0..3)
+    int32_t npg = 0;       // window: panel row groups of 64 per workgroup (0 or 1)
     int64_t fin0 = 0, nfin = 0;  // trailing update: the level's finalize tasks run in the same launch
     double flops = 0;      // algorithmic work of the launch
     double bytes = 0;
