@@ -296,6 +296,33 @@ def feasible_lp(lp, seed=7):
     return out, b, c
 
 
+def bounded_lp(lp, seed=7, upper=0.5):
+    """An LP min c^T x, A x = b, l <= x <= u on the pattern and values of `lp`, primal and dual
+    feasible by construction: l uniform in [-1, 1]; a fraction `upper` of the columns (chosen at
+    random) gets u = l + w with w uniform in [1, 3], the rest u = +inf; x0 strictly inside the
+    bounds; b = A x0 and c = A^T y0 + z^l0 - z^u0 with z^l0 uniform in [0.5, 1.5], z^u0 uniform
+    in [0, 1] where u is finite.  Returns (A as a LP dict with mode AS, b, c, l, u)."""
+    g = rng(seed, 72)
+    m, n = lp["m"], lp["n"]
+    l = g.uniform(-1.0, 1.0, n)
+    hasu = g.random(n) < upper
+    w = g.uniform(1.0, 3.0, n)
+    u = np.where(hasu, l + w, np.inf)
+    x0 = l + np.where(hasu, w * g.uniform(0.2, 0.8, n), g.uniform(0.5, 1.5, n))
+    zl0 = g.uniform(0.5, 1.5, n)
+    zu0 = np.where(hasu, g.uniform(0.0, 1.0, n), 0.0)
+    y0 = g.standard_normal(m)
+    cp, ri, v = lp["colptr"], lp["rowidx"], lp["val"]
+    b = np.zeros(m)
+    c = zl0 - zu0
+    for j in range(n):
+        rows, vals = ri[cp[j]:cp[j + 1]], v[cp[j]:cp[j + 1]]
+        b[rows] += vals * x0[j]
+        c[j] += float(vals @ y0[rows])
+    out = LP(dict(lp, mode=AS))
+    return out, b, c, l, u
+
+
 def lp_dense(lp):
     """A of an LP dict as a dense array."""
     A = np.zeros((lp["m"], lp["n"]))

@@ -1,6 +1,7 @@
 """The reference interior point method (oracle/ipm.py) against what fixes it independently:
-the optimum of SciPy's HiGHS on feasible LPs, a textbook LP with a known solution, the full
-(unreduced) Newton system for the reduced direction, and its own termination test."""
+the optimum of SciPy's HiGHS on feasible LPs with and without bounds, textbook LPs with known
+solutions, the full (unreduced) Newton system of Section 3 for the reduced direction, and its
+own termination test."""
 import numpy as np
 import pytest
 
@@ -19,7 +20,43 @@ def test_optimum_matches_highs(m, n, d, seed):
     ref = scipy_optimize.linprog(c, A_eq=A, b_eq=b, bounds=(0, None), method="highs")
     assert r["status"] == "optimal" and ref.status == 0
     assert abs(r["fp"] - ref.fun) <= 1e-7 * (1 + abs(ref.fun))
-    assert np.all(r["x"] > 0) and np.all(r["z"] > 0)
+    assert np.all(r["x"] > 0) and np.all(r["zl"] > 0)
+
+
+def highs_bounds(l, u):
+    return [(lo, None if np.isinf(hi) else hi) for lo, hi in zip(l, u)]
+
+
+@pytest.mark.parametrize("m,n,d,seed,upper", [(50, 100, 0.05, 0, 0.5), (120, 300, 0.02, 1, 1.0),
+                                              (80, 240, 0.03, 2, 0.2)])
+def test_bounded_optimum_matches_highs(m, n, d, seed, upper):
+    base = W.ne_random(m=m, n=n, density=d, seed=20 + seed)
+    lp, b, c, l, u = W.bounded_lp(base, seed=seed, upper=upper)
+    A = W.lp_dense(lp)
+    r = I.ipm(A, b, c, l, u, k=2)
+    ref = scipy_optimize.linprog(c, A_eq=A, b_eq=b, bounds=highs_bounds(l, u), method="highs")
+    assert r["status"] == "optimal" and ref.status == 0
+    assert abs(r["fp"] - ref.fun) <= 1e-7 * (1 + abs(ref.fun))
+    hasu = np.isfinite(u)
+    assert np.all(r["x"] > l) and np.all(r["x"][hasu] < u[hasu])
+    assert np.all(r["zl"] > 0) and np.all(r["zu"][hasu] > 0) and np.all(r["zu"][~hasu] == 0)
+
+
+def test_textbook_lp_with_bounds():
+    """min -x1 - 2 x2 s.t. x1 + x2 + s = 2, -1 <= x1 <= 1.5, 0 <= x2 <= 1, s >= 0: x2 sits at
+    its upper bound, x1 = 1, s = 0, value -3; the dual is y = -1, z^l_s = 1, z^u_2 = 1."""
+    A = np.array([[1.0, 1.0, 1.0]])
+    b = np.array([2.0])
+    c = np.array([-1.0, -2.0, 0.0])
+    l = np.array([-1.0, 0.0, 0.0])
+    u = np.array([1.5, 1.0, np.inf])
+    r = I.ipm(A, b, c, l, u, k=1)
+    assert r["status"] == "optimal"
+    assert abs(r["fp"] + 3.0) <= 1e-6
+    assert np.allclose(r["x"], [1.0, 1.0, 0.0], atol=1e-6)
+    assert np.allclose(r["y"], [-1.0], atol=1e-6)
+    assert np.allclose(r["zl"], [0.0, 0.0, 1.0], atol=1e-6)
+    assert np.allclose(r["zu"], [0.0, 1.0, 0.0], atol=1e-6)
 
 
 def test_textbook_lp():
@@ -35,19 +72,49 @@ def test_textbook_lp():
 
 
 def test_reduced_direction_solves_the_full_newton_system():
-    """Without regularisation the direction from the augmented system satisfies
-    A dx = r1, A^T dy + dz = r4 and Z dx + X dz = r5."""
+    """Without regularisation the direction from the augmented system and the recovery solves
+    the unreduced Newton system of Section 3 with bounds, assembled here as one dense matrix in
+    the unknowns (dx, dx^l, dx^u, dy, dz^l, dz^u):
+    A dx = r1, dx - dx^l = r2, dx + dx^u = r3, A^T dy + dz^l - dz^u = r4,
+    Z^l dx^l + X^l dz^l = r5, Z^u dx^u + X^u dz^u = r6."""
     g = W.rng(33)
-    base = W.ne_random(m=40, n=90, density=0.08, seed=33)
-    lp, b, c = W.feasible_lp(base, seed=3)
+    m, n = 40, 90
+    base = W.ne_random(m=m, n=n, density=0.08, seed=33)
+    lp, b, c, l, u = W.bounded_lp(base, seed=3, upper=1.0)  # every upper bound finite
     A = W.lp_dense(lp)
-    x, z, y = g.uniform(0.1, 2, 90), g.uniform(0.1, 2, 90), g.standard_normal(40)
-    r1, r4, r5 = b - A @ x, c - A.T @ y - z, g.standard_normal(90)
-    dx, dy, dz = I.newton_direction(A, x, z, z / x, 0.0, r1, r4, r5)
-    scale = 1 + np.abs(A).sum() * max(np.abs(dx).max(), np.abs(dy).max())
-    assert np.abs(A @ dx - r1).max() <= 1e-10 * scale
-    assert np.abs(A.T @ dy + dz - r4).max() <= 1e-10 * scale
-    assert np.abs(z * dx + x * dz - r5).max() <= 1e-10 * scale
+    s = I.State(g.uniform(-1, 1, n), g.uniform(0.1, 2, n), g.uniform(0.1, 2, n), g.standard_normal(m),
+                g.uniform(0.1, 2, n), g.uniform(0.1, 2, n))
+    hasu = np.ones(n, bool)
+    r1, r2, r3, r4, r5, r6 = (g.standard_normal(m),) + tuple(g.standard_normal(n) for _ in range(5))
+    tinv = s.zl / s.xl + s.zu / s.xu
+    d = I.newton_direction(A, s, hasu, tinv, 0.0, r1, r2, r3, r4, r5, r6)
+    Z, E = np.zeros, np.eye(n)
+    blocks = [
+        [A, Z((m, n)), Z((m, n)), Z((m, m)), Z((m, n)), Z((m, n))],
+        [E, -E, Z((n, n)), Z((n, m)), Z((n, n)), Z((n, n))],
+        [E, Z((n, n)), E, Z((n, m)), Z((n, n)), Z((n, n))],
+        [Z((n, n)), Z((n, n)), Z((n, n)), A.T, E, -E],
+        [Z((n, n)), np.diag(s.zl), Z((n, n)), Z((n, m)), np.diag(s.xl), Z((n, n))],
+        [Z((n, n)), Z((n, n)), np.diag(s.zu), Z((n, m)), Z((n, n)), np.diag(s.xu)],
+    ]
+    M = np.block(blocks)
+    v = np.concatenate([d.x, d.xl, d.xu, d.y, d.zl, d.zu])
+    rhs = np.concatenate([r1, r2, r3, r4, r5, r6])
+    scale = 1 + np.abs(M).sum(axis=1).max() * np.abs(v).max()
+    assert np.abs(M @ v - rhs).max() <= 1e-10 * scale
+
+
+def test_standard_form_is_the_special_case_without_bounds():
+    """l = 0 and u = +inf reduce the bounded method to min c^T x, A x = b, x >= 0: the same
+    iterates whether the bounds are given explicitly or left at their defaults."""
+    base = W.ne_random(m=40, n=90, density=0.06, seed=35)
+    lp, b, c = W.feasible_lp(base, seed=6)
+    A = W.lp_dense(lp)
+    r0 = I.ipm(A, b, c, k=2)
+    r1 = I.ipm(A, b, c, np.zeros(90), np.full(90, np.inf), k=2)
+    assert r0["iters"] == r1["iters"]
+    assert np.array_equal(r0["x"], r1["x"]) and np.array_equal(r0["y"], r1["y"])
+    assert np.all(r0["zu"] == 0)
 
 
 def test_iterations_reduce_mu_and_end_feasible():
@@ -57,7 +124,7 @@ def test_iterations_reduce_mu_and_end_feasible():
     r = I.ipm(A, b, c, k=3)
     mus = [h[0] for h in r["history"]]
     assert all(mus[i + 1] < mus[i] for i in range(len(mus) - 1))
-    ok, _, _ = I.converged(A, b, c, r["x"], r["y"], r["z"], 1e-8)
+    ok, _, _ = I.converged(A, b, c, np.zeros(150), np.full(150, np.inf), r["state"], 1e-8)
     assert ok
 
 
