@@ -215,22 +215,24 @@ def cpu_baseline(lp):
 
 
 def run_ipm(lp, opts, prec, args):
-    """The interior point driver (qdmf_ipm_solve) on the LP min c^T x, A x = b, x >= 0 with the
-    workload's A and b, c from workloads.feasible_lp; one untimed run (warm-up), then the timed
-    runs; value = milliseconds per IPM iteration."""
+    """The interior point driver (qdmf_ipm_solve) on the LP min c^T x, A x = b, l <= x <= u with
+    the workload's A and b, c, l, u from workloads.bounded_lp (a fraction --ipm-upper of the
+    columns with a finite upper bound); one untimed run (warm-up), then the timed runs;
+    value = milliseconds per IPM iteration."""
     import torch
     from paper_2508_04370_amd import qdmf as Q
-    lpf, b, c = W.feasible_lp(lp, seed=7)
+    lpf, b, c, l, u = W.bounded_lp(lp, seed=7, upper=args.ipm_upper)
     dev = "cuda:0"
     s = Q.Solver(lpf, device=0, **{k: v for k, v in opts.items() if k in ("ordering", "grid")})
-    bd, cd = torch.from_numpy(b).to(dev), torch.from_numpy(c).to(dev)
+    bd, cd, ld, ud = (torch.from_numpy(v).to(dev) for v in (b, c, l, u))
     x = torch.empty(lpf["n"], dtype=torch.float64, device=dev)
-    z = torch.empty(lpf["n"], dtype=torch.float64, device=dev)
+    zl = torch.empty(lpf["n"], dtype=torch.float64, device=dev)
+    zu = torch.empty(lpf["n"], dtype=torch.float64, device=dev)
     y = torch.empty(lpf["m"], dtype=torch.float64, device=dev)
     opt = Q.qdmf_ipm_default_options(prec=prec)
     runs = []
     for k in range(args.warmup + args.steps):
-        info, hist = Q.qdmf_ipm_solve(s.h, bd, cd, x, y, z, opt)
+        info, hist = Q.qdmf_ipm_solve(s.h, bd, cd, x, y, zl, opt, l=ld, u=ud, zu=zu)
         print(f"[bench] ipm run {k}: status {info['status']} iters {info['iters']} {info['ms']:.1f} ms",
               file=sys.stderr, flush=True)
         if k >= args.warmup:
@@ -241,8 +243,8 @@ def run_ipm(lp, opts, prec, args):
            "value": round(float(np.median(ms_it)), 4), "unit": "ms/iteration", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if prec == 0 else "f64+f32", "data": "synthetic",
-           "config": {"workload": lp["name"] + "_feasible_lp", "m": lpf["m"], "n": lpf["n"], "mode": "AS",
-                      "precision": args.prec},
+           "config": {"workload": lp["name"] + "_bounded_lp", "m": lpf["m"], "n": lpf["n"], "mode": "AS",
+                      "upper_bounded_fraction": args.ipm_upper, "precision": args.prec},
            "ipm": {"status": last["status"], "iterations": last["iters"], "correctors": last["correctors"],
                    "primal_obj": last["primal_obj"], "dual_obj": last["dual_obj"], "pinf": last["pinf"],
                    "dinf": last["dinf"], "ms_total": round(last["ms"], 3)}}
@@ -265,6 +267,8 @@ def main():
     ap.add_argument("--ipm", action="store_true",
                     help="instead: the interior point driver on a feasible LP over the workload's A "
                          "(one JSON line, ms per IPM iteration)")
+    ap.add_argument("--ipm-upper", type=float, default=0.5,
+                    help="--ipm: fraction of the columns with a finite upper bound")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()

@@ -273,13 +273,19 @@ int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
 /* Interior point driver around the factorise and solve calls (Section 3: Newton system
  * reduced to the augmented system, predictor with sigma = 0, centrality correctors from the
  * complementarity products at the trial point, steps to the boundary, the termination test of
- * Section 3.1; Section 4.7: the number of correctors).  LP: min c^T x subject to A x = b and
- * x >= 0, the paper's formulation with every lower bound at zero and no upper bounds; A is the
+ * Section 3.1; Section 4.7: the number of correctors).  LP of Section 2:
+ *     min c^T x  subject to  A x = b,  l <= x <= u,
+ * with slacks x^l = x - l, x^u = u - x and multipliers z^l, z^u.  Every l_j must be finite
+ * (no free variables, as the paper assumes); u_j is finite and above l_j, or +inf.  A is the
  * matrix of the handle, which must be analysed in QDMF_AS mode with qdmf_set_matrix called.
- * Start: x = z = 1, y = 0.  b (m), c (n) and x, z (n), y (m) are caller-owned device buffers;
- * x, y, z receive the last iterate.  Runs on the handle's stream and synchronises it several
- * times per iteration.  Errors: QDMF_ERR_INVALID_ARG, QDMF_ERR_NOT_ANALYSED (or not AS),
- * QDMF_ERR_NO_MATRIX, QDMF_ERR_HIP, QDMF_ERR_OOM, and the codes of qdmf_factorise / qdmf_solve. */
+ * Start: x = l + 1 (the midpoint of [l, u] where u - l < 2), z^l = 1, z^u = 1 where u is
+ * finite, y = 0.
+ * Arguments (caller-owned device buffers): b (m), c (n); l (n) or NULL for l = 0; u (n) or
+ * NULL for u = +inf everywhere; x, z^l (n) and y (m) receive the last iterate; zu (n) receives
+ * z^u (0 where u is infinite) or is NULL.  Runs on the handle's stream and synchronises it
+ * several times per iteration.  Errors: QDMF_ERR_INVALID_ARG (also for a bad bound),
+ * QDMF_ERR_NOT_ANALYSED (or not AS), QDMF_ERR_NO_MATRIX, QDMF_ERR_HIP, QDMF_ERR_OOM, and the
+ * codes of qdmf_factorise / qdmf_solve. */
 typedef struct {
     double tau;               /* feasibility and optimality tolerance (Section 3.1), 1e-8     */
     double rho, delta;        /* static regularisation of every factorisation (Section 3.2),
@@ -296,8 +302,9 @@ typedef struct {
     int32_t iters;            /* iterations taken (factorisations)                           */
     int32_t correctors;       /* correctors allowed per iteration                            */
     double primal_obj, dual_obj;
-    double pinf, dinf;        /* ||b - A x||_inf and ||c - A^T y - z||_inf at the last iterate */
-    double mu;                /* x^T z / n at the last iterate                               */
+    double pinf;              /* max of ||b - A x||_inf, ||l - x + x^l||_inf, ||u - x - x^u||_inf */
+    double dinf;              /* ||c - A^T y - z^l + z^u||_inf                               */
+    double mu;                /* mean complementarity product at the last iterate            */
     double ms;                /* wall time of the iterations                                 */
 } qdmf_ipm_info;
 
@@ -305,8 +312,9 @@ void qdmf_ipm_default_options(qdmf_ipm_options* opt);
 
 /* history: NULL or room for 4 * max_iter doubles; per iteration it receives mu, alpha_p,
  * alpha_d and the number of correctors used. */
-int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, double* x_dev, double* y_dev,
-                   double* z_dev, const qdmf_ipm_options* opt, qdmf_ipm_info* info, double* history);
+int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, const double* l_dev,
+                   const double* u_dev, double* x_dev, double* y_dev, double* zl_dev, double* zu_dev,
+                   const qdmf_ipm_options* opt, qdmf_ipm_info* info, double* history);
 
 /* Frees everything the handle owns.  NULL is ignored. */
 void qdmf_destroy(qdmf_handle h);

@@ -995,11 +995,12 @@ void qdmf_ipm_default_options(qdmf_ipm_options* o) {
     o->prec = QDMF_FP64;
 }
 
-int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, double* x_dev, double* y_dev,
-                   double* z_dev, const qdmf_ipm_options* opt_in, qdmf_ipm_info* info, double* history) {
+int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, const double* l_dev,
+                   const double* u_dev, double* x_dev, double* y_dev, double* zl_dev, double* zu_dev,
+                   const qdmf_ipm_options* opt_in, qdmf_ipm_info* info, double* history) {
     // readings shared with the reference implementation the tests compare against
     constexpr double STEP_FACTOR = 0.995, ALPHA_PLUS = 0.1, BETA_MIN = 0.1, BETA_MAX = 10.0, ACCEPT_GAIN = 0.01;
-    if (!h || !info || !b_dev || !c_dev || !x_dev || !y_dev || !z_dev || h->host_only) return QDMF_ERR_INVALID_ARG;
+    if (!h || !info || !b_dev || !c_dev || !x_dev || !y_dev || !zl_dev || h->host_only) return QDMF_ERR_INVALID_ARG;
     if (!h->analysed || h->P.mode != QDMF_AS || h->P.nsys != 1) return QDMF_ERR_NOT_ANALYSED;
     if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
     qdmf_ipm_options opt;
@@ -1029,12 +1030,17 @@ int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, doub
         mem.push_back(*p);
         return true;
     };
-    double *theta, *r1, *r4, *r5, *r7, *zm, *ax, *ay, *az, *bx, *by, *bz, *cx, *cy, *cz, *part, *out;
-    const int64_t nparts = 8 * (int64_t)ipm_blocks(std::max(n, m));
-    bool ok = alloc(&theta, n) && alloc(&r1, m) && alloc(&r4, n) && alloc(&r5, n) && alloc(&r7, n) &&
-              alloc(&zm, m) && alloc(&ax, n) && alloc(&ay, m) && alloc(&az, n) && alloc(&bx, n) && alloc(&by, m) &&
-              alloc(&bz, n) && alloc(&cx, n) && alloc(&cy, m) && alloc(&cz, n) && alloc(&part, nparts) &&
-              alloc(&out, 8);
+    auto alloc_vec = [&](IpmVec& v) {
+        return alloc(&v.x, n) && alloc(&v.xl, n) && alloc(&v.xu, n) && alloc(&v.y, m) && alloc(&v.zl, n) &&
+               alloc(&v.zu, n);
+    };
+    IpmVec pt{x_dev, nullptr, nullptr, y_dev, zl_dev, zu_dev}, da{}, db{}, dc{};
+    double *theta, *r1, *r2, *r3, *r4, *r5, *r6, *r7, *zm, *part, *out;
+    const int64_t nparts = IPM_PART * (int64_t)ipm_blocks(std::max(n, m));
+    bool ok = alloc(&pt.xl, n) && alloc(&pt.xu, n) && (zu_dev || alloc(&pt.zu, n)) && alloc_vec(da) &&
+              alloc_vec(db) && alloc_vec(dc) && alloc(&theta, n) && alloc(&r1, m) && alloc(&r2, n) &&
+              alloc(&r3, n) && alloc(&r4, n) && alloc(&r5, n) && alloc(&r6, n) && alloc(&r7, n) && alloc(&zm, m) &&
+              alloc(&part, nparts) && alloc(&out, 16);
     auto release = [&]() {
         for (void* p : mem) (void)hipFree(p);
     };
@@ -1042,80 +1048,87 @@ int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, doub
         release();
         return QDMF_ERR_OOM;
     }
-    double sc[8];
+    double sc[16];
     auto read = [&](int cnt) {
         return hipMemcpyAsync(sc, out, sizeof(double) * cnt, hipMemcpyDeviceToHost, st) == hipSuccess &&
                hipStreamSynchronize(st) == hipSuccess;
     };
     const auto t0 = std::chrono::steady_clock::now();
-    ipm_fill(x_dev, 1.0, n, st);
-    ipm_fill(z_dev, 1.0, n, st);
-    ipm_fill(y_dev, 0.0, m, st);
+    ipm_start(l_dev, u_dev, pt, n, m, part, out, st);
     ipm_fill(zm, 0.0, m, st);
+    if (!read(2)) {
+        release();
+        return QDMF_ERR_HIP;
+    }
+    if (sc[0] != 0.0) {
+        release();
+        h->msg = "qdmf_ipm_solve: every l must be finite and every finite u above its l";
+        return QDMF_ERR_INVALID_ARG;
+    }
+    const double ncomp = (double)n + sc[1];  // complementarity pairs
     qdmf_ipm_info res{};
     res.status = QDMF_WARN_NOT_CONVERGED;
     res.correctors = k;
     int it = 0;
     rc = 0;
     for (;; ++it) {
-        ipm_resid(h->D, x_dev, y_dev, z_dev, b_dev, c_dev, r1, r4, part, out, st);
-        if (!read(7)) {
+        ipm_resid(h->D, pt, b_dev, c_dev, l_dev, u_dev, r1, r2, r3, r4, part, out, st);
+        if (!read(13)) {
             rc = QDMF_ERR_HIP;
             break;
         }
-        const double pinf = sc[0], dinf = sc[1], fp = sc[2], fd = sc[3], xz = sc[4], bmax = sc[5], cmax = sc[6];
+        const double pinf = std::max(sc[0], std::max(sc[7], sc[8])), dinf = sc[1];
+        const double fp = sc[2], fd = sc[3] + sc[9] - sc[10], comp = sc[4];
+        const double pscale = std::max(sc[5], std::max(sc[11], sc[12])), cmax = sc[6];
         res.pinf = pinf;
         res.dinf = dinf;
         res.primal_obj = fp;
         res.dual_obj = fd;
-        res.mu = n ? xz / n : 0.0;
+        res.mu = ncomp > 0 ? comp / ncomp : 0.0;
         // Section 3.1, without scaling
-        if (pinf <= opt.tau * (1.0 + bmax) && dinf <= opt.tau * (1.0 + cmax) &&
+        if (pinf <= opt.tau * (1.0 + pscale) && dinf <= opt.tau * (1.0 + cmax) &&
             std::fabs(fp - fd) <= opt.tau * (1.0 + 0.5 * std::fabs(fp + fd))) {
             res.status = 0;
             break;
         }
         if (it >= opt.max_iter) break;
         const double mu = res.mu;
-        ipm_theta(x_dev, z_dev, theta, n, st);
+        ipm_theta(pt, u_dev, theta, n, st);
         if ((rc = qdmf_factorise(h, theta, opt.rho, opt.delta, opt.prec)) < 0) break;
         // predictor (sigma = 0)
-        ipm_r5r7(0, x_dev, z_dev, r4, nullptr, nullptr, 0.0, 0.0, 0.0, 0.0, 0.0, r5, r7, n, st);
-        if ((rc = qdmf_solve(h, 1, r7, r1, ax, ay)) < 0) break;
-        ipm_dz(x_dev, z_dev, r5, ax, az, n, st);
-        ipm_step(x_dev, ax, z_dev, az, part, out, n, st);
+        ipm_rhs(0, pt, da, u_dev, r2, r3, r4, 0.0, 0.0, 0.0, 0.0, 0.0, r5, r6, r7, n, st);
+        if ((rc = qdmf_solve(h, 1, r7, r1, da.x, da.y)) < 0) break;
+        ipm_recover(pt, da, u_dev, r2, r3, r5, r6, n, st);
+        ipm_step(pt, da, u_dev, part, out, n, st);
         if (!read(2)) {
             rc = QDMF_ERR_HIP;
             break;
         }
         double ap = -sc[0], ad = -sc[1];
-        ipm_comp(x_dev, ax, z_dev, az, ap, ad, part, out, n, st);
+        ipm_comp(pt, da, u_dev, ap, ad, part, out, n, st);
         if (!read(1)) {
             rc = QDMF_ERR_HIP;
             break;
         }
-        const double mu_aff = sc[0] / n, sigma = (mu_aff / mu) * (mu_aff / mu) * (mu_aff / mu), smu = sigma * mu;
-        // correctors: r1 = r4 = 0, r5 moves the products at the trial point into the band
-        double *dx = ax, *dy = ay, *dz = az, *nx = bx, *ny = by, *nz = bz;
+        const double mu_aff = sc[0] / ncomp, sigma = (mu_aff / mu) * (mu_aff / mu) * (mu_aff / mu), smu = sigma * mu;
+        // correctors: r1 = r2 = r3 = r4 = 0; r5, r6 move the products at the trial point into
+        // the band [BETA_MIN, BETA_MAX] * sigma * mu
+        IpmVec d = da, nd = db;
         int used = 0;
         for (int j = 0; j < k; ++j) {
             const double tp = std::min(1.0, ap + ALPHA_PLUS), td = std::min(1.0, ad + ALPHA_PLUS);
-            ipm_r5r7(1, x_dev, z_dev, nullptr, dx, dz, smu, tp, td, BETA_MIN, BETA_MAX, r5, r7, n, st);
-            if ((rc = qdmf_solve(h, 1, r7, zm, cx, cy)) < 0) break;
-            ipm_dz(x_dev, z_dev, r5, cx, cz, n, st);
-            ipm_add(dx, cx, nx, n, st);
-            ipm_add(dy, cy, ny, m, st);
-            ipm_add(dz, cz, nz, n, st);
-            ipm_step(x_dev, nx, z_dev, nz, part, out, n, st);
+            ipm_rhs(1, pt, d, u_dev, nullptr, nullptr, nullptr, smu, tp, td, BETA_MIN, BETA_MAX, r5, r6, r7, n, st);
+            if ((rc = qdmf_solve(h, 1, r7, zm, dc.x, dc.y)) < 0) break;
+            ipm_recover(pt, dc, u_dev, nullptr, nullptr, r5, r6, n, st);
+            ipm_add(d, dc, nd, n, m, st);
+            ipm_step(pt, nd, u_dev, part, out, n, st);
             if (!read(2)) {
                 rc = QDMF_ERR_HIP;
                 break;
             }
             const double nap = -sc[0], nad = -sc[1];
             if (j > 0 && nap + nad < (1.0 + ACCEPT_GAIN) * (ap + ad)) break;
-            std::swap(dx, nx);  // the accepted direction; the old one's buffers become the spares
-            std::swap(dy, ny);
-            std::swap(dz, nz);
+            std::swap(d, nd);  // the accepted direction; the old one's buffers become the spares
             ap = nap;
             ad = nad;
             ++used;
@@ -1127,7 +1140,7 @@ int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, doub
             history[4 * it + 2] = ad;
             history[4 * it + 3] = used;
         }
-        ipm_update(x_dev, y_dev, z_dev, dx, dy, dz, STEP_FACTOR * ap, STEP_FACTOR * ad, n, m, st);
+        ipm_update(pt, d, STEP_FACTOR * ap, STEP_FACTOR * ad, n, m, st);
     }
     if (hipStreamSynchronize(st) != hipSuccess && rc == 0) rc = QDMF_ERR_HIP;
     res.iters = it;

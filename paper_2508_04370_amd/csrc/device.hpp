@@ -155,23 +155,36 @@ void launch_solve_level(bool forward, const DevPlan& D, const DevSolve& S, const
                         hipStream_t s);
 // Inverses of the diagonal blocks used by the one-workgroup solves (after the factorisation).
 void launch_inv(const DevPlan& D, const Task* tasks, int64_t ntask, hipStream_t s);
-// Interior point driver kernels (ipm.hip).  out: device scalars; part: 8 x ipm_blocks(len)
-// doubles of partials.
+// Interior point driver kernels (ipm.hip).  A point or a direction of the bounded LP
+// min c^T x, A x = b, x - x^l = l, x + x^u = u: the six vectors x, x^l, x^u, y, z^l, z^u
+// (y of length m, the others n).  Entries of x^u and z^u without a finite upper bound stay 0.
+// l == nullptr means l = 0; u == nullptr means u = +inf everywhere.  out: device scalars;
+// part: IPM_PART x ipm_blocks(len) doubles of partials.
+struct IpmVec {
+    double *x, *xl, *xu, *y, *zl, *zu;
+};
+constexpr int IPM_PART = 16;
 int ipm_blocks(int64_t len);
-void ipm_resid(const DevPlan& D, const double* x, const double* y, const double* z, const double* b,
-               const double* c, double* r1, double* r4, double* part, double* out, hipStream_t s);
-void ipm_theta(const double* x, const double* z, double* theta, int n, hipStream_t s);
-void ipm_r5r7(int mode, const double* x, const double* z, const double* r4, const double* dx, const double* dz,
-              double smu, double tp, double td, double bmin, double bmax, double* r5, double* r7, int n,
+// start point and argument check; out[0] = number of bad bounds, out[1] = number of finite u
+void ipm_start(const double* l, const double* u, IpmVec p, int n, int m, double* part, double* out, hipStream_t s);
+// r1..r4 and the scalars of the termination test (out[0..12], see ipm.hip)
+void ipm_resid(const DevPlan& D, IpmVec p, const double* b, const double* c, const double* l, const double* u,
+               double* r1, double* r2, double* r3, double* r4, double* part, double* out, hipStream_t s);
+void ipm_theta(IpmVec p, const double* u, double* theta, int n, hipStream_t s);
+// mode 0: predictor right-hand sides r5, r6, r7; mode 1: centrality corrector from direction d
+void ipm_rhs(int mode, IpmVec p, IpmVec d, const double* u, const double* r2, const double* r3, const double* r4,
+             double smu, double tp, double td, double bmin, double bmax, double* r5, double* r6, double* r7, int n,
+             hipStream_t s);
+// the rest of a direction from its dx (r2 == r3 == nullptr: zero)
+void ipm_recover(IpmVec p, IpmVec d, const double* u, const double* r2, const double* r3, const double* r5,
+                 const double* r6, int n, hipStream_t s);
+void ipm_add(IpmVec a, IpmVec b, IpmVec out, int n, int m, hipStream_t s);
+// out[0] = -alpha_p, out[1] = -alpha_d (steps to the boundary, at most 1)
+void ipm_step(IpmVec p, IpmVec d, const double* u, double* part, double* out, int n, hipStream_t s);
+// out[0] = sum of the complementarity products at p + (ap, ad) d
+void ipm_comp(IpmVec p, IpmVec d, const double* u, double ap, double ad, double* part, double* out, int n,
               hipStream_t s);
-void ipm_dz(const double* x, const double* z, const double* r5, const double* dx, double* dz, int n, hipStream_t s);
-void ipm_add(const double* a, const double* b, double* out, int len, hipStream_t s);
-void ipm_step(const double* x, const double* dx, const double* z, const double* dz, double* part, double* out,
-              int n, hipStream_t s);
-void ipm_comp(const double* x, const double* dx, const double* z, const double* dz, double ap, double ad,
-              double* part, double* out, int n, hipStream_t s);
-void ipm_update(double* x, double* y, double* z, const double* dx, const double* dy, const double* dz, double sp,
-                double sd, int n, int m, hipStream_t s);
+void ipm_update(IpmVec p, IpmVec d, double sp, double sd, int n, int m, hipStream_t s);
 void ipm_fill(double* v, double a, int len, hipStream_t s);
 // One launch of the big-supernode solves (kind: SolveKind).
 void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L, const Task* stasks,

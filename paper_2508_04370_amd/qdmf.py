@@ -113,7 +113,7 @@ def lib():
         L.qdmf_choose_mode.argtypes = [P, I32, I32, P, P, C.POINTER(qdmf_mode_choice)]
         L.qdmf_ipm_default_options.argtypes = [C.POINTER(qdmf_ipm_options)]
         L.qdmf_ipm_default_options.restype = None
-        L.qdmf_ipm_solve.argtypes = [P, P, P, P, P, P, C.POINTER(qdmf_ipm_options), C.POINTER(qdmf_ipm_info), P]
+        L.qdmf_ipm_solve.argtypes = [P, P, P, P, P, P, P, P, P, C.POINTER(qdmf_ipm_options), C.POINTER(qdmf_ipm_info), P]
         L.qdmf_symbolic.argtypes = [P, C.POINTER(qdmf_symbolic_info)]
         L.qdmf_set_matrix.argtypes = [P, P, I32]
         L.qdmf_factorise.argtypes = [P, P, D, D, I32]
@@ -204,14 +204,16 @@ def qdmf_ipm_default_options(**overrides):
     return o
 
 
-def qdmf_ipm_solve(h, b, c, x, y, z, opt=None):
-    """Interior point driver on device tensors b (m), c (n), x, z (n), y (m) (contiguous
-    float64).  Returns (info dict, history array of shape (iters, 4): mu, alpha_p, alpha_d,
-    correctors used).  A positive status (iteration limit) is returned in the dict."""
+def qdmf_ipm_solve(h, b, c, x, y, zl, opt=None, l=None, u=None, zu=None):
+    """Interior point driver on device tensors (contiguous float64): b (m), c (n), optional
+    bounds l, u (n; None: l = 0, u = +inf), and outputs x, zl (n), y (m) and optional zu (n).
+    Returns (info dict, history array of shape (iters, 4): mu, alpha_p, alpha_d, correctors
+    used).  A positive status (iteration limit) is returned in the dict."""
     opt = opt if opt is not None else qdmf_ipm_default_options()
     info = qdmf_ipm_info()
     hist = np.zeros(4 * max(1, opt.max_iter))
-    rc = lib().qdmf_ipm_solve(h, _dev(b), _dev(c), _dev(x), _dev(y), _dev(z), C.byref(opt), C.byref(info), _np(hist))
+    rc = lib().qdmf_ipm_solve(h, _dev(b), _dev(c), _dev(l), _dev(u), _dev(x), _dev(y), _dev(zl), _dev(zu),
+                              C.byref(opt), C.byref(info), _np(hist))
     if rc < 0:
         _check(rc, "qdmf_ipm_solve", h)
     out = {k: getattr(info, k) for k, _ in qdmf_ipm_info._fields_}
