@@ -54,6 +54,10 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.orc_analyse.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, C.POINTER(P)]
+        L.orc_analyse_qp.argtypes = [C.c_int, C.c_int, P, P, P, P, P, C.POINTER(P)]
+        L.orc_factorise_qp.argtypes = [P, P, P, P, C.c_double, C.c_double, C.POINTER(Opts), C.POINTER(P)]
+        L.orc_residual_qp.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, P, P, P, P, C.c_double,
+                                      C.c_double, P, P, P, P, P, P]
         L.orc_sym_free.argtypes = [P]
         for nm in ("orc_sym_info", "orc_sym_perm", "orc_sym_parent", "orc_sym_colcount",
                    "orc_sym_snptr", "orc_sym_snparent"):
@@ -87,17 +91,32 @@ def default_opts(**kw):
     return o
 
 
+def _qp(lp):
+    """Q's lower-triangle pattern of a quadratic program (lp keys q_colptr, q_rowidx) or None."""
+    if lp.get("q_colptr") is None:
+        return None, None
+    return (np.ascontiguousarray(lp["q_colptr"], np.int64), np.ascontiguousarray(lp["q_rowidx"], np.int32))
+
+
 class Sym:
-    """Symbolic analysis: ordering, elimination tree, fundamental supernodes."""
+    """Symbolic analysis: ordering, elimination tree, fundamental supernodes.  A quadratic
+    program (AS only) carries Q's lower triangle in lp["q_colptr"], lp["q_rowidx"]."""
 
     def __init__(self, lp, perm=None):
         self.lp = lp
         self._cp = np.ascontiguousarray(lp["colptr"], np.int64)
         self._ri = np.ascontiguousarray(lp["rowidx"], np.int32)
+        self._qcp, self._qri = _qp(lp)
         up = None if perm is None else np.ascontiguousarray(perm, np.int32)
         h = C.c_void_p()
-        rc = lib().orc_analyse(lp["m"], lp["n"], _p(self._cp), _p(self._ri), lp["mode"], _p(up),
-                               C.byref(h))
+        if self._qcp is None:
+            rc = lib().orc_analyse(lp["m"], lp["n"], _p(self._cp), _p(self._ri), lp["mode"], _p(up),
+                                   C.byref(h))
+        else:
+            if lp["mode"] != AS:
+                raise ValueError("quadratic programs need the augmented system")
+            rc = lib().orc_analyse_qp(lp["m"], lp["n"], _p(self._cp), _p(self._ri), _p(self._qcp),
+                                      _p(self._qri), _p(up), C.byref(h))
         if rc != 0:
             raise ValueError(f"orc_analyse failed ({rc})")
         self.h = h
@@ -139,16 +158,22 @@ class Sym:
 
 
 class Num:
-    """Numeric factorisation P (K_static + E_dyn) P^T = L D L^T."""
+    """Numeric factorisation P (K_static + E_dyn) P^T = L D L^T.  qval: Q's lower values of a
+    quadratic program (default lp["q_val"])."""
 
-    def __init__(self, sym, aval, theta, rho, delta, opts=None):
+    def __init__(self, sym, aval, theta, rho, delta, opts=None, qval=None):
         self.sym = sym
         self.opts = opts or default_opts()
         self._a = np.ascontiguousarray(aval, np.float64)
         self._t = np.ascontiguousarray(theta, np.float64)
         h = C.c_void_p()
-        rc = lib().orc_factorise(sym.h, _p(self._a), _p(self._t), float(rho), float(delta),
-                                 C.byref(self.opts), C.byref(h))
+        if sym._qcp is None:
+            rc = lib().orc_factorise(sym.h, _p(self._a), _p(self._t), float(rho), float(delta),
+                                     C.byref(self.opts), C.byref(h))
+        else:
+            self._q = np.ascontiguousarray(sym.lp["q_val"] if qval is None else qval, np.float64)
+            rc = lib().orc_factorise_qp(sym.h, _p(self._a), _p(self._q), _p(self._t), float(rho),
+                                        float(delta), C.byref(self.opts), C.byref(h))
         if rc != 0:
             raise ValueError(f"orc_factorise failed ({rc})")
         self.h = h
@@ -186,7 +211,8 @@ class Num:
 
 
 def residual(lp, theta, rho, delta, x, b):
-    """r = b - K_static x and the backward errors, from A, Theta, rho, delta directly."""
+    """r = b - K_static x and the backward errors, from A, Theta, rho, delta (and Q of a
+    quadratic program) directly."""
     cp = np.ascontiguousarray(lp["colptr"], np.int64)
     ri = np.ascontiguousarray(lp["rowidx"], np.int32)
     av = np.ascontiguousarray(lp["val"], np.float64)
@@ -195,8 +221,17 @@ def residual(lp, theta, rho, delta, x, b):
     b = np.ascontiguousarray(b, np.float64)
     r = np.zeros_like(x)
     nw = C.c_double(); cw = C.c_double(); kn = C.c_double()
-    lib().orc_residual(lp["m"], lp["n"], _p(cp), _p(ri), _p(av), lp["mode"], _p(th), float(rho),
-                       float(delta), _p(x), _p(b), _p(r), C.byref(nw), C.byref(cw), C.byref(kn))
+    qcp, qri = _qp(lp)
+    if qcp is None:
+        lib().orc_residual(lp["m"], lp["n"], _p(cp), _p(ri), _p(av), lp["mode"], _p(th), float(rho),
+                           float(delta), _p(x), _p(b), _p(r), C.byref(nw), C.byref(cw), C.byref(kn))
+    else:
+        qv = np.ascontiguousarray(lp["q_val"], np.float64)
+        rc = lib().orc_residual_qp(lp["m"], lp["n"], _p(cp), _p(ri), _p(av), lp["mode"], _p(qcp), _p(qri),
+                                   _p(qv), _p(th), float(rho), float(delta), _p(x), _p(b), _p(r),
+                                   C.byref(nw), C.byref(cw), C.byref(kn))
+        if rc != 0:
+            raise ValueError(f"orc_residual_qp failed ({rc})")
     return r, nw.value, cw.value, kn.value
 
 

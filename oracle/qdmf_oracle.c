@@ -20,7 +20,10 @@
  *    the regularised diagonal |F_jj + s_j| (zero denominators skipped and counted);
  *  - a pivot that still has the wrong sign is flipped to sign sigma_k with magnitude
  *    max(|d|, beta, eps*||K||_1) (Section 4.6: signs must not change);
- *  - a 2x2 pivot with zero determinant falls back to a lifted 1x1 pivot.
+ *  - a 2x2 pivot with zero determinant falls back to a lifted 1x1 pivot;
+ *  - quadratic programs (AS only): the (1,1) block is -(Q + Theta^-1 + rho I); Q's
+ *    off-diagonal couplings join the pattern, and the pivot signs and shifts are those of
+ *    the LP (Q positive semidefinite keeps the matrix quasidefinite).
  */
 #include "qdmf_oracle.h"
 
@@ -50,6 +53,9 @@ struct orc_sym {
     /* copy of A pattern (needed by the numeric phase) */
     int64_t* acp;
     int32_t* ari;
+    /* quadratic programs: lower triangle of Q (n x n CSC), NULL for an LP */
+    int64_t* qcp;
+    int32_t* qri;
 };
 
 struct orc_num {
@@ -58,6 +64,7 @@ struct orc_num {
     double rho, delta;
     double* theta; /* copy */
     double* aval;  /* copy */
+    double* qval;  /* copy of Q's lower values, NULL for an LP */
     double* kval;  /* K0 values on S->kp/ki (original numbering) */
     int64_t* Lptr; /* per supernode offset of its f x p panel (ld = f) */
     double* L;
@@ -107,7 +114,7 @@ static int cmp_i32(const void* a, const void* b) {
  * (equation (augsys)).  NE nodes are the rows of A, with i -- k iff some column of A has
  * both (equation (normeq)). */
 static ivec* build_adjacency(int m, int n, const int64_t* cp, const int32_t* ri, int mode,
-                             int* Nout) {
+                             const int64_t* qcp, const int32_t* qri, int* Nout) {
     int N = (mode == ORC_AS) ? n + m : m;
     ivec* adj = (ivec*)calloc((size_t)N, sizeof(ivec));
     if (mode == ORC_AS) {
@@ -116,6 +123,14 @@ static ivec* build_adjacency(int m, int n, const int64_t* cp, const int32_t* ri,
                 iv_push(&adj[j], n + ri[e]);
                 iv_push(&adj[n + ri[e]], j);
             }
+        /* quadratic programs: x_j -- x_k iff Q_kj != 0, k != j */
+        if (qcp)
+            for (int j = 0; j < n; ++j)
+                for (int64_t e = qcp[j]; e < qcp[j + 1]; ++e)
+                    if (qri[e] != j) {
+                        iv_push(&adj[j], qri[e]);
+                        iv_push(&adj[qri[e]], j);
+                    }
     } else {
         for (int j = 0; j < n; ++j)
             for (int64_t a = cp[j]; a < cp[j + 1]; ++a)
@@ -294,11 +309,17 @@ static void postorder(int N, const int32_t* parent, int32_t* post /* post[k] = n
 /* Lower pattern of K (diagonal + lower adjacency, original numbering) and a copy of A's
  * pattern: everything the value formation and the residual need, and no factorisation. */
 static orc_sym* pattern_only(int m, int n, const int64_t* cp, const int32_t* ri, int mode,
-                             ivec** adj_out) {
+                             const int64_t* qcp, const int32_t* qri, ivec** adj_out) {
     orc_sym* S = (orc_sym*)calloc(1, sizeof(orc_sym));
     S->m = m; S->n = n; S->mode = mode;
     int N;
-    ivec* adj = build_adjacency(m, n, cp, ri, mode, &N);
+    ivec* adj = build_adjacency(m, n, cp, ri, mode, qcp, qri, &N);
+    if (qcp) {
+        S->qcp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        memcpy(S->qcp, qcp, sizeof(int64_t) * (size_t)(n + 1));
+        S->qri = (int32_t*)malloc(sizeof(int32_t) * (size_t)(qcp[n] ? qcp[n] : 1));
+        memcpy(S->qri, qri, sizeof(int32_t) * (size_t)qcp[n]);
+    }
     S->N = N;
     S->acp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
     memcpy(S->acp, cp, sizeof(int64_t) * (size_t)(n + 1));
@@ -326,11 +347,40 @@ static orc_sym* pattern_only(int m, int n, const int64_t* cp, const int32_t* ri,
     return S;
 }
 
+/* Q's lower triangle: rows >= the column, strictly increasing, inside [0, n) */
+static int q_pattern_ok(int n, const int64_t* qcp, const int32_t* qri) {
+    if (qcp[0] != 0) return 0;
+    for (int j = 0; j < n; ++j) {
+        if (qcp[j + 1] < qcp[j]) return 0;
+        for (int64_t e = qcp[j]; e < qcp[j + 1]; ++e) {
+            if (qri[e] < j || qri[e] >= n) return 0;
+            if (e > qcp[j] && qri[e] <= qri[e - 1]) return 0;
+        }
+    }
+    return 1;
+}
+
+static int analyse_impl(int m, int n, const int64_t* cp, const int32_t* ri, int mode,
+                        const int64_t* qcp, const int32_t* qri, const int32_t* user_perm,
+                        orc_sym** out);
+
 int orc_analyse(int m, int n, const int64_t* cp, const int32_t* ri, int mode,
                 const int32_t* user_perm, orc_sym** out) {
+    return analyse_impl(m, n, cp, ri, mode, NULL, NULL, user_perm, out);
+}
+
+int orc_analyse_qp(int m, int n, const int64_t* cp, const int32_t* ri, const int64_t* qcp,
+                   const int32_t* qri, const int32_t* user_perm, orc_sym** out) {
+    if (n < 0 || !qcp || !qri || !q_pattern_ok(n, qcp, qri)) return -1;
+    return analyse_impl(m, n, cp, ri, ORC_AS, qcp, qri, user_perm, out);
+}
+
+static int analyse_impl(int m, int n, const int64_t* cp, const int32_t* ri, int mode,
+                        const int64_t* qcp, const int32_t* qri, const int32_t* user_perm,
+                        orc_sym** out) {
     if (m < 0 || n < 0 || !cp || !ri || !out) return -1;
     ivec* adj = NULL;
-    orc_sym* S = pattern_only(m, n, cp, ri, mode, &adj);
+    orc_sym* S = pattern_only(m, n, cp, ri, mode, qcp, qri, &adj);
     int N = S->N;
     /* ordering */
     int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N ? N : 1));
@@ -429,7 +479,7 @@ void orc_sym_free(orc_sym* S) {
     if (!S) return;
     free(S->kp); free(S->ki); free(S->perm); free(S->iperm); free(S->parent);
     free(S->colcount); free(S->snptr); free(S->snparent); free(S->col2sn);
-    free(S->rowptr); free(S->rows); free(S->acp); free(S->ari);
+    free(S->rowptr); free(S->rows); free(S->acp); free(S->ari); free(S->qcp); free(S->qri);
     free(S);
 }
 
@@ -452,19 +502,38 @@ void orc_sym_front_rows(const orc_sym* S, int64_t* rp, int32_t* rows) {
 
 /* ------------------------------------------------------------------ values of K (Sections 3, 3.2) */
 
+/* Q_jj of a quadratic program (0 if absent or an LP) */
+static double q_diag(const int64_t* qcp, const int32_t* qri, const double* qval, int j) {
+    if (!qcp || qcp[j] == qcp[j + 1] || qri[qcp[j]] != j) return 0.0;
+    return qval[qcp[j]];
+}
+
 /* K0 = the matrix before static shifts: AS: [[-diag(1/Theta), A^T],[A, 0]] (equation
- * (augsys)); NE: A diag(theta~) A^T with theta~_j = 1/(1/Theta_j + rho) (equations (normeq),
+ * (augsys)), for a quadratic program [[-(Q + diag(1/Theta)), A^T],[A, 0]]; NE:
+ * A diag(theta~) A^T with theta~_j = 1/(1/Theta_j + rho) (equations (normeq),
  * (regul_matrix)), every entry summed over the columns j of A in ascending order.
  * Values are stored on S->kp/ki (lower part, original numbering). */
-static double* form_k0(const orc_sym* S, const double* aval, const double* theta, double rho) {
+static double* form_k0(const orc_sym* S, const double* aval, const double* qval,
+                       const double* theta, double rho) {
     int m = S->m, n = S->n, N = S->N;
     double* kval = (double*)calloc((size_t)(S->kp[N] ? S->kp[N] : 1), sizeof(double));
     if (S->mode == ORC_AS) {
         for (int j = 0; j < n; ++j) {
-            kval[S->kp[j]] = -(1.0 / theta[j]); /* diagonal of x_j; -rho is added at pivot time */
-            /* entries (n+i, j) in column j are the A column, rows ascending */
+            /* diagonal of x_j; -rho is added at pivot time */
+            kval[S->kp[j]] = -(1.0 / theta[j] + q_diag(S->qcp, S->qri, qval, j));
+            /* the lower entries of column j in ascending rows: first the x rows k > j with
+             * Q_kj != 0, then the y rows n+i with A_ij != 0 */
             int64_t w = S->kp[j] + 1;
-            for (int64_t e = S->acp[j]; e < S->acp[j + 1]; ++e) kval[w++] = aval[e];
+            if (S->qcp)
+                for (int64_t e = S->qcp[j]; e < S->qcp[j + 1]; ++e)
+                    if (S->qri[e] != j) {
+                        if (S->ki[w] != S->qri[e]) { free(kval); return NULL; }
+                        kval[w++] = -qval[e];
+                    }
+            for (int64_t e = S->acp[j]; e < S->acp[j + 1]; ++e) {
+                if (S->ki[w] != n + S->ari[e]) { free(kval); return NULL; }
+                kval[w++] = aval[e];
+            }
         }
         /* y diagonals are 0 */
     } else {
@@ -663,7 +732,14 @@ void orc_front_factor(int f, int p, double* F, int8_t* sigma, double* shift, int
 
 int orc_factorise(const orc_sym* S, const double* aval, const double* theta, double rho,
                   double delta, const orc_opts* o, orc_num** out) {
+    if (S->qcp) return -1; /* a quadratic program needs Q's values */
+    return orc_factorise_qp(S, aval, NULL, theta, rho, delta, o, out);
+}
+
+int orc_factorise_qp(const orc_sym* S, const double* aval, const double* qval, const double* theta,
+                     double rho, double delta, const orc_opts* o, orc_num** out) {
     int N = S->N, n = S->n;
+    if (S->qcp && !qval) return -1;
     for (int j = 0; j < n; ++j)
         if (!(theta[j] > 0) || !isfinite(theta[j])) return -1;
     orc_num* R = (orc_num*)calloc(1, sizeof(orc_num));
@@ -676,7 +752,13 @@ int orc_factorise(const orc_sym* S, const double* aval, const double* theta, dou
     int64_t annz = S->acp[n];
     R->aval = (double*)malloc(sizeof(double) * (size_t)(annz ? annz : 1));
     memcpy(R->aval, aval, sizeof(double) * (size_t)annz);
-    R->kval = form_k0(S, aval, theta, rho);
+    if (S->qcp) {
+        int64_t qnnz = S->qcp[n];
+        R->qval = (double*)malloc(sizeof(double) * (size_t)(qnnz ? qnnz : 1));
+        memcpy(R->qval, qval, sizeof(double) * (size_t)qnnz);
+    }
+    R->kval = form_k0(S, aval, R->qval, theta, rho);
+    if (!R->kval) { orc_num_free(R); return -3; }
     R->knorm = knorm_of(S, R->kval, rho, delta, NULL);
     int ns = S->nsuper;
     R->Lptr = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ns + 1));
@@ -776,7 +858,7 @@ int orc_factorise(const orc_sym* S, const double* aval, const double* theta, dou
 
 void orc_num_free(orc_num* R) {
     if (!R) return;
-    free(R->theta); free(R->aval); free(R->kval); free(R->Lptr); free(R->L); free(R->d);
+    free(R->theta); free(R->aval); free(R->qval); free(R->kval); free(R->Lptr); free(R->L); free(R->d);
     free(R->doff); free(R->ptype); free(R->edyn); free(R->lperm);
     free(R);
 }
@@ -891,6 +973,10 @@ typedef struct {
     const double* av;
     const double* theta;
     double rho, delta;
+    /* AS quadratic programs: Q's lower triangle, NULL for an LP */
+    const int64_t* qcp;
+    const int32_t* qri;
+    const double* qv;
     /* NE: explicit K0 lower (original numbering) */
     const int64_t* kp;
     const int32_t* ki;
@@ -904,9 +990,19 @@ static void apply_k(const sysdesc* D, const double* x, double* y, double* ay) {
     if (D->mode == ORC_AS) {
         int n = D->n;
         for (int j = 0; j < n; ++j) {
-            double dj = -(1.0 / D->theta[j] + D->rho);
+            double dj = -(1.0 / D->theta[j] + q_diag(D->qcp, D->qri, D->qv, j) + D->rho);
             y[j] += dj * x[j];
             ay[j] += fabs(dj) * fabs(x[j]);
+            if (D->qcp) /* off-diagonal -Q_kj, both triangles */
+                for (int64_t e = D->qcp[j]; e < D->qcp[j + 1]; ++e) {
+                    int k = D->qri[e];
+                    if (k == j) continue;
+                    double q = -D->qv[e];
+                    y[j] += q * x[k];
+                    ay[j] += fabs(q) * fabs(x[k]);
+                    y[k] += q * x[j];
+                    ay[k] += fabs(q) * fabs(x[j]);
+                }
             for (int64_t e = D->cp[j]; e < D->cp[j + 1]; ++e) {
                 int i = n + D->ri[e];
                 double a = D->av[e];
@@ -969,8 +1065,8 @@ static void backward_error(const sysdesc* D, double knorm, const double* rowsum,
 static void ne_explicit(int m, int n, const int64_t* cp, const int32_t* ri, const double* av,
                         const double* theta, double rho, int64_t** kpo, int32_t** kio,
                         double** kvo) {
-    orc_sym* S = pattern_only(m, n, cp, ri, ORC_NE, NULL);
-    double* kv = form_k0(S, av, theta, rho);
+    orc_sym* S = pattern_only(m, n, cp, ri, ORC_NE, NULL, NULL, NULL);
+    double* kv = form_k0(S, av, NULL, theta, rho);
     *kpo = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m + 1));
     memcpy(*kpo, S->kp, sizeof(int64_t) * (size_t)(m + 1));
     *kio = (int32_t*)malloc(sizeof(int32_t) * (size_t)(S->kp[m] ? S->kp[m] : 1));
@@ -982,7 +1078,17 @@ static void ne_explicit(int m, int n, const int64_t* cp, const int32_t* ri, cons
 int orc_residual(int m, int n, const int64_t* cp, const int32_t* ri, const double* av,
                  int mode, const double* theta, double rho, double delta, const double* x,
                  const double* b, double* r, double* berr_nw, double* berr_cw, double* knorm) {
-    sysdesc D = {m, n, mode, mode == ORC_AS ? n + m : m, cp, ri, av, theta, rho, delta, 0, 0, 0};
+    return orc_residual_qp(m, n, cp, ri, av, mode, NULL, NULL, NULL, theta, rho, delta, x, b, r,
+                           berr_nw, berr_cw, knorm);
+}
+
+int orc_residual_qp(int m, int n, const int64_t* cp, const int32_t* ri, const double* av,
+                    int mode, const int64_t* qcp, const int32_t* qri, const double* qv,
+                    const double* theta, double rho, double delta, const double* x,
+                    const double* b, double* r, double* berr_nw, double* berr_cw, double* knorm) {
+    if (qcp && (mode != ORC_AS || !qri || !qv || !q_pattern_ok(n, qcp, qri))) return -1;
+    sysdesc D = {m, n, mode, mode == ORC_AS ? n + m : m, cp, ri, av, theta, rho, delta,
+                 qcp, qri, qv, 0, 0, 0};
     int64_t* kp = NULL;
     int32_t* ki = NULL;
     double* kv = NULL;
@@ -1000,7 +1106,13 @@ int orc_residual(int m, int n, const int64_t* cp, const int32_t* ri, const doubl
             }
     } else {
         for (int j = 0; j < n; ++j) {
-            rs[j] += 1.0 / theta[j] + rho;
+            rs[j] += fabs(1.0 / theta[j] + q_diag(qcp, qri, qv, j) + rho);
+            if (qcp)
+                for (int64_t e = qcp[j]; e < qcp[j + 1]; ++e)
+                    if (qri[e] != j) {
+                        rs[j] += fabs(qv[e]);
+                        rs[qri[e]] += fabs(qv[e]);
+                    }
             for (int64_t e = cp[j]; e < cp[j + 1]; ++e) {
                 rs[j] += fabs(av[e]);
                 rs[n + ri[e]] += fabs(av[e]);
@@ -1020,7 +1132,7 @@ int orc_solve(const orc_sym* S, const orc_num* R, int nrhs, const double* r7, co
     int m = S->m, n = S->n, N = S->N;
     const orc_opts* o = &R->opts;
     sysdesc D = {m, n, S->mode, N, S->acp, S->ari, R->aval, R->theta, R->rho, R->delta,
-                 S->kp, S->ki, R->kval};
+                 S->qcp, S->qri, R->qval, S->kp, S->ki, R->kval};
     double* rs = (double*)calloc((size_t)(N ? N : 1), sizeof(double));
     double kn = knorm_of(S, R->kval, R->rho, R->delta, rs);
     double* tt = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));

@@ -43,6 +43,12 @@ void orc_default_opts(orc_opts* o);
  * postordered (children visited in ascending order) and fundamental supernodes formed.   */
 int orc_analyse(int m, int n, const int64_t* colptr, const int32_t* rowidx, int mode,
                 const int32_t* user_perm, orc_sym** out);
+/* Quadratic programs, AS mode only: the (1,1) block becomes -(Q + Theta^-1 + rho I).  Q is
+ * n x n symmetric, given by its lower triangle in CSC (qcolptr n+1, rows >= the column and
+ * strictly increasing; diagonal entries optional).  Q's couplings join the pattern. */
+int orc_analyse_qp(int m, int n, const int64_t* colptr, const int32_t* rowidx,
+                   const int64_t* qcolptr, const int32_t* qrowidx, const int32_t* user_perm,
+                   orc_sym** out);
 void orc_sym_free(orc_sym* S);
 /* info: [N, nsuper, nnzL (incl. diagonal), maxfront, flops as int64] */
 void orc_sym_info(const orc_sym* S, int64_t* info);
@@ -56,6 +62,10 @@ void orc_sym_front_rows(const orc_sym* S, int64_t* rowptr, int32_t* rows); /* ns
 /* Numeric factorisation of K_static + E_dyn (Sections 3.2, 4.1, 4.5, 4.6). */
 int orc_factorise(const orc_sym* S, const double* aval, const double* theta, double rho,
                   double delta, const orc_opts* o, orc_num** out);
+/* The same for a quadratic program (qval: Q's lower values in the order of its pattern). */
+int orc_factorise_qp(const orc_sym* S, const double* aval, const double* qval,
+                     const double* theta, double rho, double delta, const orc_opts* o,
+                     orc_num** out);
 void orc_num_free(orc_num* F);
 void orc_num_stats(const orc_num* F, orc_stats* st);
 double orc_num_knorm(const orc_num* F);
@@ -80,6 +90,12 @@ int orc_residual(int m, int n, const int64_t* colptr, const int32_t* rowidx,
                  const double* aval, int mode, const double* theta, double rho,
                  double delta, const double* x, const double* b, double* r,
                  double* berr_nw, double* berr_cw, double* knorm);
+/* The same with a quadratic program's Q (AS only; NULL pointers: an LP). */
+int orc_residual_qp(int m, int n, const int64_t* colptr, const int32_t* rowidx,
+                    const double* aval, int mode, const int64_t* qcolptr, const int32_t* qrowidx,
+                    const double* qval, const double* theta, double rho, double delta,
+                    const double* x, const double* b, double* r, double* berr_nw,
+                    double* berr_cw, double* knorm);
 
 /* Partial LDL^T of one dense front (Sections 4.4-4.6): f x f symmetric, column-major,
  * full storage, eliminating the first p pivots in windows of nb columns.  sigma: expected

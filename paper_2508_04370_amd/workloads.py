@@ -323,6 +323,56 @@ def bounded_lp(lp, seed=7, upper=0.5):
     return out, b, c, l, u
 
 
+def with_hessian(lp, seed=7, frac=0.5, per_row=3, window=50, ridge=0.1):
+    """A quadratic program on the pattern and values of `lp` (mode AS): Q = G^T G + R, positive
+    semidefinite by construction.  G has one row per column c of a random subset (a fraction
+    `frac` of the columns); the row touches c and per_row - 1 other columns within `window`
+    positions of c (local couplings, as in a staircase model's periods), values standard
+    normal.  R is diagonal, ridge * U[0.5, 1.5] on the subset.  Adds q_colptr, q_rowidx, q_val:
+    Q's lower triangle in CSC, rows ascending."""
+    g = rng(seed, 73)
+    n = lp["n"]
+    sel = np.flatnonzero(g.random(n) < frac)
+    ii, jj, vv = [], [], []
+    for c in sel:
+        lo, hi = max(0, c - window), min(n, c + window + 1)
+        others = g.choice(np.setdiff1d(np.arange(lo, hi), [c]), size=min(per_row - 1, hi - lo - 1), replace=False)
+        cols = np.concatenate([[c], others]).astype(np.int64)
+        vals = g.standard_normal(len(cols))
+        for a in range(len(cols)):
+            for b in range(len(cols)):
+                if cols[a] >= cols[b]:
+                    ii.append(cols[a])
+                    jj.append(cols[b])
+                    vv.append(vals[a] * vals[b])
+    ii.extend(sel.tolist())
+    jj.extend(sel.tolist())
+    vv.extend((ridge * g.uniform(0.5, 1.5, len(sel))).tolist())
+    ii, jj, vv = np.asarray(ii, np.int64), np.asarray(jj, np.int64), np.asarray(vv, float)
+    key, inv = np.unique(jj * n + ii, return_inverse=True)
+    val = np.zeros(len(key))
+    np.add.at(val, inv, vv)
+    c = key // n
+    colptr = np.zeros(n + 1, np.int64)
+    np.add.at(colptr, c + 1, 1)
+    out = LP(dict(lp, mode=AS, name=lp.get("name", "lp") + "_qp"))
+    out["q_colptr"] = np.cumsum(colptr)
+    out["q_rowidx"] = (key % n).astype(np.int32)
+    out["q_val"] = val
+    return out
+
+
+def q_dense(lp):
+    """Q of a quadratic program's dict as a dense symmetric array."""
+    n = lp["n"]
+    Q = np.zeros((n, n))
+    cp, ri, v = lp["q_colptr"], lp["q_rowidx"], lp["q_val"]
+    for j in range(n):
+        for e in range(cp[j], cp[j + 1]):
+            Q[ri[e], j] = Q[j, ri[e]] = v[e]
+    return Q
+
+
 def lp_dense(lp):
     """A of an LP dict as a dense array."""
     A = np.zeros((lp["m"], lp["n"]))
