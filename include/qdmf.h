@@ -141,6 +141,26 @@ int qdmf_set_stream(qdmf_handle h, void* hip_stream);
 int qdmf_analyse(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
                  const int32_t* rowidx, int32_t mode, const int32_t* user_perm);
 
+/* Quadratic programs (the extension of the augmented system to min c^T x + x^T Q x / 2 that
+ * the paper names beside its LP method): the (1,1) block of the augmented system becomes
+ * -(Q + Theta^-1 + rho I), so K_static = [[-(Q + Theta^-1 + rho I), A^T], [A, delta I]].
+ * For positive semidefinite Q the matrix stays quasidefinite (Section 4.6), and the pivoting,
+ * the regularisation and the expected inertia (n negative, m positive) are those of the LP.
+ * Analyses the pattern of A together with Q's couplings (x_j -- x_k where Q_jk != 0), in
+ * QDMF_AS mode for one system.  Q (n x n, symmetric) is given by its lower triangle in CSC
+ * (q_colptr: n+1 entries; q_rowidx: rows >= the column, strictly increasing; diagonal
+ * entries optional); host arrays, read and not retained.  Other arguments as qdmf_analyse.
+ * Errors: as qdmf_analyse, and QDMF_ERR_INVALID_ARG for a bad Q pattern. */
+int qdmf_analyse_qp(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
+                    const int32_t* rowidx, const int64_t* q_colptr, const int32_t* q_rowidx,
+                    const int32_t* user_perm);
+
+/* Values of Q's lower triangle in the order of the pattern given to qdmf_analyse_qp (FP64;
+ * host memory if on_device == 0, else device memory).  Copied; must be called before the
+ * first factorisation of a quadratic program.  Errors: QDMF_ERR_NOT_ANALYSED,
+ * QDMF_ERR_INVALID_ARG (also when the analysed problem has no Q). */
+int qdmf_set_hessian(qdmf_handle h, const double* q_val, int32_t on_device);
+
 /* Symbolic results (host memory owned by the handle).  Error: QDMF_ERR_NOT_ANALYSED. */
 int qdmf_symbolic(qdmf_handle h, qdmf_symbolic_info* out);
 
@@ -284,6 +304,7 @@ int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
  * NULL for u = +inf everywhere; x, z^l (n) and y (m) receive the last iterate; zu (n) receives
  * z^u (0 where u is infinite) or is NULL.  Runs on the handle's stream and synchronises it
  * several times per iteration.  Errors: QDMF_ERR_INVALID_ARG (also for a bad bound),
+ * QDMF_ERR_UNSUPPORTED (the handle holds a quadratic program),
  * QDMF_ERR_NOT_ANALYSED (or not AS), QDMF_ERR_NO_MATRIX, QDMF_ERR_HIP, QDMF_ERR_OOM, and the
  * codes of qdmf_factorise / qdmf_solve. */
 typedef struct {

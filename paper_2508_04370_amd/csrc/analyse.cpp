@@ -50,17 +50,27 @@ int check_csc(int32_t m, int32_t n, const int64_t* cp, const int32_t* ri, std::s
     return 0;
 }
 
-// Full adjacency of K (no diagonal), original numbering.
+// Full adjacency of K (no diagonal), original numbering.  AS: x_j -- y_i where A_ij != 0, and
+// for a quadratic program x_j -- x_k where Q_jk != 0 (j != k); each list ascending.
 void k_adjacency(const Plan& P, std::vector<int64_t>& xadj, std::vector<int32_t>& adj) {
     const int32_t N = P.N, n = P.n, m = P.m;
     xadj.assign(N + 1, 0);
     if (P.mode == QDMF_AS) {
-        for (int32_t j = 0; j < n; ++j) xadj[j + 1] = P.acp[j + 1] - P.acp[j];
+        auto qoff = [&](int32_t j) {
+            if (!P.has_q) return (int64_t)0;
+            return P.qfcp[j + 1] - P.qfcp[j] - (P.qdiag[j] >= 0 ? 1 : 0);
+        };
+        for (int32_t j = 0; j < n; ++j) xadj[j + 1] = qoff(j) + P.acp[j + 1] - P.acp[j];
         for (int32_t i = 0; i < m; ++i) xadj[n + i + 1] = P.arp[i + 1] - P.arp[i];
         for (int32_t v = 0; v < N; ++v) xadj[v + 1] += xadj[v];
         adj.resize(xadj[N]);
-        for (int32_t j = 0; j < n; ++j)
-            for (int64_t e = P.acp[j]; e < P.acp[j + 1]; ++e) adj[xadj[j] + (e - P.acp[j])] = n + P.ari[e];
+        for (int32_t j = 0; j < n; ++j) {
+            int64_t w = xadj[j];
+            if (P.has_q)
+                for (int64_t e = P.qfcp[j]; e < P.qfcp[j + 1]; ++e)
+                    if (P.qfri[e] != j) adj[w++] = P.qfri[e];
+            for (int64_t e = P.acp[j]; e < P.acp[j + 1]; ++e) adj[w++] = n + P.ari[e];
+        }
         for (int32_t i = 0; i < m; ++i)
             for (int64_t q = P.arp[i]; q < P.arp[i + 1]; ++q)
                 adj[xadj[n + i] + (q - P.arp[i])] = P.acol[P.are[q]];
@@ -296,6 +306,67 @@ int64_t ne_pattern_count(int32_t m, int32_t n, const int64_t* colptr, const int3
     return count;
 }
 
+// Q's lower triangle: rows >= the column, strictly increasing, inside [0, n); the full
+// symmetric pattern with the source of each value, and the diagonal positions.
+static int set_hessian_pattern(int32_t n, const int64_t* qcp, const int32_t* qri, Plan& P, std::string& msg) {
+    if (qcp[0] != 0) {
+        msg = "Q: colptr[0] must be 0";
+        return QDMF_ERR_INVALID_ARG;
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        if (qcp[j + 1] < qcp[j]) {
+            msg = "Q: colptr not nondecreasing";
+            return QDMF_ERR_INVALID_ARG;
+        }
+        for (int64_t e = qcp[j]; e < qcp[j + 1]; ++e) {
+            if (qri[e] < j || qri[e] >= n) {
+                msg = "Q: entries must lie in the lower triangle (row >= column, row < n)";
+                return QDMF_ERR_INVALID_ARG;
+            }
+            if (e > qcp[j] && qri[e] <= qri[e - 1]) {
+                msg = "Q: row indices not strictly increasing within a column";
+                return QDMF_ERR_INVALID_ARG;
+            }
+        }
+    }
+    if (qcp[n] > INT32_MAX) {
+        msg = "more than 2^31-1 nonzeros in Q";
+        return QDMF_ERR_INDEX_OVERFLOW;
+    }
+    const int64_t qnnz = qcp[n];
+    P.has_q = true;
+    P.qcp.assign(qcp, qcp + n + 1);
+    P.qri.assign(qri, qri + qnnz);
+    P.qdiag.assign(n, -1);
+    P.qfcp.assign(n + 1, 0);
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t e = qcp[j]; e < qcp[j + 1]; ++e) {
+            P.qfcp[j + 1]++;
+            if (qri[e] != j) P.qfcp[qri[e] + 1]++;
+            else P.qdiag[j] = e;
+        }
+    for (int32_t j = 0; j < n; ++j) P.qfcp[j + 1] += P.qfcp[j];
+    P.qfri.resize(P.qfcp[n]);
+    P.qfsrc.resize(P.qfcp[n]);
+    std::vector<int64_t> fl(P.qfcp.begin(), P.qfcp.end() - 1);
+    // column k of the full pattern: first the upper entries (rows j < k, from the lower
+    // triangle's columns j in ascending order), then column k of the lower triangle
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t e = qcp[j]; e < qcp[j + 1]; ++e) {
+            const int32_t k = qri[e];
+            if (k != j) {
+                P.qfri[fl[k]] = j;
+                P.qfsrc[fl[k]++] = e;
+            }
+        }
+    for (int32_t j = 0; j < n; ++j)
+        for (int64_t e = qcp[j]; e < qcp[j + 1]; ++e) {
+            P.qfri[fl[j]] = qri[e];
+            P.qfsrc[fl[j]++] = e;
+        }
+    return 0;
+}
+
 int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx, int32_t mode,
                const AnalyseOptions& opt, Plan& P, std::string& msg) {
     if (mode != QDMF_NE && mode != QDMF_AS) {
@@ -327,6 +398,18 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     {
         std::vector<int64_t> fill(P.arp.begin(), P.arp.end() - 1);
         for (int64_t e = 0; e < annz; ++e) P.are[fill[rowidx[e]]++] = (int32_t)e;
+    }
+    if (opt.q_colptr) {
+        if (mode != QDMF_AS || opt.nsys > 1) {
+            msg = "a quadratic program needs the augmented system of one system";
+            return QDMF_ERR_UNSUPPORTED;
+        }
+        if (n > 0 && !opt.q_rowidx && opt.q_colptr[n] > 0) {
+            msg = "Q: missing row indices";
+            return QDMF_ERR_INVALID_ARG;
+        }
+        rc = set_hessian_pattern(n, opt.q_colptr, opt.q_rowidx, P, msg);
+        if (rc) return rc;
     }
 
     std::vector<int64_t> xadj;
@@ -634,6 +717,12 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             int32_t a = P.krow_old[e], b = P.kcol_old[e];
             if (a == b) {
                 P.ksrc[e] = a < n ? -1 - (int64_t)a : KSRC_ZERO;
+            } else if (a < n && b < n) {  // an off-diagonal entry of Q
+                const int32_t lo = std::min(a, b), hi = std::max(a, b);
+                const int32_t* beg = &P.qri[0] + P.qcp[lo];
+                const int32_t* end = &P.qri[0] + P.qcp[lo + 1];
+                const int32_t* it = std::lower_bound(beg, end, hi);
+                P.ksrc[e] = -1 - (int64_t)n - (P.qcp[lo] + (it - beg));
             } else {
                 int32_t x = a < n ? a : b;  // primal index
                 int32_t y = (a < n ? b : a) - n;

@@ -25,6 +25,7 @@ struct qdmf_ctx {
 
     Plan P;
     bool analysed = false, have_matrix = false, factorised = false;
+    bool have_hessian = false;  // quadratic programs: qdmf_set_hessian called
     int last_prec = 0;
     std::vector<int32_t> user_perm;
 
@@ -160,6 +161,8 @@ int64_t plan_device_bytes(const Plan& P) {
     b += (int64_t)P.kpair.size() * 4;
     b += (int64_t)P.N * (8 * 4 + 4 + 4);
     b += (int64_t)P.acp.size() * 8 + (int64_t)P.ari.size() * 16;
+    b += (int64_t)P.qfcp.size() * 8 + (int64_t)P.qfri.size() * 12 + (int64_t)P.qdiag.size() * 16 +
+         (int64_t)P.qri.size() * 8;
     return b;
 }
 
@@ -211,6 +214,10 @@ int upload_plan(qdmf_ctx* h) {
     UP(arp, arp)
     UP(are, are)
     UP(acol, acol)
+    UP(qfcp, qfcp)
+    UP(qfri, qfri)
+    UP(qfsrc, qfsrc)
+    UP(qdiag, qdiag)
     UP(sys_col, sys_col)
     UP(sys_old, sys_old)
     UP(sys_new, sys_new)
@@ -219,6 +226,7 @@ int upload_plan(qdmf_ctx* h) {
     UP(sys_piv, sys_piv)
 #undef UP
     D.nsys = P.nsys;
+    D.has_q = P.has_q ? 1 : 0;
     const Task* tk = nullptr;
     if ((rc = dupload(h, P.tasks, &tk))) return rc;
     h->tasks_dev = const_cast<Task*>(tk);
@@ -239,6 +247,8 @@ int upload_plan(qdmf_ctx* h) {
     if ((rc = dalloc(h, h->plan_allocs, &D.aval, (int64_t)P.ari.size()))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.colabs, P.n))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.rowabs, P.m))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.qval, (int64_t)P.qri.size()))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.qoff, P.has_q ? P.n : 0))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.dinv, P.n))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.rowsum, N))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.dval, N))) return rc;
@@ -566,7 +576,8 @@ int qdmf_set_stream(qdmf_handle h, void* s) {
 namespace {
 
 int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx, int32_t mode,
-                 const int32_t* user_perm, int32_t nsys, const int64_t* col_off, const int64_t* row_off) {
+                 const int32_t* user_perm, int32_t nsys, const int64_t* col_off, const int64_t* row_off,
+                 const int64_t* q_colptr = nullptr, const int32_t* q_rowidx = nullptr) {
     if (!h->host_only) {
         int rc = set_device(h);
         if (rc) return rc;
@@ -577,6 +588,7 @@ int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     free_list(h->plan_allocs);
     h->solve_cap = 0;
     h->analysed = h->have_matrix = h->factorised = h->solved = false;
+    h->have_hessian = false;
     h->device_bytes = 0;
     AnalyseOptions ao;
     ao.ordering = h->opt.ordering;
@@ -588,6 +600,8 @@ int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     ao.nsys = nsys;
     ao.col_off = col_off;
     ao.row_off = row_off;
+    ao.q_colptr = q_colptr;
+    ao.q_rowidx = q_rowidx;
     if (h->opt.ordering == QDMF_ORDER_USER && !user_perm) return QDMF_ERR_INVALID_ARG;
     int rc = build_plan(m, n, colptr, rowidx, mode, ao, h->P, h->msg);
     if (rc) return rc;
@@ -616,6 +630,14 @@ int qdmf_analyse(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     h->batch_col_off.clear();
     h->batch_row_off.clear();
     return analyse_impl(h, m, n, colptr, rowidx, mode, user_perm, 1, nullptr, nullptr);
+}
+
+int qdmf_analyse_qp(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowidx,
+                    const int64_t* q_colptr, const int32_t* q_rowidx, const int32_t* user_perm) {
+    if (!h || !q_colptr) return QDMF_ERR_INVALID_ARG;
+    h->batch_col_off.clear();
+    h->batch_row_off.clear();
+    return analyse_impl(h, m, n, colptr, rowidx, QDMF_AS, user_perm, 1, nullptr, nullptr, q_colptr, q_rowidx);
 }
 
 int qdmf_batch_analyse(qdmf_handle h, int32_t count, const int32_t* m, const int32_t* n,
@@ -709,10 +731,28 @@ int qdmf_set_matrix(qdmf_handle h, const double* a_val, int32_t on_device) {
     return 0;
 }
 
+int qdmf_set_hessian(qdmf_handle h, const double* q_val, int32_t on_device) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
+    if (h->host_only || !h->P.has_q) return QDMF_ERR_INVALID_ARG;
+    const int64_t nnz = (int64_t)h->P.qri.size();
+    if (nnz > 0 && !q_val) return QDMF_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    if (nnz > 0 && hipMemcpyAsync(h->D.qval, q_val, sizeof(double) * (size_t)nnz,
+                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return QDMF_ERR_HIP;
+    launch_hessian_norms(h->D, h->stream);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    h->have_hessian = true;
+    h->factorised = false;
+    return 0;
+}
+
 int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double delta, int32_t prec) {
     if (!h) return QDMF_ERR_INVALID_ARG;
     if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
-    if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
+    if (!h->have_matrix || (h->P.has_q && !h->have_hessian)) return QDMF_ERR_NO_MATRIX;
     if (h->host_only || (!theta_dev && h->P.n > 0) || !(rho >= 0) || !(delta >= 0) || !std::isfinite(rho) ||
         !std::isfinite(delta) || (prec != QDMF_FP64 && prec != QDMF_MIXED))
         return QDMF_ERR_INVALID_ARG;
@@ -918,7 +958,7 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
                        double* dy_dev) {
     if (!h) return QDMF_ERR_INVALID_ARG;
     if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
-    if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
+    if (!h->have_matrix || (h->P.has_q && !h->have_hessian)) return QDMF_ERR_NO_MATRIX;
     if (h->host_only || !h->stream || nsolves < 0 || nrhs <= 0 || (!theta_dev && h->P.n > 0) ||
         (prec != QDMF_FP64 && prec != QDMF_MIXED) || !(rho >= 0) || !(delta >= 0))
         return QDMF_ERR_INVALID_ARG;
@@ -1002,6 +1042,7 @@ int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, cons
     constexpr double STEP_FACTOR = 0.995, ALPHA_PLUS = 0.1, BETA_MIN = 0.1, BETA_MAX = 10.0, ACCEPT_GAIN = 0.01;
     if (!h || !info || !b_dev || !c_dev || !x_dev || !y_dev || !zl_dev || h->host_only) return QDMF_ERR_INVALID_ARG;
     if (!h->analysed || h->P.mode != QDMF_AS || h->P.nsys != 1) return QDMF_ERR_NOT_ANALYSED;
+    if (h->P.has_q) return QDMF_ERR_UNSUPPORTED;  // the driver solves linear programs
     if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
     qdmf_ipm_options opt;
     if (opt_in) opt = *opt_in;

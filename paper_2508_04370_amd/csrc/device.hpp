@@ -75,6 +75,16 @@ struct DevPlan {
     const int64_t* arp;
     const int32_t* are;
     const int32_t* acol;
+    // quadratic programs (AS): has_q, the full symmetric pattern of Q (CSC) with the index of
+    // each value in qval (the lower triangle as given), the diagonal's index per column (-1:
+    // none), and per column the sum of |Q_kj| over k != j
+    int32_t has_q;
+    const int64_t* qfcp;
+    const int32_t* qfri;
+    const int64_t* qfsrc;
+    const int64_t* qdiag;
+    double* qval;
+    double* qoff;
     // numeric state (owned by the handle)
     double* front;
     double* kval;
@@ -119,6 +129,7 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks_dev
 int factor_stats_blocks(int64_t N);
 void launch_factor_stats(const DevPlan& D, const PivotParams& pp, double* part, hipStream_t s);
 void launch_matrix_norms(const DevPlan& D, hipStream_t s);
+void launch_hessian_norms(const DevPlan& D, hipStream_t s);
 
 // ---- solve
 // Work state of one solve call (device memory owned by the handle).

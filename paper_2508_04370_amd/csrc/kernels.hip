@@ -1092,8 +1092,13 @@ __global__ void k_theta(DevPlan D, const double* theta) {
     else D.dinv[j] = 1.0 / (1.0 / th + D.rho_sys[D.sys_col[j]]);
 }
 
-// Values of lower(K) in analyse order.  NE: K_ik = sum_j (A_ij theta~_j) A_kj over the
-// shared columns j in ascending order (fixed order, no atomics).
+// Q_jj of a quadratic program (0 where Q has no diagonal entry)
+__device__ inline double q_diag(const DevPlan& D, int j) { return D.qdiag[j] >= 0 ? D.qval[D.qdiag[j]] : 0.0; }
+
+// Values of lower(K) in analyse order.  AS: A entries, the x diagonal -1/Theta_j (for a
+// quadratic program -(1/Theta_j + Q_jj)), -Q_kj for Q's couplings, 0 on the y diagonal.
+// NE: K_ik = sum_j (A_ij theta~_j) A_kj over the shared columns j in ascending order (fixed
+// order, no atomics).
 __global__ void k_values(DevPlan D, int64_t knnz) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= knnz) return;
@@ -1102,7 +1107,12 @@ __global__ void k_values(DevPlan D, int64_t knnz) {
         double v;
         if (src >= 0) v = D.aval[src];
         else if (src == KSRC_ZERO) v = 0.0;
-        else v = -D.dinv[-1 - src];
+        else {
+            const int64_t t = -1 - src;
+            if (t >= D.n) v = -D.qval[t - D.n];
+            else if (D.has_q) v = -(D.dinv[t] + q_diag(D, (int)t));
+            else v = -D.dinv[t];
+        }
         D.kval[e] = v;
     } else {
         double acc = 0.0;
@@ -1122,8 +1132,12 @@ __global__ void k_rowsum(DevPlan D) {
     const double rho = D.rho_sys[sys], delta = D.delta_sys[sys];
     double s;
     if (D.mode == 1) {
-        if (i < D.n) s = (D.dinv[i] + rho) + D.colabs[i];
-        else s = D.rowabs[i - D.n] + delta;
+        if (i < D.n) {
+            if (D.has_q) s = fabs((D.dinv[i] + q_diag(D, i)) + rho) + D.qoff[i] + D.colabs[i];
+            else s = (D.dinv[i] + rho) + D.colabs[i];
+        } else {
+            s = D.rowabs[i - D.n] + delta;
+        }
     } else {
         s = 0.0;
         for (int64_t q = D.krs_ptr[i]; q < D.krs_ptr[i + 1]; ++q) {
@@ -1156,6 +1170,16 @@ __global__ __launch_bounds__(1024) void k_knorm(DevPlan D) {
         D.knorm_sys[q] = red[0];
         if (D.nsys == 1) D.sc->knorm = red[0];
     }
+}
+
+// Sum over k != j of |Q_kj| per column of a quadratic program's Q (once per Q).
+__global__ void k_hessian_norms(DevPlan D) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= D.n) return;
+    double s = 0.0;
+    for (int64_t e = D.qfcp[j]; e < D.qfcp[j + 1]; ++e)
+        if (D.qfri[e] != j) s += fabs(D.qval[D.qfsrc[e]]);
+    D.qoff[j] = s;
 }
 
 // Sum_i |A_ij| per column and sum_j |A_ij| per row (once per matrix).
@@ -2123,9 +2147,17 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const d
         double kx = 0.0, akx = 0.0;
         if (D.mode == 1) {
             if (i < D.n) {
-                const double dj = -(D.dinv[i] + rho);
+                const double dj = D.has_q ? -((D.dinv[i] + q_diag(D, i)) + rho) : -(D.dinv[i] + rho);
                 kx = dj * x[i];
                 akx = fabs(dj) * fabs(x[i]);
+                if (D.has_q)
+                    for (int64_t e = D.qfcp[i]; e < D.qfcp[i + 1]; ++e) {
+                        const int k = D.qfri[e];
+                        if (k == i) continue;
+                        const double q = -D.qval[D.qfsrc[e]];
+                        kx += q * x[k];
+                        akx += fabs(q) * fabs(x[k]);
+                    }
                 for (int64_t e = D.acp[i]; e < D.acp[i + 1]; ++e) {
                     const double a = D.aval[e], xv = x[D.n + D.ari[e]];
                     kx += a * xv;
@@ -2337,7 +2369,10 @@ __global__ __launch_bounds__(256) void k_matvec(DevPlan D, const double* vin, do
     double kx = 0.0;
     if (D.mode == 1) {
         if (i < D.n) {
-            kx = -(D.dinv[i] + rho) * v[i];
+            kx = (D.has_q ? -((D.dinv[i] + q_diag(D, i)) + rho) : -(D.dinv[i] + rho)) * v[i];
+            if (D.has_q)
+                for (int64_t e = D.qfcp[i]; e < D.qfcp[i + 1]; ++e)
+                    if (D.qfri[e] != i) kx -= D.qval[D.qfsrc[e]] * v[D.qfri[e]];
             for (int64_t e = D.acp[i]; e < D.acp[i + 1]; ++e) kx += D.aval[e] * v[D.n + D.ari[e]];
         } else {
             const int row = i - D.n;
@@ -2463,6 +2498,10 @@ void launch_knorm(const DevPlan& D, hipStream_t s) {
 void launch_matrix_norms(const DevPlan& D, hipStream_t s) {
     int64_t mx = D.n > D.m ? D.n : D.m;
     if (mx > 0) hipLaunchKernelGGL(k_matrix_norms, dim3(nblocks(mx, 256)), dim3(256), 0, s, D);
+}
+
+void launch_hessian_norms(const DevPlan& D, hipStream_t s) {
+    if (D.n > 0) hipLaunchKernelGGL(k_hessian_norms, dim3(nblocks(D.n, 256)), dim3(256), 0, s, D);
 }
 
 void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, const PivotParams& pp,

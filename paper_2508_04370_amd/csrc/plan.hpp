@@ -60,6 +60,14 @@ struct Plan {
     std::vector<int64_t> arp;   // A pattern, CSR: row pointers
     std::vector<int32_t> are;   // CSR -> CSC entry index
     std::vector<int32_t> acol;  // column of each CSC entry
+    // quadratic programs (AS only): Q's lower triangle as given (CSC, n columns), and the full
+    // symmetric pattern (CSC) with, per entry, the index of its value in the lower triangle;
+    // per column the index of Q_jj or -1.  Empty for an LP.
+    bool has_q = false;
+    std::vector<int64_t> qcp;
+    std::vector<int32_t> qri;
+    std::vector<int64_t> qfcp, qfsrc, qdiag;
+    std::vector<int32_t> qfri;
 
     // ordering (new -> old, old -> new) after postordering
     std::vector<int32_t> perm, iperm;
@@ -90,7 +98,8 @@ struct Plan {
     std::vector<int32_t> kcl;           // column position inside that front
     std::vector<int32_t> asm_child, asm_col;  // assembly lists of large-front columns
     std::vector<int32_t> krow_old, kcol_old;  // original indices of each entry (row >= col in new order)
-    std::vector<int64_t> ksrc;          // AS: >= 0 A entry, -1-j primal diagonal j, KSRC_ZERO dual diagonal
+    std::vector<int64_t> ksrc;          // AS: >= 0 A entry, -1-j primal diagonal j, -1-n-q entry q of Q's
+                                        // lower triangle, KSRC_ZERO dual diagonal
     std::vector<int64_t> kpair_ptr;     // NE: per entry, pairs of A entries (a, b), column ascending
     std::vector<int32_t> kpair;         // 2 per pair
     // NE residual / norm: per original row, the K entries touching it
@@ -147,6 +156,9 @@ struct AnalyseOptions {
     int32_t nsys = 1;
     const int64_t* col_off = nullptr;
     const int64_t* row_off = nullptr;
+    // quadratic programs (AS, one system): Q's lower triangle, CSC with n columns
+    const int64_t* q_colptr = nullptr;
+    const int32_t* q_rowidx = nullptr;
 };
 
 // Approximate minimum degree ordering of a symmetric pattern given as full adjacency

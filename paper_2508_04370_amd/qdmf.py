@@ -36,7 +36,7 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_graph_capture", "qdmf_graph_launch", "qdmf_destroy", "qdmf_status_string",
             "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read", "qdmf_batch_analyse",
             "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats", "qdmf_choose_mode",
-            "qdmf_ipm_default_options", "qdmf_ipm_solve"]
+            "qdmf_ipm_default_options", "qdmf_ipm_solve", "qdmf_analyse_qp", "qdmf_set_hessian"]
 QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD = range(7)
 KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
                      6: "k_bwd"}
@@ -110,6 +110,8 @@ def lib():
         L.qdmf_create.argtypes = [C.POINTER(P), C.c_int, P, C.POINTER(qdmf_options)]
         L.qdmf_set_stream.argtypes = [P, P]
         L.qdmf_analyse.argtypes = [P, I32, I32, P, P, I32, P]
+        L.qdmf_analyse_qp.argtypes = [P, I32, I32, P, P, P, P, P]
+        L.qdmf_set_hessian.argtypes = [P, P, I32]
         L.qdmf_choose_mode.argtypes = [P, I32, I32, P, P, C.POINTER(qdmf_mode_choice)]
         L.qdmf_ipm_default_options.argtypes = [C.POINTER(qdmf_ipm_options)]
         L.qdmf_ipm_default_options.restype = None
@@ -194,6 +196,24 @@ def qdmf_analyse(h, m, n, colptr, rowidx, mode, user_perm=None):
     up = None if user_perm is None else np.ascontiguousarray(user_perm, np.int32)
     return _check(lib().qdmf_analyse(h, int(m), int(n), _np(cp), _np(ri), int(mode), _np(up)),
                   "qdmf_analyse", h)
+
+
+def qdmf_analyse_qp(h, m, n, colptr, rowidx, q_colptr, q_rowidx, user_perm=None):
+    """Quadratic program: A's pattern with Q's lower triangle (CSC, n columns)."""
+    cp = np.ascontiguousarray(colptr, np.int64)
+    ri = np.ascontiguousarray(rowidx, np.int32)
+    qcp = np.ascontiguousarray(q_colptr, np.int64)
+    qri = np.ascontiguousarray(q_rowidx, np.int32)
+    up = None if user_perm is None else np.ascontiguousarray(user_perm, np.int32)
+    return _check(lib().qdmf_analyse_qp(h, int(m), int(n), _np(cp), _np(ri), _np(qcp), _np(qri), _np(up)),
+                  "qdmf_analyse_qp", h)
+
+
+def qdmf_set_hessian(h, q_val, on_device=False):
+    if on_device:
+        return _check(lib().qdmf_set_hessian(h, _dev(q_val), 1), "qdmf_set_hessian", h)
+    q = np.ascontiguousarray(q_val, np.float64)
+    return _check(lib().qdmf_set_hessian(h, _np(q), 0), "qdmf_set_hessian", h)
 
 
 def qdmf_ipm_default_options(**overrides):
@@ -370,9 +390,10 @@ def qdmf_status_string(code):
 class Solver:
     """One analysed system on one GPU: analyse once, then factorise/solve per iteration.
 
-    ``lp`` is a dict with m, n, colptr, rowidx, val, mode (see workloads.py).  Device
-    buffers are torch tensors on ``cuda:device``; ``device=-1`` gives a host-only handle
-    (analyse and symbolic information only).
+    ``lp`` is a dict with m, n, colptr, rowidx, val, mode (see workloads.py); a quadratic
+    program also has q_colptr, q_rowidx, q_val (Q's lower triangle).  Device buffers are
+    torch tensors on ``cuda:device``; ``device=-1`` gives a host-only handle (analyse and
+    symbolic information only).
     """
 
     def __init__(self, lp, device=0, stream=None, perm=None, systems=None, **opts):
@@ -388,14 +409,20 @@ class Solver:
             import torch
             stream = torch.cuda.current_stream(device).cuda_stream
         self.h = qdmf_create(device, stream, self.opt)
+        qp = lp.get("q_colptr") is not None
         if systems is not None:
             qdmf_batch_analyse(self.h, systems, lp["mode"])
+        elif qp:
+            qdmf_analyse_qp(self.h, lp["m"], lp["n"], lp["colptr"], lp["rowidx"], lp["q_colptr"], lp["q_rowidx"],
+                            perm)
         else:
             qdmf_analyse(self.h, lp["m"], lp["n"], lp["colptr"], lp["rowidx"], lp["mode"], perm)
         self.sym = qdmf_symbolic(self.h)
         self.N = self.sym["N"]
         if device >= 0:
             qdmf_set_matrix(self.h, lp["val"])
+            if qp:
+                qdmf_set_hessian(self.h, lp["q_val"])
 
     def close(self):
         if getattr(self, "h", None):
