@@ -2,10 +2,13 @@
 Section 2 (formulation with bounds), Section 3 (Newton system, its reduction to the augmented
 system, recovery, termination, regularisation) and Section 4.7 (number of correctors):
 
-    min c^T x  subject to  A x = b,  x - x^l = l,  x + x^u = u,  x^l, x^u >= 0,
+    min c^T x (+ x^T Q x / 2)  subject to  A x = b,  x - x^l = l,  x + x^u = u,  x^l, x^u >= 0,
 
 with every lower bound finite (no free variables, as the paper assumes) and upper bounds
-finite or +inf (then x^u and z^u are absent: zero in every formula).
+finite or +inf (then x^u and z^u are absent: zero in every formula).  The optional Q (dense,
+symmetric positive semidefinite) gives the quadratic-programming variant: the dual residual
+gains +Q x, the (1,1) block of the augmented system becomes -(Q + Theta^-1 + rho I), and both
+objectives carry x^T Q x / 2.
 
 TEST INFRASTRUCTURE ONLY: imported by the test-suite, never by the product library.  Dense
 NumPy linear algebra; every step in the order the paper gives it.  The readings of what the
@@ -43,14 +46,16 @@ def start(l, u, m):
     return State(x, xl, xu, np.zeros(m), zl, zu)
 
 
-def residuals(A, b, c, l, u, s):
+def residuals(A, b, c, l, u, s, Q=None):
     """Section 3: r1 = b - A x, r2 = l - x + x^l, r3 = u - x - x^u (finite u only),
-    r4 = c - A^T y - z^l + z^u."""
+    r4 = c - A^T y - z^l + z^u (+ Q x for a quadratic program)."""
     hasu = np.isfinite(u)
     r1 = b - A @ s.x
     r2 = l - s.x + s.xl
     r3 = np.where(hasu, u - s.x - s.xu, 0.0)
     r4 = c - A.T @ s.y - s.zl + s.zu
+    if Q is not None:
+        r4 = r4 + Q @ s.x
     return r1, r2, r3, r4
 
 
@@ -58,15 +63,16 @@ def mu_of(s, hasu):
     return float(s.xl @ s.zl + s.xu[hasu] @ s.zu[hasu]) / (len(s.x) + int(hasu.sum()))
 
 
-def newton_direction(A, s, hasu, tinv_reg, delta, r1, r2, r3, r4, r5, r6):
+def newton_direction(A, s, hasu, tinv_reg, delta, r1, r2, r3, r4, r5, r6, Q=None):
     """Section 3: the Newton system reduced to [[-(Theta^-1 + rho I), A^T], [A, delta I]]
-    [dx; dy] = [r7; r1] with Theta^-1 = z^l/x^l + z^u/x^u and
+    [dx; dy] = [r7; r1] (the (1,1) block -(Q + Theta^-1 + rho I) for a quadratic program)
+    with Theta^-1 = z^l/x^l + z^u/x^u and
     r7 = r4 - (X^l)^-1 (r5 + Z^l r2) + (X^u)^-1 (r6 - Z^u r3); then
     dx^l = dx - r2, dx^u = r3 - dx, dz^l = (X^l)^-1 (r5 - Z^l dx^l),
     dz^u = (X^u)^-1 (r6 - Z^u dx^u)."""
     m, n = A.shape
     K = np.zeros((n + m, n + m))
-    K[:n, :n] = -np.diag(tinv_reg)
+    K[:n, :n] = -np.diag(tinv_reg) if Q is None else -(Q + np.diag(tinv_reg))
     K[:n, n:] = A.T
     K[n:, :n] = A
     K[n:, n:] = delta * np.eye(m)
@@ -109,13 +115,14 @@ def corrector_count(nnz_l, flops_fact, f, alpha_f, kmax):
     return max(1, min(kmax, k))
 
 
-def converged(A, b, c, l, u, s, tau):
+def converged(A, b, c, l, u, s, tau, Q=None):
     """Section 3.1, without scaling: primal and dual feasibility and the relative gap, with
-    f_p = c^T x and f_d = b^T y + l^T z^l - u^T z^u."""
+    f_p = c^T x (+ x^T Q x / 2) and f_d = b^T y + l^T z^l - u^T z^u (- x^T Q x / 2)."""
     hasu = np.isfinite(u)
-    r1, r2, r3, r4 = residuals(A, b, c, l, u, s)
-    fp = float(c @ s.x)
-    fd = float(b @ s.y + l @ s.zl - u[hasu] @ s.zu[hasu])
+    r1, r2, r3, r4 = residuals(A, b, c, l, u, s, Q)
+    half_xqx = 0.0 if Q is None else 0.5 * float(s.x @ (Q @ s.x))
+    fp = float(c @ s.x) + half_xqx
+    fd = float(b @ s.y + l @ s.zl - u[hasu] @ s.zu[hasu]) - half_xqx
     pinf = max(np.max(np.abs(r1), initial=0.0), np.max(np.abs(r2), initial=0.0), np.max(np.abs(r3), initial=0.0))
     pscale = max(np.max(np.abs(b), initial=0.0), np.max(np.abs(l), initial=0.0),
                  np.max(np.abs(u[hasu]), initial=0.0))
@@ -125,10 +132,10 @@ def converged(A, b, c, l, u, s, tau):
     return ok, fp, fd
 
 
-def ipm(A, b, c, l=None, u=None, rho=1e-10, delta=1e-10, k=1, tau=1e-8, max_iter=100):
+def ipm(A, b, c, l=None, u=None, rho=1e-10, delta=1e-10, k=1, tau=1e-8, max_iter=100, Q=None):
     """Returns dict(x, y, zl, zu, state, iters, status ('optimal' | 'max_iter'), history, fp, fd)
     where history holds per iteration (mu, alpha_p, alpha_d, correctors used).  l defaults to
-    0 and u to +inf."""
+    0 and u to +inf; Q (dense) makes it a quadratic program."""
     A = np.asarray(A, dtype=float)
     m, n = A.shape
     l = np.zeros(n) if l is None else np.asarray(l, dtype=float)
@@ -138,16 +145,16 @@ def ipm(A, b, c, l=None, u=None, rho=1e-10, delta=1e-10, k=1, tau=1e-8, max_iter
     history = []
     it = 0
     for it in range(max_iter + 1):
-        ok, fp, fd = converged(A, b, c, l, u, s, tau)
+        ok, fp, fd = converged(A, b, c, l, u, s, tau, Q)
         if ok or it == max_iter:
             break
-        r1, r2, r3, r4 = residuals(A, b, c, l, u, s)
+        r1, r2, r3, r4 = residuals(A, b, c, l, u, s, Q)
         mu = mu_of(s, hasu)
         xu_safe = np.where(hasu, s.xu, 1.0)
         tinv = s.zl / s.xl + np.where(hasu, s.zu / xu_safe, 0.0) + rho  # plus the primal regularisation
         # predictor: sigma = 0
         r5, r6 = -s.xl * s.zl, np.where(hasu, -s.xu * s.zu, 0.0)
-        da = newton_direction(A, s, hasu, tinv, delta, r1, r2, r3, r4, r5, r6)
+        da = newton_direction(A, s, hasu, tinv, delta, r1, r2, r3, r4, r5, r6, Q)
         apa, ada = steps(s, da, hasu)
         nc = n + int(hasu.sum())
         comp = float((s.xl + apa * da.xl) @ (s.zl + ada * da.zl)
@@ -170,7 +177,7 @@ def ipm(A, b, c, l=None, u=None, rho=1e-10, delta=1e-10, k=1, tau=1e-8, max_iter
 
             t5 = target(s.xl, d.xl, s.zl, d.zl)
             t6 = np.where(hasu, target(s.xu, d.xu, s.zu, d.zu), 0.0)
-            e = newton_direction(A, s, hasu, tinv, delta, zero_m, zero_n, zero_n, zero_n, t5, t6)
+            e = newton_direction(A, s, hasu, tinv, delta, zero_m, zero_n, zero_n, zero_n, t5, t6, Q)
             nd = add(d, e)
             nap, nad = steps(s, nd, hasu)
             if j > 0 and nap + nad < (1.0 + ACCEPT_GAIN) * (ap + ad):

@@ -15,6 +15,10 @@ synthetic stand-in with the shape of the systems the paper factorises (Sections 
 * ``as_batch``       -- many independent small random LPs, augmented-system form.
 * ``as_dense_cols``  -- grid-coupled LP with a few dense columns, augmented-system form.
 * ``dense_front``    -- a single dense symmetric front with quasi-definite diagonal signs.
+* ``feasible_lp``, ``bounded_lp`` -- b, c (and bounds l, u) making an LP over a workload's A
+                        primal and dual feasible, for the interior point driver.
+* ``with_hessian``   -- a sparse positive semidefinite Q on a workload's columns (quadratic
+                        programs).
 
 All randomness comes from ``numpy.random.Generator(PCG64(SeedSequence(seed_list)))``.
 """
@@ -301,7 +305,9 @@ def bounded_lp(lp, seed=7, upper=0.5):
     feasible by construction: l uniform in [-1, 1]; a fraction `upper` of the columns (chosen at
     random) gets u = l + w with w uniform in [1, 3], the rest u = +inf; x0 strictly inside the
     bounds; b = A x0 and c = A^T y0 + z^l0 - z^u0 with z^l0 uniform in [0.5, 1.5], z^u0 uniform
-    in [0, 1] where u is finite.  Returns (A as a LP dict with mode AS, b, c, l, u)."""
+    in [0, 1] where u is finite.  For a quadratic program (`lp` with Q, see with_hessian) c is
+    lowered by Q x0, so that (x0, y0, z0) is feasible for the dual of min c^T x + x^T Q x / 2.
+    Returns (A as a LP dict with mode AS, b, c, l, u)."""
     g = rng(seed, 72)
     m, n = lp["m"], lp["n"]
     l = g.uniform(-1.0, 1.0, n)
@@ -319,6 +325,14 @@ def bounded_lp(lp, seed=7, upper=0.5):
         rows, vals = ri[cp[j]:cp[j + 1]], v[cp[j]:cp[j + 1]]
         b[rows] += vals * x0[j]
         c[j] += float(vals @ y0[rows])
+    if lp.get("q_colptr") is not None:
+        qcp, qri, qv = lp["q_colptr"], lp["q_rowidx"], lp["q_val"]
+        for j in range(n):
+            for e in range(qcp[j], qcp[j + 1]):
+                i = qri[e]
+                c[i] -= qv[e] * x0[j]
+                if i != j:
+                    c[j] -= qv[e] * x0[i]
     out = LP(dict(lp, mode=AS))
     return out, b, c, l, u
 

@@ -133,3 +133,83 @@ def test_corrector_count_bounds():
     assert I.corrector_count(1000, 1e12, 2, 1.0, 6) == 6  # dear factorisation: the maximum
     ks = [I.corrector_count(1000, f, 1, 1.0, 50) for f in (1e4, 1e5, 1e6, 1e7)]
     assert ks == sorted(ks)
+
+
+# ---------------------------------------------------------------- quadratic programs
+
+def test_textbook_qp():
+    """min (x1^2 + x2^2)/2 - 2 x1 s.t. x1 + x2 + s = 1, x >= 0: the unconstrained minimiser
+    x1 = 2 is cut off, so x = (1, 0, 0) with value -1.5; the dual is y = -1, z = (0, 1, 1)."""
+    A = np.array([[1.0, 1.0, 1.0]])
+    b = np.array([1.0])
+    c = np.array([-2.0, 0.0, 0.0])
+    Qm = np.diag([1.0, 1.0, 0.0])
+    r = I.ipm(A, b, c, k=1, Q=Qm)
+    assert r["status"] == "optimal"
+    assert abs(r["fp"] + 1.5) <= 1e-6
+    assert np.allclose(r["x"], [1.0, 0.0, 0.0], atol=1e-6)
+    assert np.allclose(r["y"], [-1.0], atol=1e-6)
+    assert np.allclose(r["zl"], [0.0, 1.0, 1.0], atol=1e-6)
+
+
+def kkt_violation(A, b, c, Qm, l, u, x, y, zl, zu):
+    """Largest violation of the optimality conditions of the convex QP, written out here:
+    A x = b, l <= x <= u, c + Q x - A^T y - z^l + z^u = 0, z >= 0, (x - l) z^l = (u - x) z^u = 0."""
+    hasu = np.isfinite(u)
+    v = [np.abs(A @ x - b).max(), np.maximum(l - x, 0).max(), np.maximum(x - u, 0)[hasu].max(initial=0.0),
+         np.abs(c + Qm @ x - A.T @ y - zl + zu).max(), np.maximum(-zl, 0).max(), np.maximum(-zu, 0).max(),
+         np.abs((x - l) * zl).max(), np.abs(np.where(hasu, (np.where(hasu, u, 0.0) - x) * zu, 0.0)).max()]
+    return max(v)
+
+
+@pytest.mark.parametrize("m,n,d,seed,upper", [(30, 70, 0.08, 0, 0.5), (60, 150, 0.04, 1, 0.0)])
+def test_qp_optimum_satisfies_kkt(m, n, d, seed, upper):
+    base = W.ne_random(m=m, n=n, density=d, seed=50 + seed)
+    lpq = W.with_hessian(W.LP(dict(base, mode=W.AS)), seed=seed, window=8)
+    lp, b, c, l, u = W.bounded_lp(lpq, seed=seed, upper=upper)
+    A, Qm = W.lp_dense(lp), W.q_dense(lpq)
+    r = I.ipm(A, b, c, l, u, k=2, Q=Qm)
+    assert r["status"] == "optimal"
+    scale = 1 + max(np.abs(b).max(), np.abs(c).max())
+    assert kkt_violation(A, b, c, Qm, l, u, r["x"], r["y"], r["zl"], r["zu"]) <= 1e-6 * scale
+    # the gap of the termination test is the duality gap of the QP
+    assert abs(r["fp"] - r["fd"]) <= 1e-7 * (1 + abs(r["fp"]))
+
+
+def test_qp_with_far_bounds_is_the_equality_constrained_minimiser():
+    """With Q positive definite and every bound far from the optimum, the QP's solution is that
+    of the linear KKT system [[Q, -A^T], [A, 0]] [x; y] = [-c; b] (LAPACK)."""
+    base = W.ne_random(m=25, n=60, density=0.1, seed=57)
+    lpq = W.with_hessian(W.LP(dict(base, mode=W.AS)), seed=4, frac=1.0, window=6, ridge=1.0)
+    A, Qm = W.lp_dense(lpq), W.q_dense(lpq)
+    g = W.rng(58)
+    m, n = A.shape
+    b, c = A @ g.uniform(-1, 1, n), g.standard_normal(n)
+    K = np.block([[Qm, -A.T], [A, np.zeros((m, m))]])
+    sol = np.linalg.solve(K, np.concatenate([-c, b]))
+    x_star, y_star = sol[:n], sol[n:]
+    l = np.full(n, x_star.min() - 1e3)
+    r = I.ipm(A, b, c, l, k=2, Q=Qm)
+    assert r["status"] == "optimal"
+    assert np.allclose(r["x"], x_star, atol=1e-6 * (1 + np.abs(x_star).max()))
+    assert np.allclose(r["y"], y_star, atol=1e-6 * (1 + np.abs(y_star).max()))
+
+
+def test_reduced_qp_direction_solves_the_full_newton_system():
+    """The direction of a quadratic program against the unreduced Newton system, whose dual row
+    reads -Q dx + A^T dy + dz^l - dz^u = r4."""
+    g = W.rng(34)
+    m, n = 30, 70
+    base = W.ne_random(m=m, n=n, density=0.08, seed=34)
+    lpq = W.with_hessian(W.LP(dict(base, mode=W.AS)), seed=5, window=8)
+    A, Qm = W.lp_dense(lpq), W.q_dense(lpq)
+    s = I.State(g.uniform(-1, 1, n), g.uniform(0.1, 2, n), g.uniform(0.1, 2, n), g.standard_normal(m),
+                g.uniform(0.1, 2, n), g.uniform(0.1, 2, n))
+    hasu = np.ones(n, bool)
+    r1, r2, r3, r4, r5, r6 = (g.standard_normal(m),) + tuple(g.standard_normal(n) for _ in range(5))
+    d = I.newton_direction(A, s, hasu, s.zl / s.xl + s.zu / s.xu, 0.0, r1, r2, r3, r4, r5, r6, Qm)
+    assert np.abs(A @ d.x - r1).max() <= 1e-9
+    assert np.abs(d.x - d.xl - r2).max() <= 1e-9 and np.abs(d.x + d.xu - r3).max() <= 1e-9
+    assert np.abs(-Qm @ d.x + A.T @ d.y + d.zl - d.zu - r4).max() <= 1e-9 * (1 + np.abs(d.y).max())
+    assert np.abs(s.zl * d.xl + s.xl * d.zl - r5).max() <= 1e-9
+    assert np.abs(s.zu * d.xu + s.xu * d.zu - r6).max() <= 1e-9
