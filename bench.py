@@ -90,6 +90,8 @@ def make_workload(name):
     if name == "as_dense_cols":
         lp = W.as_dense_cols()
         return lp, dict(ordering=2, grid=lp["grid"])
+    if name == "as_staircase_qp":  # the staircase with a Hessian on half of its columns
+        return W.with_hessian(W.as_staircase(), seed=1, frac=0.5, per_row=3, window=50), dict()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -259,7 +261,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="as_staircase",
                     help="as_staircase | ne_random | ne_grid | ne_grid_small | as_batch | as_batch_small | "
-                         "as_dense_cols | ne_dense_front[_<f>]")
+                         "as_dense_cols | ne_dense_front[_<f>] | as_staircase_qp")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--nsolves", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")

@@ -303,8 +303,10 @@ int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
  * Arguments (caller-owned device buffers): b (m), c (n); l (n) or NULL for l = 0; u (n) or
  * NULL for u = +inf everywhere; x, z^l (n) and y (m) receive the last iterate; zu (n) receives
  * z^u (0 where u is infinite) or is NULL.  Runs on the handle's stream and synchronises it
- * several times per iteration.  Errors: QDMF_ERR_INVALID_ARG (also for a bad bound),
- * QDMF_ERR_UNSUPPORTED (the handle holds a quadratic program),
+ * several times per iteration.  A handle analysed with qdmf_analyse_qp (Q set with
+ * qdmf_set_hessian) solves the quadratic program min c^T x + x^T Q x / 2 under the same
+ * constraints: the dual residual gains +Q x, the factorised block is -(Q + Theta^-1 + rho I)
+ * and both objectives carry x^T Q x / 2.  Errors: QDMF_ERR_INVALID_ARG (also for a bad bound),
  * QDMF_ERR_NOT_ANALYSED (or not AS), QDMF_ERR_NO_MATRIX, QDMF_ERR_HIP, QDMF_ERR_OOM, and the
  * codes of qdmf_factorise / qdmf_solve. */
 typedef struct {
@@ -324,7 +326,7 @@ typedef struct {
     int32_t correctors;       /* correctors allowed per iteration                            */
     double primal_obj, dual_obj;
     double pinf;              /* max of ||b - A x||_inf, ||l - x + x^l||_inf, ||u - x - x^u||_inf */
-    double dinf;              /* ||c - A^T y - z^l + z^u||_inf                               */
+    double dinf;              /* ||c - A^T y - z^l + z^u (+ Q x)||_inf                       */
     double mu;                /* mean complementarity product at the last iterate            */
     double ms;                /* wall time of the iterations                                 */
 } qdmf_ipm_info;

@@ -1042,8 +1042,7 @@ int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, cons
     constexpr double STEP_FACTOR = 0.995, ALPHA_PLUS = 0.1, BETA_MIN = 0.1, BETA_MAX = 10.0, ACCEPT_GAIN = 0.01;
     if (!h || !info || !b_dev || !c_dev || !x_dev || !y_dev || !zl_dev || h->host_only) return QDMF_ERR_INVALID_ARG;
     if (!h->analysed || h->P.mode != QDMF_AS || h->P.nsys != 1) return QDMF_ERR_NOT_ANALYSED;
-    if (h->P.has_q) return QDMF_ERR_UNSUPPORTED;  // the driver solves linear programs
-    if (!h->have_matrix) return QDMF_ERR_NO_MATRIX;
+    if (!h->have_matrix || (h->P.has_q && !h->have_hessian)) return QDMF_ERR_NO_MATRIX;
     qdmf_ipm_options opt;
     if (opt_in) opt = *opt_in;
     else qdmf_ipm_default_options(&opt);
@@ -1114,12 +1113,13 @@ int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, cons
     rc = 0;
     for (;; ++it) {
         ipm_resid(h->D, pt, b_dev, c_dev, l_dev, u_dev, r1, r2, r3, r4, part, out, st);
-        if (!read(13)) {
+        if (!read(14)) {
             rc = QDMF_ERR_HIP;
             break;
         }
         const double pinf = std::max(sc[0], std::max(sc[7], sc[8])), dinf = sc[1];
-        const double fp = sc[2], fd = sc[3] + sc[9] - sc[10], comp = sc[4];
+        const double half_xqx = 0.5 * sc[13];  // 0 for a linear program
+        const double fp = sc[2] + half_xqx, fd = sc[3] + sc[9] - sc[10] - half_xqx, comp = sc[4];
         const double pscale = std::max(sc[5], std::max(sc[11], sc[12])), cmax = sc[6];
         res.pinf = pinf;
         res.dinf = dinf;

@@ -1,10 +1,12 @@
 // Device kernels of the interior point driver (Section 3 of the paper) for the LP with bounds
 // of Section 2: min c^T x subject to A x = b, x - x^l = l, x + x^u = u, x^l, x^u >= 0, with
-// every l finite and u finite or +inf.  The kernels compute the residuals and the scalars of
-// the termination test, Theta, the right-hand sides of the predictor and of the centrality
-// correctors, the recovery of a direction from its dx, step lengths to the boundary, the
-// complementarity at a trial point, and the update.  Reductions are per-block partials
-// combined in a fixed order by one workgroup, so every run gives the same bits.
+// every l finite and u finite or +inf; for a quadratic program the objective gains
+// x^T Q x / 2 (Q from the handle) and the dual residual +Q x.  The kernels compute the
+// residuals and the scalars of the termination test, Theta, the right-hand sides of the
+// predictor and of the centrality correctors, the recovery of a direction from its dx, step
+// lengths to the boundary, the complementarity at a trial point, and the update.  Reductions
+// are per-block partials combined in a fixed order by one workgroup, so every run gives the
+// same bits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,10 +65,11 @@ __global__ __launch_bounds__(IPM_T) void k_ipm_start(const double* l, const doub
 }
 
 // Residuals of Section 3: r1 = b - A x (rows); r2 = l - x + x^l, r3 = u - x - x^u (0 where
-// u is infinite), r4 = c - A^T y - z^l + z^u (columns).  Per block, the quantities
+// u is infinite), r4 = c - A^T y - z^l + z^u (+ Q x) (columns).  Per block, the quantities
 //   0 max|r1|  1 max|r4|  2 sum c x  3 sum b y  4 sum x^l z^l + x^u z^u  5 max|b|  6 max|c|
 //   7 max|r2|  8 max|r3|  9 sum l z^l  10 sum u z^u (finite u)  11 max|l|  12 max|u| (finite u)
-constexpr int RESID_Q = 13;
+//   13 sum x (Q x)
+constexpr int RESID_Q = 14;
 constexpr unsigned RESID_MAX_MASK = (1u << 0) | (1u << 1) | (1u << 5) | (1u << 6) | (1u << 7) | (1u << 8) |
                                     (1u << 11) | (1u << 12);
 
@@ -92,7 +95,10 @@ __global__ __launch_bounds__(IPM_T) void k_ipm_resid(DevPlan D, IpmVec p, const 
     if (i < D.n) {
         double aty = 0.0;
         for (int64_t e = D.acp[i]; e < D.acp[i + 1]; ++e) aty += D.aval[e] * p.y[D.ari[e]];
-        const double ra = c[i] - aty - p.zl[i] + p.zu[i];
+        double qx = 0.0;
+        if (D.has_q)
+            for (int64_t e = D.qfcp[i]; e < D.qfcp[i + 1]; ++e) qx += D.qval[D.qfsrc[e]] * p.x[D.qfri[e]];
+        const double ra = D.has_q ? (c[i] - aty - p.zl[i] + p.zu[i]) + qx : c[i] - aty - p.zl[i] + p.zu[i];
         r4[i] = ra;
         const double li = lower(l, i);
         const bool hu = has_upper(u, i);
@@ -110,6 +116,7 @@ __global__ __launch_bounds__(IPM_T) void k_ipm_resid(DevPlan D, IpmVec p, const 
         v[10] = hu ? u[i] * p.zu[i] : 0.0;
         v[11] = fabs(li);
         v[12] = hu ? fabs(u[i]) : 0.0;
+        v[13] = p.x[i] * qx;
     }
     for (int q = 0; q < RESID_Q; ++q) {
         const double s = block_reduce(v[q], red, (RESID_MAX_MASK >> q) & 1u);

@@ -138,3 +138,34 @@ def test_bounded_ipm_rejects_bad_bounds(torch_dev):
         with pytest.raises(Q.QdmfError) as e:
             gpu_ipm(torch_dev, lp, b, c, l2, u2)
         assert e.value.code == Q.QDMF_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("m,n,d,seed,upper", [(50, 100, 0.05, 0, 0.5), (80, 240, 0.03, 2, 0.0)])
+def test_qp_ipm_matches_reference_iterations(torch_dev, m, n, d, seed, upper):
+    """A quadratic program (Q from workloads.with_hessian) through qdmf_analyse_qp: the driver
+    against the reference method with the same Q, iteration by iteration, and the optimality
+    conditions of the convex QP at its last iterate."""
+    base = W.ne_random(m=m, n=n, density=d, seed=60 + seed)
+    lpq = W.with_hessian(W.LP(dict(base, mode=W.AS)), seed=seed, window=10)
+    lp, b, c, l, u = W.bounded_lp(lpq, seed=seed, upper=upper)
+    print(f"[gpu case] qp ipm m={m} n={n} seed={seed} upper={upper}", flush=True)
+    g = gpu_ipm(torch_dev, lp, b, c, l, u, correctors=2)
+    A, Qm = W.lp_dense(lp), W.q_dense(lp)
+    r = I.ipm(A, b, c, l, u, k=2, Q=Qm)
+    info = g["info"]
+    print(f"  gpu: status {info['status']} iters {info['iters']} obj {info['primal_obj']:.12g} "
+          f"{info['ms']:.1f} ms; reference iters {r['iters']} obj {r['fp']:.12g}")
+    assert info["status"] == 0 and r["status"] == "optimal"
+    assert abs(info["iters"] - r["iters"]) <= 1
+    assert abs(info["primal_obj"] - r["fp"]) <= 1e-7 * (1 + abs(r["fp"]))
+    hg, hr = g["hist"], np.array(r["history"])
+    for it in range(3):
+        assert hg[it, 3] == hr[it, 3], it
+        assert np.allclose(hg[it, :3], hr[it, :3], rtol=1e-8, atol=0), (it, hg[it], hr[it])
+    hasu = np.isfinite(u)
+    x, y, zl, zu = g["x"], g["y"], g["zl"], g["zu"]
+    scale = 1 + max(np.abs(b).max(), np.abs(c).max())
+    assert np.abs(A @ x - b).max() <= 1e-6 * scale
+    assert np.all(x > l) and np.all(x[hasu] < u[hasu]) and np.all(zl > 0) and np.all(zu[hasu] > 0)
+    assert np.abs(c + Qm @ x - A.T @ y - zl + zu).max() <= 1e-6 * scale
+    assert np.abs((x - l) * zl).max() <= 1e-6 * scale
