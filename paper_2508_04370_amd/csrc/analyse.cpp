@@ -308,6 +308,9 @@ int64_t ne_pattern_count(int32_t m, int32_t n, const int64_t* colptr, const int3
 
 // Q's lower triangle: rows >= the column, strictly increasing, inside [0, n); the full
 // symmetric pattern with the source of each value, and the diagonal positions.
+// pivot columns of one window of the factorisation kernels (Section 4.4's block of nb columns)
+constexpr int64_t AMALG_WINDOW = 64;
+
 static int set_hessian_pattern(int32_t n, const int64_t* qcp, const int32_t* qri, Plan& P, std::string& msg) {
     if (qcp[0] != 0) {
         msg = "Q: colptr[0] must be 0";
@@ -544,6 +547,12 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     std::vector<int64_t> s_f(ns0);
     for (int32_t s = 0; s < ns0; ++s) s_f[s] = fsize(s);
     std::vector<int32_t> merged_into(ns0, -1);
+    // children of the alive supernodes and the height of each finished one (0 for a leaf): the
+    // tree levels the launch plan will follow
+    std::vector<std::vector<int32_t>> s_kids(ns0);
+    for (int32_t s = 0; s < ns0; ++s)
+        if (s_par[s] >= 0) s_kids[s_par[s]].push_back(s);
+    std::vector<int32_t> s_h(ns0, 0);
     if (opt.amalgamate) {
         for (int32_t s = 0; s < ns0; ++s) {
             for (;;) {
@@ -563,9 +572,19 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                 int64_t ent = pm * fm - pm * (pm - 1) / 2;
                 int64_t zeros = s_zero[c] + s_zero[s] + pc * delta;
                 // (the third rule: large nearly dense fronts, whose separate square storage
-                // and pivot windows would cost more than the few zeros)
+                // and pivot windows would cost more than the few zeros; the fourth: a merged
+                // supernode that still fits one pivot window, which saves the child's
+                // contribution-block copy and, on chains of such supernodes, tree levels,
+                // without lengthening the sequence of pivot steps of the level it lands on)
                 bool ok = (s_nk[s] == 1 && delta <= 8) || (pc < 16 && (double)zeros <= 0.05 * (double)ent) ||
                           (fm >= 512 && (double)zeros <= 0.01 * (double)ent);
+                if (!ok && pm <= AMALG_WINDOW && (double)zeros <= 0.05 * (double)ent) {
+                    // the fourth rule only on chains: every other child of s is a leaf, so c
+                    // alone sets s's level and the merge removes a level of the subtree
+                    ok = true;
+                    for (int32_t k : s_kids[s])
+                        if (k != c && s_h[k] > 0) ok = false;
+                }
                 if (!ok) break;
                 // merge c into s
                 alive[c] = 0;
@@ -575,7 +594,12 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                 s_f[s] = fm;
                 s_zero[s] = zeros;
                 s_nk[s] += s_nk[c] - 1;
+                auto& ks = s_kids[s];
+                ks.erase(std::find(ks.begin(), ks.end(), c));
+                ks.insert(ks.end(), s_kids[c].begin(), s_kids[c].end());
+                std::vector<int32_t>().swap(s_kids[c]);
             }
+            for (int32_t k : s_kids[s]) s_h[s] = std::max(s_h[s], s_h[k] + 1);
         }
     }
     // resolve parents through merges, renumber alive supernodes (ascending start = postorder)
