@@ -1540,18 +1540,27 @@ __device__ void fwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
                     v[u] = (on && t < p) ? xw[c0 + t] : 0.0;
                     dst[u] = on ? (t < p ? D.lpinv[c0 + t] : t) : -1;
                 }
+                // four contributions of each of the four rows per trip: their source indices,
+                // then their values, in flight together (added in list order)
                 bool more = true;
                 while (more) {
-                    int64_t src[4];
+                    int64_t src[4][4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) src[u] = qa[u] < qe[u] ? D.fg_src[qa[u]] : -1;
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) src[u][j] = qa[u] + j < qe[u] ? D.fg_src[qa[u] + j] : -1;
+                    double val[4][4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) val[u][j] = src[u][j] >= 0 ? ub[src[u][j]] : 0.0;
                     more = false;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        if (src[u] >= 0) {
-                            v[u] += ub[src[u]];
-                            ++qa[u];
-                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (src[u][j] >= 0) v[u] += val[u][j];
+                        qa[u] += 4;
                         more |= qa[u] < qe[u];
                     }
                 }
@@ -1768,7 +1777,17 @@ __global__ __launch_bounds__(256) void k_sgather(DevPlan D, DevSolve S, const Ta
         const double* xw = S.xw + (int64_t)r * D.N;
         const double* ub = S.ub + (int64_t)r * D.ub_total;
         double v = i < p ? xw[c0 + i] : 0.0;
-        for (int64_t q = q0; q < q1; ++q) v += ub[D.fg_src[q]];
+        for (int64_t q = q0; q < q1; q += 4) {  // four contributions in flight, added in list order
+            int64_t src[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) src[j] = q + j < q1 ? D.fg_src[q + j] : -1;
+            double val[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) val[j] = src[j] >= 0 ? ub[src[j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (src[j] >= 0) v += val[j];
+        }
         S.Y[dst + (int64_t)r * S.ytot] = v;
     }
 }
@@ -2067,7 +2086,17 @@ __global__ __launch_bounds__(256) void k_fwd_wave(DevPlan D, DevSolve S, const i
         double* xw = S.xw + (int64_t)r * D.N;
         double* ub = S.ub + (int64_t)r * D.ub_total;
         double y = (on && lane < p) ? xw[c0 + t] : 0.0;
-        for (int64_t q = q0; q < q1; ++q) y += ub[D.fg_src[q]];
+        for (int64_t q = q0; q < q1; q += 4) {  // four contributions in flight, added in list order
+            int64_t src[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) src[j] = q + j < q1 ? D.fg_src[q + j] : -1;
+            double val[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) val[j] = src[j] >= 0 ? ub[src[j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (src[j] >= 0) y += val[j];
+        }
 #pragma unroll
         for (int k = 0; k < PM; ++k) {  // every pivot, the last one too: rows below are lanes >= p
             if (k < p) {
