@@ -537,6 +537,17 @@ __device__ inline int wave_argmax_nn(double x, bool ok) {
     return __ffsll((long long)ballot64(key != 0ull && hi == mh && lo == ml)) - 1;
 }
 
+// The rest of wave_argmax_nn once mh = wave_umax(upper half of key) is known (the reduction
+// can then be issued early and the selection finished later).
+__device__ inline int wave_argmax_finish(unsigned long long key, unsigned mh) {
+    const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+    const unsigned long long m1 = ballot64(key != 0ull && hi == mh);
+    if (m1 == 0ull) return -1;
+    if ((m1 & (m1 - 1ull)) == 0ull) return __ffsll((long long)m1) - 1;
+    const unsigned ml = wave_umax(hi == mh ? lo : 0u);
+    return __ffsll((long long)ballot64(key != 0ull && hi == mh && lo == ml)) - 1;
+}
+
 // In one interleaved pass: the argmax r of x >= 0 over the okx lanes (lowest lane on ties,
 // -1 if none) with its value xm, and the maximum ym of y >= 0 over the oky lanes (0 if none).
 __device__ inline void wave_argmax_max_nn(double x, bool okx, double y, bool oky, int& r, double& xm,
@@ -648,33 +659,37 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
     int o_pt = 0, o_fl = 0, o_zs = 0;
     int par = 0;
     int k = 0;
+    // presort (largest |diagonal| of the window to position kk), done for pivot k + 1 (or k + 2)
+    // at the end of the step of pivot k, as soon as the diagonal is updated
+    auto presort_at = [&](int kk, int q) {
+        q = (q < kk || q >= nbw) ? kk : q;  // no candidate (NaN input): no swap
+        // exchanging position kk with itself changes nothing: no branch needed
+        slotW = xchg_i(slotW, kk, q, lane);
+        dgP = xchg_d(dgP, kk, q, lane);
+        derive();
+    };
+    if (pp.presort && nbw > 0) presort_at(0, wave_argmax_nn(fabs(dgP), lane < nbw));
     while (k < nbw) {
-        if (pp.presort) {  // largest |diagonal| of the window to position k
-            int q = wave_argmax_nn(fabs(dgP), lane >= k && lane < nbw);
-            q = (q < k || q >= nbw) ? k : q;  // no candidate (NaN input): no swap
-            // exchanging position k with itself changes nothing: no branch needed
-            slotW = xchg_i(slotW, k, q, lane);
-            dgP = xchg_d(dgP, k, q, lane);
-            derive();
-        }
         const int sk = __builtin_amdgcn_readlane(slotP, k);
         if (cq == (sk >> 4)) {
 #pragma unroll
             for (int g = 0; g < RG; ++g) colA[par][64 * g + lane] = T[g][sk & 15];
         }
+        // what the tests below need apart from the pivot column, before the barrier
+        const double fkk = readlane_d(dgP, k);
+        const int sgk0 = __builtin_amdgcn_readlane(sgP, k);
+        const bool below = lane > k && lane < nbw;
+        const double den = fabs(dgP + shP);
+        const bool same = below && sgP == sgk0;
+        const double rden = recip(den);
         __syncthreads();
         // gamma_p (largest |F_ik| below k in the window) and, for a 1x1 pivot on this column,
         // the Proposition 3 bound over same-sign positions, in one pass
-        const double fkk = readlane_d(dgP, k);
-        const int sgk0 = __builtin_amdgcn_readlane(sgP, k);
         const double cP = colA[par][slotP];
-        const bool below = lane > k && lane < nbw;
         double gp, beta;
         int r, nz;
         {
-            const double den = fabs(dgP + shP);
-            const bool same = below && sgP == sgk0;
-            const double qv = (same && den != 0.0) ? cP * cP * recip(den) : 0.0;
+            const double qv = (same && den != 0.0) ? cP * cP * rden : 0.0;
             wave_argmax_max_nn(fabs(cP), below, qv, same && den != 0.0, r, gp, beta);
             nz = __popcll(ballot64(same && den == 0.0));
             if (!(gp > 0.0)) {
@@ -793,6 +808,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
                     o_fl = 0;
                     o_zs = 0;
                 }
+                if (pp.presort && k + 2 < nbw) presort_at(k + 2, wave_argmax_nn(fabs(dgP), lane > k + 1 && lane < nbw));
                 par ^= 1;
                 k += 2;
                 continue;
@@ -816,6 +832,23 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         const double e = dk - (fkk_before + shk);
         elim |= 1ull << piv;
         const double rdk = recip(dk);
+        {  // diagonal of the remaining positions, first: the next presort needs it
+            const double cw = colP[slotP];
+            dgP = (lane > k && lane < nbw) ? dgP - (cw * rdk) * cw : dgP;
+        }
+        if (lane == k) {
+            o_d = dk;
+            o_off = 0.0;
+            o_pt = 0;
+            o_ed = e;
+            o_fl = flag;
+            o_zs = nz;
+        }
+        // the wave maximum for the next presort is issued before the trailing update, so that
+        // its dependent steps and the update's independent multiply-adds overlap
+        const bool pnext = pp.presort && k + 1 < nbw;
+        const unsigned long long nkey = nn_key(fabs(dgP), pnext && lane > k && lane < nbw);
+        const unsigned nmh = wave_umax((unsigned)(nkey >> 32));
         {
             double wq[16];
 #pragma unroll
@@ -833,18 +866,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
                 }
             }
         }
-        {  // diagonal of the remaining positions
-            const double cw = colP[slotP];
-            if (lane > k && lane < nbw) dgP -= (cw * rdk) * cw;
-        }
-        if (lane == k) {
-            o_d = dk;
-            o_off = 0.0;
-            o_pt = 0;
-            o_ed = e;
-            o_fl = flag;
-            o_zs = nz;
-        }
+        if (pnext) presort_at(k + 1, wave_argmax_finish(nkey, nmh));
         par ^= 1;
         k += 1;
     }
