@@ -555,6 +555,16 @@ __device__ inline void wave_argmax_max_nn(double x, bool okx, double y, bool oky
     const unsigned long long kx = nn_key(x, okx), ky = nn_key(y, oky);
     unsigned hx = (unsigned)(kx >> 32), hy = (unsigned)(ky >> 32);
     wave_umax2(hx, hy);
+    {  // the usual case: at most one lane attains each largest upper half, whose key is the maximum
+        const unsigned long long bx = ballot64(kx != 0ull && (unsigned)(kx >> 32) == hx);
+        const unsigned long long by = ballot64(ky != 0ull && (unsigned)(ky >> 32) == hy);
+        if ((bx & (bx - 1ull)) == 0ull && (by & (by - 1ull)) == 0ull) {
+            r = bx ? __ffsll((long long)bx) - 1 : -1;
+            xm = bx ? readlane_d(x, r) : 0.0;
+            ym = by ? readlane_d(y, __ffsll((long long)by) - 1) : 0.0;
+            return;
+        }
+    }
     unsigned lx = (unsigned)(kx >> 32) == hx ? (unsigned)kx : 0u;
     unsigned ly = (unsigned)(ky >> 32) == hy ? (unsigned)ky : 0u;
     wave_umax2(lx, ly);
@@ -686,6 +696,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         // gamma_p (largest |F_ik| below k in the window) and, for a 1x1 pivot on this column,
         // the Proposition 3 bound over same-sign positions, in one pass
         const double cP = colA[par][slotP];
+
         double gp, beta;
         int r, nz;
         {
@@ -832,6 +843,11 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         const double e = dk - (fkk_before + shk);
         elim |= 1ull << piv;
         const double rdk = recip(dk);
+        double wq[16], lin[RG];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) wq[q] = colP[16 * cq + q];
+#pragma unroll
+        for (int g = 0; g < RG; ++g) lin[g] = colP[64 * g + lane];
         {  // diagonal of the remaining positions, first: the next presort needs it
             const double cw = colP[slotP];
             dgP = (lane > k && lane < nbw) ? dgP - (cw * rdk) * cw : dgP;
@@ -850,14 +866,11 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
         const unsigned long long nkey = nn_key(fabs(dgP), pnext && lane > k && lane < nbw);
         const unsigned nmh = wave_umax((unsigned)(nkey >> 32));
         {
-            double wq[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) wq[q] = colP[16 * cq + q];
             const bool crem = lane < nbw && !((elim >> lane) & 1);
 #pragma unroll
             for (int g = 0; g < RG; ++g) {
                 const bool rem = g > 0 ? prow0 + 64 * g < f : crem;
-                const double li = rem ? colP[64 * g + lane] * rdk : 0.0;
+                const double li = rem ? lin[g] * rdk : 0.0;
 #pragma unroll
                 for (int q = 0; q < 16; ++q) T[g][q] -= li * wq[q];
                 if (cq == 0) {
