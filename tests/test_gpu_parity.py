@@ -165,6 +165,23 @@ def test_matched_mode_reproduces_oracle_pivots(torch_dev, trange, reg):
         assert rel.max() <= 1e-6
 
 
+def test_matched_mode_without_presort(torch_dev):
+    """The same with the presort swap switched off on both sides: the window's pivot steps take
+    positions in order, and every decision must still match the oracle's."""
+    lp = W.as_staircase(periods=3, rows=40, cols=80, link_cols=8, seed=9, theta_range=(1e-1, 1e1),
+                        rho=1e-2, delta=1e-2)
+    S = O.Sym(lp)
+    g = gpu_solve(torch_dev, lp, perm=S.perm(), amalgamate=0, presort=0)
+    ex = O.Num(S, lp["val"], lp["theta"], lp["rho"], lp["delta"], opts=O.default_opts(presort=0)).export()
+    gd = g["solver"].export_d()
+    assert np.array_equal(gd["pivot_order"], ex["fperm"])
+    assert np.array_equal(gd["ptype"], ex["ptype"])
+    assert np.array_equal(gd["edyn"] != 0, ex["edyn"] != 0)
+    rel = np.abs(gd["d"] - ex["d"]) / np.abs(ex["d"])
+    print("max relative pivot difference", rel.max())
+    assert rel.max() <= 1e-12
+
+
 def test_full_staircase_fp64(torch_dev):
     lp = W.as_staircase()
     g = gpu_solve(torch_dev, lp)
