@@ -28,7 +28,9 @@ PEAK_FP64 = 78.6e12   # MI355X dense FP64, matrix and vector (FLOP/s)
 PEAK_FP32 = 157.3e12  # dense FP32 matrix (FLOP/s)
 PEAK_HBM = 8.0e12     # HBM3E (bytes/s)
 
-# which resource bounds each kernel kind ("Kernels and their rooflines")
+# which resource bounds each kernel kind: the dependent FP64 steps of the pivot chains (small
+# fronts, windows), HBM for assembly, finalize and the solves, the matrix units for the trailing
+# update
 KIND_BOUND = {0: "alu", 1: "hbm", 2: "alu", 3: "mfma", 4: "hbm", 5: "hbm", 6: "hbm"}
 
 
@@ -278,8 +280,9 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: multi-GPU execution is not part of this build "
-              "(DESIGN.md describes how the factorisation would shard)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU (--gpus 1): the library factorises on one device; "
+              "across several, the elimination tree's subtrees would go to different GPUs and only the "
+              "subtree roots' contribution blocks would travel", file=sys.stderr)
         sys.exit(2)
     lp, opts = make_workload(args.workload)
     prec = 1 if args.prec == "mixed" else 0
