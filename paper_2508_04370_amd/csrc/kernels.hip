@@ -1728,12 +1728,14 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
                 else load_block<NBM>(bb, F, ld, k0, nb, tid);
                 store_block<NBM>(Lb, bb, tid);  // read only after the barriers below
             }
-            {  // rows below the block, sum_i L(i, k) y_i: tiles of 64 rows loaded coalesced
-               // (lane = row; the next tile in flight while the current one is summed through
-               // LDS by thread (column = lane, rows wv, wv + 4, ...))
+            {  // rows below the block, sum_i L(i, k) y_i: tiles of 64 rows loaded coalesced (lane =
+               // row, wave wv takes columns wv, wv + 4, ...; the next tile in flight while the
+               // current one is accumulated per lane), then one reduction over the lanes: column
+               // c's four partial sums are its lanes 0-15, 16-31, 32-47 and 48-63, in order
                 constexpr int NT = NBM / 4;
-                double acc = 0.0;
-                double cur[NT], nxt[NT];
+                double accv[NT], cur[NT], nxt[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) accv[t] = 0.0;
                 auto load = [&](int i0, double* v) {
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
@@ -1746,22 +1748,20 @@ __device__ void bwd_supernode(const DevPlan& D, const DevSolve& S, int s, const 
                     if (i0 + 64 < f) load(i0 + 64, nxt);
                     const double yi = i0 + lane < f ? y[i0 + lane] : 0.0;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) Lt[(wv + 4 * t) * 65 + lane] = cur[t] * yi;
-                    __syncthreads();
-                    if (lane < NBM) {
-                        double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-                        for (int t = 0; t < 16; t += 2) {
-                            a0 += Lt[lane * 65 + wv + 4 * t];
-                            a1 += Lt[lane * 65 + wv + 4 * t + 4];
-                        }
-                        acc += a0 + a1;
-                    }
-                    __syncthreads();
+                    for (int t = 0; t < NT; ++t) accv[t] += cur[t] * yi;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) cur[t] = nxt[t];
                 }
-                part[wv * 64 + lane] = acc;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) Lt[(wv + 4 * t) * 65 + lane] = accv[t];
+                __syncthreads();
+                const int c = tid & 63;
+                double sq = 0.0;
+                if (c < NBM) {
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) sq += Lt[c * 65 + 16 * wv + j];
+                }
+                part[wv * 64 + c] = sq;
             }
             __syncthreads();
             if constexpr (INV) {
@@ -2222,18 +2222,42 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const d
                         kx += q * x[k];
                         akx += fabs(q) * fabs(x[k]);
                     }
-                for (int64_t e = D.acp[i]; e < D.acp[i + 1]; ++e) {
-                    const double a = D.aval[e], xv = x[D.n + D.ari[e]];
-                    kx += a * xv;
-                    akx += fabs(a) * fabs(xv);
+                // four entries per trip, their loads in flight together, added in order
+                const int64_t e1 = D.acp[i + 1];
+                for (int64_t e = D.acp[i]; e < e1; e += 4) {
+                    double a[4], xv[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const bool on = e + j < e1;
+                        a[j] = on ? D.aval[e + j] : 0.0;
+                        xv[j] = on ? x[D.n + D.ari[e + j]] : 0.0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (e + j < e1) {
+                            kx += a[j] * xv[j];
+                            akx += fabs(a[j]) * fabs(xv[j]);
+                        }
                 }
             } else {
                 const int row = i - D.n;
-                for (int64_t q = D.arp[row]; q < D.arp[row + 1]; ++q) {
-                    const int32_t e = D.are[q];
-                    const double a = D.aval[e], xv = x[D.acol[e]];
-                    kx += a * xv;
-                    akx += fabs(a) * fabs(xv);
+                const int64_t q1 = D.arp[row + 1];
+                for (int64_t q = D.arp[row]; q < q1; q += 4) {
+                    int32_t ej[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) ej[j] = q + j < q1 ? D.are[q + j] : -1;
+                    double a[4], xv[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        a[j] = ej[j] >= 0 ? D.aval[ej[j]] : 0.0;
+                        xv[j] = ej[j] >= 0 ? x[D.acol[ej[j]]] : 0.0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (ej[j] >= 0) {
+                            kx += a[j] * xv[j];
+                            akx += fabs(a[j]) * fabs(xv[j]);
+                        }
                 }
                 kx += delta * x[i];
                 akx += delta * fabs(x[i]);
