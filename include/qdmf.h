@@ -175,7 +175,8 @@ int qdmf_set_matrix(qdmf_handle h, const double* a_val, int32_t on_device);
  * until the stream reaches this call's end.  rho, delta >= 0 are the static
  * regularisations.  prec: QDMF_FP64 or QDMF_MIXED (FP32 MFMA Schur updates on fronts of
  * order >= opt.f_mix; everything else FP64).  L, D are owned by the handle.  Returns < 0
- * only for argument errors; numerical outcomes come from qdmf_factor_stats. */
+ * only for argument errors; numerical outcomes come from qdmf_factor_stats.  An empty
+ * system (m + n == 0) launches nothing and reports zero pivots. */
 int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double delta,
                    int32_t prec);
 
@@ -187,7 +188,8 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
  * refinement steps the call waits for the stream to read the device's stop flags and
  * launches no further step once every right-hand side meets the target; under graph
  * capture (qdmf_graph_capture) it waits for nothing and enqueues every step, whose kernels
- * then return at once for finished right-hand sides.
+ * then return at once for finished right-hand sides.  An empty system (m + n == 0)
+ * launches nothing and reports zero backward error.
  * Errors: QDMF_ERR_NOT_FACTORISED, QDMF_ERR_INVALID_ARG. */
 int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev,
                double* dx_dev, double* dy_dev);
@@ -250,7 +252,8 @@ int qdmf_export_front(qdmf_handle h, int32_t s, double* panel, int32_t* rows);
 /* Captures factorise + nsolves x solve (each with refinement) once as a HIP graph; later
  * qdmf_graph_launch replays it on the handle's stream, reading Theta and the right-hand
  * sides from the same device buffers (the caller refreshes them in place).
- * Errors: QDMF_ERR_HIP, QDMF_ERR_NOT_ANALYSED. */
+ * Errors: QDMF_ERR_HIP, QDMF_ERR_NOT_ANALYSED, QDMF_ERR_INVALID_ARG (also for an empty
+ * system, which has nothing to capture). */
 int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, double delta,
                        int32_t prec, int32_t nsolves, int32_t nrhs, const double* r7_dev,
                        const double* r1_dev, double* dx_dev, double* dy_dev);
@@ -306,7 +309,8 @@ int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
  * several times per iteration.  A handle analysed with qdmf_analyse_qp (Q set with
  * qdmf_set_hessian) solves the quadratic program min c^T x + x^T Q x / 2 under the same
  * constraints: the dual residual gains +Q x, the factorised block is -(Q + Theta^-1 + rho I)
- * and both objectives carry x^T Q x / 2.  Errors: QDMF_ERR_INVALID_ARG (also for a bad bound),
+ * and both objectives carry x^T Q x / 2.  Errors: QDMF_ERR_INVALID_ARG (also for a bad bound
+ * and for m == 0 or n == 0),
  * QDMF_ERR_NOT_ANALYSED (or not AS), QDMF_ERR_NO_MATRIX, QDMF_ERR_HIP, QDMF_ERR_OOM, and the
  * codes of qdmf_factorise / qdmf_solve. */
 typedef struct {

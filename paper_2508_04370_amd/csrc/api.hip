@@ -758,7 +758,7 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
         return QDMF_ERR_INVALID_ARG;
     int rc = set_device(h);
     if (rc) return rc;
-    enqueue_factorise(h, theta_dev, rho, delta, nullptr, prec);
+    if (h->P.N > 0) enqueue_factorise(h, theta_dev, rho, delta, nullptr, prec);  // an empty system: nothing to do
     if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
     h->last_prec = prec;
     h->factorised = true;
@@ -797,7 +797,7 @@ int qdmf_batch_factorise(qdmf_handle h, const double* theta_dev, const double* r
     if (hipMemcpyAsync(h->shift_dev, h->shift_host, sizeof(double) * 2 * ns, hipMemcpyHostToDevice, h->stream) !=
         hipSuccess)
         return QDMF_ERR_HIP;
-    enqueue_factorise(h, theta_dev, rho[0], delta[0], h->shift_dev, prec);
+    if (h->P.N > 0) enqueue_factorise(h, theta_dev, rho[0], delta[0], h->shift_dev, prec);
     if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
     h->last_prec = prec;
     h->factorised = true;
@@ -835,6 +835,11 @@ int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* 
         return QDMF_ERR_INVALID_ARG;
     int rc = set_device(h);
     if (rc) return rc;
+    if (h->P.N == 0) {  // an empty system: empty solution, zero backward error
+        h->last_nrhs = nrhs;
+        h->solved = true;
+        return 0;
+    }
     if ((rc = ensure_solve(h, nrhs))) return rc;
     enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
     if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
@@ -848,6 +853,10 @@ int qdmf_factor_stats(qdmf_handle h, qdmf_factor_info* out) {
     if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;
     if (set_device(h)) return QDMF_ERR_HIP;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    if (h->P.N == 0) {  // an empty system: no pivots
+        *out = qdmf_factor_info{};
+        return 0;
+    }
     DevStats st;
     DevScalars sc;
     if (hipMemcpy(&st, h->D.st, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
@@ -877,6 +886,15 @@ int qdmf_solve_stats(qdmf_handle h, qdmf_solve_info* out, double* berr_nw_per_rh
     if (!h->solved) return QDMF_ERR_NOT_FACTORISED;
     if (set_device(h)) return QDMF_ERR_HIP;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    if (h->P.N == 0) {  // an empty system
+        *out = qdmf_solve_info{};
+        out->nrhs = h->last_nrhs;
+        for (int32_t r = 0; r < h->last_nrhs; ++r) {
+            if (berr_nw_per_rhs) berr_nw_per_rhs[r] = 0.0;
+            if (steps_per_rhs) steps_per_rhs[r] = 0;
+        }
+        return 0;
+    }
     const int32_t nr = h->last_nrhs, ns = h->P.nsys;
     std::vector<double> bu(4 * (size_t)nr * ns), be(4 * (size_t)nr, 0.0);
     std::vector<int32_t> su((size_t)nr * ns), steps(nr, 0);
@@ -917,6 +935,7 @@ int qdmf_export_d(qdmf_handle h, int32_t* pivot_order, double* d, double* doff, 
     if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
     const Plan& P = h->P;
     const size_t N = (size_t)P.N;
+    if (N == 0) return 0;
     if (d && hipMemcpy(d, h->D.dval, 8 * N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
     if (doff && hipMemcpy(doff, h->D.doff, 8 * N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
     if (ptype && hipMemcpy(ptype, h->D.ptype, N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
@@ -959,7 +978,7 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     if (!h) return QDMF_ERR_INVALID_ARG;
     if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
     if (!h->have_matrix || (h->P.has_q && !h->have_hessian)) return QDMF_ERR_NO_MATRIX;
-    if (h->host_only || !h->stream || nsolves < 0 || nrhs <= 0 || (!theta_dev && h->P.n > 0) ||
+    if (h->host_only || !h->stream || nsolves < 0 || nrhs <= 0 || h->P.N == 0 || (!theta_dev && h->P.n > 0) ||
         (prec != QDMF_FP64 && prec != QDMF_MIXED) || !(rho >= 0) || !(delta >= 0))
         return QDMF_ERR_INVALID_ARG;
     if (set_device(h)) return QDMF_ERR_HIP;
@@ -1043,6 +1062,7 @@ int qdmf_ipm_solve(qdmf_handle h, const double* b_dev, const double* c_dev, cons
     if (!h || !info || !b_dev || !c_dev || !x_dev || !y_dev || !zl_dev || h->host_only) return QDMF_ERR_INVALID_ARG;
     if (!h->analysed || h->P.mode != QDMF_AS || h->P.nsys != 1) return QDMF_ERR_NOT_ANALYSED;
     if (!h->have_matrix || (h->P.has_q && !h->have_hessian)) return QDMF_ERR_NO_MATRIX;
+    if (h->P.m == 0 || h->P.n == 0) return QDMF_ERR_INVALID_ARG;
     qdmf_ipm_options opt;
     if (opt_in) opt = *opt_in;
     else qdmf_ipm_default_options(&opt);

@@ -9,6 +9,8 @@ from oracle import oracle as O
 from paper_2508_04370_amd import qdmf as Q
 from paper_2508_04370_amd import workloads as W
 
+from test_oracle import lp_from_dense
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -215,3 +217,48 @@ def test_no_float_atomics_in_kernels():
     for m in re.finditer(r"(atomic[A-Za-z]+|__hip_atomic_[a-z_]+)\s*\(([^,;]*)", src):
         target = m.group(2)
         assert re.search(r"bad_theta", target), m.group(0)
+
+
+def degenerate(name, seed=0, nrhs=2):
+    """Small systems whose K has an empty block, an isolated variable or an isolated row."""
+    g = W.rng(71, seed)
+    if name == "as_1x1":
+        A, mode = np.array([[2.0]]), W.AS
+    elif name == "as_empty_col":
+        A, mode = np.array([[1.0, 0.0, 2.0], [0.5, 0.0, -1.0]]), W.AS
+    elif name == "ne_empty_row":
+        A, mode = np.array([[1.0, 2.0, 0.0], [0.0, 0.0, 0.0], [0.0, 3.0, 1.0]]), W.NE
+    elif name == "as_no_rows":
+        A, mode = np.zeros((0, 5)), W.AS
+    elif name == "ne_no_cols":
+        A, mode = np.zeros((3, 0)), W.NE
+    else:
+        raise KeyError(name)
+    m, n = A.shape
+    theta = W.log_uniform(g, 1e-2, 1e2, n)
+    if n:
+        lp = lp_from_dense(A, mode, theta, 1e-8, 1e-8, name=name)
+    else:
+        lp = W.LP(m=m, n=0, colptr=np.zeros(1, np.int64), rowidx=np.zeros(0, np.int32), val=np.zeros(0),
+                  theta=theta, rho=1e-8, delta=1e-8, mode=mode, name=name)
+    lp["r1"] = np.asfortranarray(g.standard_normal((m, nrhs)))
+    lp["r7"] = np.asfortranarray(g.standard_normal((n, nrhs)))
+    return lp
+
+
+@pytest.mark.parametrize("name", ["as_1x1", "as_empty_col", "ne_empty_row", "as_no_rows", "ne_no_cols"])
+def test_degenerate_patterns_analyse_like_the_oracle(name):
+    """An isolated variable, an empty row, no constraints or no variables: the host analysis
+    accepts the pattern and its factor has the oracle's size."""
+    lp = degenerate(name)
+    s = host_solver(lp)
+    S = O.Sym(lp)
+    assert s.sym["N"] == S.N == (lp["n"] + lp["m"] if lp["mode"] == W.AS else lp["m"])
+    assert s.sym["nnz_l"] == S.nnzL
+
+
+def test_empty_system_analyses_to_nothing():
+    lp = W.LP(m=0, n=0, colptr=np.zeros(1, np.int64), rowidx=np.zeros(0, np.int32), val=np.zeros(0),
+              theta=np.zeros(0), rho=0.0, delta=0.0, mode=W.AS, name="empty")
+    s = host_solver(lp)
+    assert (s.sym["N"], s.sym["nnz_l"], s.sym["nsuper"], s.sym["max_front"]) == (0, 0, 0, 0)
