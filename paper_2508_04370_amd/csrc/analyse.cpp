@@ -306,11 +306,13 @@ int64_t ne_pattern_count(int32_t m, int32_t n, const int64_t* colptr, const int3
     return count;
 }
 
-// Q's lower triangle: rows >= the column, strictly increasing, inside [0, n); the full
-// symmetric pattern with the source of each value, and the diagonal positions.
 // pivot columns of one window of the factorisation kernels (Section 4.4's block of nb columns)
 constexpr int64_t AMALG_WINDOW = 64;
+// smallest front that joins a level's multi-workgroup solve launches
+constexpr int32_t SPLIT_JOIN_FRONT = 128;
 
+// Q's lower triangle: rows >= the column, strictly increasing, inside [0, n); the full
+// symmetric pattern with the source of each value, and the diagonal positions.
 static int set_hessian_pattern(int32_t n, const int64_t* qcp, const int32_t* qri, Plan& P, std::string& msg) {
     if (qcp[0] != 0) {
         msg = "Q: colptr[0] must be 0";
@@ -894,10 +896,23 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     P.lvl_sn.resize(ns);
     P.lvl_small.assign(P.nlevels, 0);
     {
+        // a level that holds a front of at least split_solve_front pays the multi-workgroup
+        // launches anyway (one diagonal solve and one update launch per 64-pivot block of its
+        // largest such front): its other fronts of at least SPLIT_JOIN_FRONT rows with no more
+        // blocks join those launches rather than occupy one workgroup each for the whole level
+        std::vector<int32_t> lvl_nb(P.nlevels, 0);
+        for (int32_t t = 0; t < ns; ++t)
+            if (P.sn_f[t] >= opt.split_solve_front)
+                lvl_nb[P.sn_level[t]] = std::max(lvl_nb[P.sn_level[t]], (P.sn_p[t] + 63) / 64);
+        auto split = [&](int32_t t) {
+            if (P.sn_f[t] >= opt.split_solve_front) return true;
+            const int32_t nb = lvl_nb[P.sn_level[t]];
+            return nb > 0 && P.sn_f[t] >= std::min(SPLIT_JOIN_FRONT, opt.split_solve_front) && (P.sn_p[t] + 63) / 64 <= nb;
+        };
         std::vector<int64_t> fl(P.lvl_ptr.begin(), P.lvl_ptr.end() - 1);
         for (int pass = 0; pass < 2; ++pass)
             for (int32_t t = 0; t < ns; ++t)
-                if ((P.sn_f[t] >= opt.split_solve_front) == (pass == 1)) {
+                if (split(t) == (pass == 1)) {
                     P.lvl_sn[fl[P.sn_level[t]]++] = t;
                     if (pass == 0) P.lvl_small[P.sn_level[t]]++;
                 }
