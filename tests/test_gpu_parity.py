@@ -261,6 +261,27 @@ def test_split_solves_match_oracle(torch_dev, case):
     check_against_oracle(lp, g)
 
 
+def test_joined_split_solves_match_oracle(torch_dev):
+    """A level that holds a front of at least split_solve_front rows takes its other fronts of
+    at least 128 rows (with no more 64-pivot blocks) into the same multi-workgroup launches:
+    a staircase whose levels mix both kinds, against the oracle."""
+    lp = W.as_staircase(periods=4, rows=300, cols=600, link_cols=60, seed=24, nrhs=3)
+    split = 200
+    g = gpu_solve(torch_dev, lp, split_solve_front=split)
+    sym = g["solver"].sym
+    f, lv = np.asarray(sym["sn_front"]), np.asarray(sym["sn_level"])
+    nblk = (np.diff(np.asarray(sym["sn_ptr"])) + 63) // 64
+    joined = 0
+    for level in np.unique(lv):
+        on = lv == level
+        big = on & (f >= split)
+        if big.any():
+            joined += int((on & (f >= 128) & (f < split) & (nblk <= nblk[big].max())).sum())
+    print(f"  fronts joining split launches: {joined}")
+    assert joined > 0
+    check_against_oracle(lp, g)
+
+
 def test_split_solves_wide_theta_own_factor(torch_dev):
     """Theta over [1e-10, 1e10] (2x2 pivots and tiny pivots possible): with no refinement
     the multi-workgroup solves are backward stable for the GPU's own factor, like the
