@@ -79,8 +79,10 @@ typedef struct {
     int32_t small_front;      /* fronts of order <= small_front are factorised in LDS, 64  */
     int64_t mem_cap_bytes;    /* 0: none; analyse fails with QDMF_ERR_OOM above it         */
     int32_t split_solve_front; /* fronts of order >= this are solved by many workgroups per
-                                  step, all right-hand sides together; smaller ones by one
-                                  workgroup each; >= 1, 1024                               */
+                                  step, all right-hand sides together, and so are the fronts
+                                  of at least min(128, this) rows on the same tree level with
+                                  no more 64-pivot blocks; the rest by one workgroup each;
+                                  >= 1, 1024                                               */
 } qdmf_options;
 
 typedef struct {
