@@ -83,6 +83,11 @@ typedef struct {
                                   of at least min(128, this) rows on the same tree level with
                                   no more 64-pivot blocks; the rest by one workgroup each;
                                   >= 1, 1024                                               */
+    int32_t syrk_group_front; /* fronts of order >= this (0: none) apply the Schur update of
+                                 syrk_group consecutive pivot windows to their trailing
+                                 matrix at once (the columns of each next window of the
+                                 group are updated as soon as it is reached); 512         */
+    int32_t syrk_group;       /* windows per such group, 1..4; 4                           */
 } qdmf_options;
 
 typedef struct {

@@ -1053,11 +1053,13 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             }
             by += 16.0 * rows * (k1 - k0);
         } else if (kind == L_SYRK) {  // one 64 x 64 tile of the lower trailing update
-            const double k1 = std::min<double>(p, tk.k0 + NB), nbw = k1 - tk.k0;
+            const double k0 = tk.k0 & SYRK_K0_MASK, cnt = ((tk.k0 >> SYRK_COUNT_SHIFT) & 7) + 1;
+            const double k1 = std::min<double>(p, k0 + NB * cnt), nbw = k1 - k0;
+            const double cmax = (tk.k0 & SYRK_NARROW) ? std::min<double>(p, k1 + NB) : f;
             const double r0 = k1 + 64.0 * tk.a, c0 = k1 + 64.0 * tk.b;
-            const double nr = std::max(0.0, std::min(64.0, f - r0)), nc = std::max(0.0, std::min(64.0, f - c0));
+            const double nr = std::max(0.0, std::min(64.0, f - r0)), nc = std::max(0.0, std::min(64.0, cmax - c0));
             double lower = nr * nc;
-            if (tk.a == tk.b) lower = nr * (nr + 1) / 2;
+            if (tk.a == tk.b) lower = nc * (nc + 1) / 2 + (nr - nc) * nc;
             fl += 2.0 * nbw * lower;
             by += 8.0 * (2 * lower + (nr + nc) * nbw);
         } else if (kind == L_FINALIZE) {  // one 64-column block of one window: read + write
@@ -1065,11 +1067,13 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             by += tk.a * NB == tk.k0 ? 16.0 * nc * (nc - 1) / 2 : 16.0 * nc * nr;
         }
     };
-    auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf, int32_t npg = 0) {
+    auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf, int32_t npg = 0,
+                          int32_t grouped = 0) {
         int64_t cnt = (int64_t)P.tasks.size() - t0;
         if (cnt > 0) {
             Launch L{kind, lvl, t0, cnt, lds, maxf};
             L.npg = npg;
+            L.grouped = grouped;
             for (int64_t q = t0; q < t0 + cnt; ++q) task_work(kind, npg, P.tasks[q], L.flops, L.bytes);
             P.launches.push_back(L);
         }
@@ -1135,15 +1139,34 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                     mf = std::max(mf, P.sn_f[t]);
                 }
             add_launch(L_WINDOW, l, t0, 0, mf, npg);
-            t0 = (int64_t)P.tasks.size();
-            for (int32_t t : large)
-                if (w < P.sn_nwin[t]) {
-                    int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
-                    int32_t R = (P.sn_f[t] - k1 + 63) / 64;
-                    for (int32_t bj = 0; bj < R; ++bj)
-                        for (int32_t bi = bj; bi < R; ++bi) P.tasks.push_back(Task{t, w * NB, bi, bj});
-                }
-            add_launch(L_SYRK, l, t0, 0, mf);
+            // Schur update after window w.  A front of at least syrk_group_front rows takes its
+            // windows in groups of syrk_group: inside a group, only the next window's columns
+            // receive the update of the group's windows so far (what that window's
+            // factorisation needs); after the group's last window, the rest of the trailing
+            // matrix receives the update of all its windows at once, so each trailing entry is
+            // read and written once per group instead of once per window.
+            // (the tasks of grouped fronts go to a launch of their own kernel)
+            for (int pass = 0; pass < 2; ++pass) {
+                t0 = (int64_t)P.tasks.size();
+                for (int32_t t : large)
+                    if (w < P.sn_nwin[t]) {
+                        const bool grouped = opt.syrk_group_front > 0 && opt.syrk_group > 1 &&
+                                             P.sn_f[t] >= opt.syrk_group_front;
+                        if (grouped != (pass == 1)) continue;
+                        const int32_t G = grouped ? opt.syrk_group : 1;
+                        const int32_t g = (w / G) * G, last = std::min(g + G, P.sn_nwin[t]) - 1;
+                        const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                        const int32_t R = (P.sn_f[t] - k1 + 63) / 64;
+                        const int32_t code = g * NB | (w - g) << SYRK_COUNT_SHIFT;
+                        if (w < last) {  // window w + 1 is whole or partial, its columns start at k1
+                            for (int32_t bi = 0; bi < R; ++bi) P.tasks.push_back(Task{t, code | SYRK_NARROW, bi, 0});
+                        } else {
+                            for (int32_t bj = 0; bj < R; ++bj)
+                                for (int32_t bi = bj; bi < R; ++bi) P.tasks.push_back(Task{t, code, bi, bj});
+                        }
+                    }
+                add_launch(L_SYRK, l, t0, 0, mf, 0, pass);
+            }
         }
         t0 = (int64_t)P.tasks.size();
         for (int32_t t : large)

@@ -537,6 +537,8 @@ void qdmf_default_options(qdmf_options* o) {
     o->small_front = 64;
     o->mem_cap_bytes = 0;
     o->split_solve_front = 1024;
+    o->syrk_group_front = 512;
+    o->syrk_group = 4;
 }
 
 int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_options* opt) {
@@ -546,6 +548,7 @@ int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_optio
     if (opt) h->opt = *opt;
     else qdmf_default_options(&h->opt);
     if (h->opt.nb != 64 || h->opt.small_front < 1 || h->opt.small_front > 64 || h->opt.split_solve_front < 1 ||
+        h->opt.syrk_group_front < 0 || h->opt.syrk_group < 1 || h->opt.syrk_group > SYRK_GROUP_MAX ||
         h->opt.max_refine < 0 ||
         h->opt.max_refine_mixed < 0 || h->opt.ordering < QDMF_ORDER_AMD || h->opt.ordering > QDMF_ORDER_AUTO) {
         delete h;
@@ -596,6 +599,8 @@ int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     ao.amalgamate = h->opt.amalgamate;
     ao.small_front = h->opt.small_front;
     ao.split_solve_front = h->opt.split_solve_front;
+    ao.syrk_group_front = h->opt.syrk_group_front;
+    ao.syrk_group = h->opt.syrk_group;
     ao.user_perm = user_perm;
     ao.nsys = nsys;
     ao.col_off = col_off;
@@ -1227,6 +1232,8 @@ int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
     ao.amalgamate = h->opt.amalgamate;
     ao.small_front = h->opt.small_front;
     ao.split_solve_front = h->opt.split_solve_front;
+    ao.syrk_group_front = h->opt.syrk_group_front;
+    ao.syrk_group = h->opt.syrk_group;
     {  // the augmented system first
         Plan Pa;
         const int rc = build_plan(m, n, colptr, rowidx, QDMF_AS, ao, Pa, h->msg);

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -1018,6 +1019,136 @@ __device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int
     }
 }
 
+// One chunk of the inner dimension (one window's columns kb .. kb + nbw) into registers: the
+// L21 rows of the tile's row block (va) and column block (vc), all loads in flight at once.
+__device__ inline void syrk_load_chunk(const double* F, int ld, int f, int cmax, int kb, int nbw, int R0, int C0,
+                                       double* va, double* vc) {
+    const int r = threadIdx.x & 63, kq = threadIdx.x >> 6;  // row r, columns kq, kq + 4, ...
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int kk = kq + 4 * t;
+        va[t] = (kk < nbw && R0 + r < f) ? F[R0 + r + (int64_t)(kb + kk) * ld] : 0.0;
+        vc[t] = (kk < nbw && C0 + r < cmax) ? F[C0 + r + (int64_t)(kb + kk) * ld] : 0.0;
+    }
+}
+
+// The chunk into LDS: As = L21 rows, Bs = W = L21 D on the column block (a 1x1 pivot scales
+// its column, a 2x2 block mixes its two columns; the partner column is read again, 2x2 pivots
+// are rare and never span two windows).  dd, od, pt: D of the chunk's columns.
+template <typename T>
+__device__ inline void syrk_stage_chunk(const double* F, int ld, int cmax, int kb, int nbw, int C0,
+                                        const double* va, const double* vc, const double* dd, const double* od,
+                                        const int* pt, T* As, T* Bs) {
+    const int r = threadIdx.x & 63, kq = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) As[r * LDT + kq + 4 * t] = (T)va[t];
+    double wb[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int kk = kq + 4 * t;
+        double b = 0.0;
+        if (kk < nbw && C0 + r < cmax) {
+            const int ty = pt[kk];
+            const double* cr = F + C0 + r + (int64_t)kb * ld;
+            if (ty == 0) b = vc[t] * dd[kk];
+            else if (ty == 1) b = vc[t] * dd[kk] + cr[(int64_t)(kk + 1) * ld] * od[kk];
+            else b = cr[(int64_t)(kk - 1) * ld] * od[kk - 1] + vc[t] * dd[kk];
+        }
+        wb[t] = b;
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) Bs[r * LDT + kq + 4 * t] = (T)wb[t];
+}
+
+// C -= L21 W21^T on one 64 x 64 tile (rows R0.., columns C0.. below cmax, lower part) over the
+// inner dimension in chunks of one window (starting at column k0, nin columns in all).
+// The products accumulate in the matrix cores and C is read and written once; the next
+// chunk's loads are in flight during the current chunk's products.
+template <typename T>
+__device__ void syrk_tile_group(double* F, int ld, int f, int cmax, int k0, int nin, int R0, int C0,
+                          const double* dd, const double* od, const int* pt, T* As, T* Bs) {
+    const int tid = threadIdx.x;
+    double va[16], vc[16];
+    syrk_load_chunk(F, ld, f, cmax, k0, min(64, nin), R0, C0, va, vc);
+    syrk_stage_chunk<T>(F, ld, cmax, k0, min(64, nin), C0, va, vc, dd, od, pt, As, Bs);
+    const int wv = tid >> 6, l = tid & 63;
+    const int wc = (wv >> 1) * 32, wr = (wv & 1) * 32;
+    const int li = l & 15, lk = l >> 4;
+    // this thread's 16 elements of the tile, loaded before the products so that their
+    // latency overlaps them; element (i, j, v) at column C0 + wc + 16 i + cofs(v), row
+    // R0 + wr + 16 j + li (f64 16x16x4 output: element (lk + 4v, li) of a 16 x 16 block;
+    // f32 16x16x4 output: element (4 lk + v, li))
+    double cv[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = C0 + wc + i * 16 + (sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v);
+                const int row = R0 + wr + j * 16 + li;
+                cv[i][j][v] = (row < f && col < cmax && row >= col) ? F[row + (int64_t)col * ld] : 0.0;
+            }
+    using AccT = typename std::conditional<sizeof(T) == 8, d4, f4>::type;
+    AccT acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = AccT{0, 0, 0, 0};
+    const int nch = (nin + 63) / 64;
+    for (int c = 0; c < nch; ++c) {
+        const int nbw = min(64, nin - 64 * c);
+        const int kmax = (nbw + 3) & ~3;  // columns beyond the window are zero
+        __syncthreads();
+        for (int kk = 0; kk < kmax; kk += 4) {
+            const T a0 = Bs[(wc + li) * LDT + kk + lk];
+            const T a1 = Bs[(wc + 16 + li) * LDT + kk + lk];
+            const T b0 = As[(wr + li) * LDT + kk + lk];
+            const T b1 = As[(wr + 16 + li) * LDT + kk + lk];
+            if constexpr (sizeof(T) == 8) {
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            } else {
+                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        }
+        if constexpr (sizeof(T) == 4) {
+            // FP32 products are applied to the FP64 tile window by window, as without grouping,
+            // so that no more than one window's terms are summed in FP32
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) cv[i][j][v] -= (double)acc[i][j][v];
+                    acc[i][j] = AccT{0, 0, 0, 0};
+                }
+        }
+        if (c + 1 < nch) {
+            syrk_load_chunk(F, ld, f, cmax, k0 + 64 * (c + 1), min(64, nin - 64 * (c + 1)), R0, C0, va, vc);
+            __syncthreads();  // every wave has read this chunk from As and Bs
+            syrk_stage_chunk<T>(F, ld, cmax, k0 + 64 * (c + 1), min(64, nin - 64 * (c + 1)), C0, va, vc,
+                                dd + 64 * (c + 1), od + 64 * (c + 1), pt + 64 * (c + 1), As, Bs);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = C0 + wc + i * 16 + (sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v);
+                const int row = R0 + wr + j * 16 + li;
+                if (row < f && col < cmax && row >= col)
+                    F[row + (int64_t)col * ld] = sizeof(T) == 4 ? cv[i][j][v] : cv[i][j][v] - (double)acc[i][j][v];
+            }
+}
+
 // After all windows of a front: one task per (pivot window c, window w >= c).  w == c moves
 // the window's factored diagonal block from the upper triangle into place; w > c permutes
 // the rows of window w inside the 64 columns of window c as window w's pivot interchanges
@@ -1094,6 +1225,45 @@ __global__ __launch_bounds__(256) void k_syrk(DevPlan D, const Task* tasks, int6
         syrk_tile<double>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, As, Bs);
 }
 
+
+// Trailing-update tiles of fronts whose windows are grouped: the task packs the inner range
+// (one or more windows) and whether only the next window's columns are updated.
+__global__ __launch_bounds__(256, 2) void k_syrk_group(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp,
+                                                    int64_t nsy, int64_t fin0) {
+    if ((int64_t)blockIdx.x >= nsy) {
+        finalize_task(D, tasks[fin0 + (int64_t)blockIdx.x - nsy]);
+        return;
+    }
+    __shared__ double As[64 * LDT];
+    __shared__ double Bs[64 * LDT];
+    __shared__ double dd[NB * SYRK_GROUP_MAX], od[NB * SYRK_GROUP_MAX];
+    __shared__ int pt[NB * SYRK_GROUP_MAX];
+    const Task t = tasks[t0 + blockIdx.x];
+    const int s = t.s, k0 = t.k0 & SYRK_K0_MASK, cnt = ((t.k0 >> SYRK_COUNT_SHIFT) & 7) + 1;
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
+    const int k1 = min(k0 + NB * cnt, p), nin = k1 - k0;
+    // a narrow update stops at the end of the next window's columns
+    const int cmax = (t.k0 & SYRK_NARROW) ? min(p, k1 + NB) : f;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < NB * SYRK_GROUP_MAX; q += 256) {
+        if (q < nin) {
+            dd[q] = D.dval[c0 + k0 + q];
+            od[q] = D.doff[c0 + k0 + q];
+            pt[q] = D.ptype[c0 + k0 + q];
+        } else {
+            dd[q] = 0.0;
+            od[q] = 0.0;
+            pt[q] = 0;
+        }
+    }
+    __syncthreads();
+    double* F = D.front + D.sn_off[s];
+    const int R0 = k1 + 64 * t.a, C0 = k1 + 64 * t.b;
+    if (pp.mixed && f >= pp.f_mix)
+        syrk_tile_group<float>(F, ld, f, cmax, k0, nin, R0, C0, dd, od, pt, (float*)As, (float*)Bs);
+    else
+        syrk_tile_group<double>(F, ld, f, cmax, k0, nin, R0, C0, dd, od, pt, As, Bs);
+}
 
 __global__ __launch_bounds__(256) void k_finalize(DevPlan D, const Task* tasks, int64_t t0) {
     finalize_task(D, tasks[t0 + blockIdx.x]);
@@ -2616,8 +2786,12 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
             }
             break;
         case L_SYRK:
-            hipLaunchKernelGGL(k_syrk, dim3((unsigned)(L.ntask + L.nfin)), dim3(256), 0, s, D, tasks, L.task0, pp,
-                               L.ntask, L.fin0);
+            if (L.grouped)
+                hipLaunchKernelGGL(k_syrk_group, dim3((unsigned)(L.ntask + L.nfin)), dim3(256), 0, s, D, tasks, L.task0,
+                                   pp, L.ntask, L.fin0);
+            else
+                hipLaunchKernelGGL(k_syrk, dim3((unsigned)(L.ntask + L.nfin)), dim3(256), 0, s, D, tasks, L.task0, pp,
+                                   L.ntask, L.fin0);
             break;
         case L_FINALIZE: hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, D, tasks, L.task0); break;
         default: break;

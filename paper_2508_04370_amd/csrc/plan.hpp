@@ -8,13 +8,21 @@
 namespace qdmf {
 
 constexpr int NB = 64;  // pivot window width used by the device kernels
+// A trailing-update task (L_SYRK) packs into Task.k0 the first inner column k0 (a window start),
+// the number of consecutive windows whose update it applies at once, less one, and whether it
+// updates only the next window's columns (the narrow update inside a group of windows).  The
+// tile origin is the end of the inner range: rows k1 + 64 a, columns k1 + 64 b.
+constexpr int32_t SYRK_K0_MASK = (1 << 24) - 1;
+constexpr int SYRK_COUNT_SHIFT = 24;  // three bits: up to SYRK_GROUP_MAX windows
+constexpr int32_t SYRK_NARROW = 1 << 28;
+constexpr int SYRK_GROUP_MAX = 4;
 
 // One task of a batched launch.  Meaning per kernel:
 //   small front / solve: s = supernode
 //   window: s, k0 = window start, a = chunk of 64*npg rows below the window
 //   finalize: s, k0 = first of 64 pivot columns
 //   assemble: s, k0 = front column, [a, a+b) = range of its (child, child column) list
-//   syrk:   s, k0 = window start, a = row tile, b = column tile
+//   syrk:   s, k0 = window start, a = row tile, b = column tile (grouped: k0 packed, below)
 struct Task {
     int32_t s, k0, a, b;
 };
@@ -34,6 +42,7 @@ struct Launch {
     int32_t lds;           // dynamic LDS bytes (assembly)
     int32_t maxf;          // largest front order among the tasks
     int32_t npg = 0;       // window: panel row groups of 64 per workgroup (0 or 1)
+    int32_t grouped = 0;   // trailing update: tasks of fronts with grouped windows (packed k0)
     int64_t fin0 = 0, nfin = 0;  // trailing update: the level's finalize tasks run in the same launch
     double flops = 0;      // algorithmic work of the launch
     double bytes = 0;
@@ -150,6 +159,8 @@ struct AnalyseOptions {
     int amalgamate = 1;
     int small_front = 64;
     int split_solve_front = 1024;  // fronts at least this big: multi-workgroup solves
+    int syrk_group_front = 512;    // fronts at least this big: grouped trailing updates (0: none)
+    int syrk_group = 4;            // windows per group
     const int32_t* user_perm = nullptr;
     // batch: nsys systems, system s owns columns [col_off[s], col_off[s+1]) and rows
     // [row_off[s], row_off[s+1]) of the block-diagonal A (nullptr: one system)

@@ -48,7 +48,8 @@ class qdmf_options(C.Structure):
                 ("target_berr", C.c_double), ("target_berr_mixed", C.c_double),
                 ("tau_big", C.c_double), ("ordering", C.c_int32), ("grid", C.c_int32 * 3),
                 ("amalgamate", C.c_int32), ("f_mix", C.c_int32), ("small_front", C.c_int32),
-                ("mem_cap_bytes", C.c_int64), ("split_solve_front", C.c_int32)]
+                ("mem_cap_bytes", C.c_int64), ("split_solve_front", C.c_int32),
+                ("syrk_group_front", C.c_int32), ("syrk_group", C.c_int32)]
 
 
 class qdmf_mode_choice(C.Structure):
