@@ -366,15 +366,21 @@ def test_mixed_precision_hard_case_is_safe(torch_dev, seed):
     assert (ss["status"] == Q.QDMF_WARN_NOT_CONVERGED) == (ss["berr_nw"] > 1e-10)
 
 
-def test_graph_replay_matches_eager(torch_dev):
+@pytest.mark.parametrize("case", ["small", "grouped"])
+def test_graph_replay_matches_eager(torch_dev, case):
     """factorise + 2 solves captured once; replays read refreshed Theta and rhs in place
-    and must reproduce the eager results bitwise, every replay."""
+    and must reproduce the eager results bitwise, every replay.  "grouped": fronts of up to
+    ~300 rows with their trailing updates grouped three windows at a time."""
     torch, dev = torch_dev
     from paper_2508_04370_amd import qdmf as Q
-    lp = W.as_staircase(periods=4, rows=50, cols=100, link_cols=10)
+    if case == "small":
+        lp, opts = W.as_staircase(periods=4, rows=50, cols=100, link_cols=10), {}
+    else:
+        lp = W.as_staircase(periods=4, rows=300, cols=600, link_cols=60, seed=24)
+        opts = dict(syrk_group_front=64, syrk_group=3)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        s = Q.Solver(lp, device=0, stream=stream.cuda_stream)
+        s = Q.Solver(lp, device=0, stream=stream.cuda_stream, **opts)
         th = torch.empty(lp["n"], dtype=torch.float64, device=dev)
         r7 = torch.empty((1, lp["n"]), dtype=torch.float64, device=dev).T
         r1 = torch.empty((1, lp["m"]), dtype=torch.float64, device=dev).T
@@ -396,7 +402,7 @@ def test_graph_replay_matches_eager(torch_dev):
             stream.synchronize()
             gx, gy = dx.cpu().numpy().copy(), dy.cpu().numpy().copy()
             # eager on a fresh handle with the same inputs
-            e = Q.Solver(lp, device=0, stream=stream.cuda_stream)
+            e = Q.Solver(lp, device=0, stream=stream.cuda_stream, **opts)
             e.factorise(th, lp["rho"], lp["delta"], 0)
             ex, ey = e.solve(r7, r1)
             e.solve(r7, r1, ex, ey)
