@@ -86,7 +86,7 @@ typedef struct {
     int32_t syrk_group_front; /* fronts of order >= this (0: none) apply the Schur update of
                                  syrk_group consecutive pivot windows to their trailing
                                  matrix at once (the columns of each next window of the
-                                 group are updated as soon as it is reached); 512         */
+                                 group are updated as soon as it is reached); 1024        */
     int32_t syrk_group;       /* windows per such group, 1..4; 4                           */
 } qdmf_options;
 

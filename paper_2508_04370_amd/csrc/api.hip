@@ -537,7 +537,7 @@ void qdmf_default_options(qdmf_options* o) {
     o->small_front = 64;
     o->mem_cap_bytes = 0;
     o->split_solve_front = 1024;
-    o->syrk_group_front = 512;
+    o->syrk_group_front = 1024;
     o->syrk_group = 4;
 }
 

@@ -159,7 +159,7 @@ struct AnalyseOptions {
     int amalgamate = 1;
     int small_front = 64;
     int split_solve_front = 1024;  // fronts at least this big: multi-workgroup solves
-    int syrk_group_front = 512;    // fronts at least this big: grouped trailing updates (0: none)
+    int syrk_group_front = 1024;   // fronts at least this big: grouped trailing updates (0: none)
     int syrk_group = 4;            // windows per group
     const int32_t* user_perm = nullptr;
     // batch: nsys systems, system s owns columns [col_off[s], col_off[s+1]) and rows

@@ -40,7 +40,7 @@ def test_options_struct_layout_matches_defaults():
     o = Q.qdmf_default_options()
     assert o.nb == 64 and o.presort == 1 and o.max_refine == 2 and o.max_refine_mixed == 10
     assert o.alpha == (1 + np.sqrt(17)) / 8 and o.eps_lift == 2.0 ** -52
-    assert o.split_solve_front == 1024 and o.syrk_group_front == 512 and o.syrk_group == 4
+    assert o.split_solve_front == 1024 and o.syrk_group_front == 1024 and o.syrk_group == 4
     assert o.target_berr == 1e-12 and o.target_berr_mixed == 1e-10 and o.tau_big == 1e-8
     assert o.f_mix == 1024 and o.small_front == 64 and o.amalgamate == 1 and o.mem_cap_bytes == 0
 
