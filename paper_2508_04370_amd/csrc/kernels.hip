@@ -1019,13 +1019,18 @@ __device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int
     }
 }
 
-// One chunk of the inner dimension (one window's columns kb .. kb + nbw) into registers: the
-// L21 rows of the tile's row block (va) and column block (vc), all loads in flight at once.
+// Grouped trailing updates stage the inner dimension in chunks of SYRK_CW columns (half a
+// window): small LDS tiles and register arrays, so that four workgroups share a compute unit.
+constexpr int SYRK_CW = 32;
+constexpr int LDTG = SYRK_CW + 1;  // leading dimension of those LDS tiles, odd to spread banks
+
+// One chunk of the inner dimension (columns kb .. kb + nbw) into registers: the L21 rows of
+// the tile's row block (va) and column block (vc), all loads in flight at once.
 __device__ inline void syrk_load_chunk(const double* F, int ld, int f, int cmax, int kb, int nbw, int R0, int C0,
                                        double* va, double* vc) {
     const int r = threadIdx.x & 63, kq = threadIdx.x >> 6;  // row r, columns kq, kq + 4, ...
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
+    for (int t = 0; t < SYRK_CW / 4; ++t) {
         const int kk = kq + 4 * t;
         va[t] = (kk < nbw && R0 + r < f) ? F[R0 + r + (int64_t)(kb + kk) * ld] : 0.0;
         vc[t] = (kk < nbw && C0 + r < cmax) ? F[C0 + r + (int64_t)(kb + kk) * ld] : 0.0;
@@ -1034,17 +1039,18 @@ __device__ inline void syrk_load_chunk(const double* F, int ld, int f, int cmax,
 
 // The chunk into LDS: As = L21 rows, Bs = W = L21 D on the column block (a 1x1 pivot scales
 // its column, a 2x2 block mixes its two columns; the partner column is read again, 2x2 pivots
-// are rare and never span two windows).  dd, od, pt: D of the chunk's columns.
+// are rare; the partner is read from the front, so a block across two chunks is fine).  dd,
+// od, pt: D of the chunk's columns (od[-1] is the previous chunk's last column).
 template <typename T>
 __device__ inline void syrk_stage_chunk(const double* F, int ld, int cmax, int kb, int nbw, int C0,
                                         const double* va, const double* vc, const double* dd, const double* od,
                                         const int* pt, T* As, T* Bs) {
     const int r = threadIdx.x & 63, kq = threadIdx.x >> 6;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) As[r * LDT + kq + 4 * t] = (T)va[t];
-    double wb[16];
+    for (int t = 0; t < SYRK_CW / 4; ++t) As[r * LDTG + kq + 4 * t] = (T)va[t];
+    double wb[SYRK_CW / 4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
+    for (int t = 0; t < SYRK_CW / 4; ++t) {
         const int kk = kq + 4 * t;
         double b = 0.0;
         if (kk < nbw && C0 + r < cmax) {
@@ -1057,20 +1063,20 @@ __device__ inline void syrk_stage_chunk(const double* F, int ld, int cmax, int k
         wb[t] = b;
     }
 #pragma unroll
-    for (int t = 0; t < 16; ++t) Bs[r * LDT + kq + 4 * t] = (T)wb[t];
+    for (int t = 0; t < SYRK_CW / 4; ++t) Bs[r * LDTG + kq + 4 * t] = (T)wb[t];
 }
 
 // C -= L21 W21^T on one 64 x 64 tile (rows R0.., columns C0.. below cmax, lower part) over the
-// inner dimension in chunks of one window (starting at column k0, nin columns in all).
+// inner dimension in chunks of SYRK_CW columns (starting at column k0, nin columns in all).
 // The products accumulate in the matrix cores and C is read and written once; the next
 // chunk's loads are in flight during the current chunk's products.
 template <typename T>
 __device__ void syrk_tile_group(double* F, int ld, int f, int cmax, int k0, int nin, int R0, int C0,
                           const double* dd, const double* od, const int* pt, T* As, T* Bs) {
     const int tid = threadIdx.x;
-    double va[16], vc[16];
-    syrk_load_chunk(F, ld, f, cmax, k0, min(64, nin), R0, C0, va, vc);
-    syrk_stage_chunk<T>(F, ld, cmax, k0, min(64, nin), C0, va, vc, dd, od, pt, As, Bs);
+    double va[SYRK_CW / 4], vc[SYRK_CW / 4];
+    syrk_load_chunk(F, ld, f, cmax, k0, min(SYRK_CW, nin), R0, C0, va, vc);
+    syrk_stage_chunk<T>(F, ld, cmax, k0, min(SYRK_CW, nin), C0, va, vc, dd, od, pt, As, Bs);
     const int wv = tid >> 6, l = tid & 63;
     const int wc = (wv >> 1) * 32, wr = (wv & 1) * 32;
     const int li = l & 15, lk = l >> 4;
@@ -1095,16 +1101,16 @@ __device__ void syrk_tile_group(double* F, int ld, int f, int cmax, int k0, int 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = AccT{0, 0, 0, 0};
-    const int nch = (nin + 63) / 64;
+    const int nch = (nin + SYRK_CW - 1) / SYRK_CW;
     for (int c = 0; c < nch; ++c) {
-        const int nbw = min(64, nin - 64 * c);
-        const int kmax = (nbw + 3) & ~3;  // columns beyond the window are zero
+        const int nbw = min(SYRK_CW, nin - SYRK_CW * c);
+        const int kmax = (nbw + 3) & ~3;  // columns beyond the chunk are zero
         __syncthreads();
         for (int kk = 0; kk < kmax; kk += 4) {
-            const T a0 = Bs[(wc + li) * LDT + kk + lk];
-            const T a1 = Bs[(wc + 16 + li) * LDT + kk + lk];
-            const T b0 = As[(wr + li) * LDT + kk + lk];
-            const T b1 = As[(wr + 16 + li) * LDT + kk + lk];
+            const T a0 = Bs[(wc + li) * LDTG + kk + lk];
+            const T a1 = Bs[(wc + 16 + li) * LDTG + kk + lk];
+            const T b0 = As[(wr + li) * LDTG + kk + lk];
+            const T b1 = As[(wr + 16 + li) * LDTG + kk + lk];
             if constexpr (sizeof(T) == 8) {
                 acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
                 acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
@@ -1118,8 +1124,8 @@ __device__ void syrk_tile_group(double* F, int ld, int f, int cmax, int k0, int 
             }
         }
         if constexpr (sizeof(T) == 4) {
-            // FP32 products are applied to the FP64 tile window by window, as without grouping,
-            // so that no more than one window's terms are summed in FP32
+            // FP32 products are applied to the FP64 tile chunk by chunk, so that no more terms
+            // are summed in FP32 than without grouping (one window)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -1130,10 +1136,10 @@ __device__ void syrk_tile_group(double* F, int ld, int f, int cmax, int k0, int 
                 }
         }
         if (c + 1 < nch) {
-            syrk_load_chunk(F, ld, f, cmax, k0 + 64 * (c + 1), min(64, nin - 64 * (c + 1)), R0, C0, va, vc);
+            const int kn = SYRK_CW * (c + 1), nn = min(SYRK_CW, nin - kn);
+            syrk_load_chunk(F, ld, f, cmax, k0 + kn, nn, R0, C0, va, vc);
             __syncthreads();  // every wave has read this chunk from As and Bs
-            syrk_stage_chunk<T>(F, ld, cmax, k0 + 64 * (c + 1), min(64, nin - 64 * (c + 1)), C0, va, vc,
-                                dd + 64 * (c + 1), od + 64 * (c + 1), pt + 64 * (c + 1), As, Bs);
+            syrk_stage_chunk<T>(F, ld, cmax, k0 + kn, nn, C0, va, vc, dd + kn, od + kn, pt + kn, As, Bs);
         }
     }
 #pragma unroll
@@ -1228,14 +1234,14 @@ __global__ __launch_bounds__(256) void k_syrk(DevPlan D, const Task* tasks, int6
 
 // Trailing-update tiles of fronts whose windows are grouped: the task packs the inner range
 // (one or more windows) and whether only the next window's columns are updated.
-__global__ __launch_bounds__(256, 2) void k_syrk_group(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp,
+__global__ __launch_bounds__(256, 3) void k_syrk_group(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp,
                                                     int64_t nsy, int64_t fin0) {
     if ((int64_t)blockIdx.x >= nsy) {
         finalize_task(D, tasks[fin0 + (int64_t)blockIdx.x - nsy]);
         return;
     }
-    __shared__ double As[64 * LDT];
-    __shared__ double Bs[64 * LDT];
+    __shared__ double As[64 * LDTG];
+    __shared__ double Bs[64 * LDTG];
     __shared__ double dd[NB * SYRK_GROUP_MAX], od[NB * SYRK_GROUP_MAX];
     __shared__ int pt[NB * SYRK_GROUP_MAX];
     const Task t = tasks[t0 + blockIdx.x];
