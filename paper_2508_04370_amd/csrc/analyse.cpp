@@ -1067,13 +1067,11 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             by += tk.a * NB == tk.k0 ? 16.0 * nc * (nc - 1) / 2 : 16.0 * nc * nr;
         }
     };
-    auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf, int32_t npg = 0,
-                          int32_t grouped = 0) {
+    auto add_launch = [&](int32_t kind, int32_t lvl, int64_t t0, int32_t lds, int32_t maxf, int32_t npg = 0) {
         int64_t cnt = (int64_t)P.tasks.size() - t0;
         if (cnt > 0) {
             Launch L{kind, lvl, t0, cnt, lds, maxf};
             L.npg = npg;
-            L.grouped = grouped;
             for (int64_t q = t0; q < t0 + cnt; ++q) task_work(kind, npg, P.tasks[q], L.flops, L.bytes);
             P.launches.push_back(L);
         }
@@ -1145,28 +1143,23 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             // factorisation needs); after the group's last window, the rest of the trailing
             // matrix receives the update of all its windows at once, so each trailing entry is
             // read and written once per group instead of once per window.
-            // (the tasks of grouped fronts go to a launch of their own kernel)
-            for (int pass = 0; pass < 2; ++pass) {
-                t0 = (int64_t)P.tasks.size();
-                for (int32_t t : large)
-                    if (w < P.sn_nwin[t]) {
-                        const bool grouped = opt.syrk_group_front > 0 && opt.syrk_group > 1 &&
-                                             P.sn_f[t] >= opt.syrk_group_front;
-                        if (grouped != (pass == 1)) continue;
-                        const int32_t G = grouped ? opt.syrk_group : 1;
-                        const int32_t g = (w / G) * G, last = std::min(g + G, P.sn_nwin[t]) - 1;
-                        const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
-                        const int32_t R = (P.sn_f[t] - k1 + 63) / 64;
-                        const int32_t code = g * NB | (w - g) << SYRK_COUNT_SHIFT;
-                        if (w < last) {  // window w + 1 is whole or partial, its columns start at k1
-                            for (int32_t bi = 0; bi < R; ++bi) P.tasks.push_back(Task{t, code | SYRK_NARROW, bi, 0});
-                        } else {
-                            for (int32_t bj = 0; bj < R; ++bj)
-                                for (int32_t bi = bj; bi < R; ++bi) P.tasks.push_back(Task{t, code, bi, bj});
-                        }
+            t0 = (int64_t)P.tasks.size();
+            for (int32_t t : large)
+                if (w < P.sn_nwin[t]) {
+                    const bool grouped = opt.syrk_group_front > 0 && P.sn_f[t] >= opt.syrk_group_front;
+                    const int32_t G = grouped ? opt.syrk_group : 1;
+                    const int32_t g = (w / G) * G, last = std::min(g + G, P.sn_nwin[t]) - 1;
+                    const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                    const int32_t R = (P.sn_f[t] - k1 + 63) / 64;
+                    const int32_t code = g * NB | (w - g) << SYRK_COUNT_SHIFT;
+                    if (w < last) {  // window w + 1 is whole or partial, its columns start at k1
+                        for (int32_t bi = 0; bi < R; ++bi) P.tasks.push_back(Task{t, code | SYRK_NARROW, bi, 0});
+                    } else {
+                        for (int32_t bj = 0; bj < R; ++bj)
+                            for (int32_t bi = bj; bi < R; ++bi) P.tasks.push_back(Task{t, code, bi, bj});
                     }
-                add_launch(L_SYRK, l, t0, 0, mf, 0, pass);
-            }
+                }
+            add_launch(L_SYRK, l, t0, 0, mf);
         }
         t0 = (int64_t)P.tasks.size();
         for (int32_t t : large)

@@ -21,7 +21,6 @@ namespace qdmf {
 
 namespace {
 
-constexpr int LDT = 65;  // leading dimension of LDS tiles (doubles), odd to spread banks
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d16 __attribute__((ext_vector_type(16)));
@@ -910,117 +909,8 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
 // The tile is computed transposed (C^T = W L21^T) so that each group of 16 lanes stores
 // 16 consecutive rows of one column.  T = double: FP64 MFMA 16x16x4; T = float: operands
 // rounded to FP32, FP32 MFMA with FP32 accumulation, result subtracted in FP64.
-template <typename T>
-__device__ void syrk_tile(double* F, int ld, int f, int k0, int nbw, int R0, int C0,
-                          const double* dd, const double* od, const int* pt, T* As, T* Bs) {
-    const int tid = threadIdx.x;
-    // L21 rows of the tile's row block (A) and column block (C), all loads in flight at once
-    double va[16], vc[16];
-    const int r = tid & 63, kq = tid >> 6;  // this thread: row r, columns kq, kq + 4, ...
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int kk = kq + 4 * t;
-        va[t] = (kk < nbw && R0 + r < f) ? F[R0 + r + (int64_t)(k0 + kk) * ld] : 0.0;
-        vc[t] = (kk < nbw && C0 + r < f) ? F[C0 + r + (int64_t)(k0 + kk) * ld] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) As[r * LDT + kq + 4 * t] = (T)va[t];
-    // W = L21 D on the column block: a 1x1 pivot scales its column, a 2x2 block mixes its
-    // two columns (the partner column is read again; 2x2 pivots are rare)
-    double wb[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int kk = kq + 4 * t;
-        double b = 0.0;
-        if (kk < nbw && C0 + r < f) {
-            const int ty = pt[kk];
-            const double* cr = F + C0 + r + (int64_t)k0 * ld;
-            if (ty == 0) b = vc[t] * dd[kk];
-            else if (ty == 1) b = vc[t] * dd[kk] + cr[(int64_t)(kk + 1) * ld] * od[kk];
-            else b = cr[(int64_t)(kk - 1) * ld] * od[kk - 1] + vc[t] * dd[kk];
-        }
-        wb[t] = b;
-    }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) Bs[r * LDT + kq + 4 * t] = (T)wb[t];
-    const int wv = tid >> 6, l = tid & 63;
-    const int wc = (wv >> 1) * 32, wr = (wv & 1) * 32;
-    const int li = l & 15, lk = l >> 4;
-    // this thread's 16 elements of the tile, loaded before the products so that their
-    // latency overlaps them; element (i, j, v) at column C0 + wc + 16 i + cofs(v), row
-    // R0 + wr + 16 j + li
-    double cv[2][2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int col = C0 + wc + i * 16 + (sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v);
-                const int row = R0 + wr + j * 16 + li;
-                cv[i][j][v] = (row < f && col < f && row >= col) ? F[row + (int64_t)col * ld] : 0.0;
-            }
-    const int kmax = (nbw + 3) & ~3;  // columns beyond the window are zero
-    __syncthreads();
-    if constexpr (sizeof(T) == 8) {
-        d4 acc[2][2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-        for (int kk = 0; kk < kmax; kk += 4) {
-            double a0 = Bs[(wc + li) * LDT + kk + lk];
-            double a1 = Bs[(wc + 16 + li) * LDT + kk + lk];
-            double b0 = As[(wr + li) * LDT + kk + lk];
-            double b1 = As[(wr + 16 + li) * LDT + kk + lk];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    // f64 16x16x4 output: element (lk + 4v, li) of the 16 x 16 block
-                    const int col = C0 + wc + i * 16 + lk + 4 * v;
-                    const int row = R0 + wr + j * 16 + li;
-                    if (row < f && col < f && row >= col) F[row + (int64_t)col * ld] = cv[i][j][v] - acc[i][j][v];
-                }
-    } else {
-        f4 acc[2][2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        for (int kk = 0; kk < kmax; kk += 4) {
-            float a0 = Bs[(wc + li) * LDT + kk + lk];
-            float a1 = Bs[(wc + 16 + li) * LDT + kk + lk];
-            float b0 = As[(wr + li) * LDT + kk + lk];
-            float b1 = As[(wr + 16 + li) * LDT + kk + lk];
-            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    // f32 16x16x4 output: element (4 lk + v, li) of the 16 x 16 block
-                    const int col = C0 + wc + i * 16 + 4 * lk + v;
-                    const int row = R0 + wr + j * 16 + li;
-                    if (row < f && col < f && row >= col) F[row + (int64_t)col * ld] = cv[i][j][v] - (double)acc[i][j][v];
-                }
-    }
-}
-
-// Grouped trailing updates stage the inner dimension in chunks of SYRK_CW columns (half a
-// window): small LDS tiles and register arrays, so that four workgroups share a compute unit.
+// Trailing updates stage the inner dimension in chunks of SYRK_CW columns (half a window):
+// small LDS tiles and register arrays, so that three workgroups share a compute unit.
 constexpr int SYRK_CW = 32;
 constexpr int LDTG = SYRK_CW + 1;  // leading dimension of those LDS tiles, odd to spread banks
 
@@ -1071,7 +961,7 @@ __device__ inline void syrk_stage_chunk(const double* F, int ld, int cmax, int k
 // The products accumulate in the matrix cores and C is read and written once; the next
 // chunk's loads are in flight during the current chunk's products.
 template <typename T>
-__device__ void syrk_tile_group(double* F, int ld, int f, int cmax, int k0, int nin, int R0, int C0,
+__device__ void syrk_tile(double* F, int ld, int f, int cmax, int k0, int nin, int R0, int C0,
                           const double* dd, const double* od, const int* pt, T* As, T* Bs) {
     const int tid = threadIdx.x;
     double va[SYRK_CW / 4], vc[SYRK_CW / 4];
@@ -1196,45 +1086,10 @@ __device__ inline void finalize_task(const DevPlan& D, const Task t) {
 
 // Tiles of the trailing update; workgroups past the first nsy take the level's finalize tasks
 // from fin0 on (a launch may hold both: they touch disjoint parts of the fronts).
-__global__ __launch_bounds__(256) void k_syrk(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp,
-                                              int64_t nsy, int64_t fin0) {
-    if ((int64_t)blockIdx.x >= nsy) {
-        finalize_task(D, tasks[fin0 + (int64_t)blockIdx.x - nsy]);
-        return;
-    }
-    __shared__ double As[64 * LDT];
-    __shared__ double Bs[64 * LDT];
-    __shared__ double dd[64], od[64];
-    __shared__ int pt[64];
-    const Task t = tasks[t0 + blockIdx.x];
-    const int s = t.s, k0 = t.k0;
-    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
-    const int k1 = min(k0 + NB, p), nbw = k1 - k0;
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        if (tid < nbw) {
-            dd[tid] = D.dval[c0 + k0 + tid];
-            od[tid] = D.doff[c0 + k0 + tid];
-            pt[tid] = D.ptype[c0 + k0 + tid];
-        } else {
-            dd[tid] = 0.0;
-            od[tid] = 0.0;
-            pt[tid] = 0;
-        }
-    }
-    __syncthreads();
-    double* F = D.front + D.sn_off[s];
-    const int R0 = k1 + 64 * t.a, C0 = k1 + 64 * t.b;
-    if (pp.mixed && f >= pp.f_mix)
-        syrk_tile<float>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, (float*)As, (float*)Bs);
-    else
-        syrk_tile<double>(F, ld, f, k0, nbw, R0, C0, dd, od, pt, As, Bs);
-}
-
-
-// Trailing-update tiles of fronts whose windows are grouped: the task packs the inner range
-// (one or more windows) and whether only the next window's columns are updated.
-__global__ __launch_bounds__(256, 3) void k_syrk_group(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp,
+// Trailing-update tiles (lower 64 x 64 tiles of the trailing matrix): the task packs the inner
+// range (one window, or several for a front with grouped windows) and whether only the next
+// window's columns are updated.
+__global__ __launch_bounds__(256, 3) void k_syrk(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp,
                                                     int64_t nsy, int64_t fin0) {
     if ((int64_t)blockIdx.x >= nsy) {
         finalize_task(D, tasks[fin0 + (int64_t)blockIdx.x - nsy]);
@@ -1266,9 +1121,9 @@ __global__ __launch_bounds__(256, 3) void k_syrk_group(DevPlan D, const Task* ta
     double* F = D.front + D.sn_off[s];
     const int R0 = k1 + 64 * t.a, C0 = k1 + 64 * t.b;
     if (pp.mixed && f >= pp.f_mix)
-        syrk_tile_group<float>(F, ld, f, cmax, k0, nin, R0, C0, dd, od, pt, (float*)As, (float*)Bs);
+        syrk_tile<float>(F, ld, f, cmax, k0, nin, R0, C0, dd, od, pt, (float*)As, (float*)Bs);
     else
-        syrk_tile_group<double>(F, ld, f, cmax, k0, nin, R0, C0, dd, od, pt, As, Bs);
+        syrk_tile<double>(F, ld, f, cmax, k0, nin, R0, C0, dd, od, pt, As, Bs);
 }
 
 __global__ __launch_bounds__(256) void k_finalize(DevPlan D, const Task* tasks, int64_t t0) {
@@ -2792,12 +2647,8 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
             }
             break;
         case L_SYRK:
-            if (L.grouped)
-                hipLaunchKernelGGL(k_syrk_group, dim3((unsigned)(L.ntask + L.nfin)), dim3(256), 0, s, D, tasks, L.task0,
-                                   pp, L.ntask, L.fin0);
-            else
-                hipLaunchKernelGGL(k_syrk, dim3((unsigned)(L.ntask + L.nfin)), dim3(256), 0, s, D, tasks, L.task0, pp,
-                                   L.ntask, L.fin0);
+            hipLaunchKernelGGL(k_syrk, dim3((unsigned)(L.ntask + L.nfin)), dim3(256), 0, s, D, tasks, L.task0, pp,
+                               L.ntask, L.fin0);
             break;
         case L_FINALIZE: hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, D, tasks, L.task0); break;
         default: break;

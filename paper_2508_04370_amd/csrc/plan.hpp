@@ -22,7 +22,7 @@ constexpr int SYRK_GROUP_MAX = 4;
 //   window: s, k0 = window start, a = chunk of 64*npg rows below the window
 //   finalize: s, k0 = first of 64 pivot columns
 //   assemble: s, k0 = front column, [a, a+b) = range of its (child, child column) list
-//   syrk:   s, k0 = window start, a = row tile, b = column tile (grouped: k0 packed, below)
+//   syrk:   s, k0 = packed inner range (below), a = row tile, b = column tile
 struct Task {
     int32_t s, k0, a, b;
 };
@@ -42,7 +42,6 @@ struct Launch {
     int32_t lds;           // dynamic LDS bytes (assembly)
     int32_t maxf;          // largest front order among the tasks
     int32_t npg = 0;       // window: panel row groups of 64 per workgroup (0 or 1)
-    int32_t grouped = 0;   // trailing update: tasks of fronts with grouped windows (packed k0)
     int64_t fin0 = 0, nfin = 0;  // trailing update: the level's finalize tasks run in the same launch
     double flops = 0;      // algorithmic work of the launch
     double bytes = 0;
