@@ -2294,12 +2294,31 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const d
                 akx += delta * fabs(x[i]);
             }
         } else {
-            for (int64_t q = D.krs_ptr[i]; q < D.krs_ptr[i + 1]; ++q) {
-                const int o = D.krs_other[q];
-                double v = D.kval[D.krs_ent[q]];
-                if (o == i) v += delta;
-                kx += v * x[o];
-                akx += fabs(v) * fabs(x[o]);
+            // four entries of row i per trip: their indices, then their values, in flight
+            // together; added in list order
+            const int64_t q1 = D.krs_ptr[i + 1];
+            for (int64_t q = D.krs_ptr[i]; q < q1; q += 4) {
+                int o[4];
+                int32_t ent[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool on = q + j < q1;
+                    o[j] = on ? D.krs_other[q + j] : -1;
+                    ent[j] = on ? D.krs_ent[q + j] : -1;
+                }
+                double v[4], xv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    v[j] = o[j] >= 0 ? D.kval[ent[j]] : 0.0;
+                    xv[j] = o[j] >= 0 ? x[o[j]] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (o[j] >= 0) {
+                        const double vj = o[j] == i ? v[j] + delta : v[j];
+                        kx += vj * xv[j];
+                        akx += fabs(vj) * fabs(xv[j]);
+                    }
             }
         }
         const double rv = b[i] - kx;
