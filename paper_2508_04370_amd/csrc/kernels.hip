@@ -480,8 +480,6 @@ __device__ inline double shfl_d(double v, int src) {  // value of lane src (ds_b
     return __hiloint2double(hi, lo);
 }
 
-__device__ inline int shfl_i(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
-
 // Wave maximum of an unsigned 32-bit value (DPP rows then row broadcasts; lanes without a
 // source contribute 0), read back from lane 63.
 __device__ inline unsigned wave_umax(unsigned v) {
@@ -958,8 +956,8 @@ __device__ inline void syrk_stage_chunk(const double* F, int ld, int cmax, int k
 
 // C -= L21 W21^T on one 64 x 64 tile (rows R0.., columns C0.. below cmax, lower part) over the
 // inner dimension in chunks of SYRK_CW columns (starting at column k0, nin columns in all).
-// The products accumulate in the matrix cores and C is read and written once; the next
-// chunk's loads are in flight during the current chunk's products.
+// The products accumulate in the matrix cores (FP64) or are applied chunk by chunk (FP32), and
+// C is read and written once.
 template <typename T>
 __device__ void syrk_tile(double* F, int ld, int f, int cmax, int k0, int nin, int R0, int C0,
                           const double* dd, const double* od, const int* pt, T* As, T* Bs) {
@@ -1526,22 +1524,6 @@ __device__ inline double trsv_bwd_wave(const double* Lb, double y, int lane) {
         if (lane < i) y -= c[i] * z;
     }
     return y;
-}
-
-// y_i -= sum_{k < nb} L(i, k0 + k) y[k0 + k] for one row i below the block, the row's
-// loads in flight together.
-template <int NBM>
-__device__ inline double gemv_row(const double* Li, int ld, int nb, const double* yk) {
-    double l[NBM];
-#pragma unroll
-    for (int k = 0; k < NBM; ++k) l[k] = k < nb ? Li[(int64_t)k * ld] : 0.0;
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-    for (int k = 0; k < NBM; k += 2) {
-        if (k < nb) a0 += l[k] * yk[k];
-        if (k + 1 < nb) a1 += l[k + 1] * yk[k + 1];
-    }
-    return a0 + a1;
 }
 
 // Forward substitution with unit L and the D solve for one supernode.  The parent gathers
