@@ -208,6 +208,21 @@ def test_invalid_options_rejected():
     _expect(Q.QDMF_ERR_INVALID_ARG, lambda: Q.qdmf_create(-1, None, o))
     o = Q.qdmf_default_options(split_solve_front=0)
     _expect(Q.QDMF_ERR_INVALID_ARG, lambda: Q.qdmf_create(-1, None, o))
+    for bad in (dict(syrk_group=0), dict(syrk_group=5), dict(syrk_group_front=-1)):
+        o = Q.qdmf_default_options(**bad)
+        _expect(Q.QDMF_ERR_INVALID_ARG, lambda: Q.qdmf_create(-1, None, o))
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_grouped_windows_leave_the_symbolic_plan_unchanged(group):
+    """Grouping the trailing updates changes only the launch plan: the ordering, supernodes,
+    factor size and flop count stay those of the ungrouped analysis."""
+    lp = W.ne_dense_front(300, seed=3)
+    a = host_solver(lp, syrk_group_front=0).sym
+    b = host_solver(lp, syrk_group_front=64, syrk_group=group).sym
+    for key in ("N", "nnz_l", "nsuper", "max_front", "flops_fact"):
+        assert a[key] == b[key], key
+    assert np.array_equal(np.asarray(a["perm"]), np.asarray(b["perm"]))
 
 
 def test_no_float_atomics_in_kernels():
