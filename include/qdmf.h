@@ -252,6 +252,13 @@ int qdmf_solve_stats(qdmf_handle h, qdmf_solve_info* out, double* berr_nw_per_rh
 int qdmf_export_d(qdmf_handle h, int32_t* pivot_order, double* d, double* doff,
                   int8_t* ptype, double* edyn);
 
+/* Dynamic regularisation of each pivot position (host memory, N bytes, synchronises): bit 0
+ * a lift (Section 4.5: both the pivot and its column below tiny), bit 1 Proposition 3
+ * (Section 4.6: the pivot raised to beta), bit 2 the sign rule (Section 4.6: the pivot
+ * forced to its expected sign); 0 for positions of 2x2 blocks and unmodified pivots.
+ * Positions as in qdmf_export_d.  Errors: QDMF_ERR_NOT_FACTORISED, QDMF_ERR_INVALID_ARG. */
+int qdmf_export_flags(qdmf_handle h, uint8_t* flags);
+
 /* Copies supernode s's factored front columns (f x p panel of L, rows in the front's
  * pivoted order, ld = f) and its row list (global original indices, length f) to host. */
 int qdmf_export_front(qdmf_handle h, int32_t s, double* panel, int32_t* rows);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "qdmf_oracle.c")
 
 NE, AS = 0, 1
+EF_LIFT, EF_PROP3, EF_SIGN = 1, 2, 4  # dynamic regularisation bits per pivot
 
 
 def build(force=True):
@@ -37,7 +38,7 @@ class Stats(C.Structure):
     _fields_ = [("nneg", C.c_int64), ("npos", C.c_int64), ("nzero", C.c_int64),
                 ("n2x2", C.c_int64), ("nlift", C.c_int64), ("nprop3", C.c_int64),
                 ("nsign", C.c_int64), ("nzskip", C.c_int64), ("max_edyn", C.c_double),
-                ("large_reg", C.c_int)]
+                ("large_reg", C.c_int), ("nbkd", C.c_int64)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,6 +70,7 @@ def lib():
         L.orc_num_knorm.argtypes = [P]
         L.orc_num_knorm.restype = C.c_double
         L.orc_num_export.argtypes = [P] * 7
+        L.orc_num_eflags.argtypes = [P, P]
         L.orc_solve.argtypes = [P, P, C.c_int, P, P, P, P, P, P, P]
         L.orc_residual.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, P, C.c_double,
                                    C.c_double, P, P, P, P, P, P]
@@ -195,7 +197,9 @@ class Num:
         L = np.zeros((N, N), order="F") if dense else None
         d = np.zeros(N); doff = np.zeros(N); pt = np.zeros(N, np.int8); ed = np.zeros(N)
         lib().orc_num_export(self.h, _p(fperm), _p(L), _p(d), _p(doff), _p(pt), _p(ed))
-        return dict(fperm=fperm, L=L, d=d, doff=doff, ptype=pt, edyn=ed)
+        ef = np.zeros(N, np.int8)
+        lib().orc_num_eflags(self.h, _p(ef))
+        return dict(fperm=fperm, L=L, d=d, doff=doff, ptype=pt, edyn=ed, eflag=ef)
 
     def solve(self, r7, r1):
         lp = self.sym.lp

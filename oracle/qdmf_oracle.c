@@ -72,6 +72,7 @@ struct orc_num {
     double* doff;
     int8_t* ptype;
     double* edyn;
+    int8_t* eflag;  /* by position: which dynamic regularisation fired (ORC_EF_* bits) */
     int32_t* lperm; /* by position: local original position within the supernode */
     orc_stats st;
     orc_opts opts;
@@ -612,9 +613,9 @@ static void sym_swap(double* F, int f, int a, int b, int8_t* sigma, double* shif
     int32_t tp = perm[a]; perm[a] = perm[b]; perm[b] = tp;
 }
 
-void orc_front_factor(int f, int p, double* F, int8_t* sigma, double* shift, int32_t* perm,
-                      double knorm, const orc_opts* o, double* d, double* doff, int8_t* ptype,
-                      double* edyn, orc_stats* st) {
+static void front_factor(int f, int p, double* F, int8_t* sigma, double* shift, int32_t* perm,
+                         double knorm, const orc_opts* o, double* d, double* doff, int8_t* ptype,
+                         double* edyn, int8_t* eflag, orc_stats* st) {
     const double alpha = o->alpha;
     const double tiny = o->eps_lift * knorm; /* delta * ||M||_1 of Section 4.5 */
     for (int k = 0; k < f; ++k) perm[k] = k;
@@ -651,6 +652,7 @@ void orc_front_factor(int f, int p, double* F, int8_t* sigma, double* shift, int
                 } else if (fabs(FE(F, f, r, r)) >= alpha * gr) {
                     sym_swap(F, f, k, r, sigma, shift, perm);
                     fkk_before = FE(F, f, k, k);
+                    st->nbkd++;
                 } else {
                     sym_swap(F, f, k + 1, r, sigma, shift, perm);
                     two = 1;
@@ -670,6 +672,7 @@ void orc_front_factor(int f, int p, double* F, int8_t* sigma, double* shift, int
                     /* 2x2 pivot: L2 = F[k+2:, k:k+2] D2^{-1}; Schur update */
                     d[k] = a; d[k + 1] = c; doff[k] = b; doff[k + 1] = 0.0;
                     ptype[k] = 1; ptype[k + 1] = 2;
+                    if (eflag) eflag[k] = eflag[k + 1] = 0;
                     edyn[k] = 0.0; edyn[k + 1] = 0.0;
                     for (int j = k + 2; j < f; ++j) {
                         double u0 = FE(F, f, j, k), u1 = FE(F, f, j, k + 1);
@@ -704,14 +707,17 @@ void orc_front_factor(int f, int p, double* F, int8_t* sigma, double* shift, int
                 double q = FE(F, f, j, k) * FE(F, f, j, k) / den;
                 if (q > beta) beta = q;
             }
-            if (fabs(dk) < beta) { dk = sigma[k] * beta; st->nprop3++; }
+            int8_t ef = lifted ? ORC_EF_LIFT : 0;
+            if (fabs(dk) < beta) { dk = sigma[k] * beta; st->nprop3++; ef |= ORC_EF_PROP3; }
             if (!((sigma[k] > 0 && dk > 0) || (sigma[k] < 0 && dk < 0))) {
                 double mag = fabs(dk);
                 if (beta > mag) mag = beta;
                 if (tiny > mag) mag = tiny;
                 dk = sigma[k] * mag;
                 st->nsign++;
+                ef |= ORC_EF_SIGN;
             }
+            if (eflag) eflag[k] = ef;
             d[k] = dk; doff[k] = 0.0; ptype[k] = 0;
             edyn[k] = dk - (fkk_before + shift[k]);
             if (fabs(edyn[k]) > st->max_edyn) st->max_edyn = fabs(edyn[k]);
@@ -726,6 +732,12 @@ void orc_front_factor(int f, int p, double* F, int8_t* sigma, double* shift, int
             k += 1;
         }
     }
+}
+
+void orc_front_factor(int f, int p, double* F, int8_t* sigma, double* shift, int32_t* perm,
+                      double knorm, const orc_opts* o, double* d, double* doff, int8_t* ptype,
+                      double* edyn, orc_stats* st) {
+    front_factor(f, p, F, sigma, shift, perm, knorm, o, d, doff, ptype, edyn, NULL, st);
 }
 
 /* ------------------------------------------------------------------ multifrontal factorisation (Section 4.1) */
@@ -773,6 +785,7 @@ int orc_factorise_qp(const orc_sym* S, const double* aval, const double* qval, c
     R->doff = (double*)calloc((size_t)(N ? N : 1), sizeof(double));
     R->ptype = (int8_t*)calloc((size_t)(N ? N : 1), 1);
     R->edyn = (double*)calloc((size_t)(N ? N : 1), sizeof(double));
+    R->eflag = (int8_t*)calloc((size_t)(N ? N : 1), 1);
     R->lperm = (int32_t*)calloc((size_t)(N ? N : 1), sizeof(int32_t));
     /* K0 lower entries regrouped by final column (new numbering) */
     int64_t knnz = S->kp[N];
@@ -835,8 +848,8 @@ int orc_factorise_qp(const orc_sym* S, const double* aval, const double* qval, c
             sg[a] = primal ? -1 : 1;
             sh[a] = primal ? -rho : delta;
         }
-        orc_front_factor(f, p, Fr, sg, sh, pm, R->knorm, o, R->d + c0, R->doff + c0,
-                         R->ptype + c0, R->edyn + c0, &R->st);
+        front_factor(f, p, Fr, sg, sh, pm, R->knorm, o, R->d + c0, R->doff + c0, R->ptype + c0,
+                     R->edyn + c0, R->eflag + c0, &R->st);
         for (int k = 0; k < p; ++k) R->lperm[c0 + k] = pm[k];
         double* Ls = R->L + R->Lptr[s];
         for (int k = 0; k < p; ++k)
@@ -859,11 +872,14 @@ int orc_factorise_qp(const orc_sym* S, const double* aval, const double* qval, c
 void orc_num_free(orc_num* R) {
     if (!R) return;
     free(R->theta); free(R->aval); free(R->qval); free(R->kval); free(R->Lptr); free(R->L); free(R->d);
-    free(R->doff); free(R->ptype); free(R->edyn); free(R->lperm);
+    free(R->doff); free(R->ptype); free(R->edyn); free(R->eflag); free(R->lperm);
     free(R);
 }
 
 void orc_num_stats(const orc_num* R, orc_stats* st) { *st = R->st; }
+void orc_num_eflags(const orc_num* R, int8_t* eflag) {
+    memcpy(eflag, R->eflag, (size_t)R->S->N);
+}
 double orc_num_knorm(const orc_num* R) { return R->knorm; }
 
 /* index (new numbering) of front row a of supernode s after pivoting */

@@ -15,6 +15,8 @@ extern "C" {
 #endif
 
 enum { ORC_NE = 0, ORC_AS = 1 };
+/* dynamic regularisation applied to a 1x1 pivot (Sections 4.5-4.6) */
+enum { ORC_EF_LIFT = 1, ORC_EF_PROP3 = 2, ORC_EF_SIGN = 4 };
 
 typedef struct {
     int nb;             /* pivot window width (Section 4.4: blocks of 32/64/128 columns)     */
@@ -31,6 +33,7 @@ typedef struct {
     int64_t n2x2, nlift, nprop3, nsign, nzskip;
     double max_edyn;             /* max |E_dyn|                                            */
     int large_reg;               /* some |E_dyn| > tau_big * ||K||_1                       */
+    int64_t nbkd;                /* Bunch-Kaufman branch (d): r swapped to k, 1x1 at k    */
 } orc_stats;
 
 typedef struct orc_sym orc_sym;
@@ -74,6 +77,9 @@ double orc_num_knorm(const orc_num* F);
  * 1: first of 2x2, 2: second), E_dyn at each position.  For small N only.               */
 void orc_num_export(const orc_num* F, int32_t* fperm, double* Ldense, double* d, double* doff,
                     int8_t* ptype, double* edyn);
+/* By position: the ORC_EF_* bits of the dynamic regularisation each 1x1 pivot received
+ * (0 for 2x2 blocks). */
+void orc_num_eflags(const orc_num* F, int8_t* eflag);
 
 /* Solve with refinement (Sections 3, 4.5).  Column-major, leading dimension = rows.
  * NE: r7 (n x nrhs) may be NULL (zero); returns dx (n x nrhs) and dy (m x nrhs).

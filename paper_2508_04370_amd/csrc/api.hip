@@ -954,6 +954,16 @@ int qdmf_export_d(qdmf_handle h, int32_t* pivot_order, double* d, double* doff, 
     return 0;
 }
 
+int qdmf_export_flags(qdmf_handle h, uint8_t* flags) {
+    if (!h || !flags) return QDMF_ERR_INVALID_ARG;
+    if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;
+    if (set_device(h)) return QDMF_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    const size_t N = (size_t)h->P.N;
+    if (N && hipMemcpy(flags, h->D.pflag, N, hipMemcpyDeviceToHost) != hipSuccess) return QDMF_ERR_HIP;
+    return 0;
+}
+
 int qdmf_export_front(qdmf_handle h, int32_t s, double* panel, int32_t* rows) {
     if (!h) return QDMF_ERR_INVALID_ARG;
     if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;

@@ -36,7 +36,8 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_graph_capture", "qdmf_graph_launch", "qdmf_destroy", "qdmf_status_string",
             "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read", "qdmf_batch_analyse",
             "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats", "qdmf_choose_mode",
-            "qdmf_ipm_default_options", "qdmf_ipm_solve", "qdmf_analyse_qp", "qdmf_set_hessian"]
+            "qdmf_ipm_default_options", "qdmf_ipm_solve", "qdmf_analyse_qp", "qdmf_set_hessian",
+            "qdmf_export_flags"]
 QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD = range(7)
 KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
                      6: "k_bwd"}
@@ -124,6 +125,7 @@ def lib():
         L.qdmf_factor_stats.argtypes = [P, C.POINTER(qdmf_factor_info)]
         L.qdmf_solve_stats.argtypes = [P, C.POINTER(qdmf_solve_info), P, P]
         L.qdmf_export_d.argtypes = [P, P, P, P, P, P]
+        L.qdmf_export_flags.argtypes = [P, P]
         L.qdmf_export_front.argtypes = [P, I32, P, P]
         L.qdmf_graph_capture.argtypes = [P, P, D, D, I32, I32, I32, P, P, P, P]
         L.qdmf_graph_launch.argtypes = [P]
@@ -308,6 +310,12 @@ def qdmf_export_d(h, N):
     return dict(pivot_order=po, d=d, doff=doff, ptype=pt, edyn=ed)
 
 
+def qdmf_export_flags(h, N):
+    fl = np.zeros(N, np.uint8)
+    _check(lib().qdmf_export_flags(h, _np(fl)), "qdmf_export_flags", h)
+    return fl
+
+
 def qdmf_export_front(h, s, f, p):
     panel = np.zeros((f, p), order="F")
     rows = np.zeros(f, np.int32)
@@ -458,6 +466,9 @@ class Solver:
 
     def export_d(self):
         return qdmf_export_d(self.h, self.N)
+
+    def export_flags(self):
+        return qdmf_export_flags(self.h, self.N)
 
     def export_front(self, s):
         f = int(self.sym["sn_front"][s])

@@ -376,6 +376,110 @@ def with_hessian(lp, seed=7, frac=0.5, per_row=3, window=50, ridge=0.1):
     return out
 
 
+def as_dense_interleaved(m=100, n=200, density=0.3, seed=0, theta_range=(1e2, 1e6), rho=1e-10,
+                         delta=1e-10, nrhs=1, scale=1.0):
+    """A dense-ish random LP (Bernoulli(density) pattern, N(0,1) values, no empty row or
+    column) in augmented-system form, and an elimination order that interleaves primal and
+    dual variables (x_0, then y_0, x_1, x_2, y_1, ...), so that after x_0 the rest of K forms
+    one front of mixed-sign pivots of order ~ n + m - 1.  Returns (lp, perm), perm new -> old
+    in the augmented numbering (x first, then y)."""
+    g = rng(300, seed)
+    A = np.where(g.random((m, n)) < density, scale * g.standard_normal((m, n)), 0.0)
+    for j in np.flatnonzero(~A.any(axis=0)):
+        A[g.integers(m), j] = scale * g.standard_normal()
+    for i in np.flatnonzero(~A.any(axis=1)):
+        A[i, g.integers(n)] = scale * g.standard_normal()
+    cols = [np.flatnonzero(A[:, j]) for j in range(n)]
+    colptr = np.zeros(n + 1, np.int64)
+    for j, c in enumerate(cols):
+        colptr[j + 1] = colptr[j] + len(c)
+    rowidx = np.concatenate(cols).astype(np.int32)
+    val = np.concatenate([A[c, j] for j, c in enumerate(cols)])
+    theta = log_uniform(g, *theta_range, n)
+    gr = rng(300, seed, 1)
+    r7 = gr.standard_normal((nrhs, n)).T.copy(order="F")
+    r1 = gr.standard_normal((nrhs, m)).T.copy(order="F")
+    lp = LP(m=m, n=n, colptr=colptr, rowidx=rowidx, val=val, theta=theta, rho=rho, delta=delta,
+            mode=AS, r1=r1, r7=r7, name=f"as_dense_interleaved_{m}x{n}")
+    xs, ys = list(range(n)), list(range(n, n + m))
+    perm = [xs.pop(0)]
+    while xs or ys:
+        if ys:
+            perm.append(ys.pop(0))
+        if xs:
+            perm.append(xs.pop(0))
+        if xs and len(xs) > len(ys):
+            perm.append(xs.pop(0))
+    return lp, np.asarray(perm, np.int32)
+
+
+def indefinite_hessian(lp, seed=0, per_row=3, window=30, diag_scale=1.0):
+    """A symmetric Q on the columns of `lp` that is NOT positive semidefinite: every column c
+    is coupled to per_row others within `window` positions (N(0,1) values, each pair drawn
+    once per direction and summed) and has an N(0, diag_scale^2) diagonal of either sign.
+    With it the (1,1) block -(Q + Theta^-1 + rho I) is indefinite, so the augmented system
+    is no longer quasidefinite.  Adds q_colptr, q_rowidx, q_val (lower triangle, CSC)."""
+    g = rng(310, seed)
+    n = lp["n"]
+    Q = np.zeros((n, n))
+    for c in range(n):
+        lo, hi = max(0, c - window), min(n, c + window + 1)
+        others = g.choice(np.setdiff1d(np.arange(lo, hi), [c]), size=per_row, replace=False)
+        for o in others:
+            v = g.standard_normal()
+            Q[c, o] += v
+            Q[o, c] += v
+        Q[c, c] = diag_scale * g.standard_normal()
+    lower = np.tril(Q)
+    cols = [np.flatnonzero(lower[:, j]) for j in range(n)]
+    qcp = np.zeros(n + 1, np.int64)
+    for j in range(n):
+        qcp[j + 1] = qcp[j] + len(cols[j])
+    out = LP(dict(lp, mode=AS, name=lp.get("name", "lp") + "_indefinite_qp"))
+    out["q_colptr"] = qcp
+    out["q_rowidx"] = np.concatenate(cols).astype(np.int32)
+    out["q_val"] = np.concatenate([lower[c, j] for j, c in enumerate(cols)])
+    return out
+
+
+def planted_hessian(lp, perm, seed=0, npairs=2, coupling=0.01):
+    """A Hessian that is indefinite on `npairs` planted pairs of primal columns (k, j), moved to
+    the end of the elimination order `perm` (new -> old, augmented numbering) so that they are
+    the last pivots of the last front.  On a pair, Theta is 1, the A column is scaled by
+    `coupling`, and Q_kk = a - 1, Q_jj = -b - 1, Q_kj = -c with a ~ U[2, 3], b ~ U[0.5, 1],
+    c = sqrt(a b) U[1.2, 1.4]; Q is zero elsewhere.  The (1,1) block of K_static then holds
+    [[-a, c], [c, +b]] (up to rho) on each pair: a diagonal of the expected sign next to a
+    partner of the wrong sign whose coupling exceeds sqrt(a b) by at least 20 %.  Returns
+    (lp with q_colptr, q_rowidx, q_val (lower triangle, CSC), the new order)."""
+    g = rng(311, seed)
+    n = lp["n"]
+    pairs = [(n - 2 * npairs + 2 * i, n - 2 * npairs + 2 * i + 1) for i in range(npairs)]
+    out = LP(dict(lp, mode=AS, name=lp.get("name", "lp") + "_planted_qp"))
+    theta = np.array(lp["theta"], float)
+    val = np.array(lp["val"], float)
+    cols, vals = [[] for _ in range(n)], [[] for _ in range(n)]
+    for k, j in pairs:
+        a, b = g.uniform(2.0, 3.0), g.uniform(0.5, 1.0)
+        c = np.sqrt(a * b) * g.uniform(1.2, 1.4)
+        cols[k] += [k, j]
+        vals[k] += [a - 1.0, -c]
+        cols[j] += [j]
+        vals[j] += [-b - 1.0]
+        for q in (k, j):
+            theta[q] = 1.0
+            val[lp["colptr"][q]:lp["colptr"][q + 1]] *= coupling
+    qcp = np.zeros(n + 1, np.int64)
+    for q in range(n):
+        qcp[q + 1] = qcp[q] + len(cols[q])
+    out["theta"], out["val"] = theta, val
+    out["q_colptr"] = qcp
+    out["q_rowidx"] = np.asarray([r for c in cols for r in c], np.int32)
+    out["q_val"] = np.asarray([v for c in vals for v in c], float)
+    planted = [q for pr in pairs for q in pr]
+    rest = [int(v) for v in perm if int(v) not in set(planted)]
+    return out, np.asarray(rest + planted, np.int32)
+
+
 def q_dense(lp):
     """Q of a quadratic program's dict as a dense symmetric array."""
     n = lp["n"]

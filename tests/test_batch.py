@@ -8,6 +8,7 @@ from oracle import oracle as O
 from paper_2508_04370_amd import qdmf as Q
 from paper_2508_04370_amd import workloads as W
 
+import parity_bounds as PB
 from test_analyse import _brute_structure
 
 
@@ -137,7 +138,11 @@ def test_batch_gpu_per_system_parity(mode):
         ro = F.solve(rhs[q][0], rhs[q][1])
         xo = np.concatenate([ro["dx"][:, 0], ro["dy"][:, 0]]) if mode == W.AS else ro["dy"][:, 0]
         rel = np.abs(x - xo).max() / max(np.abs(xo).max(), 1e-300)
-        print(f"  system {q}: m={lp['m']} berr_nw={nw:.2e} reported={bs['berr_nw'][0, q]:.2e} rel={rel:.2e}")
+        K = PB.dense_k_static(lp, thetas[q], lp["rho"], lp["delta"])
+        gap, bound = PB.solution_gap_bound(K, b, x, xo)
+        print(f"  system {q}: m={lp['m']} berr_nw={nw:.2e} reported={bs['berr_nw'][0, q]:.2e} rel={rel:.2e} "
+              f"bound {bound / max(np.abs(xo).max(), 1e-300):.2e}")
+        assert gap <= bound
         assert nw <= 1e-12
         assert bs["berr_nw"][0, q] <= 1e-12
         st = F.stats()

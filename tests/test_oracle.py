@@ -286,6 +286,28 @@ def test_residual_function_matches_dense_definition():
         assert np.isclose(cw, (np.abs(b - K @ x) / den).max(), rtol=1e-10)
 
 
+def test_componentwise_error_small_denominator_substitution():
+    """The componentwise backward error's substitution for tiny denominators (Section 4.5
+    cites Arioli, Demmel and Duff; the threshold 1000 N u (||K_i||_1 ||x||_inf + |b_i|) is our
+    reading).  K = I (NE, A = I, Theta = 1, rho = delta = 0), b = [1, 0]:
+    * x = [1, 1e-300]: r = [0, -1e-300]; row 1's denominator |K||x| + |b| = 1e-300 is below the
+      threshold 2000 u, so it becomes |K||x| + ||x||_inf |K|e = 1 + 1e-300 and the row's error is
+      1e-300 (it would be 1 without the substitution);
+    * x = [1, 1e-12]: the denominator 1e-12 is above the threshold, the row's error is
+      1e-12 / 1e-12 = 1.
+    The normwise error is ||r||_inf / (||K|| ||x|| + ||b||) = |x_1| / 2 in both cases."""
+    lp = lp_from_dense(np.eye(2), W.NE, np.ones(2), 0.0, 0.0)
+    b = np.array([1.0, 0.0])
+    r, nw, cw, kn = O.residual(lp, lp["theta"], 0.0, 0.0, np.array([1.0, 1e-300]), b)
+    assert kn == 1.0
+    assert r.tolist() == [0.0, -1e-300]
+    assert cw == 1e-300
+    assert nw == 1e-300 / 2
+    r, nw, cw, kn = O.residual(lp, lp["theta"], 0.0, 0.0, np.array([1.0, 1e-12]), b)
+    assert cw == 1.0
+    assert nw == 1e-12 / 2
+
+
 def test_ne_equals_as_for_the_same_regularised_system():
     """Equations (augsys)/(normeq) with (regul_matrix): both give the same (dx, dy)."""
     g = W.rng(11)
@@ -425,6 +447,29 @@ def test_bk_branch_d_swap():
     # gamma_r = 2, 1*2 < alpha*4, |F11| = 10 >= alpha*2: swap r <-> k, 1x1 of value 10
     r = _ff([[1, 2, 0], [2, 10, 1], [0, 1, 3]], [1, 1, 1])
     assert r["perm"][:2].tolist() == [1, 0] and r["d"][0] == 10.0 and r["ptype"][0] == 0
+    assert r["stats"]["nbkd"] == 1
+
+
+def test_two_by_two_with_zero_determinant_falls_back_to_a_lift():
+    """Reading of the 2x2 case (the paper gives no rule for a singular block): [[0, 1], [1, 0]]
+    with both static shifts +1 reaches branch (e) (|F00| = |F11| = 0 < alpha * 1), and the
+    shifted block [[1, 1], [1, 1]] has det = 0 exactly.  By hand: the pivot at 0 is lifted to
+    sigma * eps * ||K||_1 = 2^-52, shifted to d0 = 1 + 2^-52 (exact in FP64), E_dyn = 2^-52;
+    the second pivot is 1 - 1/(1 + 2^-52) = 2^-52 to first order, positive as its sign."""
+    F = np.asfortranarray(np.array([[0.0, 1.0], [1.0, 0.0]]))
+    eps = 2.0 ** -52
+    r = O.front_factor(F, 2, np.array([1, 1], np.int8), np.array([1.0, 1.0]), 1.0,
+                       O.default_opts(presort=0))
+    assert r["ptype"].tolist() == [0, 0]
+    assert r["stats"]["n2x2"] == 0 and r["stats"]["nlift"] == 1
+    assert r["d"][0] == 1.0 + eps
+    assert r["edyn"][0] == eps
+    assert r["edyn"][1] == 0.0 and 0.0 < r["d"][1] <= 2 * eps
+    assert r["stats"]["npos"] == 2 and r["stats"]["nneg"] == 0
+    # with a nonzero determinant the same window is a 2x2 block (branch e proper)
+    r2 = O.front_factor(F, 2, np.array([1, 1], np.int8), np.array([0.5, 0.5]), 1.0,
+                        O.default_opts(presort=0))
+    assert r2["ptype"].tolist() == [1, 2] and r2["d"].tolist() == [0.5, 0.5] and r2["doff"][0] == 1.0
 
 
 def test_bk_branch_e_with_three():
