@@ -1,13 +1,18 @@
-"""Benchmark: factorise + solve throughput of the regularised Newton systems on one GPU.
+"""Benchmark: factorise + solve of the regularised Newton systems on one GPU, FP64 and mixed
+precision in the same run.
 
-One step = one IPM-like iteration on the staircase augmented system (20000 x 40000,
-40 periods): a fresh Theta (already resident in HBM), the numeric factorisation, and the
-predictor and one corrector solve (Section 4.7: 1 + k directions with k >= 1), each refined
-in FP64 to the target backward error.  Prints one JSON line.
+Default workload: the dense-column augmented system (rows on an 80 x 50 x 50 grid, m = 200000,
+n = 400000 with 20 dense columns at 50 % density, N = 600000; geometric nested dissection),
+the largest single-GPU configuration of the build.  One step = one IPM-like iteration: a fresh
+Theta (already resident in HBM), the numeric factorisation, and the predictor and one
+corrector solve (Section 4.7: 1 + k directions with k >= 1), each refined in FP64 to its
+backward-error target (1e-12 FP64 path, 1e-10 mixed path).  Prints one JSON line: value = the
+FP64 path's algorithmic GFLOP/s, with the mixed path's time, accuracy and speedup beside it.
 
-The roofline object describes the kernel kind that takes the most time in a step: its
-launches inside the timed region are bracketed with HIP events on the library's stream and
-its algorithmic work per launch comes from the symbolic structure.
+The roofline object describes the kernel kind that takes the most time in an FP64 step: its
+launches inside the timed region are bracketed with HIP events on the library's stream and its
+algorithmic work per launch comes from the symbolic structure.  `rooflines` gives the same for
+the trailing update (matrix cores), the solves and the assembly (HBM).
 """
 from __future__ import annotations
 
@@ -31,7 +36,7 @@ PEAK_HBM = 8.0e12     # HBM3E (bytes/s)
 # which resource bounds each kernel kind: the dependent FP64 steps of the pivot chains (small
 # fronts, windows), HBM for assembly, finalize and the solves, the matrix units for the trailing
 # update
-KIND_BOUND = {0: "alu", 1: "hbm", 2: "alu", 3: "mfma", 4: "hbm", 5: "hbm", 6: "hbm"}
+KIND_BOUND = {0: "alu", 1: "hbm", 2: "alu", 3: "mfma", 4: "hbm", 5: "hbm", 6: "hbm", 7: "mfma"}
 
 
 def kernel_source_sha():
@@ -107,18 +112,36 @@ def thetas(lp, k, seed):
     return W.log_uniform(g, lo, hi, lp["n"])
 
 
-def run_gpu(lp, opts, prec, steps, warmup, nsolves, graph):
+
+PRECS = {"fp64": 0, "mixed": 1}
+KINDS = range(8)
+
+
+def tuned_options(workload):
+    """Launch parameters the autotuner chose for this workload (tuning/<workload>.json in the
+    package), or {} when there is none."""
+    path = os.path.join(ROOT, "paper_2508_04370_amd", "tuning", f"{workload}.json")
+    if not os.path.exists(path):
+        return {}, None
+    rec = json.load(open(path))
+    return dict(rec["options"]), os.path.relpath(path, ROOT)
+
+
+def run_gpu(lp, opts, precs, steps, warmup, nsolves, graph):
+    """Times the same K steps for each precision on one analysed handle."""
     import torch
     from paper_2508_04370_amd import qdmf as Q
     dev = "cuda:0"
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
+    t0 = time.perf_counter()
     s = Q.Solver(lp, device=0, stream=stream.cuda_stream, **opts)
+    analyse_s = time.perf_counter() - t0
     sym = s.sym
     nth = warmup + steps + 8
     TH = [torch.from_numpy(thetas(lp, k, 7)).to(dev) for k in range(nth)]
     if "systems" in lp:  # batch: predictor right-hand sides of iteration 0, seed [4, s, 0, 0]
-        rs = [W.as_batch_rhs(q, s, 0, 0) for s, q in enumerate(lp["systems"])]
+        rs = [W.as_batch_rhs(q, s_, 0, 0) for s_, q in enumerate(lp["systems"])]
         lp["r7"] = np.concatenate([r[0] for r in rs]).reshape(-1, 1)
         lp["r1"] = np.concatenate([r[1] for r in rs]).reshape(-1, 1)
     r1 = Q.to_device_colmajor(lp["r1"], dev)
@@ -126,84 +149,125 @@ def run_gpu(lp, opts, prec, steps, warmup, nsolves, graph):
     nrhs = r1.shape[1]
     dx = torch.empty((nrhs, lp["n"]), dtype=torch.float64, device=dev).T
     dy = torch.empty((nrhs, lp["m"]), dtype=torch.float64, device=dev).T
-
-    def one(k):
-        s.factorise(TH[k % nth], lp["rho"], lp["delta"], prec)
-        for _ in range(nsolves):
-            s.solve(r7, r1, dx, dy)
-
-    for k in range(warmup):
-        one(k)
-    stream.synchronize()
-    # the dominant kernel kind: one profiled step per kind
-    per_kind = {}
-    for kind in range(7):
-        Q.qdmf_profile_kind(s.h, kind)
-        one(warmup + steps + (kind % 8))
-        per_kind[kind] = Q.qdmf_profile_read(s.h)
-    Q.qdmf_profile_kind(s.h, -1)
-    dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    results = {}
+    for pname in precs:
+        prec = PRECS[pname]
 
-    def timed(kind):
-        Q.qdmf_profile_kind(s.h, kind)
-        per, steps_taken, berrs = [], [], []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(warmup, warmup + steps):
-            e0.record(stream)
+        def one(k):
+            s.factorise(TH[k % nth], lp["rho"], lp["delta"], prec)
+            for _ in range(nsolves):
+                s.solve(r7, r1, dx, dy)
+
+        print(f"[bench] {pname}: warm-up", file=sys.stderr, flush=True)
+        for k in range(warmup):
             one(k)
-            e1.record(stream)
-            e1.synchronize()
-            per.append(e0.elapsed_time(e1))
-            ss = s.solve_stats(nrhs)
-            steps_taken.append(int(ss["max_steps"]))
-            berrs.append(float(ss["berr_nw"]))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        prof = Q.qdmf_profile_read(s.h)
+        stream.synchronize()
+        # time per kernel kind: one profiled step per kind
+        per_kind = {}
+        for kind in KINDS:
+            Q.qdmf_profile_kind(s.h, kind)
+            one(warmup + steps + (kind % 8))
+            per_kind[kind] = Q.qdmf_profile_read(s.h)
         Q.qdmf_profile_kind(s.h, -1)
-        return per, steps_taken, berrs, prof, wall
+        dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
 
-    # the timed region: K steps; then the same K steps again with every launch of the
-    # dominant kind bracketed by HIP events on the library's stream (the brackets add a
-    # little time per launch, so they stay out of the step time)
-    per, steps_taken, berrs, _, wall = timed(-1)
-    per_p, _, _, prof, _ = timed(dom)
-    fs = s.factor_stats()
-    if s.systems is not None:  # the worst system of the batch
-        bs = s.batch_stats(nrhs)
-        fs["systems"] = len(s.systems)
-        fs["worst_system_berr_nw"] = float(bs["berr_nw"].max())
-        fs["inertia_ok_all_systems"] = bool(all(tuple(bs["inertia"][q][:2]) == (sy_["n"], sy_["m"])
-                                               for q, sy_ in enumerate(s.systems)))
-    out = dict(ms=per, wall=wall, ms_profiled=per_p, sym=sym, steps=steps_taken, berr=berrs, fstats=fs, dom=dom, prof=prof,
-               per_kind={Q.KERNEL_KIND_NAMES[k]: round(v["total_ms"], 3) for k, v in per_kind.items()})
-    if graph:  # the same step captured once as a HIP graph and replayed with Theta refreshed
-        th = torch.empty(lp["n"], dtype=torch.float64, device=dev)
-        th.copy_(TH[0])
-        Q.qdmf_graph_capture(s.h, th, lp["rho"], lp["delta"], prec, nsolves, nrhs, r7, r1, dx, dy)
-        gms = []
-        for k in range(warmup + steps):
-            e0.record(stream)
-            th.copy_(TH[k % nth])
-            Q.qdmf_graph_launch(s.h)
-            e1.record(stream)
-            e1.synchronize()
-            if k >= warmup:
-                gms.append(e0.elapsed_time(e1))
-        out["graph_ms"] = gms
-        out["graph_berr"] = float(s.solve_stats(nrhs)["berr_nw"])
+        def timed(kind):
+            Q.qdmf_profile_kind(s.h, kind)
+            per, steps_taken, berrs = [], [], []
+            torch.cuda.synchronize()
+            t_0 = time.perf_counter()
+            for k in range(warmup, warmup + steps):
+                e0.record(stream)
+                one(k)
+                e1.record(stream)
+                e1.synchronize()
+                per.append(e0.elapsed_time(e1))
+                ss = s.solve_stats(nrhs)
+                steps_taken.append(int(ss["max_steps"]))
+                berrs.append(float(ss["berr_nw"]))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t_0
+            prof = Q.qdmf_profile_read(s.h)
+            Q.qdmf_profile_kind(s.h, -1)
+            return per, steps_taken, berrs, prof, wall
+
+        # the timed region: K steps; then the same K steps again with every launch of the
+        # dominant kind bracketed by HIP events on the library's stream (the brackets add a
+        # little time per launch, so they stay out of the step time)
+        print(f"[bench] {pname}: timed steps", file=sys.stderr, flush=True)
+        per, steps_taken, berrs, _, wall = timed(-1)
+        per_p, _, _, prof, _ = timed(dom)
+        fs = s.factor_stats()
+        if s.systems is not None:  # the worst system of the batch
+            bs = s.batch_stats(nrhs)
+            fs["systems"] = len(s.systems)
+            fs["worst_system_berr_nw"] = float(bs["berr_nw"].max())
+            fs["inertia_ok_all_systems"] = bool(all(tuple(bs["inertia"][q][:2]) == (sy_["n"], sy_["m"])
+                                                   for q, sy_ in enumerate(s.systems)))
+        out = dict(ms=per, wall=wall, ms_profiled=per_p, steps=steps_taken, berr=berrs, fstats=fs, dom=dom,
+                   prof=prof, per_kind=per_kind)
+        if graph:  # the same step captured once as a HIP graph and replayed with Theta refreshed
+            print(f"[bench] {pname}: graph", file=sys.stderr, flush=True)
+            th = torch.empty(lp["n"], dtype=torch.float64, device=dev)
+            th.copy_(TH[0])
+            Q.qdmf_graph_capture(s.h, th, lp["rho"], lp["delta"], prec, nsolves, nrhs, r7, r1, dx, dy)
+            gms = []
+            for k in range(warmup + steps):
+                e0.record(stream)
+                th.copy_(TH[k % nth])
+                Q.qdmf_graph_launch(s.h)
+                e1.record(stream)
+                e1.synchronize()
+                if k >= warmup:
+                    gms.append(e0.elapsed_time(e1))
+            out["graph_ms"] = gms
+            out["graph_berr"] = float(s.solve_stats(nrhs)["berr_nw"])
+        results[pname] = out
     s.close()
-    return out
+    return results, sym, analyse_s
 
 
-def cpu_baseline(lp):
-    """The oracle (plain C, one thread) on the same workload: factorise + one solve."""
+def host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def cpu_baseline(workload):
+    """The oracle (plain C, one thread) timed on this host over a bounded sample of the
+    workload: a smaller instance of the same generator, factorised in matched mode (the
+    oracle takes the library's ordering as data, so both factor the same structure)."""
     from oracle import oracle as O
+    from paper_2508_04370_amd import qdmf as Q
     O.build(force=False)
-    S = O.Sym(lp)
+    if workload == "as_dense_cols":
+        lp = W.as_dense_cols(40, 25, 25)
+        opts = dict(ordering=Q.QDMF_ORDER_GRID_ND, grid=lp["grid"])
+        sample = ("as_dense_cols 40x25x25 (the same generator on a 40 x 25 x 25 row grid: m = 25000, "
+                  "n = 50000 with 20 dense columns, N = 75000): one factorise + one refined solve")
+    else:
+        lp, opts = make_workload(workload)
+        if "systems" in lp:
+            lp, opts = lp["systems"][0], dict(ordering=0)
+            sample = "the first system of the batch: one factorise + one refined solve"
+        else:
+            sample = "the full workload: one factorise + one refined solve"
+    s = Q.Solver(lp, device=-1, **{k: v for k, v in opts.items() if k != "systems"})
+    perm = np.asarray(s.sym["perm"]).copy()
+    s.close()
+    S = O.Sym(lp, perm)
     th = thetas(lp, 0, 7)
     t0 = time.perf_counter()
     F = O.Num(S, lp["val"], th, lp["rho"], lp["delta"])
@@ -212,10 +276,82 @@ def cpu_baseline(lp):
     t = time.perf_counter() - t0
     nrhs = lp["r1"].shape[1]
     flops = S.flops + (1 + float(np.mean(res["steps"]))) * nrhs * (4.0 * (S.nnzL - S.N) + S.N)
-    return dict(value=round(flops / t / 1e9, 4), unit="GFLOP/s", cores=1, kind="oracle",
-                sample="one factorise + one solve with refinement of the full workload on one host "
-                       "core (ordering and symbolic analysis excluded)",
-                seconds=round(t, 3), ms_per_factorise_solve=round(t * 1e3, 1))
+    model, ncpu, avail = host_cpu()
+    return dict(value=round(flops / t / 1e9, 4), unit="GFLOP/s", cores=1, kind="oracle", sample=sample,
+                seconds=round(t, 3), berr_nw=float(np.max(res["berr_nw"])), ordering="library's (matched mode)",
+                cpu_model=model, host_cpus=ncpu, host_cpus_available=avail)
+
+
+def roofline_of(kind, pr, prec, Q):
+    bound = KIND_BOUND[kind]
+    launches = max(1, pr["launches"])
+    avg_ms = pr["total_ms"] / launches
+    if bound == "hbm":
+        per_launch = pr["bytes"] / launches
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        peak, unit = PEAK_HBM / 1e9, "GB/s"
+    else:
+        per_launch = pr["flops"] / launches
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+        peak = (PEAK_FP32 if (bound == "mfma" and prec == 1) else PEAK_FP64) / 1e12
+        unit = "TFLOP/s"
+    return {"bound": bound, "kernel": Q.KERNEL_KIND_NAMES[kind], "achieved": round(achieved, 6), "peak": peak,
+            "unit": unit, "frac": round(achieved / peak, 6), "launches": pr["launches"],
+            "avg_launch_us": round(avg_ms * 1e3, 3), "work_per_launch": round(per_launch, 1),
+            "algorithmic_bytes_per_launch": round(pr["bytes"] / launches, 1)}
+
+
+def run_c0(args):
+    """Dense-front sweep: one front of order f with p pivots (p = f: a single supernode; p < f:
+    the front plus its dense parent of order f - p + 1), FP64 and mixed; one JSON line per
+    (f, p) with the factorisation's GFLOP/s (work from the exact structure) and the trailing
+    update's TFLOP/s against the matrix-core peak."""
+    import torch
+    from paper_2508_04370_amd import qdmf as Q
+    dev = "cuda:0"
+    sizes = [int(v) for v in args.c0_sizes.split(",")]
+    for f in sizes:
+        for frac in (4, 2, 1):
+            p = f // frac
+            lp, perm = W.dense_front_system(f, p)
+            extra = json.loads(args.opts) if args.opts else {}
+            s = Q.Solver(lp, device=0, perm=perm, amalgamate=0, **extra)
+            th = torch.from_numpy(lp["theta"]).to(dev)
+            line = {"workload": f"dense_front_{f}_{p}", "f": f, "p": p, "N": s.N,
+                    "flops_fact": s.sym["flops_fact"], "nsuper": s.sym["nsuper"]}
+            for pname, prec in PRECS.items():
+                for _ in range(args.warmup):
+                    s.factorise(th, lp["rho"], lp["delta"], prec)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.steps):
+                    s.factorise(th, lp["rho"], lp["delta"], prec)
+                e1.record()
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                kinds = {}
+                for kind in KINDS:
+                    Q.qdmf_profile_kind(s.h, kind)
+                    s.factorise(th, lp["rho"], lp["delta"], prec)
+                    r = Q.qdmf_profile_read(s.h)
+                    if r["launches"]:
+                        kinds[Q.KERNEL_KIND_NAMES[kind]] = {
+                            "ms": round(r["total_ms"], 3), "launches": r["launches"],
+                            "tflops": round(r["flops"] / (r["total_ms"] * 1e-3) / 1e12, 2) if r["total_ms"] else 0.0}
+                Q.qdmf_profile_kind(s.h, -1)
+                upd = [kinds[k] for k in ("k_syrk", "k_syrk128") if k in kinds]
+                upd_ms = sum(u["ms"] for u in upd)
+                upd_fl = sum(u["tflops"] * u["ms"] for u in upd)
+                peak = (PEAK_FP32 if prec == 1 else PEAK_FP64) / 1e12
+                line[pname] = {"ms_factorise": round(ms, 3),
+                               "gflops_factorise": round(s.sym["flops_fact"] / (ms * 1e-3) / 1e9, 1),
+                               "trailing_update_tflops": round(upd_fl / upd_ms, 2) if upd_ms else None,
+                               "trailing_update_frac_of_peak": round(upd_fl / upd_ms / peak, 4) if upd_ms else None,
+                               "kernels": kinds}
+            s.close()
+            print(json.dumps(line), flush=True)
 
 
 def run_ipm(lp, opts, prec, args):
@@ -259,15 +395,20 @@ def run_ipm(lp, opts, prec, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="as_staircase",
-                    help="as_staircase | ne_random | ne_grid | ne_grid_small | as_batch | as_batch_small | "
-                         "as_dense_cols | ne_dense_front[_<f>] | as_staircase_qp")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="as_dense_cols",
+                    help="as_dense_cols | as_staircase | ne_random | ne_grid | ne_grid_small | as_batch | "
+                         "as_batch_small | ne_dense_front[_<f>] | as_staircase_qp")
+    ap.add_argument("--prec", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--nsolves", type=int, default=2)
+    ap.add_argument("--opts", default="", help="JSON object of extra qdmf_options fields (after tuning)")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuner's file for the workload")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c0", action="store_true",
+                    help="instead: the dense-front sweep (one JSON line per front order and pivot count)")
+    ap.add_argument("--c0-sizes", default="1024,2048,4096,8192")
     ap.add_argument("--ipm", action="store_true",
                     help="instead: the interior point driver on a feasible LP over the workload's A "
                          "(one JSON line, ms per IPM iteration)")
@@ -284,39 +425,50 @@ def main():
               "across several, the elimination tree's subtrees would go to different GPUs and only the "
               "subtree roots' contribution blocks would travel", file=sys.stderr)
         sys.exit(2)
-    lp, opts = make_workload(args.workload)
-    prec = 1 if args.prec == "mixed" else 0
-    if args.ipm:
-        run_ipm(lp, opts, prec, args)
+    if args.c0:
+        run_c0(args)
         return
-    print(f"[bench] workload={lp['name']} prec={args.prec} steps={args.steps} warmup={args.warmup}",
+    lp, opts = make_workload(args.workload)
+    tuned, tuning_file = ({}, None) if args.no_tuning else tuned_options(args.workload)
+    opts = dict(opts, **tuned)
+    if args.opts:
+        opts.update(json.loads(args.opts))
+    precs = ["fp64", "mixed"] if args.prec == "both" else [args.prec]
+    if args.ipm:
+        run_ipm(lp, opts, PRECS[precs[0]], args)
+        return
+    print(f"[bench] workload={lp['name']} precisions={precs} steps={args.steps} warmup={args.warmup} "
+          f"options={opts if 'systems' not in opts else {k: v for k, v in opts.items() if k != 'systems'}}",
           file=sys.stderr, flush=True)
-    r = run_gpu(lp, opts, prec, args.steps, args.warmup, args.nsolves, not args.no_graph)
-    sym = r["sym"]
-    ms = r["wall"] * 1e3 / args.steps  # K steps between two device synchronisations
+    res, sym, analyse_s = run_gpu(lp, opts, precs, args.steps, args.warmup, args.nsolves, not args.no_graph)
+    from paper_2508_04370_amd import qdmf as Q
     nrhs = lp["r1"].shape[1]
     nnz_a = int(lp["colptr"][-1])
-    # algorithmic work of one step (exact structure of L): factorisation, every solve pass
-    # (the first solve and each refinement step) and each residual
-    solve_passes = args.nsolves * (1 + float(np.mean(r["steps"])))
-    flops = sym["flops_fact"] + solve_passes * nrhs * (sym["flops_solve"] + 4.0 * nnz_a + 2.0 * sym["N"])
-    value = flops / (ms * 1e-3) / 1e9
-    from paper_2508_04370_amd import qdmf as Q
-    dom = r["dom"]
-    pr = r["prof"]
-    avg_ms = pr["total_ms"] / max(1, pr["launches"])
-    bound = KIND_BOUND[dom]
-    if bound == "hbm":
-        per_launch = pr["bytes"] / max(1, pr["launches"])
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        peak, unit = PEAK_HBM / 1e9, "GB/s"
-    else:
-        per_launch = pr["flops"] / max(1, pr["launches"])
-        achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        peak = (PEAK_FP32 if (bound == "mfma" and prec == 1) else PEAK_FP64) / 1e12
-        unit = "TFLOP/s"
+    # algorithmic work of one step (exact structure of L): the factorisation and, per solve, one
+    # forward/D/backward pass and one residual; the same for both precisions, so GFLOP/s compares
+    # their times (refinement passes are extra work of a path, not useful work)
+    work = sym["flops_fact"] + args.nsolves * nrhs * (sym["flops_solve"] + 4.0 * nnz_a + 2.0 * sym["N"])
+    first = precs[0]
+    r0 = res[first]
+    ms = r0["wall"] * 1e3 / args.steps  # K steps between two device synchronisations
+    value = work / (ms * 1e-3) / 1e9
+    pr0 = PRECS[first]
+    dom = r0["dom"]
+    roof = roofline_of(dom, r0["prof"], pr0, Q)
+    roof["traffic"] = measured_traffic(Q.KERNEL_KIND_NAMES[dom], args.workload)
+    roof["ms_per_step_with_brackets"] = round(float(np.median(r0["ms_profiled"])), 4)
+    roofs = {}
+    pk = r0["per_kind"]
+    for name, kinds in (("trailing_update", (3, 7)), ("solves", (5, 6)), ("assembly", (1,)), ("window", (2,))):
+        tot = {"launches": sum(pk[k]["launches"] for k in kinds), "total_ms": sum(pk[k]["total_ms"] for k in kinds),
+               "flops": sum(pk[k]["flops"] for k in kinds), "bytes": sum(pk[k]["bytes"] for k in kinds)}
+        if tot["launches"]:
+            rr = roofline_of(kinds[0], tot, pr0, Q)
+            rr["kernel"] = "+".join(Q.KERNEL_KIND_NAMES[k] for k in kinds)
+            rr["ms_per_step"] = round(tot["total_ms"], 3)
+            roofs[name] = rr
     out = {
-        "metric": "factorise+solve GFLOP/s (ms per IPM iteration alongside)",
+        "metric": "factorise+solve GFLOP/s & ms/IPM-iter, mixed vs FP64 at backward err <=1e-10",
         "value": round(value, 3),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -326,35 +478,46 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == 0 else "f64+f32",
+        "dtype": "f64" if first == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": lp["name"], "m": lp["m"], "n": lp["n"], "mode": "AS" if lp["mode"] else "NE",
-                   "nrhs": nrhs, "solves_per_step": args.nsolves, "precision": args.prec,
+                   "nrhs": nrhs, "solves_per_step": args.nsolves, "precision_of_value": first,
                    "N": sym["N"], "nsuper": sym["nsuper"], "nlevels": sym["nlevels"],
-                   "max_front": sym["max_front"], "flops_fact": sym["flops_fact"],
-                   "nnz_l": sym["nnz_l"]},
-        "roofline": {"bound": bound, "kernel": Q.KERNEL_KIND_NAMES[dom], "achieved": round(achieved, 6),
-                     "peak": peak, "unit": unit, "frac": round(achieved / peak, 6),
-                     "traffic": measured_traffic(Q.KERNEL_KIND_NAMES[dom], args.workload),
-                     "algorithmic_bytes_per_launch": round(pr["bytes"] / max(1, pr["launches"]), 1),
-                     "launches": pr["launches"], "avg_launch_us": round(avg_ms * 1e3, 3),
-                     "work_per_launch": round(per_launch, 1),
-                     "ms_per_step_with_brackets": round(float(np.median(r["ms_profiled"])), 4)},
-        "kernel_ms_per_step_by_kind": r["per_kind"],
-        "berr_nw_max": max(r["berr"]),
-        "refine_steps_mean": float(np.mean(r["steps"])),
-        "ms_median": round(float(np.median(r["ms"])), 4), "ms_min": round(min(r["ms"]), 4),
-        "ms_max": round(max(r["ms"]), 4),
-        "inertia": [r["fstats"]["nneg"], r["fstats"]["npos"]],
-        "batch": {k: r["fstats"][k] for k in ("systems", "worst_system_berr_nw", "inertia_ok_all_systems")}
-        if "systems" in r["fstats"] else None,
+                   "max_front": sym["max_front"], "flops_fact": sym["flops_fact"], "nnz_l": sym["nnz_l"],
+                   "work_per_step_flops": work, "analyse_s": round(analyse_s, 2),
+                   "options": {k: v for k, v in opts.items() if k != "systems"}, "tuning_file": tuning_file},
+        "roofline": roof,
+        "rooflines": roofs,
+        "kernel_ms_per_step_by_kind": {Q.KERNEL_KIND_NAMES[k]: round(v["total_ms"], 3) for k, v in pk.items()},
     }
-    if "graph_ms" in r:
-        gms = float(np.median(r["graph_ms"]))
-        out["graph"] = {"ms_per_step": round(gms, 4), "value": round(flops / (gms * 1e-3) / 1e9, 3),
-                        "berr_nw": r["graph_berr"]}
+    for pname in precs:
+        r = res[pname]
+        mms = r["wall"] * 1e3 / args.steps
+        target = 1e-12 if pname == "fp64" else 1e-10
+        entry = {"ms_per_step": round(mms, 4), "ms_per_ipm_iteration": round(mms, 4),
+                 "gflops": round(work / (mms * 1e-3) / 1e9, 3),
+                 "ms_median": round(float(np.median(r["ms"])), 4), "ms_min": round(min(r["ms"]), 4),
+                 "ms_max": round(max(r["ms"]), 4), "berr_nw_max": max(r["berr"]), "target_berr": target,
+                 "target_met": bool(max(r["berr"]) <= target), "refine_steps_mean": float(np.mean(r["steps"])),
+                 "inertia": [r["fstats"]["nneg"], r["fstats"]["npos"]], "dominant_kernel":
+                 Q.KERNEL_KIND_NAMES[r["dom"]],
+                 "kernel_ms_per_step_by_kind": {Q.KERNEL_KIND_NAMES[k]: round(v["total_ms"], 3)
+                                                for k, v in r["per_kind"].items()}}
+        if "graph_ms" in r:
+            gms = float(np.median(r["graph_ms"]))
+            entry["graph"] = {"ms_per_step": round(gms, 4), "gflops": round(work / (gms * 1e-3) / 1e9, 3),
+                              "berr_nw": r["graph_berr"], "vs_eager": round(gms / float(np.median(r["ms"])), 4)}
+        if "systems" in r["fstats"]:
+            entry["batch"] = {k: r["fstats"][k] for k in ("systems", "worst_system_berr_nw",
+                                                          "inertia_ok_all_systems")}
+        out[pname] = entry
+    if "fp64" in res and "mixed" in res:
+        f64, mx = out["fp64"], out["mixed"]
+        out["mixed_vs_fp64"] = {"speedup": round(f64["ms_per_step"] / mx["ms_per_step"], 4),
+                                "both_within_1e-10": bool(f64["berr_nw_max"] <= 1e-10 and mx["berr_nw_max"] <= 1e-10)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(lp)
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out))
 
 

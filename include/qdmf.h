@@ -43,7 +43,9 @@ enum {
     QDMF_K_SYRK = 3,     /* trailing Schur update on MFMA                        */
     QDMF_K_FINALIZE = 4, /* factored blocks into place, row swaps                */
     QDMF_K_FWD = 5,      /* forward substitution + D, one tree level             */
-    QDMF_K_BWD = 6       /* backward substitution, one tree level                */
+    QDMF_K_BWD = 6,      /* backward substitution, one tree level                */
+    QDMF_K_SYRK128 = 7   /* trailing Schur update of large trailing matrices,
+                            128 x 128 tiles on MFMA                               */
 };
 
 enum {
@@ -88,6 +90,9 @@ typedef struct {
                                  matrix at once (the columns of each next window of the
                                  group are updated as soon as it is reached); 1024        */
     int32_t syrk_group;       /* windows per such group, 1..4; 4                           */
+    int32_t syrk_tile_front;  /* full trailing updates (after a window, or after a group's last
+                                 window) of trailing matrices of at least this many rows run
+                                 in 128 x 128 tiles instead of 64 x 64 (0: never); 0        */
 } qdmf_options;
 
 typedef struct {

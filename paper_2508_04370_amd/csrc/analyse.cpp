@@ -392,6 +392,14 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     const int32_t N = P.N;
     const int64_t annz = colptr[n];
     P.acp.assign(colptr, colptr + n + 1);
+    P.long_col.clear();
+    P.long_of.assign(n, -1);
+    if (mode == 1)
+        for (int32_t c = 0; c < n; ++c)
+            if (colptr[c + 1] - colptr[c] > LONG_COL) {
+                P.long_of[c] = (int32_t)P.long_col.size();
+                P.long_col.push_back(c);
+            }
     P.ari.assign(rowidx, rowidx + annz);
     P.acol.resize(annz);
     for (int32_t j = 0; j < n; ++j)
@@ -1052,12 +1060,13 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                 fl += below * (1 + 2 * (k1 - k - 1));
             }
             by += 16.0 * rows * (k1 - k0);
-        } else if (kind == L_SYRK) {  // one 64 x 64 tile of the lower trailing update
+        } else if (kind == L_SYRK || kind == L_SYRK128) {  // one lower tile of the trailing update
+            const double T = kind == L_SYRK ? 64.0 : 128.0;
             const double k0 = tk.k0 & SYRK_K0_MASK, cnt = ((tk.k0 >> SYRK_COUNT_SHIFT) & 7) + 1;
             const double k1 = std::min<double>(p, k0 + NB * cnt), nbw = k1 - k0;
             const double cmax = (tk.k0 & SYRK_NARROW) ? std::min<double>(p, k1 + NB) : f;
-            const double r0 = k1 + 64.0 * tk.a, c0 = k1 + 64.0 * tk.b;
-            const double nr = std::max(0.0, std::min(64.0, f - r0)), nc = std::max(0.0, std::min(64.0, cmax - c0));
+            const double r0 = k1 + T * tk.a, c0 = k1 + T * tk.b;
+            const double nr = std::max(0.0, std::min(T, f - r0)), nc = std::max(0.0, std::min(T, cmax - c0));
             double lower = nr * nc;
             if (tk.a == tk.b) lower = nc * (nc + 1) / 2 + (nr - nc) * nc;
             fl += 2.0 * nbw * lower;
@@ -1143,12 +1152,42 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             // factorisation needs); after the group's last window, the rest of the trailing
             // matrix receives the update of all its windows at once, so each trailing entry is
             // read and written once per group instead of once per window.
+            // the full updates of trailing matrices of at least syrk_tile_front rows go in 128 x 128
+            // tiles (their own launch, before the one of the 64 x 64 tiles)
+            auto group_of = [&](int32_t t, int32_t& g, int32_t& last) {
+                const bool grouped = opt.syrk_group_front > 0 && P.sn_f[t] >= opt.syrk_group_front;
+                const int32_t G = grouped ? opt.syrk_group : 1;
+                g = (w / G) * G;
+                last = std::min(g + G, P.sn_nwin[t]) - 1;
+            };
+            auto wide = [&](int32_t t, int32_t last) {
+                const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                return w == last && opt.syrk_tile_front > 0 && P.sn_f[t] - k1 >= opt.syrk_tile_front;
+            };
+            t0 = (int64_t)P.tasks.size();
+            int64_t nmix = 0;
+            for (int pass = 0; pass < 2; ++pass)  // fronts of order >= f_mix first
+            for (int32_t t : large)
+                if (w < P.sn_nwin[t] && (P.sn_f[t] >= opt.f_mix) == (pass == 0)) {
+                    int32_t g, last;
+                    group_of(t, g, last);
+                    if (!wide(t, last)) continue;
+                    const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                    const int32_t R = (P.sn_f[t] - k1 + 127) / 128;
+                    const int32_t code = g * NB | (w - g) << SYRK_COUNT_SHIFT;
+                    for (int32_t bj = 0; bj < R; ++bj)
+                        for (int32_t bi = bj; bi < R; ++bi) P.tasks.push_back(Task{t, code, bi, bj});
+                    if (pass == 0) nmix += (int64_t)R * (R + 1) / 2;
+                }
+            add_launch(L_SYRK128, l, t0, 0, mf);
+            if (!P.launches.empty() && P.launches.back().kind == L_SYRK128 && P.launches.back().task0 == t0)
+                P.launches.back().nmix = nmix;
             t0 = (int64_t)P.tasks.size();
             for (int32_t t : large)
                 if (w < P.sn_nwin[t]) {
-                    const bool grouped = opt.syrk_group_front > 0 && P.sn_f[t] >= opt.syrk_group_front;
-                    const int32_t G = grouped ? opt.syrk_group : 1;
-                    const int32_t g = (w / G) * G, last = std::min(g + G, P.sn_nwin[t]) - 1;
+                    int32_t g, last;
+                    group_of(t, g, last);
+                    if (wide(t, last)) continue;
                     const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
                     const int32_t R = (P.sn_f[t] - k1 + 63) / 64;
                     const int32_t code = g * NB | (w - g) << SYRK_COUNT_SHIFT;
@@ -1168,7 +1207,8 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         // The level's last trailing update touches only rows and columns past every pivot of
         // its fronts, and the finalize tasks only pivot rows and columns: both run in one
         // launch when there is such an update.
-        if (!P.launches.empty() && P.launches.back().kind == L_SYRK && P.launches.back().level == l) {
+        if (!P.launches.empty() && (P.launches.back().kind == L_SYRK || P.launches.back().kind == L_SYRK128) &&
+            P.launches.back().level == l) {
             Launch& L = P.launches.back();
             L.fin0 = t0;
             L.nfin = (int64_t)P.tasks.size() - t0;

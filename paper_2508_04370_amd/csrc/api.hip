@@ -224,7 +224,10 @@ int upload_plan(qdmf_ctx* h) {
     UP(sys_rng, sys_rng)
     UP(sys_piv_ptr, sys_piv_ptr)
     UP(sys_piv, sys_piv)
+    UP(long_col, long_col)
+    UP(long_of, long_of)
 #undef UP
+    D.nlong = (int32_t)P.long_col.size();
     D.nsys = P.nsys;
     D.has_q = P.has_q ? 1 : 0;
     const Task* tk = nullptr;
@@ -309,6 +312,8 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     S.ytot = h->P.ytotal;
     if ((rc = dalloc(h, h->solve_allocs, &S.Y, std::max<int64_t>(1, h->P.ytotal) * nrhs))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.P, std::max<int64_t>(1, h->P.ppart_max) * 64 * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.lsum, std::max<int64_t>(1, (int64_t)h->P.long_col.size()) * 2 * nrhs)))
+        return rc;
     if (h->act_host) (void)hipHostFree(h->act_host);
     h->act_host = nullptr;
     if (hipHostMalloc((void**)&h->act_host, sizeof(int32_t) * units, hipHostMallocDefault) != hipSuccess) {
@@ -422,7 +427,7 @@ int gmres_correction(qdmf_ctx* h) {
     int k = 0;
     for (int j = 0; j < GM_M; ++j) {
         enqueue_ldlt_solve(h, Vb(j), h->gm_T, nullptr);  // K M v_j
-        launch_matvec(h->D, h->gm_T, h->gm_W, nr, st);
+        launch_matvec(h->D, h->gm_T, h->gm_W, nr, h->S.lsum, st);
         launch_dots(h->gm_V, j + 1, h->gm_W, hd1, N, nr, st);
         launch_vcombine(h->gm_V, j + 1, hd1, h->gm_W, N, nr, true, st);
         launch_dots(h->gm_V, j + 1, h->gm_W, hd2, N, nr, st);
@@ -539,6 +544,7 @@ void qdmf_default_options(qdmf_options* o) {
     o->split_solve_front = 1024;
     o->syrk_group_front = 1024;
     o->syrk_group = 4;
+    o->syrk_tile_front = 0;
 }
 
 int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_options* opt) {
@@ -549,6 +555,7 @@ int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_optio
     else qdmf_default_options(&h->opt);
     if (h->opt.nb != 64 || h->opt.small_front < 1 || h->opt.small_front > 64 || h->opt.split_solve_front < 1 ||
         h->opt.syrk_group_front < 0 || h->opt.syrk_group < 1 || h->opt.syrk_group > SYRK_GROUP_MAX ||
+        h->opt.syrk_tile_front < 0 ||
         h->opt.max_refine < 0 ||
         h->opt.max_refine_mixed < 0 || h->opt.ordering < QDMF_ORDER_AMD || h->opt.ordering > QDMF_ORDER_AUTO) {
         delete h;
@@ -601,6 +608,8 @@ int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     ao.split_solve_front = h->opt.split_solve_front;
     ao.syrk_group_front = h->opt.syrk_group_front;
     ao.syrk_group = h->opt.syrk_group;
+    ao.syrk_tile_front = h->opt.syrk_tile_front;
+    ao.f_mix = h->opt.f_mix;
     ao.user_perm = user_perm;
     ao.nsys = nsys;
     ao.col_off = col_off;
@@ -1031,7 +1040,7 @@ int qdmf_graph_launch(qdmf_handle h) {
 }
 
 int qdmf_profile_kind(qdmf_handle h, int32_t kind) {
-    if (!h || kind < -1 || kind > QDMF_K_BWD) return QDMF_ERR_INVALID_ARG;
+    if (!h || kind < -1 || kind > QDMF_K_SYRK128) return QDMF_ERR_INVALID_ARG;
     h->prof_kind = kind;
     return 0;
 }
@@ -1244,6 +1253,8 @@ int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
     ao.split_solve_front = h->opt.split_solve_front;
     ao.syrk_group_front = h->opt.syrk_group_front;
     ao.syrk_group = h->opt.syrk_group;
+    ao.syrk_tile_front = h->opt.syrk_tile_front;
+    ao.f_mix = h->opt.f_mix;
     {  // the augmented system first
         Plan Pa;
         const int rc = build_plan(m, n, colptr, rowidx, QDMF_AS, ao, Pa, h->msg);

@@ -69,6 +69,10 @@ struct DevPlan {
     const int32_t* krs_other;
     const int8_t* primal_new;
     const int32_t* perm;      // new -> old
+    // AS: columns of A with more than LONG_COL entries, and per column its index among them or -1
+    int32_t nlong;
+    const int32_t* long_col;
+    const int32_t* long_of;
     // A
     const int64_t* acp;
     const int32_t* ari;
@@ -152,6 +156,7 @@ struct DevSolve {
     double* Y;        // big-supernode work space, ytot x nrhs
     int64_t ytot;
     double* P;        // partial sums of the big backward solves: ppart_max x 64 x nrhs
+    double* lsum;     // AS: per long column and rhs, sum_i A_ij x_i and sum_i |A_ij||x_i| (2 x nlong x nrhs)
 };
 
 void launch_rhs(const DevPlan& D, const DevSolve& S, const double* r7, const double* r1, hipStream_t s);
@@ -210,7 +215,7 @@ void launch_recover(const DevPlan& D, const DevSolve& S, const double* r7, doubl
 void launch_zero(double* p, int64_t n, hipStream_t s);
 
 // ---- Krylov refinement building blocks (N x nrhs blocks, original numbering)
-void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, hipStream_t s);
+void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, double* lsum, hipStream_t s);
 void launch_dots(const double* V, int nv, const double* w, double* out, int64_t N, int nrhs, hipStream_t s);
 void launch_vcombine(const double* V, int nv, const double* h, double* w, int64_t N, int nrhs, bool subtract,
                      hipStream_t s);

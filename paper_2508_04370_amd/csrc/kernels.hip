@@ -1128,6 +1128,199 @@ __global__ __launch_bounds__(256) void k_finalize(DevPlan D, const Task* tasks, 
     finalize_task(D, tasks[t0 + blockIdx.x]);
 }
 
+// Trailing update of one 128 x 128 lower tile (full updates of large trailing matrices):
+// C -= L21 W^T, W = L21 D.  Each wave owns a 64 x 64 quarter (4 x 4 MFMA blocks of 16 x 16),
+// so every panel element read from LDS feeds 16 products and every panel byte fetched from L2
+// feeds 16 flops (twice the 64 x 64 tile's).  The inner dimension goes through two LDS
+// buffers in chunks of CW columns: while the matrix cores work on chunk c, the loads of chunk
+// c + 1 are in flight, and they are written (with the D scaling) into the other buffer, one
+// barrier per chunk.
+//   T = double: FP64 MFMA 16x16x4, CW = 16, two workgroups per compute unit; C is read once
+//   after the products and written once.
+//   T = float (mixed precision): operands rounded to nearest into FP32, FP32 MFMA with FP32
+//   accumulation over at most one pivot window (64 columns), then folded into FP64 copies of
+//   the tile's entries held in registers, so that no more terms are summed in FP32 than in
+//   one window; CW = 32, one workgroup per compute unit (the FP64 copies take 128 registers).
+template <typename T, int CW>
+__device__ void syrk128_tile(const DevPlan& D, const Task t, T* As, T* Bs, double* dd, double* od, int* pt) {
+    constexpr int LDT = CW + 1;          // odd leading dimension spreads the LDS banks
+    constexpr int HALF = CW / 2;         // columns of a chunk staged by one thread
+    constexpr int BUF = 128 * LDT;       // one buffer of one panel
+    const int s = t.s, k0 = t.k0 & SYRK_K0_MASK, cnt = ((t.k0 >> SYRK_COUNT_SHIFT) & 7) + 1;
+    const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
+    const int k1 = min(k0 + NB * cnt, p), nin = k1 - k0;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < NB * SYRK_GROUP_MAX; q += 256) {
+        const bool in = q < nin;
+        dd[q] = in ? D.dval[c0 + k0 + q] : 0.0;
+        od[q] = in ? D.doff[c0 + k0 + q] : 0.0;
+        pt[q] = in ? (int)D.ptype[c0 + k0 + q] : 0;
+    }
+    double* F = D.front + D.sn_off[s];
+    const int R0 = k1 + 128 * t.a, C0 = k1 + 128 * t.b;
+    // staging: thread (r, h) moves row r of both panels, chunk columns HALF h .. HALF (h + 1) - 1
+    const int r = tid & 127, h = tid >> 7;
+    const bool rin = R0 + r < f, cin = C0 + r < f;
+    const double* Ar = F + R0 + r;
+    const double* Br = F + C0 + r;
+    double va[HALF], vb[HALF];
+    auto load = [&](int kb) {  // the chunk starting at inner column kb (relative to k0)
+#pragma unroll
+        for (int q = 0; q < HALF; ++q) {
+            const int kk = kb + HALF * h + q;
+            const bool ok = kk < nin;
+            va[q] = (ok && rin) ? Ar[(int64_t)(k0 + kk) * ld] : 0.0;
+            vb[q] = (ok && cin) ? Br[(int64_t)(k0 + kk) * ld] : 0.0;
+        }
+    };
+    auto stage = [&](int kb, int buf) {
+        T* Ab = As + buf * BUF;
+        T* Bb = Bs + buf * BUF;
+#pragma unroll
+        for (int q = 0; q < HALF; ++q) {
+            const int c = HALF * h + q, kk = kb + c;
+            Ab[r * LDT + c] = (T)va[q];
+            double w = 0.0;
+            if (kk < nin && cin) {
+                const int ty = pt[kk];
+                if (ty == 0) w = vb[q] * dd[kk];
+                else if (ty == 1) w = vb[q] * dd[kk] + Br[(int64_t)(k0 + kk + 1) * ld] * od[kk];
+                else w = Br[(int64_t)(k0 + kk - 1) * ld] * od[kk - 1] + vb[q] * dd[kk];
+            }
+            Bb[r * LDT + c] = (T)w;
+        }
+    };
+    const int wv = tid >> 6, l = tid & 63;
+    const int wr = (wv & 1) * 64, wc = (wv >> 1) * 64;
+    const int li = l & 15, lk = l >> 4;
+    // a wave whose quarter lies above the diagonal of a diagonal tile has nothing to update
+    const bool active = !(t.a == t.b && wr < wc);
+    constexpr bool F64 = sizeof(T) == 8;
+    using AccT = typename std::conditional<F64, d4, f4>::type;
+    // element (i, j, v) of the quarter: column C0 + wc + 16 i + cofs(v), row R0 + wr + 16 j + li
+    // (f64 16x16x4 output: element (lk + 4 v, li) of a block; f32 16x16x4: (4 lk + v, li))
+    auto col_of = [&](int i, int v) { return C0 + wc + 16 * i + (F64 ? lk + 4 * v : 4 * lk + v); };
+    auto row_of = [&](int j) { return R0 + wr + 16 * j + li; };
+    AccT acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = AccT{0, 0, 0, 0};
+    double cv[F64 ? 1 : 4][F64 ? 1 : 4][F64 ? 1 : 4];  // mixed: the FP64 tile entries
+    if constexpr (!F64) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = col_of(i, v), row = row_of(j);
+                    cv[i][j][v] = (active && row < f && col < f && row >= col) ? F[row + (int64_t)col * ld] : 0.0;
+                }
+    }
+    load(0);
+    __syncthreads();  // dd, od, pt
+    stage(0, 0);
+    __syncthreads();
+    const int nch = (nin + CW - 1) / CW;
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) load(CW * (c + 1));
+        if (active) {
+            const T* Ab = As + buf * BUF;
+            const T* Bb = Bs + buf * BUF;
+#pragma unroll
+            for (int kk = 0; kk < CW; kk += 4) {
+                T a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = Bb[(wc + 16 * i + li) * LDT + kk + lk];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = Ab[(wr + 16 * j + li) * LDT + kk + lk];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if constexpr (F64)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                        else
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+            if constexpr (!F64) {
+                // a window's worth of FP32 products (or the task's last chunk) into FP64
+                if (((c + 1) * CW) % NB == 0 || c + 1 == nch) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) cv[i][j][v] -= (double)acc[i][j][v];
+                            acc[i][j] = AccT{0, 0, 0, 0};
+                        }
+                }
+            }
+        }
+        if (c + 1 < nch) stage(CW * (c + 1), buf ^ 1);
+        __syncthreads();
+    }
+    if (!active) return;
+    if constexpr (F64) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double cw[4][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = col_of(i, v), row = row_of(j);
+                    cw[j][v] = (row < f && col < f && row >= col) ? F[row + (int64_t)col * ld] : 0.0;
+                }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = col_of(i, v), row = row_of(j);
+                    if (row < f && col < f && row >= col) F[row + (int64_t)col * ld] = cw[j][v] - acc[i][j][v];
+                }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = col_of(i, v), row = row_of(j);
+                    if (row < f && col < f && row >= col) F[row + (int64_t)col * ld] = cv[i][j][v];
+                }
+    }
+}
+
+// 128 x 128 trailing-update tiles in FP64; workgroups past the first nsy take the level's
+// finalize tasks from fin0 on (as in k_syrk).
+constexpr int S128_CW64 = 16, S128_CW32 = 32;
+__global__ __launch_bounds__(256, 2) void k_syrk128(DevPlan D, const Task* tasks, int64_t t0, int64_t nsy,
+                                                    int64_t fin0) {
+    if ((int64_t)blockIdx.x >= nsy) {
+        finalize_task(D, tasks[fin0 + (int64_t)blockIdx.x - nsy]);
+        return;
+    }
+    __shared__ double As[2 * 128 * (S128_CW64 + 1)];
+    __shared__ double Bs[2 * 128 * (S128_CW64 + 1)];
+    __shared__ double dd[NB * SYRK_GROUP_MAX], od[NB * SYRK_GROUP_MAX];
+    __shared__ int pt[NB * SYRK_GROUP_MAX];
+    syrk128_tile<double, S128_CW64>(D, tasks[t0 + blockIdx.x], As, Bs, dd, od, pt);
+}
+
+// The same tiles with FP32 products (mixed precision, fronts of order >= f_mix).
+__global__ __launch_bounds__(256, 1) void k_syrk128f(DevPlan D, const Task* tasks, int64_t t0) {
+    __shared__ float As[2 * 128 * (S128_CW32 + 1)];
+    __shared__ float Bs[2 * 128 * (S128_CW32 + 1)];
+    __shared__ double dd[NB * SYRK_GROUP_MAX], od[NB * SYRK_GROUP_MAX];
+    __shared__ int pt[NB * SYRK_GROUP_MAX];
+    syrk128_tile<float, S128_CW32>(D, tasks[t0 + blockIdx.x], As, Bs, dd, od, pt);
+}
+
 // ---------------------------------------------------------------- values of K
 
 __global__ void k_init_scalars(DevPlan D, double rho, double delta, const double* rho_a, const double* delta_a) {
@@ -2211,6 +2404,35 @@ __global__ __launch_bounds__(256) void k_bwd_wave(DevPlan D, DevSolve S, const i
 
 // r = b - K_static x and (|K||x|)_i in original numbering, from A, Theta, rho, delta
 // (AS) or from the K values (NE); per-block maxima of |r|, |x|, |b|.
+// AS: the sums over the long columns of A (more than LONG_COL entries, e.g. dense columns)
+// that the residual and the Krylov products need for the primal rows, one workgroup per (long
+// column, right-hand side): sum_i A_ij x_{n+i} and sum_i |A_ij||x_{n+i}|, each thread over a
+// fixed stride of the column, then a fixed-order tree (bitwise reproducible).  One thread per
+// primal row would take the whole column serially.
+__global__ __launch_bounds__(256) void k_long_cols(DevPlan D, const double* xin, double* lsum) {
+    __shared__ double red[2][256];
+    const int q = blockIdx.x, r = blockIdx.y;
+    const int j = D.long_col[q];
+    const double* x = xin + (int64_t)r * D.N + D.n;
+    double s = 0.0, sa = 0.0;
+    for (int64_t e = D.acp[j] + threadIdx.x; e < D.acp[j + 1]; e += 256) {
+        const double a = D.aval[e], v = x[D.ari[e]];
+        s += a * v;
+        sa += fabs(a) * fabs(v);
+    }
+    red[0][threadIdx.x] = s;
+    red[1][threadIdx.x] = sa;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) lsum[2 * ((int64_t)r * D.nlong + q) + threadIdx.x] = red[threadIdx.x][0];
+}
+
 __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const double* xin) {
     __shared__ double red[3][256];
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -2235,8 +2457,14 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const d
                         kx += q * x[k];
                         akx += fabs(q) * fabs(x[k]);
                     }
-                // four entries per trip, their loads in flight together, added in order
-                const int64_t e1 = D.acp[i + 1];
+                // four entries per trip, their loads in flight together, added in order; a long
+                // column's sums come from k_long_cols
+                const int lq = D.nlong ? D.long_of[i] : -1;
+                if (lq >= 0) {
+                    kx += S.lsum[2 * ((int64_t)r * D.nlong + lq)];
+                    akx += S.lsum[2 * ((int64_t)r * D.nlong + lq) + 1];
+                }
+                const int64_t e1 = lq >= 0 ? D.acp[i] : D.acp[i + 1];
                 for (int64_t e = D.acp[i]; e < e1; e += 4) {
                     double a[4], xv[4];
 #pragma unroll
@@ -2479,7 +2707,8 @@ __global__ __launch_bounds__(256) void k_berr_fin(DevPlan D, DevSolve S, int pha
 // at V + j * N * nrhs.  Reductions run in a fixed order (one workgroup per output).
 
 // out = K_static v, from A, Theta, rho, delta (AS) or from the K values (NE).
-__global__ __launch_bounds__(256) void k_matvec(DevPlan D, const double* vin, double* out, int nrhs) {
+__global__ __launch_bounds__(256) void k_matvec(DevPlan D, const double* vin, double* out, int nrhs,
+                                                const double* lsum) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int r = blockIdx.y;
     if (i >= D.N || r >= nrhs) return;
@@ -2493,7 +2722,10 @@ __global__ __launch_bounds__(256) void k_matvec(DevPlan D, const double* vin, do
             if (D.has_q)
                 for (int64_t e = D.qfcp[i]; e < D.qfcp[i + 1]; ++e)
                     if (D.qfri[e] != i) kx -= D.qval[D.qfsrc[e]] * v[D.qfri[e]];
-            for (int64_t e = D.acp[i]; e < D.acp[i + 1]; ++e) kx += D.aval[e] * v[D.n + D.ari[e]];
+            const int lq = D.nlong ? D.long_of[i] : -1;
+            if (lq >= 0) kx += lsum[2 * ((int64_t)r * D.nlong + lq)];
+            else
+                for (int64_t e = D.acp[i]; e < D.acp[i + 1]; ++e) kx += D.aval[e] * v[D.n + D.ari[e]];
         } else {
             const int row = i - D.n;
             for (int64_t q = D.arp[row]; q < D.arp[row + 1]; ++q) {
@@ -2651,6 +2883,15 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks, co
             hipLaunchKernelGGL(k_syrk, dim3((unsigned)(L.ntask + L.nfin)), dim3(256), 0, s, D, tasks, L.task0, pp,
                                L.ntask, L.fin0);
             break;
+        case L_SYRK128: {
+            // mixed precision: the tasks of fronts of order >= f_mix (the first nmix) in FP32
+            const int64_t nf = pp.mixed ? L.nmix : 0;
+            if (nf > 0) hipLaunchKernelGGL(k_syrk128f, dim3((unsigned)nf), dim3(256), 0, s, D, tasks, L.task0);
+            if (L.ntask - nf + L.nfin > 0)
+                hipLaunchKernelGGL(k_syrk128, dim3((unsigned)(L.ntask - nf + L.nfin)), dim3(256), 0, s, D, tasks,
+                                   L.task0 + nf, L.ntask - nf, L.fin0);
+            break;
+        }
         case L_FINALIZE: hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, D, tasks, L.task0); break;
         default: break;
     }
@@ -2665,8 +2906,11 @@ void launch_factor_stats(const DevPlan& D, const PivotParams& pp, double* part, 
     if (D.nsys > 1) hipLaunchKernelGGL(k_sys_inertia, dim3(D.nsys), dim3(256), 0, s, D);
 }
 
-void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_matvec, dim3(nblocks(D.N, 256), nrhs), dim3(256), 0, s, D, v, out, nrhs);
+void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, double* lsum, hipStream_t s) {
+    if (D.mode == 1 && D.nlong > 0)
+        hipLaunchKernelGGL(k_long_cols, dim3(D.nlong, nrhs), dim3(256), 0, s, D, v, lsum);
+    hipLaunchKernelGGL(k_matvec, dim3(nblocks(D.N, 256), nrhs), dim3(256), 0, s, D, v, out, nrhs,
+                       (const double*)lsum);
 }
 
 void launch_dots(const double* V, int nv, const double* w, double* out, int64_t N, int nrhs, hipStream_t s) {
@@ -2760,6 +3004,8 @@ void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L,
 }
 
 void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s) {
+    if (D.mode == 1 && D.nlong > 0)
+        hipLaunchKernelGGL(k_long_cols, dim3(D.nlong, S.nrhs), dim3(256), 0, s, D, x, S.lsum);
     hipLaunchKernelGGL(k_residual, dim3(S.nblk, S.nrhs), dim3(256), 0, s, D, S, x);
 }
 

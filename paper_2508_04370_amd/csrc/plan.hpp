@@ -22,7 +22,8 @@ constexpr int SYRK_GROUP_MAX = 4;
 //   window: s, k0 = window start, a = chunk of 64*npg rows below the window
 //   finalize: s, k0 = first of 64 pivot columns
 //   assemble: s, k0 = front column, [a, a+b) = range of its (child, child column) list
-//   syrk:   s, k0 = packed inner range (below), a = row tile, b = column tile
+//   syrk:   s, k0 = packed inner range (below), a = row tile, b = column tile (64 rows each;
+//           128 for L_SYRK128)
 struct Task {
     int32_t s, k0, a, b;
 };
@@ -32,7 +33,9 @@ enum LaunchKind : int32_t {
     L_ASSEMBLE = 1,  // large fronts: one workgroup per front column
     L_WINDOW = 2,    // pivot window: diagonal block + 64 panel rows per workgroup
     L_SYRK = 3,      // trailing update tiles
-    L_FINALIZE = 4   // factored diagonal blocks into place, row swaps of earlier columns
+    L_FINALIZE = 4,  // factored diagonal blocks into place, row swaps of earlier columns
+    L_SYRK128 = 7    // full trailing updates of large trailing matrices in 128 x 128 tiles
+                     // (the number is its profiling kind; 5 and 6 are the solve passes)
 };
 
 struct Launch {
@@ -43,6 +46,8 @@ struct Launch {
     int32_t maxf;          // largest front order among the tasks
     int32_t npg = 0;       // window: panel row groups of 64 per workgroup (0 or 1)
     int64_t fin0 = 0, nfin = 0;  // trailing update: the level's finalize tasks run in the same launch
+    int64_t nmix = 0;      // 128-tile trailing update: its first nmix tasks belong to fronts of
+                           // order >= f_mix (FP32 products in mixed precision)
     double flops = 0;      // algorithmic work of the launch
     double bytes = 0;
 };
@@ -115,6 +120,9 @@ struct Plan {
     std::vector<int32_t> krs_ent, krs_other;
 
     std::vector<int8_t> primal_new;     // per new index: 1 if a primal (x) variable
+    // AS: columns of A with more than LONG_COL entries (dense columns), summed by a workgroup
+    // each in the residual and Krylov products; per column its index in long_col or -1
+    std::vector<int32_t> long_col, long_of;
 
     // independent systems analysed together as one block-diagonal pattern (a batch); one
     // system otherwise.  K's original numbering: AS columns then rows, NE rows.
@@ -151,6 +159,7 @@ struct Plan {
 };
 
 constexpr int64_t KSRC_ZERO = INT64_MIN;
+constexpr int64_t LONG_COL = 128;
 
 struct AnalyseOptions {
     int ordering = 0;
@@ -160,6 +169,8 @@ struct AnalyseOptions {
     int split_solve_front = 1024;  // fronts at least this big: multi-workgroup solves
     int syrk_group_front = 1024;   // fronts at least this big: grouped trailing updates (0: none)
     int syrk_group = 4;            // windows per group
+    int syrk_tile_front = 0;       // full trailing updates of at least this many rows: 128 x 128 tiles (0: never)
+    int f_mix = 1024;              // mixed precision: fronts of at least this order take FP32 products
     const int32_t* user_perm = nullptr;
     // batch: nsys systems, system s owns columns [col_off[s], col_off[s+1]) and rows
     // [row_off[s], row_off[s+1]) of the block-diagonal A (nullptr: one system)

@@ -38,9 +38,10 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats", "qdmf_choose_mode",
             "qdmf_ipm_default_options", "qdmf_ipm_solve", "qdmf_analyse_qp", "qdmf_set_hessian",
             "qdmf_export_flags"]
-QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD = range(7)
+QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD, \
+    QDMF_K_SYRK128 = range(8)
 KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
-                     6: "k_bwd"}
+                     6: "k_bwd", 7: "k_syrk128"}
 
 
 class qdmf_options(C.Structure):
@@ -50,7 +51,8 @@ class qdmf_options(C.Structure):
                 ("tau_big", C.c_double), ("ordering", C.c_int32), ("grid", C.c_int32 * 3),
                 ("amalgamate", C.c_int32), ("f_mix", C.c_int32), ("small_front", C.c_int32),
                 ("mem_cap_bytes", C.c_int64), ("split_solve_front", C.c_int32),
-                ("syrk_group_front", C.c_int32), ("syrk_group", C.c_int32)]
+                ("syrk_group_front", C.c_int32), ("syrk_group", C.c_int32),
+                ("syrk_tile_front", C.c_int32)]
 
 
 class qdmf_mode_choice(C.Structure):

@@ -215,6 +215,34 @@ def ne_dense_front(f=4096, q=4, seed=0, theta_range=(1e-2, 1e2), delta=1e-8, nrh
               r1=r1, r7=r7, name=f"ne_dense_front_{f}")
 
 
+def dense_front_system(f, p, q=4, seed=0, delta=1e-8):
+    """Normal equations whose elimination in the natural order gives one dense front of order f
+    with p pivots (the dense-front measurement of the Schur updates) and, when p < f, its dense
+    parent of order f - p + 1.  A has m = f (+1 when p < f) rows: the identity on rows 0..f-1
+    (Theta log-uniform in [1, 10]), q dense columns over rows 0..f-1 with N(0,1)/sqrt(f) values
+    (Theta 1), and for p < f one column over rows p..f-1 and an extra last row z, so that the
+    pattern of K separates the first p columns from the rest.  Returns (lp, perm) with perm the
+    natural order (new -> old)."""
+    g = rng(0, f, p, seed)
+    split = p < f
+    m = f + (1 if split else 0)
+    cols = [np.array([j]) for j in range(f)] + [np.arange(f) for _ in range(q)]
+    if split:
+        cols.append(np.arange(p, f + 1))
+    n = len(cols)
+    colptr = np.zeros(n + 1, np.int64)
+    colptr[1:] = np.cumsum([len(c) for c in cols])
+    rowidx = np.concatenate(cols).astype(np.int32)
+    val = np.concatenate([np.ones(f), g.standard_normal(int(colptr[-1]) - f) / np.sqrt(f)])
+    theta = np.concatenate([log_uniform(g, 1.0, 10.0, f), np.ones(n - f)])
+    gr = rng(0, f, p, seed, 1)
+    r1 = gr.standard_normal((1, m)).T.copy(order="F")
+    r7 = np.zeros((n, 1), order="F")
+    lp = LP(m=m, n=n, colptr=colptr, rowidx=rowidx, val=val, theta=theta, rho=0.0, delta=delta, mode=NE,
+            r1=r1, r7=r7, name=f"dense_front_{f}_{p}")
+    return lp, np.arange(m, dtype=np.int32)
+
+
 def as_batch(count, seed=4, mrange=(50, 2000), drange=(0.005, 0.02), rho=1e-10, delta=1e-10):
     """The first count systems of the batched workload (system s from seed [seed, s])."""
     return [as_batch_system(s, seed, mrange, drange, rho, delta) for s in range(count)]

@@ -10,6 +10,8 @@ from paper_2508_04370_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+U = 2.0 ** -53
+
 
 @pytest.fixture(scope="module")
 def torch_dev():
@@ -68,21 +70,27 @@ def test_grid_ne_full_fp64_and_mixed(torch_dev):
     print(f"grid mixed: initial {ss['berr_nw_initial']:.2e} final {ss['berr_nw']:.2e} oracle {nwm.max():.2e} "
           f"steps {ss['max_steps']} status {ss['status']}")
     assert ss["berr_nw"] <= ss["berr_nw_initial"]
-    assert abs(nwm.max() - ss["berr_nw"]) <= 0.1 * nwm.max()
-    assert (ss["status"] == Q.QDMF_WARN_NOT_CONVERGED) == (ss["berr_nw"] > 1e-10)
+    # the reported error is the true one up to the residual's own rounding (rows of up to 25
+    # entries: at most 26 u of the normalising denominator)
+    assert abs(nwm.max() - ss["berr_nw"]) <= 0.1 * nwm.max() + 26 * U
+    assert nwm.max() <= 1e-10 and ss["berr_nw"] <= 1e-10 and ss["status"] == 0
 
 
-def test_batch_full_512_systems(torch_dev):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_full_512_systems(torch_dev, prec):
     """All 512 systems of the batched workload (m in [50, 2000], n = 2m, AMD per system):
-    FP64, every system to 1e-12 against its own K_static with its own inertia."""
+    FP64, every system to 1e-12 against its own K_static with its own inertia; mixed precision,
+    every system to 1e-10 (inertia may differ through FP32-updated 2x2 blocks, which the
+    library reports)."""
     lps = W.as_batch(512)
     cat = W.concat_systems(lps)
     cat["theta"] = np.concatenate([W.as_batch_theta(q, s, 0) for s, q in enumerate(lps)])
     rs = [W.as_batch_rhs(q, s, 0, 0) for s, q in enumerate(lps)]
     cat["r7"] = np.concatenate([r[0] for r in rs]).reshape(-1, 1)
     cat["r1"] = np.concatenate([r[1] for r in rs]).reshape(-1, 1)
-    g = run(torch_dev, cat, 0, systems=lps, ordering=0)
+    g = run(torch_dev, cat, prec, systems=lps, ordering=0)
     bs = g["bs"]
+    tol = 1e-12 if prec == 0 else 1e-10
     worst = 0.0
     for q, lp in enumerate(lps):
         c0, c1 = cat["col_off"][q], cat["col_off"][q + 1]
@@ -92,10 +100,11 @@ def test_batch_full_512_systems(torch_dev):
         b = O.system_rhs(lp, cat["r7"][c0:c1, 0], cat["r1"][r0:r1, 0], th)
         _, nw, _, _ = O.residual(lp, th, lp["rho"], lp["delta"], x, b)
         worst = max(worst, nw)
-        assert nw <= 1e-12, (q, nw)
-        assert tuple(bs["inertia"][q][:2]) == (lp["n"], lp["m"]), q
-    print(f"batch 512: worst system berr {worst:.2e}, reported worst {bs['berr_nw'].max():.2e}")
-    assert bs["berr_nw"].max() <= 1e-12
+        assert nw <= tol, (q, nw)
+        if prec == 0:
+            assert tuple(bs["inertia"][q][:2]) == (lp["n"], lp["m"]), q
+    print(f"batch 512 prec {prec}: worst system berr {worst:.2e}, reported worst {bs['berr_nw'].max():.2e}")
+    assert bs["berr_nw"].max() <= tol
 
 
 def test_dense_column_as_full_fp64(torch_dev):
@@ -108,3 +117,18 @@ def test_dense_column_as_full_fp64(torch_dev):
     print(f"dense columns: max f {g['sym']['max_front']} berr {nw}")
     assert nw.max() <= 1e-12
     assert (g["fs"]["nneg"], g["fs"]["npos"]) == (lp["n"], lp["m"])
+    assert abs(nw.max() - g["ss"]["berr_nw"]) <= 0.1 * nw.max() + 64 * U
+
+
+def test_dense_column_as_full_mixed(torch_dev):
+    """The same workload in mixed precision: FP32 Schur updates on fronts of order >= 1024,
+    refined in FP64 to a normwise backward error <= 1e-10 against the oracle's residual."""
+    from paper_2508_04370_amd import qdmf as Q
+    lp = W.as_dense_cols()
+    g = run(torch_dev, lp, 1, ordering=Q.QDMF_ORDER_GRID_ND, grid=lp["grid"])
+    nw = berr_columns(lp, g)
+    ss = g["ss"]
+    print(f"dense columns mixed: initial {ss['berr_nw_initial']:.2e} final {ss['berr_nw']:.2e} oracle {nw.max():.2e} "
+          f"steps {ss['max_steps']}")
+    assert nw.max() <= 1e-10 and ss["berr_nw"] <= 1e-10 and ss["status"] == 0
+    assert abs(nw.max() - ss["berr_nw"]) <= 0.1 * nw.max() + 64 * U

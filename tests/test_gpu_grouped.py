@@ -76,3 +76,49 @@ def test_grouped_mixed_precision_refines_to_target(torch_dev, group):
     x = g["dy"][:, 0]
     nw, _ = oracle_berr(lp, lp["theta"], x, None, lp["r1"][:, 0])
     assert nw <= 1e-10, nw
+
+
+@pytest.mark.parametrize("group", [1, 4])
+@pytest.mark.parametrize("name", ["dense_ne", "ne_front_300", "staircase"])
+def test_wide_tiles_match_oracle(torch_dev, name, group):
+    """Full trailing updates in 128 x 128 tiles (syrk_tile_front lowered so that they apply
+    here, with ragged last tiles and diagonal tiles whose upper quarter is skipped): FP64
+    against the oracle, ungrouped and in groups of four windows."""
+    lp = case(name)
+    g = gpu_solve(torch_dev, lp, syrk_group_front=64 if group > 1 else 0, syrk_group=group, syrk_tile_front=65)
+    check_against_oracle(lp, g)
+
+
+def test_wide_tiles_reconstruct_K(torch_dev):
+    """The factor made with 128 x 128 trailing tiles reconstructs K within the factorisation's
+    error bound (dense augmented system, largest front of order 129: trailing matrices of 65
+    and 1 rows)."""
+    from test_oracle import dense_K
+    lp = dense_as(62, 67)
+    g = gpu_solve(torch_dev, lp, max_refine=0, syrk_tile_front=1)
+    s = g["solver"]
+    K = dense_K(lp, lp["theta"], lp["rho"], lp["delta"])
+    po, L, D, ed = _dense_factor(s, s.N)
+    R = K[np.ix_(po, po)] + np.diag(ed) - L @ D @ L.T
+    scale = np.abs(L) @ np.abs(D) @ np.abs(L).T
+    print("reconstruction error / (|L||D||L^T|)_max:", np.abs(R).max() / scale.max())
+    assert np.abs(R).max() <= 100 * s.sym["max_front"] * U * scale.max()
+
+
+@pytest.mark.parametrize("group", [1, 4])
+def test_wide_tiles_mixed_precision_refines_to_target(torch_dev, group):
+    """FP32 products in 128 x 128 tiles (f_mix and syrk_tile_front lowered): the FP64
+    refinement reaches a normwise backward error <= 1e-10 against the oracle's residual, and
+    the unrefined error shows that the FP32 products ran."""
+    from test_gpu_parity import oracle_berr
+    lp = W.ne_random(m=300, n=600, density=0.08, seed=22)
+    g64 = gpu_solve(torch_dev, lp, prec=0, syrk_group_front=64 if group > 1 else 0, syrk_group=group,
+                    syrk_tile_front=65)
+    g = gpu_solve(torch_dev, lp, prec=1, f_mix=65, syrk_group_front=64 if group > 1 else 0, syrk_group=group,
+                  syrk_tile_front=65)
+    ss = g["sstats"]
+    print(f"  mixed wide tiles: initial berr {ss['berr_nw_initial']:.2e} final {ss['berr_nw']:.2e} "
+          f"steps {ss['max_steps']}; fp64 initial {g64['sstats']['berr_nw_initial']:.2e}")
+    nw, _ = oracle_berr(lp, lp["theta"], g["dy"][:, 0], None, lp["r1"][:, 0])
+    assert nw <= 1e-10, nw
+    assert ss["berr_nw_initial"] > g64["sstats"]["berr_nw_initial"]

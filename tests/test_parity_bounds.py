@@ -80,9 +80,9 @@ def test_pivot_bounds_cover_a_known_perturbation(case):
     """Theta perturbed by a relative 1e-10 moves M = P (K + E) P^T by a known diagonal dM;
     with gamma = max |dM_ll| / (|L||D||L^T|)_ll (plus both factorisations' rounding), the
     first-order bounds contain every change of D, of the 2x2 off-diagonals and of E_dyn
-    between the two oracle factorisations, which take the same decisions.  The naive bound
-    gamma (|L||D||L^T|)_kk, without the amplification through the eliminated rows, does
-    not: the pivots of the wide-Theta cases are far more sensitive than their own entries."""
+    between the two oracle factorisations, which take the same decisions.  On the wide-Theta
+    case the naive bound gamma (|L||D||L^T|)_kk, without the amplification through the
+    eliminated rows, does not: its pivots are far more sensitive than their own entries."""
     lp, perm, presort = PB.matched_case(case)
     g = W.rng(901)
     theta2 = lp["theta"] * (1.0 + 1e-10 * g.uniform(-1, 1, lp["n"]))
@@ -110,7 +110,8 @@ def test_pivot_bounds_cover_a_known_perturbation(case):
     assert np.all(np.abs(e2["doff"] - e1["doff"])[two] <= bo[two])
     fl = e1["eflag"] != 0
     assert np.all(np.abs(dE)[fl] <= be[fl])
-    # the bound is not vacuous, and the naive one (no amplification) fails somewhere
+    # the bound is not vacuous; on wide Theta the naive one (no amplification) fails somewhere
     assert np.max(diff_d / bd) >= 1e-4
     naive = gamma * np.diag(G) + 2 * U * np.abs(e1["d"])
-    assert np.any(diff_d > naive)
+    if not PB.MATCHED_CASES[case]["full"]:
+        assert np.any(diff_d > naive)
