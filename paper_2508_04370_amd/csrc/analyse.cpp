@@ -905,17 +905,18 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     P.lvl_small.assign(P.nlevels, 0);
     {
         // a level that holds a front of at least split_solve_front pays the multi-workgroup
-        // launches anyway (one diagonal solve and one update launch per 64-pivot block of its
-        // largest such front): its other fronts of at least SPLIT_JOIN_FRONT rows with no more
-        // blocks join those launches rather than occupy one workgroup each for the whole level
+        // launches anyway (one diagonal solve and one update launch per SOLVE_BLOCK-pivot block
+        // of its largest such front): its other fronts of at least SPLIT_JOIN_FRONT rows with no
+        // more blocks join those launches rather than occupy one workgroup each for the level
         std::vector<int32_t> lvl_nb(P.nlevels, 0);
         for (int32_t t = 0; t < ns; ++t)
             if (P.sn_f[t] >= opt.split_solve_front)
-                lvl_nb[P.sn_level[t]] = std::max(lvl_nb[P.sn_level[t]], (P.sn_p[t] + 63) / 64);
+                lvl_nb[P.sn_level[t]] = std::max(lvl_nb[P.sn_level[t]], (P.sn_p[t] + SOLVE_BLOCK - 1) / SOLVE_BLOCK);
         auto split = [&](int32_t t) {
             if (P.sn_f[t] >= opt.split_solve_front) return true;
             const int32_t nb = lvl_nb[P.sn_level[t]];
-            return nb > 0 && P.sn_f[t] >= std::min(SPLIT_JOIN_FRONT, opt.split_solve_front) && (P.sn_p[t] + 63) / 64 <= nb;
+            return nb > 0 && P.sn_f[t] >= std::min(SPLIT_JOIN_FRONT, opt.split_solve_front) &&
+                   (P.sn_p[t] + SOLVE_BLOCK - 1) / SOLVE_BLOCK <= nb;
         };
         std::vector<int64_t> fl(P.lvl_ptr.begin(), P.lvl_ptr.end() - 1);
         for (int pass = 0; pass < 2; ++pass)
@@ -938,7 +939,7 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         for (int32_t t : big) {
             P.yoff[t] = P.ytotal;
             P.ytotal += P.sn_f[t];
-            nbmax = std::max(nbmax, (P.sn_p[t] + 63) / 64);
+            nbmax = std::max(nbmax, (P.sn_p[t] + SOLVE_BLOCK - 1) / SOLVE_BLOCK);
         }
         auto add = [&](std::vector<SolveLaunch>& plan, int32_t kind, int64_t t0) {
             const int64_t cnt = (int64_t)P.stasks.size() - t0;
@@ -952,12 +953,12 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             for (int32_t j = 0; j < nbmax; ++j) {
                 t0 = (int64_t)P.stasks.size();
                 for (int32_t t : big)
-                    if (64 * j < P.sn_p[t]) P.stasks.push_back(Task{t, j, 0, 0});
+                    if (SOLVE_BLOCK * j < P.sn_p[t]) P.stasks.push_back(Task{t, j, 0, 0});
                 add(P.fwd_plan, S_FDIAG, t0);
                 t0 = (int64_t)P.stasks.size();
                 for (int32_t t : big)
-                    if (64 * j < P.sn_p[t]) {
-                        const int32_t k1 = std::min(P.sn_p[t], 64 * (j + 1));
+                    if (SOLVE_BLOCK * j < P.sn_p[t]) {
+                        const int32_t k1 = std::min(P.sn_p[t], SOLVE_BLOCK * (j + 1));
                         for (int32_t c = 0; c < chunks(P.sn_f[t] - k1); ++c) P.stasks.push_back(Task{t, j, c, 0});
                     }
                 add(P.fwd_plan, S_FUPD, t0);
@@ -977,8 +978,8 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                 int32_t q = 0;
                 for (size_t bi = 0; bi < big.size(); ++bi) {
                     const int32_t t = big[bi];
-                    if (64 * j >= P.sn_p[t]) continue;
-                    const int32_t k1 = std::min(P.sn_p[t], 64 * (j + 1));
+                    if (SOLVE_BLOCK * j >= P.sn_p[t]) continue;
+                    const int32_t k1 = std::min(P.sn_p[t], SOLVE_BLOCK * (j + 1));
                     range[bi].first = q;
                     for (int32_t c = 0; c < chunks(P.sn_f[t] - k1); ++c) P.stasks.push_back(Task{t, j, c, q++});
                     range[bi].second = q - range[bi].first;
@@ -987,7 +988,8 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                 add(P.bwd_plan, S_BPART, t0);
                 t0 = (int64_t)P.stasks.size();
                 for (size_t bi = 0; bi < big.size(); ++bi)
-                    if (64 * j < P.sn_p[big[bi]]) P.stasks.push_back(Task{big[bi], j, range[bi].first, range[bi].second});
+                    if (SOLVE_BLOCK * j < P.sn_p[big[bi]])
+                        P.stasks.push_back(Task{big[bi], j, range[bi].first, range[bi].second});
                 add(P.bwd_plan, S_BDIAG, t0);
             }
             t0 = (int64_t)P.stasks.size();

@@ -311,7 +311,8 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     if ((rc = dalloc(h, h->solve_allocs, &S.ract, nrhs))) return rc;
     S.ytot = h->P.ytotal;
     if ((rc = dalloc(h, h->solve_allocs, &S.Y, std::max<int64_t>(1, h->P.ytotal) * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.P, std::max<int64_t>(1, h->P.ppart_max) * 64 * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &S.P, std::max<int64_t>(1, h->P.ppart_max) * SOLVE_BLOCK * nrhs)))
+        return rc;
     if ((rc = dalloc(h, h->solve_allocs, &S.lsum, std::max<int64_t>(1, (int64_t)h->P.long_col.size()) * 2 * nrhs)))
         return rc;
     if (h->act_host) (void)hipHostFree(h->act_host);

@@ -155,7 +155,7 @@ struct DevSolve {
     int32_t* ract;    // per rhs: some system of it still refines (gates the solve kernels)
     double* Y;        // big-supernode work space, ytot x nrhs
     int64_t ytot;
-    double* P;        // partial sums of the big backward solves: ppart_max x 64 x nrhs
+    double* P;        // partial sums of the big backward solves: ppart_max x SOLVE_BLOCK x nrhs
     double* lsum;     // AS: per long column and rhs, sum_i A_ij x_i and sum_i |A_ij||x_i| (2 x nlong x nrhs)
 };
 

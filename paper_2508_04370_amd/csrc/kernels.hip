@@ -2033,63 +2033,120 @@ __global__ __launch_bounds__(256) void k_sgather(DevPlan D, DevSolve S, const Ta
     }
 }
 
+// Big supernodes are solved in blocks of SB = 256 pivots: per block one launch of one workgroup
+// per supernode (the block's diagonal solve: four 64-pivot sub-blocks in sequence, y kept in
+// LDS) and one launch over the rows below (all 256 columns of the block at once), so that a
+// pass takes two launches per 256 pivots.
+constexpr int SB = SOLVE_BLOCK;
+static_assert(SB == 256, "one row per thread of a 256-thread workgroup within a block");
+
+// forward: y_J <- L_JJ^{-1} y_J for the block J of 256 pivots, right-hand sides eight at a time
 __global__ __launch_bounds__(256) void k_sfdiag(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
                                                 const int32_t* active) {
     __shared__ double Lb[64 * 65];
+    __shared__ double yb[SB * 8];
     if (big_inactive(S, active)) return;
     const Task t = tasks[t0 + blockIdx.x];
-    const int s = t.s, k0 = 64 * t.k0;
+    const int s = t.s, k0 = SB * t.k0;
     const int p = D.sn_p[s], ld = D.sn_ld[s];
-    const int nb = min(64, p - k0);
+    const int nbJ = min(SB, p - k0);
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-    stage_block<64>(Lb, D.front + D.sn_off[s], ld, k0, nb, tid);
-    __syncthreads();
-    for (int r = wv; r < S.nrhs; r += 4) {
-        if (active && !active[r]) continue;
-        double* y = S.Y + D.yoff[s] + k0 + (int64_t)r * S.ytot;
-        const double v = trsv_fwd_wave<64>(Lb, lane < nb ? y[lane] : 0.0, lane);
-        if (lane < nb) y[lane] = v;
+    const double* F = D.front + D.sn_off[s];
+    double* Ys = S.Y + D.yoff[s] + k0;
+    for (int rg = 0; rg < S.nrhs; rg += 8) {
+        const int nr = min(8, S.nrhs - rg);
+        for (int idx = tid; idx < SB * 8; idx += 256) {
+            const int i = idx & (SB - 1), rr = idx / SB;
+            yb[idx] = (i < nbJ && rr < nr) ? Ys[i + (int64_t)(rg + rr) * S.ytot] : 0.0;
+        }
+        for (int a = 0; 64 * a < nbJ; ++a) {
+            const int nb = min(64, nbJ - 64 * a);
+            __syncthreads();  // yb written; the previous sub-block's update is done with Lb
+            stage_block<64>(Lb, F, ld, k0 + 64 * a, nb, tid);
+            __syncthreads();
+            for (int rr = wv; rr < nr; rr += 4) {
+                if (active && !active[rg + rr]) continue;
+                double* y = yb + SB * rr + 64 * a;
+                const double v = trsv_fwd_wave<64>(Lb, lane < nb ? y[lane] : 0.0, lane);
+                if (lane < nb) y[lane] = v;
+            }
+            __syncthreads();
+            // the rest of the block: rows 64 (a + 1) .. nbJ, columns of sub-block a
+            const int i = 64 * (a + 1) + tid;
+            if (i < nbJ) {
+                double l[64];
+                const double* Li = F + k0 + i + (int64_t)(k0 + 64 * a) * ld;
+#pragma unroll
+                for (int k = 0; k < 64; ++k) l[k] = k < nb ? Li[(int64_t)k * ld] : 0.0;
+                for (int rr = 0; rr < nr; ++rr) {
+                    const double* yv = yb + SB * rr + 64 * a;
+                    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 64; k += 2) {
+                        a0 += l[k] * yv[k];
+                        a1 += l[k + 1] * yv[k + 1];
+                    }
+                    yb[SB * rr + i] -= a0 + a1;
+                }
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < SB * 8; idx += 256) {
+            const int i = idx & (SB - 1), rr = idx / SB;
+            if (i < nbJ && rr < nr && (!active || active[rg + rr])) Ys[i + (int64_t)(rg + rr) * S.ytot] = yb[idx];
+        }
+        __syncthreads();
     }
 }
 
-// rows below block j: y_i -= sum_k L(i, k0 + k) y_{k0 + k}; the row of L stays in registers
-// while the block's y values pass through LDS sixteen right-hand sides at a time
+// rows below block J: y_i -= sum_k L(i, k0 + k) y_{k0 + k} over the block's 256 columns, 64 at
+// a time with that part of the row in registers; the block's y values pass through LDS sixteen
+// right-hand sides at a time; one row per thread, 256 rows per workgroup
 __global__ __launch_bounds__(256) void k_sfupd(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
                                                const int32_t* active) {
-    __shared__ double Yb[64 * 16];
+    __shared__ double Yb[SB * 16];
     if (big_inactive(S, active)) return;
     const Task t = tasks[t0 + blockIdx.x];
-    const int s = t.s, k0 = 64 * t.k0;
+    const int s = t.s, k0 = SB * t.k0;
     const int f = D.sn_f[s], p = D.sn_p[s], ld = D.sn_ld[s];
-    const int k1 = min(k0 + 64, p), nb = k1 - k0;
+    const int k1 = min(k0 + SB, p), nbJ = k1 - k0;
     const int tid = threadIdx.x;
     double* Ys = S.Y + D.yoff[s];
     const int i = k1 + 256 * t.a + tid;
-    double l[64];
-    {
-        const double* Li = D.front + D.sn_off[s] + min(i, f - 1) + (int64_t)k0 * ld;
-#pragma unroll
-        for (int k = 0; k < 64; ++k) l[k] = k < nb ? Li[(int64_t)k * ld] : 0.0;
-    }
+    const double* Li = D.front + D.sn_off[s] + min(i, f - 1) + (int64_t)k0 * ld;
     for (int rg = 0; rg < S.nrhs; rg += 16) {
         const int nr = min(16, S.nrhs - rg);
         __syncthreads();  // the previous group is done with Yb
-        for (int idx = tid; idx < 64 * 16; idx += 256) {
-            const int k = idx & 63, rr = idx >> 6;
-            Yb[idx] = (k < nb && rr < nr) ? Ys[k0 + k + (int64_t)(rg + rr) * S.ytot] : 0.0;
+        for (int idx = tid; idx < SB * 16; idx += 256) {
+            const int k = idx & (SB - 1), rr = idx / SB;
+            Yb[idx] = (k < nbJ && rr < nr) ? Ys[k0 + k + (int64_t)(rg + rr) * S.ytot] : 0.0;
         }
         __syncthreads();
         if (i >= f) continue;
+        double acc[16];
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) acc[rr] = 0.0;
+        for (int q = 0; 64 * q < nbJ; ++q) {
+            const int nb = min(64, nbJ - 64 * q);
+            double l[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) l[k] = k < nb ? Li[(int64_t)(64 * q + k) * ld] : 0.0;
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                if (rr >= nr) break;
+                const double* yb = Yb + SB * rr + 64 * q;
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < 64; k += 2) {
+                    a0 += l[k] * yb[k];
+                    a1 += l[k + 1] * yb[k + 1];
+                }
+                acc[rr] += a0 + a1;
+            }
+        }
         for (int rr = 0; rr < nr; ++rr) {
             if (active && !active[rg + rr]) continue;
-            const double* yb = Yb + 64 * rr;
-            double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-            for (int k = 0; k < 64; k += 2) {
-                a0 += l[k] * yb[k];
-                a1 += l[k + 1] * yb[k + 1];
-            }
-            Ys[i + (int64_t)(rg + rr) * S.ytot] -= a0 + a1;
+            Ys[i + (int64_t)(rg + rr) * S.ytot] -= acc[rr];
         }
     }
 }
@@ -2134,9 +2191,10 @@ __global__ __launch_bounds__(256) void k_sbload(DevPlan D, DevSolve S, const Tas
         if (!active || active[r]) S.Y[D.yoff[s] + i + (int64_t)r * S.ytot] = S.xw[(int64_t)r * D.N + src];
 }
 
-// partial sums over one 256-row chunk below block j: P[(b * 64 + k) * nrhs + r] =
-// sum_i L(i, k0 + k) y_i[r]; the rows are taken in 64-row tiles loaded coalesced (lane = row)
-// and summed through LDS (lane = column), right-hand sides eight at a time
+// partial sums over one 256-row chunk below block J: P[(b * SB + k) * nrhs + r] =
+// sum_i L(i, k0 + k) y_i[r] for the block's 256 columns, 64 columns at a time; the rows are
+// taken in 64-row tiles loaded coalesced (lane = row) and summed through LDS (lane = column),
+// right-hand sides eight at a time
 __global__ __launch_bounds__(256) void k_sbpart(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
                                                 const int32_t* active) {
     __shared__ double Lt[64 * 65];
@@ -2144,73 +2202,128 @@ __global__ __launch_bounds__(256) void k_sbpart(DevPlan D, DevSolve S, const Tas
     __shared__ double red[4 * 64 * 8];
     if (big_inactive(S, active)) return;
     const Task t = tasks[t0 + blockIdx.x];
-    const int s = t.s, k0 = 64 * t.k0;
+    const int s = t.s, kJ = SB * t.k0;
     const int f = D.sn_f[s], p = D.sn_p[s], ld = D.sn_ld[s];
-    const int k1 = min(k0 + 64, p), nb = k1 - k0;
+    const int k1 = min(kJ + SB, p), nbJ = k1 - kJ;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const double* F = D.front + D.sn_off[s];
     const double* Ys = S.Y + D.yoff[s];
     const int r0 = k1 + 256 * t.a, r1 = min(f, r0 + 256);
-    for (int rg = 0; rg < S.nrhs; rg += 8) {
-        const int nr = min(8, S.nrhs - rg);
-        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int i0 = r0; i0 < r1; i0 += 64) {
-            double v[16];
+    for (int a = 0; 64 * a < nbJ; ++a) {
+        const int k0 = kJ + 64 * a, nb = min(64, nbJ - 64 * a);
+        for (int rg = 0; rg < S.nrhs; rg += 8) {
+            const int nr = min(8, S.nrhs - rg);
+            double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int i0 = r0; i0 < r1; i0 += 64) {
+                double v[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int k = wv + 4 * q, i = i0 + lane;
-                v[q] = (k < nb && i < r1) ? F[i + (int64_t)(k0 + k) * ld] : 0.0;
-            }
-            __syncthreads();  // the previous tile's sums are done with Lt, Yt
+                for (int q = 0; q < 16; ++q) {
+                    const int k = wv + 4 * q, i = i0 + lane;
+                    v[q] = (k < nb && i < r1) ? F[i + (int64_t)(k0 + k) * ld] : 0.0;
+                }
+                __syncthreads();  // the previous tile's sums are done with Lt, Yt
 #pragma unroll
-            for (int q = 0; q < 16; ++q) Lt[(wv + 4 * q) * 65 + lane] = v[q];
-            for (int idx = tid; idx < 8 * 64; idx += 256) {
-                const int i = idx & 63, rr = idx >> 6;
-                Yt[idx] = (rr < nr && i0 + i < r1) ? Ys[i0 + i + (int64_t)(rg + rr) * S.ytot] : 0.0;
+                for (int q = 0; q < 16; ++q) Lt[(wv + 4 * q) * 65 + lane] = v[q];
+                for (int idx = tid; idx < 8 * 64; idx += 256) {
+                    const int i = idx & 63, rr = idx >> 6;
+                    Yt[idx] = (rr < nr && i0 + i < r1) ? Ys[i0 + i + (int64_t)(rg + rr) * S.ytot] : 0.0;
+                }
+                __syncthreads();
+                for (int q = 0; q < 16; ++q) {  // rows wv + 4q of the tile, column lane
+                    const int i = wv + 4 * q;
+                    const double lv = Lt[lane * 65 + i];
+#pragma unroll
+                    for (int rr = 0; rr < 8; ++rr) acc[rr] += lv * Yt[rr * 64 + i];
+                }
             }
+#pragma unroll
+            for (int rr = 0; rr < 8; ++rr) red[(wv * 64 + lane) * 8 + rr] = acc[rr];
             __syncthreads();
-            for (int q = 0; q < 16; ++q) {  // rows wv + 4q of the tile, column lane
-                const int i = wv + 4 * q;
-                const double lv = Lt[lane * 65 + i];
-#pragma unroll
-                for (int rr = 0; rr < 8; ++rr) acc[rr] += lv * Yt[rr * 64 + i];
-            }
+            if (wv == 0)
+                for (int rr = 0; rr < nr; ++rr) {
+                    const double sum = ((red[(0 * 64 + lane) * 8 + rr] + red[(1 * 64 + lane) * 8 + rr]) +
+                                        red[(2 * 64 + lane) * 8 + rr]) + red[(3 * 64 + lane) * 8 + rr];
+                    S.P[((int64_t)t.b * SB + 64 * a + lane) * S.nrhs + rg + rr] = sum;
+                }
+            __syncthreads();
         }
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr) red[(wv * 64 + lane) * 8 + rr] = acc[rr];
-        __syncthreads();
-        if (wv == 0)
-            for (int rr = 0; rr < nr; ++rr) {
-                const double sum = ((red[(0 * 64 + lane) * 8 + rr] + red[(1 * 64 + lane) * 8 + rr]) +
-                                    red[(2 * 64 + lane) * 8 + rr]) + red[(3 * 64 + lane) * 8 + rr];
-                S.P[((int64_t)t.b * 64 + lane) * S.nrhs + rg + rr] = sum;
-            }
-        __syncthreads();
     }
 }
 
+// backward: y_J <- L_JJ^{-T} (y_J - sum of the block's partial sums, chunks in fixed order),
+// sub-blocks of 64 from the last: y_a -= L_ba^T y_b for the later sub-blocks b of the block
+// (L_ba staged through LDS, four row quarters summed in a fixed order), then the sub-block's
+// own triangular solve; right-hand sides eight at a time
 __global__ __launch_bounds__(256) void k_sbdiag(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
                                                 const int32_t* active) {
     __shared__ double Lb[64 * 65];
+    __shared__ double yb[SB * 8];
+    __shared__ double part[4 * 64 * 8];
     if (big_inactive(S, active)) return;
     const Task t = tasks[t0 + blockIdx.x];
-    const int s = t.s, k0 = 64 * t.k0;
+    const int s = t.s, kJ = SB * t.k0;
     const int p = D.sn_p[s], ld = D.sn_ld[s];
-    const int nb = min(64, p - k0);
+    const int nbJ = min(SB, p - kJ);
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-    stage_block<64>(Lb, D.front + D.sn_off[s], ld, k0, nb, tid);
-    __syncthreads();
-    for (int r = wv; r < S.nrhs; r += 4) {
-        if (active && !active[r]) continue;
-        double* y = S.Y + D.yoff[s] + k0 + (int64_t)r * S.ytot;
-        double v = 0.0;
-        if (lane < nb) {
-            double sum = 0.0;
-            for (int c = 0; c < t.b; ++c) sum += S.P[((int64_t)(t.a + c) * 64 + lane) * S.nrhs + r];
-            v = y[lane] - sum;
+    const double* F = D.front + D.sn_off[s];
+    double* Ys = S.Y + D.yoff[s] + kJ;
+    const int nsub = (nbJ + 63) / 64;
+    for (int rg = 0; rg < S.nrhs; rg += 8) {
+        const int nr = min(8, S.nrhs - rg);
+        for (int idx = tid; idx < SB * 8; idx += 256) {
+            const int i = idx & (SB - 1), rr = idx / SB;
+            double v = 0.0;
+            if (i < nbJ && rr < nr) {
+                double sum = 0.0;
+                for (int c = 0; c < t.b; ++c) sum += S.P[((int64_t)(t.a + c) * SB + i) * S.nrhs + rg + rr];
+                v = Ys[i + (int64_t)(rg + rr) * S.ytot] - sum;
+            }
+            yb[idx] = v;
         }
-        v = trsv_bwd_wave<64>(Lb, v, lane);
-        if (lane < nb) y[lane] = v;
+        for (int a = nsub - 1; a >= 0; --a) {
+            const int nb = min(64, nbJ - 64 * a);
+            for (int b = a + 1; b < nsub; ++b) {  // y_a -= L_ba^T y_b
+                const int nbb = min(64, nbJ - 64 * b);
+                double v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {  // L(64 b + lane, 64 a + k), k = wv + 4 q
+                    const int k = wv + 4 * q;
+                    v[q] = (k < nb && lane < nbb) ? F[kJ + 64 * b + lane + (int64_t)(kJ + 64 * a + k) * ld] : 0.0;
+                }
+                __syncthreads();  // earlier readers of Lb, part and yb are done
+#pragma unroll
+                for (int q = 0; q < 16; ++q) Lb[(wv + 4 * q) * 65 + lane] = v[q];
+                __syncthreads();
+                // thread (k = lane, quarter wv): rows 16 wv .. 16 wv + 15 of L_ba column k
+                for (int rr = 0; rr < nr; ++rr) {
+                    const double* yv = yb + SB * rr + 64 * b;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) acc += Lb[lane * 65 + 16 * wv + u] * yv[16 * wv + u];
+                    part[(wv * 64 + lane) * 8 + rr] = acc;
+                }
+                __syncthreads();
+                if (wv == 0 && lane < nb)
+                    for (int rr = 0; rr < nr; ++rr)
+                        yb[SB * rr + 64 * a + lane] -= ((part[(0 * 64 + lane) * 8 + rr] + part[(1 * 64 + lane) * 8 + rr]) +
+                                                         part[(2 * 64 + lane) * 8 + rr]) + part[(3 * 64 + lane) * 8 + rr];
+            }
+            __syncthreads();
+            stage_block<64>(Lb, F, ld, kJ + 64 * a, nb, tid);
+            __syncthreads();
+            for (int rr = wv; rr < nr; rr += 4) {
+                if (active && !active[rg + rr]) continue;
+                double* y = yb + SB * rr + 64 * a;
+                const double vv = trsv_bwd_wave<64>(Lb, lane < nb ? y[lane] : 0.0, lane);
+                if (lane < nb) y[lane] = vv;
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < SB * 8; idx += 256) {
+            const int i = idx & (SB - 1), rr = idx / SB;
+            if (i < nbJ && rr < nr && (!active || active[rg + rr])) Ys[i + (int64_t)(rg + rr) * S.ytot] = yb[idx];
+        }
+        __syncthreads();
     }
 }
 

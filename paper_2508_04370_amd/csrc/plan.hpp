@@ -8,6 +8,7 @@
 namespace qdmf {
 
 constexpr int NB = 64;  // pivot window width used by the device kernels
+constexpr int SOLVE_BLOCK = 256;  // pivots per block of the multi-workgroup solves of big supernodes
 // A trailing-update task (L_SYRK) packs into Task.k0 the first inner column k0 (a window start),
 // the number of consecutive windows whose update it applies at once, less one, and whether it
 // updates only the next window's columns (the narrow update inside a group of windows).  The
@@ -55,9 +56,10 @@ struct Launch {
 // Solve launches of big supernodes (front order >= the split_solve_front option), spread over
 // many workgroups (all right-hand sides at once).  Task fields per kind:
 //   S_GATHER, S_FFIN, S_BLOAD, S_BSTORE: s, k0 = 256-row chunk of the front
-//   S_FDIAG: s, k0 = pivot block j;  S_BDIAG: s, k0 = j, [a, a + b) = its partial sums
+//   S_FDIAG: s, k0 = pivot block j (SOLVE_BLOCK pivots);  S_BDIAG: s, k0 = j, [a, a + b) = its
+//            partial sums
 //   S_FUPD: s, k0 = j, a = 256-row chunk below the block
-//   S_BPART: s, k0 = j, a = 256-row chunk below the block, b = index of its partial sum
+//   S_BPART: s, k0 = j, a = 256-row chunk below the block, b = index of its partial sums
 enum SolveKind : int32_t { S_GATHER = 0, S_FDIAG, S_FUPD, S_FFIN, S_BLOAD, S_BPART, S_BDIAG, S_BSTORE };
 
 struct SolveLaunch {

@@ -117,16 +117,22 @@ def test_dense_ne_large_front_windows(torch_dev):
     check_against_oracle(lp, g)
 
 
+@pytest.mark.parametrize("split", [1024, 1])
 @pytest.mark.parametrize("case", ["dense_ne", "staircase"])
-def test_mid_size_fronts_solves(torch_dev, case):
+def test_mid_size_fronts_solves(torch_dev, case, split):
     """Fronts of order 256..1024 with more than 32 pivots: the one-workgroup solve kernels take
-    several trips over the rows below each block (and several blocks); solution and backward
-    error against the oracle."""
+    several trips over the rows below each block (and several blocks); with split_solve_front
+    = 1 the multi-workgroup solves take them in 256-pivot blocks (two or more, the last
+    partial); solution and backward error against the oracle."""
     if case == "dense_ne":
         lp = W.ne_random(m=420, n=840, density=0.05, seed=23)
     else:
         lp = W.as_staircase(periods=4, rows=300, cols=600, link_cols=60, seed=24)
-    g = gpu_solve(torch_dev, lp)
+    if split == 1:
+        lp = W.LP(dict(lp, r1=np.hstack([lp["r1"]] * 3), r7=np.hstack([lp["r7"]] * 3)))
+        lp["r1"][:, 1] *= -2.0
+        lp["r1"][:, 2] = W.rng(25).standard_normal(lp["m"])
+    g = gpu_solve(torch_dev, lp, split_solve_front=split)
     sym = g["solver"].sym
     print(f"  max front {sym['max_front']}")
     assert 256 < sym["max_front"] < 1024
