@@ -70,7 +70,8 @@ typedef struct {
     double eps_lift;          /* lift threshold factor (Section 4.5), 2^-52                 */
     int32_t presort;          /* swap the largest diagonal first (Section 4.5), 1           */
     int32_t max_refine;       /* refinement steps, FP64 path (Section 4.5), 2               */
-    int32_t max_refine_mixed; /* refinement steps, mixed path, 10                           */
+    int32_t max_refine_mixed; /* refinement steps, mixed path, 3 (each a GMRES correction of
+                                 up to 3 Krylov steps preconditioned by the factor)        */
     double target_berr;       /* normwise backward error target, FP64 path, 1e-12          */
     double target_berr_mixed; /* normwise backward error target, mixed path, 1e-10         */
     double tau_big;           /* "too large" regularisation threshold (Section 4.6), 1e-8  */
@@ -120,6 +121,7 @@ typedef struct {
     double max_edyn;                  /* max |E_dyn|                                        */
     double knorm;                     /* ||K_static||_1                                     */
     int32_t status;                   /* 0 or the first QDMF_WARN_* that applies            */
+    int32_t nredo_fp64;               /* mixed precision: systems factorised again in FP64  */
 } qdmf_factor_info;
 
 typedef struct {
@@ -186,9 +188,13 @@ int qdmf_set_matrix(qdmf_handle h, const double* a_val, int32_t on_device);
  * a bad value makes qdmf_factor_stats return QDMF_ERR_INVALID_ARG); it must stay valid
  * until the stream reaches this call's end.  rho, delta >= 0 are the static
  * regularisations.  prec: QDMF_FP64 or QDMF_MIXED (FP32 MFMA Schur updates on fronts of
- * order >= opt.f_mix; everything else FP64).  L, D are owned by the handle.  Returns < 0
- * only for argument errors; numerical outcomes come from qdmf_factor_stats.  An empty
- * system (m + n == 0) launches nothing and reports zero pivots. */
+ * order >= opt.f_mix; everything else FP64).  In mixed precision a system whose factor
+ * then holds a pivot that is not finite, or one that needed Proposition 3 or the sign rule
+ * (the FP32 rounding of the updates changed a pivot's sign), is factorised again in FP64,
+ * and only that system; qdmf_factor_info.nredo_fp64 counts them.  Executed eagerly, this
+ * call then waits for the stream to read that count.  L, D are owned by the handle.
+ * Returns < 0 only for argument errors; numerical outcomes come from qdmf_factor_stats.
+ * An empty system (m + n == 0) launches nothing and reports zero pivots. */
 int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double delta,
                    int32_t prec);
 
@@ -196,12 +202,14 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
  * dx = theta~ (A^T dy - r7) (NE, Section 3 eq. (normeq)), then refines in FP64 against
  * K_static until the normwise backward error reaches the target or the step limit
  * (Section 4.5).  All vectors are device memory, column-major: r7 and dx n x nrhs, r1 and
- * dy m x nrhs; r7 may be NULL (zero).  Outputs must not alias inputs.  Between
- * refinement steps the call waits for the stream to read the device's stop flags and
- * launches no further step once every right-hand side meets the target; under graph
- * capture (qdmf_graph_capture) it waits for nothing and enqueues every step, whose kernels
- * then return at once for finished right-hand sides.  An empty system (m + n == 0)
- * launches nothing and reports zero backward error.
+ * dy m x nrhs; r7 may be NULL (zero).  Outputs must not alias inputs.  A correction of
+ * the FP64 path is d = (L D L^T)^{-1} r; of the mixed path, GMRES on K_static (L D L^T)^{-1}
+ * with at most 3 Krylov steps, its small dense part and stop flags on the device.  Between
+ * refinement steps (and between Krylov steps) the call waits for the stream to read the
+ * device's stop flags and launches no further step once every right-hand side is done;
+ * under graph capture (qdmf_graph_capture) it waits for nothing and enqueues every step,
+ * whose kernels then return at once for finished right-hand sides: both compute the same
+ * result.  An empty system (m + n == 0) launches nothing and reports zero backward error.
  * Errors: QDMF_ERR_NOT_FACTORISED, QDMF_ERR_INVALID_ARG. */
 int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev,
                double* dx_dev, double* dy_dev);
@@ -270,7 +278,10 @@ int qdmf_export_front(qdmf_handle h, int32_t s, double* panel, int32_t* rows);
 
 /* Captures factorise + nsolves x solve (each with refinement) once as a HIP graph; later
  * qdmf_graph_launch replays it on the handle's stream, reading Theta and the right-hand
- * sides from the same device buffers (the caller refreshes them in place).
+ * sides from the same device buffers (the caller refreshes them in place).  Capturing runs
+ * nothing and leaves the handle's factorisation and solve state as they were; a launch makes
+ * it the graph's (the stats and export calls then report the replayed factorisation and
+ * solves).  The result of a replay equals that of the same calls made eagerly.
  * Errors: QDMF_ERR_HIP, QDMF_ERR_NOT_ANALYSED, QDMF_ERR_INVALID_ARG (also for an empty
  * system, which has nothing to capture). */
 int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, double delta,

@@ -38,17 +38,19 @@ struct qdmf_ctx {
     Task* inv_tasks_dev = nullptr;            // diagonal blocks whose inverse the solves use
     std::vector<int32_t> maxf_lvl, maxp_lvl;  // per level: largest front order and pivot count
     int64_t knnz = 0;
+    int64_t max_sys_piv = 0;  // largest pivot count of one system
     int64_t device_bytes = 0;
 
     // solve work space
     std::vector<void*> solve_allocs;
     DevSolve S{};
     int32_t solve_cap = 0;
-    // Krylov refinement work space (mixed precision, eager solves), allocated on first use
-    double* gm_V = nullptr;    // (GM_M + 1) blocks of N x nrhs
-    double* gm_T = nullptr;    // N x nrhs
+    // Krylov refinement work space (mixed precision), allocated on first use
+    double* gm_V = nullptr;    // (GM_M + 1) blocks of N x nrhs: the Arnoldi basis
+    double* gm_Z = nullptr;    // GM_M blocks of N x nrhs: the preconditioned basis M v_j
     double* gm_W = nullptr;    // N x nrhs
-    double* gm_dev = nullptr;  // device scalars: 2 (GM_M + 1) + 1 + GM_M per rhs
+    DevGmres gm{};             // the small dense state, per rhs (device)
+    int32_t* gm_act_host = nullptr;  // pinned copy of gm.act (eager solves)
     int32_t gm_cap = 0;
     int32_t* act_host = nullptr;  // pinned copy of the refinement flags (eager solves)
     double* shift_host = nullptr;  // pinned staging of per-system rho, delta (batch factorise)
@@ -64,6 +66,8 @@ struct qdmf_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool capturing = false;
+    // what a launch of the captured graph leaves behind (set by qdmf_graph_launch)
+    int32_t graph_prec = 0, graph_nrhs = 0, graph_nsolves = 0;
 
     // measurement: event pairs around launches of one kernel kind
     int32_t prof_kind = -1;
@@ -227,6 +231,14 @@ int upload_plan(qdmf_ctx* h) {
     UP(long_col, long_col)
     UP(long_of, long_of)
 #undef UP
+    {
+        std::vector<int32_t> sn_sys(P.ns, 0);
+        for (int32_t q = 0; q < P.ns; ++q) sn_sys[q] = P.sys_new.empty() ? 0 : P.sys_new[P.sn_ptr[q]];
+        if ((rc = dupload(h, sn_sys, &D.sn_sys))) return rc;
+        h->max_sys_piv = 0;
+        for (int32_t q = 0; q < P.nsys; ++q)
+            h->max_sys_piv = std::max<int64_t>(h->max_sys_piv, P.sys_piv_ptr[q + 1] - P.sys_piv_ptr[q]);
+    }
     D.nlong = (int32_t)P.long_col.size();
     D.nsys = P.nsys;
     D.has_q = P.has_q ? 1 : 0;
@@ -268,6 +280,7 @@ int upload_plan(qdmf_ctx* h) {
     if ((rc = dalloc(h, h->plan_allocs, &D.rho_sys, P.nsys))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.delta_sys, P.nsys))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &D.inertia_sys, (int64_t)3 * P.nsys))) return rc;
+    if ((rc = dalloc(h, h->plan_allocs, &D.redo, (int64_t)P.nsys + 1))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &h->shift_dev, (int64_t)2 * P.nsys))) return rc;
     if ((rc = dalloc(h, h->plan_allocs, &h->stats_part, (int64_t)10 * factor_stats_blocks(P.N)))) return rc;
     // largest front (dynamic LDS of the one-workgroup solve kernels) and pivot count (kernel
@@ -290,7 +303,8 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     }
     free_list(h->solve_allocs);
     destroy_graph(h);
-    h->gm_V = h->gm_T = h->gm_W = h->gm_dev = nullptr;
+    h->gm_V = h->gm_Z = h->gm_W = nullptr;
+    h->gm = DevGmres{};
     h->gm_cap = 0;
     DevSolve& S = h->S;
     const int64_t N = h->P.N;
@@ -350,14 +364,38 @@ void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delt
     }
     launch_inv(h->D, h->inv_tasks_dev, (int64_t)h->P.inv_tasks.size(), h->stream);
     launch_factor_stats(h->D, pp, h->stats_part, h->stream);
+    if (!pp.mixed) return;
+    // Mixed precision: the systems whose FP32 updates broke down are factorised again in FP64
+    // (the same launches, gated to those systems' supernodes).  Eager execution reads the count
+    // and skips the second pass when it is zero; a captured graph always holds it.
+    launch_mixed_check(h->D, h->max_sys_piv, h->stream);
+    if (!h->capturing) {
+        int32_t nredo = 0;
+        if (hipMemcpyAsync(&nredo, h->D.redo + h->P.nsys, sizeof(nredo), hipMemcpyDeviceToHost, h->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            nredo = 1;  // unknown: take the safe path
+        if (nredo == 0) return;
+    }
+    DevPlan G = h->D;
+    G.gate = h->D.redo;
+    const PivotParams p64 = pivot_params(h, QDMF_FP64);
+    for (const Launch& L : h->P.launches) {
+        ProfScope ps(h, L.kind, 0.0, 0.0);
+        launch_factor_step(G, L, h->tasks_dev, p64, h->stream);
+    }
+    launch_inv(G, h->inv_tasks_dev, (int64_t)h->P.inv_tasks.size(), h->stream);
+    launch_factor_stats(h->D, p64, h->stats_part, h->stream);
 }
 
 // (L D L^T)^{-1} src -> dst, level by level (forward leaves first, backward roots first).
-void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32_t* active) {
+// active: NULL, or per refinement unit (rhs x system; a batch gates the kernels by "some system
+// of the rhs still refines") when per_rhs is false, or already per rhs when it is true.
+void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32_t* active, bool per_rhs = false) {
     const Plan& P = h->P;
     const DevSolve& S = h->S;
     hipStream_t st = h->stream;
-    if (P.nsys > 1 && active) active = S.ract;  // flags are per system: any system of the rhs
+    if (P.nsys > 1 && active && !per_rhs) active = S.ract;
     launch_permute(h->D, S, src, active, st);
     // per level: the supernodes solved one per workgroup, then the steps of the big ones
     for (int32_t l = 0; l < P.nlevels; ++l) {
@@ -378,109 +416,91 @@ void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32
 }
 
 // ---- FP64 refinement with a Krylov correction (mixed precision)
-// Each correction d of K_static d = r is computed by GMRES on K_static M, right-preconditioned
-// by the mixed-precision factor M = (L D L^T)^{-1}, so that the FP64 residual ||r - K d||_2
-// itself is minimised (classical Gram-Schmidt applied twice, Givens rotations on the host),
-// instead of d = M r: the correction stays accurate when the FP32 Schur updates leave
-// ||I - K M|| above one, which plain refinement needs below one.
-constexpr int GM_M = 30;         // Krylov dimension of one correction
-constexpr double GM_TOL = 1e-10;  // reduction of the preconditioned residual norm
+// Each correction d of K_static d = r comes from GMRES on K_static M, right-preconditioned by
+// the mixed-precision factor M = (L D L^T)^{-1}, with the preconditioned vectors z_j = M v_j
+// kept (so d = Z y needs no further solve): it minimises the FP64 residual ||r - K d||_2 over the
+// Krylov space, and still converges when the FP32 updates leave ||I - K M|| above one, where
+// plain refinement d = M r diverges.  GM_M steps at most per correction (restarted by the
+// refinement loop), classical Gram-Schmidt applied twice; the Hessenberg reduction, the stop
+// flags and the small triangular solve run on the device.  Every step is enqueued when the
+// sequence is captured into a graph (its kernels return at once for converged right-hand
+// sides); eager solves read the device's flags before each further step and stop launching
+// once none is left, which skips only launches that would have done nothing (the results are
+// the same bit for bit).
+constexpr double GM_TOL = 1e-6;  // reduction of ||r - K d||_2 that ends a correction
 
 int ensure_gmres(qdmf_ctx* h) {
     const int32_t nr = h->S.nrhs;
     if (h->gm_V && h->gm_cap >= nr) return 0;
     const int64_t N = h->P.N;
     const int32_t cap = std::max(nr, h->solve_cap);
+    const int64_t nu = (int64_t)cap * h->P.nsys;  // refinement units
     int rc = 0;
+    DevGmres& G = h->gm;
     if ((rc = dalloc(h, h->solve_allocs, &h->gm_V, (int64_t)(GM_M + 1) * N * cap))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &h->gm_T, N * cap))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &h->gm_Z, (int64_t)GM_M * N * cap))) return rc;
     if ((rc = dalloc(h, h->solve_allocs, &h->gm_W, N * cap))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &h->gm_dev, (int64_t)(3 * GM_M + 4) * cap))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.h1, (GM_M + 1) * nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.h2, (GM_M + 1) * nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.nrm, nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.beta, nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.g, (GM_M + 1) * nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.cs, GM_M * nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.sn, GM_M * nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.R, (int64_t)GM_M * GM_M * nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.y, GM_M * nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.kr, nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.act, nu))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &G.ract, (int64_t)cap))) return rc;
+    if (h->gm_act_host) (void)hipHostFree(h->gm_act_host);
+    h->gm_act_host = nullptr;
+    if (hipHostMalloc((void**)&h->gm_act_host, sizeof(int32_t) * cap, hipHostMallocDefault) != hipSuccess) {
+        h->gm_act_host = nullptr;
+        return QDMF_ERR_OOM;
+    }
     h->gm_cap = cap;
     return 0;
 }
 
-// S.d = approximate solution of K_static d = S.r (all right-hand sides).
-int gmres_correction(qdmf_ctx* h) {
+// S.d = the Krylov correction of K_static d = S.r for every refinement unit that continues.
+// The work space must exist (ensure_gmres) before a capture starts: nothing is allocated here.
+int enqueue_gmres_correction(qdmf_ctx* h) {
     DevSolve& S = h->S;
-    const int32_t nr = S.nrhs;
+    const int32_t nr = S.nrhs, ns = h->P.nsys, nu = nr * ns;
     const int64_t N = h->P.N;
     hipStream_t st = h->stream;
-    int rc = ensure_gmres(h);
-    if (rc) return rc;
+    if (!h->gm_V || h->gm_cap < nr) return QDMF_ERR_INVALID_ARG;
+    const DevGmres& G = h->gm;
+    const DevPlan& D = h->D;
     auto Vb = [&](int j) { return h->gm_V + (int64_t)j * N * nr; };
-    double* hd1 = h->gm_dev;                       // (GM_M + 1) x nr
-    double* hd2 = hd1 + (int64_t)(GM_M + 1) * nr;  // (GM_M + 1) x nr
-    double* nrm = hd2 + (int64_t)(GM_M + 1) * nr;  // nr
-    double* yd = nrm + nr;                         // GM_M x nr
-    launch_dots(S.r, 1, S.r, nrm, N, nr, st);
-    std::vector<double> beta(nr), g((size_t)(GM_M + 1) * nr, 0.0), cs((size_t)GM_M * nr), sn((size_t)GM_M * nr);
-    std::vector<double> R((size_t)GM_M * GM_M * nr, 0.0);  // R[(i * GM_M + j) * nr + r], upper triangular
-    std::vector<double> h1((size_t)(GM_M + 1) * nr), h2((size_t)(GM_M + 1) * nr), nn(nr);
-    if (hipMemcpyAsync(nn.data(), nrm, sizeof(double) * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return QDMF_ERR_HIP;
-    for (int r = 0; r < nr; ++r) {
-        beta[r] = std::sqrt(nn[r]);
-        g[r] = beta[r];
-    }
-    launch_vscale(S.r, nrm, Vb(0), N, nr, st);
-    int k = 0;
+    auto Zb = [&](int j) { return h->gm_Z + (int64_t)j * N * nr; };
+    launch_dots(D, S.r, 1, S.r, G.nrm, nr, nullptr, st);
+    launch_gm_start(G, S.active, nu, st);  // per unit: the refinement continues and r != 0
+    launch_gm_gate(G, nr, ns, st);  // per rhs: some unit takes the first step
+    launch_vscale(D, S.r, G.nrm, Vb(0), nr, G.act, st);
     for (int j = 0; j < GM_M; ++j) {
-        enqueue_ldlt_solve(h, Vb(j), h->gm_T, nullptr);  // K M v_j
-        launch_matvec(h->D, h->gm_T, h->gm_W, nr, h->S.lsum, st);
-        launch_dots(h->gm_V, j + 1, h->gm_W, hd1, N, nr, st);
-        launch_vcombine(h->gm_V, j + 1, hd1, h->gm_W, N, nr, true, st);
-        launch_dots(h->gm_V, j + 1, h->gm_W, hd2, N, nr, st);
-        launch_vcombine(h->gm_V, j + 1, hd2, h->gm_W, N, nr, true, st);
-        launch_dots(h->gm_W, 1, h->gm_W, nrm, N, nr, st);
-        launch_vscale(h->gm_W, nrm, Vb(j + 1), N, nr, st);
-        if (hipMemcpyAsync(h1.data(), hd1, sizeof(double) * (j + 1) * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(h2.data(), hd2, sizeof(double) * (j + 1) * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(nn.data(), nrm, sizeof(double) * nr, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return QDMF_ERR_HIP;
-        k = j + 1;
-        bool all = true;
-        for (int r = 0; r < nr; ++r) {
-            std::vector<double> col(j + 2);
-            for (int i = 0; i <= j; ++i) col[i] = h1[(size_t)i * nr + r] + h2[(size_t)i * nr + r];
-            col[j + 1] = std::sqrt(nn[r]);
-            for (int i = 0; i < j; ++i) {  // earlier rotations
-                const double c = cs[(size_t)i * nr + r], s_ = sn[(size_t)i * nr + r];
-                const double a = c * col[i] + s_ * col[i + 1];
-                col[i + 1] = -s_ * col[i] + c * col[i + 1];
-                col[i] = a;
-            }
-            const double a = col[j], b = col[j + 1];
-            const double den = std::hypot(a, b);
-            const double c = den > 0 ? a / den : 1.0, s_ = den > 0 ? b / den : 0.0;
-            cs[(size_t)j * nr + r] = c;
-            sn[(size_t)j * nr + r] = s_;
-            col[j] = den;
-            for (int i = 0; i <= j; ++i) R[((size_t)i * GM_M + j) * nr + r] = col[i];
-            const double gj = g[(size_t)j * nr + r];
-            g[(size_t)j * nr + r] = c * gj;
-            g[(size_t)(j + 1) * nr + r] = -s_ * gj;
-            if (!(std::fabs(g[(size_t)(j + 1) * nr + r]) <= GM_TOL * beta[r])) all = false;
+        if (!h->capturing && j > 0) {
+            if (hipMemcpyAsync(h->gm_act_host, G.ract, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return QDMF_ERR_HIP;
+            bool any = false;
+            for (int r = 0; r < nr; ++r) any = any || h->gm_act_host[r] != 0;
+            if (!any) break;
         }
-        if (all) break;
+        enqueue_ldlt_solve(h, Vb(j), Zb(j), G.ract, true);  // z_j = M v_j
+        launch_matvec(D, Zb(j), h->gm_W, nr, S.lsum, G.ract, st);  // w = K z_j
+        launch_dots(D, h->gm_V, j + 1, h->gm_W, G.h1, nr, G.act, st);
+        launch_vcombine(D, h->gm_V, j + 1, G.h1, h->gm_W, nr, true, G.act, nullptr, st);
+        launch_dots(D, h->gm_V, j + 1, h->gm_W, G.h2, nr, G.act, st);
+        launch_vcombine(D, h->gm_V, j + 1, G.h2, h->gm_W, nr, true, G.act, nullptr, st);
+        launch_dots(D, h->gm_W, 1, h->gm_W, G.nrm, nr, G.act, st);
+        launch_vscale(D, h->gm_W, G.nrm, Vb(j + 1), nr, G.act, st);
+        launch_gm_rotate(G, j, nr, ns, GM_TOL, st);
     }
-    // y = R^{-1} g (back substitution; a zero pivot from a breakdown contributes nothing)
-    std::vector<double> y((size_t)GM_M * nr, 0.0);
-    for (int r = 0; r < nr; ++r)
-        for (int i = k - 1; i >= 0; --i) {
-            double v = g[(size_t)i * nr + r];
-            for (int jj = i + 1; jj < k; ++jj) v -= R[((size_t)i * GM_M + jj) * nr + r] * y[(size_t)jj * nr + r];
-            const double d = R[((size_t)i * GM_M + i) * nr + r];
-            y[(size_t)i * nr + r] = d != 0.0 ? v / d : 0.0;
-        }
-    if (hipMemcpyAsync(yd, y.data(), sizeof(double) * k * nr, hipMemcpyHostToDevice, st) != hipSuccess)
-        return QDMF_ERR_HIP;
-    launch_vcombine(h->gm_V, k, yd, h->gm_T, N, nr, false, st);
-    enqueue_ldlt_solve(h, h->gm_T, S.d, nullptr);  // d = M V y
-    // the host vector y must outlive the copy
-    return hipStreamSynchronize(st) == hipSuccess ? 0 : QDMF_ERR_HIP;
+    launch_gm_solve(G, nu, st);
+    launch_vcombine(D, h->gm_Z, GM_M, G.y, S.d, nr, false, nullptr, G.kr, st);  // d = Z y per unit
+    return 0;
 }
 
 void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, double* dy) {
@@ -490,6 +510,7 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
     const double target = mixed ? h->opt.target_berr_mixed : h->opt.target_berr;
     const int max_steps = mixed ? h->opt.max_refine_mixed : h->opt.max_refine;
     hipStream_t st = h->stream;
+    if (mixed && max_steps > 0 && !h->capturing && ensure_gmres(h)) return;  // no work space: no refinement
     launch_rhs(D, S, r7, r1, st);
     enqueue_ldlt_solve(h, S.b, S.x, nullptr);
     launch_residual(D, S, S.x, st);
@@ -509,8 +530,8 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
             if (!any) break;
         }
         launch_refine_begin(D, S, st);
-        if (mixed && !h->capturing) {
-            if (gmres_correction(h)) break;
+        if (mixed) {
+            if (enqueue_gmres_correction(h)) break;
         } else {
             enqueue_ldlt_solve(h, S.r, S.d, S.active);
         }
@@ -533,7 +554,7 @@ void qdmf_default_options(qdmf_options* o) {
     o->eps_lift = 2.220446049250313e-16;
     o->presort = 1;
     o->max_refine = 2;
-    o->max_refine_mixed = 10;
+    o->max_refine_mixed = 3;
     o->target_berr = 1e-12;
     o->target_berr_mixed = 1e-10;
     o->tau_big = 1e-8;
@@ -886,6 +907,10 @@ int qdmf_factor_stats(qdmf_handle h, qdmf_factor_info* out) {
     out->nzskip = st.nzskip;
     out->max_edyn = st.max_edyn;
     out->knorm = sc.knorm;
+    out->nredo_fp64 = 0;
+    if (h->last_prec == QDMF_MIXED &&
+        hipMemcpy(&out->nredo_fp64, h->D.redo + h->P.nsys, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return QDMF_ERR_HIP;
     int status = 0;
     if (st.bad_theta) status = QDMF_ERR_INVALID_ARG;
     else if (st.large_reg) status = QDMF_WARN_LARGE_REG;
@@ -1009,17 +1034,24 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     if (set_device(h)) return QDMF_ERR_HIP;
     int rc = ensure_solve(h, nrhs);
     if (rc) return rc;
+    // every buffer the captured work uses exists before the capture starts
+    if (prec == QDMF_MIXED && h->opt.max_refine_mixed > 0 && (rc = ensure_gmres(h))) return rc;
     destroy_graph(h);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return QDMF_ERR_HIP;
+    // the enqueue code reads the precision of the factorisation it follows; nothing has run
+    // yet, so the handle's own state is restored after the capture
+    const int32_t prec_before = h->last_prec;
     h->last_prec = prec;
     h->capturing = true;
     enqueue_factorise(h, theta_dev, rho, delta, nullptr, prec);
     for (int32_t q = 0; q < nsolves; ++q) enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
     h->capturing = false;
+    h->last_prec = prec_before;
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(h->stream, &g) != hipSuccess || !g) {
         (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
         return QDMF_ERR_HIP;
     }
     h->graph = g;
@@ -1028,16 +1060,22 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
         destroy_graph(h);
         return QDMF_ERR_HIP;
     }
-    h->factorised = true;
-    h->last_nrhs = nrhs;
-    h->solved = nsolves > 0;
+    h->graph_prec = prec;
+    h->graph_nrhs = nrhs;
+    h->graph_nsolves = nsolves;
     return 0;
 }
 
 int qdmf_graph_launch(qdmf_handle h) {
     if (!h || !h->gexec) return QDMF_ERR_INVALID_ARG;
     if (set_device(h)) return QDMF_ERR_HIP;
-    return hipGraphLaunch(h->gexec, h->stream) == hipSuccess ? 0 : QDMF_ERR_HIP;
+    if (hipGraphLaunch(h->gexec, h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    // the handle now holds the graph's factorisation and, with solves, their statistics
+    h->last_prec = h->graph_prec;
+    h->factorised = true;
+    h->last_nrhs = h->graph_nrhs;
+    h->solved = h->graph_nsolves > 0;
+    return 0;
 }
 
 int qdmf_profile_kind(qdmf_handle h, int32_t kind) {
@@ -1294,6 +1332,7 @@ void qdmf_destroy(qdmf_handle h) {
     }
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->act_host) (void)hipHostFree(h->act_host);
+    if (h->gm_act_host) (void)hipHostFree(h->gm_act_host);
     if (h->shift_host) (void)hipHostFree(h->shift_host);
     destroy_graph(h);
     free_list(h->solve_allocs);

@@ -115,6 +115,13 @@ struct DevPlan {
     const int64_t* sys_rng;      // per system: [a0, a1), [b0, b1) in original numbering
     const int64_t* sys_piv_ptr;  // per system: pivot positions
     const int32_t* sys_piv;
+    const int32_t* sn_sys;       // per supernode: its system
+    // Mixed precision: per system 1 if its factorisation is redone in FP64 (the FP32 Schur
+    // updates broke down), then the number of such systems (nsys + 1 entries).  The factor
+    // kernels launched with gate = redo skip the supernodes of the systems marked 0; gate is
+    // NULL otherwise.
+    int32_t* redo;
+    const int32_t* gate;
     double* knorm_sys;
     double* rho_sys;
     double* delta_sys;
@@ -132,6 +139,9 @@ void launch_factor_step(const DevPlan& D, const Launch& L, const Task* tasks_dev
 // part: factor_stats_blocks(N) x 10 doubles of device scratch
 int factor_stats_blocks(int64_t N);
 void launch_factor_stats(const DevPlan& D, const PivotParams& pp, double* part, hipStream_t s);
+// Marks in D.redo the systems whose mixed-precision factor broke down and counts them in
+// D.redo[nsys]; max_piv is the largest pivot count of one system.
+void launch_mixed_check(const DevPlan& D, int64_t max_piv, hipStream_t s);
 void launch_matrix_norms(const DevPlan& D, hipStream_t s);
 void launch_hessian_norms(const DevPlan& D, hipStream_t s);
 
@@ -214,11 +224,29 @@ void launch_recover(const DevPlan& D, const DevSolve& S, const double* r7, doubl
                     hipStream_t s);
 void launch_zero(double* p, int64_t n, hipStream_t s);
 
-// ---- Krylov refinement building blocks (N x nrhs blocks, original numbering)
-void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, double* lsum, hipStream_t s);
-void launch_dots(const double* V, int nv, const double* w, double* out, int64_t N, int nrhs, hipStream_t s);
-void launch_vcombine(const double* V, int nv, const double* h, double* w, int64_t N, int nrhs, bool subtract,
-                     hipStream_t s);
-void launch_vscale(const double* src, const double* nrm2, double* dst, int64_t N, int nrhs, hipStream_t s);
+// ---- Krylov refinement building blocks (N x nrhs blocks, original numbering; act: per rhs,
+// skip where 0, or NULL)
+// Krylov correction of mixed-precision refinement (device GMRES, right-preconditioned by the
+// factor), one Krylov process per refinement unit u = r * nsys + q (U = nrhs * nsys units):
+// h1, h2, nrm ((GM_M + 1) x U, unit fastest: the Gram-Schmidt coefficients of both passes and
+// squared norms), beta (U), g ((GM_M + 1) per unit), cs, sn (GM_M per unit), R (GM_M x GM_M per
+// unit), y (GM_M x U, unit fastest), kr and act (U), ract (nrhs: some unit of the rhs is active).
+constexpr int GM_M = 8;
+struct DevGmres {
+    double *h1, *h2, *nrm, *beta, *g, *cs, *sn, *R, *y;
+    int32_t *kr, *act, *ract;
+};
+void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, double* lsum, const int32_t* act,
+                   hipStream_t s);
+void launch_dots(const DevPlan& D, const double* V, int nv, const double* w, double* out, int nrhs,
+                 const int32_t* act, hipStream_t s);
+void launch_vcombine(const DevPlan& D, const double* V, int nv, const double* h, double* w, int nrhs, bool subtract,
+                     const int32_t* act, const int32_t* nvr, hipStream_t s);
+void launch_vscale(const DevPlan& D, const double* src, const double* nrm2, double* dst, int nrhs,
+                   const int32_t* act, hipStream_t s);
+void launch_gm_start(const DevGmres& G, const int32_t* gate, int nu, hipStream_t s);
+void launch_gm_rotate(const DevGmres& G, int j, int nrhs, int nsys, double tol, hipStream_t s);
+void launch_gm_gate(const DevGmres& G, int nrhs, int nsys, hipStream_t s);
+void launch_gm_solve(const DevGmres& G, int nu, hipStream_t s);
 
 }  // namespace qdmf

@@ -325,12 +325,16 @@ __device__ inline void store_pivots(const PivShared<FM>& S, const DevPlan& D, in
 
 // Small fronts (f <= FM <= 64): assembly of original entries and children's contribution blocks
 // straight into LDS, then the whole partial factorisation there.
+// A factor kernel launched for the FP64 redo of some systems skips the other systems' supernodes.
+__device__ inline bool gated_off(const DevPlan& D, int s) { return D.gate && !D.gate[D.sn_sys[s]]; }
+
 template <int FM>
 __global__ __launch_bounds__(64) void k_small(DevPlan D, const Task* tasks, int64_t t0, PivotParams pp) {
     __shared__ PivShared<FM> S;
     constexpr int LDW = PivShared<FM>::LDW;
     const int lane = threadIdx.x;
     const int s = tasks[t0 + blockIdx.x].s;
+    if (gated_off(D, s)) return;
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     double* F = D.front + D.sn_off[s];
     const int32_t* rows = D.rows + D.sn_rowptr[s];
@@ -392,6 +396,7 @@ __global__ __launch_bounds__(64) void k_small(DevPlan D, const Task* tasks, int6
 __global__ __launch_bounds__(256) void k_assemble(DevPlan D, const Task* tasks, int64_t t0) {
     extern __shared__ double buf[];
     const Task t = tasks[t0 + blockIdx.x];
+    if (gated_off(D, t.s)) return;
     const int s = t.s, j = t.k0;
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const int nr = f - j;
@@ -428,6 +433,7 @@ __global__ __launch_bounds__(256) void k_assemble_w(DevPlan D, const Task* tasks
     double* buf = wbuf + (int64_t)wv * maxf;
     const Task t = tasks[t0 + ti];
     const int s = t.s, j = t.k0;
+    if (gated_off(D, s)) return;  // one task per wave, no barriers below
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const int nr = f - j;
     for (int i = lane; i < nr; i += 64) buf[i] = 0.0;
@@ -617,6 +623,7 @@ __global__ __launch_bounds__(256) void k_window(DevPlan D, const Task* tasks, in
     const int tid = threadIdx.x, lane = tid & 63, cq = tid >> 6;
     const Task t = tasks[t0 + blockIdx.x];
     const int s = t.s, k0 = t.k0, chunk = t.a;
+    if (gated_off(D, s)) return;
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const int k1 = min(k0 + NB, p), nbw = k1 - k0;
     double* F = D.front + D.sn_off[s];
@@ -1049,6 +1056,7 @@ __device__ void syrk_tile(double* F, int ld, int f, int cmax, int k0, int nin, i
 // require.  Wave v handles columns 16v .. 16v+15, lane = row; each wave loads all of its
 // values before it stores any, so no barrier is needed.
 __device__ inline void finalize_task(const DevPlan& D, const Task t) {
+    if (gated_off(D, t.s)) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int s = t.s, kc = t.k0, w = t.a;
     const int p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
@@ -1099,6 +1107,7 @@ __global__ __launch_bounds__(256, 3) void k_syrk(DevPlan D, const Task* tasks, i
     __shared__ int pt[NB * SYRK_GROUP_MAX];
     const Task t = tasks[t0 + blockIdx.x];
     const int s = t.s, k0 = t.k0 & SYRK_K0_MASK, cnt = ((t.k0 >> SYRK_COUNT_SHIFT) & 7) + 1;
+    if (gated_off(D, s)) return;
     const int f = D.sn_f[s], p = D.sn_p[s], c0 = D.sn_ptr[s], ld = D.sn_ld[s];
     const int k1 = min(k0 + NB * cnt, p), nin = k1 - k0;
     // a narrow update stops at the end of the next window's columns
@@ -1309,6 +1318,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk128(DevPlan D, const Task* tasks
     __shared__ double Bs[2 * 128 * (S128_CW64 + 1)];
     __shared__ double dd[NB * SYRK_GROUP_MAX], od[NB * SYRK_GROUP_MAX];
     __shared__ int pt[NB * SYRK_GROUP_MAX];
+    if (gated_off(D, tasks[t0 + blockIdx.x].s)) return;
     syrk128_tile<double, S128_CW64>(D, tasks[t0 + blockIdx.x], As, Bs, dd, od, pt);
 }
 
@@ -1318,6 +1328,7 @@ __global__ __launch_bounds__(256, 1) void k_syrk128f(DevPlan D, const Task* task
     __shared__ float Bs[2 * 128 * (S128_CW32 + 1)];
     __shared__ double dd[NB * SYRK_GROUP_MAX], od[NB * SYRK_GROUP_MAX];
     __shared__ int pt[NB * SYRK_GROUP_MAX];
+    if (gated_off(D, tasks[t0 + blockIdx.x].s)) return;
     syrk128_tile<float, S128_CW32>(D, tasks[t0 + blockIdx.x], As, Bs, dd, od, pt);
 }
 
@@ -1570,7 +1581,48 @@ __global__ __launch_bounds__(256) void k_sys_inertia(DevPlan D) {
     if (threadIdx.x < 3) D.inertia_sys[3 * q + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Mixed precision: marks the systems whose factor broke down, i.e. that hold a pivot that is
+// not finite or one that took Proposition 3 or the sign rule.  An exact quasi-definite matrix
+// needs neither rule, so on such a system the FP32 rounding of the Schur updates has changed a
+// pivot's sign (the cancellation in the updates exceeds FP32's precision).  Block (c, q)
+// scans chunk c of system q's pivot positions; redo is zero when the launch starts.
+constexpr int MC_CHUNK = 4096;
+
+__global__ __launch_bounds__(256) void k_mixed_check(DevPlan D) {
+    const int q = blockIdx.y;
+    const int64_t a = D.sys_piv_ptr[q] + (int64_t)blockIdx.x * MC_CHUNK;
+    const int64_t b = min(D.sys_piv_ptr[q + 1], a + MC_CHUNK);
+    int bad = 0;
+    for (int64_t t = a + threadIdx.x; t < b; t += 256) {
+        const int k = D.sys_piv[t];
+        bad |= !isfinite(D.dval[k]) || !isfinite(D.doff[k]) || (D.pflag[k] & (PF_PROP3 | PF_SIGN)) != 0;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(D.redo + q, 1);
+}
+
+__global__ __launch_bounds__(256) void k_mixed_count(DevPlan D) {
+    __shared__ int red[256];
+    int c = 0;
+    for (int q = threadIdx.x; q < D.nsys; q += 256) c += D.redo[q];
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) D.redo[D.nsys] = red[0];
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // ---------------------------------------------------------------- solve kernels
+
+// Maximum that keeps a NaN: a residual or solution that is not finite must not report a small
+// backward error.
+__device__ inline double nmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
 __global__ void k_zero(double* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2367,6 +2419,7 @@ __global__ __launch_bounds__(64) void k_inv(DevPlan D, const Task* tasks) {
     __shared__ double Ls[64 * 65];  // Ls[k * 65 + j] = L(k, j), strictly lower, zero elsewhere
     const Task t = tasks[blockIdx.x];
     const int s = t.s, k0 = 64 * t.k0, lane = threadIdx.x;
+    if (gated_off(D, s)) return;
     const int p = D.sn_p[s], ld = D.sn_ld[s];
     const int nb = min(64, p - k0);
     const double* F = D.front + D.sn_off[s] + k0 + (int64_t)k0 * ld;
@@ -2522,9 +2575,11 @@ __global__ __launch_bounds__(256) void k_bwd_wave(DevPlan D, DevSolve S, const i
 // column, right-hand side): sum_i A_ij x_{n+i} and sum_i |A_ij||x_{n+i}|, each thread over a
 // fixed stride of the column, then a fixed-order tree (bitwise reproducible).  One thread per
 // primal row would take the whole column serially.
-__global__ __launch_bounds__(256) void k_long_cols(DevPlan D, const double* xin, double* lsum) {
+__global__ __launch_bounds__(256) void k_long_cols(DevPlan D, const double* xin, double* lsum,
+                                                   const int32_t* act) {
     __shared__ double red[2][256];
     const int q = blockIdx.x, r = blockIdx.y;
+    if (act && !act[r]) return;
     const int j = D.long_col[q];
     const double* x = xin + (int64_t)r * D.N + D.n;
     double s = 0.0, sa = 0.0;
@@ -2657,7 +2712,7 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan D, DevSolve S, const d
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w)
-            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = nmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
         __syncthreads();
     }
     if (threadIdx.x < 3) S.part[(int64_t)r * 3 * S.nblk + threadIdx.x * S.nblk + blockIdx.x] = red[threadIdx.x][0];
@@ -2706,9 +2761,9 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
     for (int part = 0; part < 2; ++part)
 #pragma unroll 8
         for (int64_t i = rg[2 * part] + threadIdx.x; i < rg[2 * part + 1]; i += 1024) {
-            mr = fmax(mr, fabs(rr[i]));
-            mx = fmax(mx, fabs(x[i]));
-            mb = fmax(mb, fabs(b[i]));
+            mr = nmax(mr, fabs(rr[i]));
+            mx = nmax(mx, fabs(x[i]));
+            mb = nmax(mb, fabs(b[i]));
         }
     red[0][threadIdx.x] = mr;
     red[1][threadIdx.x] = mx;
@@ -2716,7 +2771,7 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
         if (threadIdx.x < w)
-            for (int v = 0; v < 3; ++v) red[v][threadIdx.x] = fmax(red[v][threadIdx.x], red[v][threadIdx.x + w]);
+            for (int v = 0; v < 3; ++v) red[v][threadIdx.x] = nmax(red[v][threadIdx.x], red[v][threadIdx.x + w]);
         __syncthreads();
     }
     const double rmax = red[0][0], xmax = red[1][0], bmax = red[2][0];
@@ -2728,13 +2783,13 @@ __global__ __launch_bounds__(1024) void k_berr(DevPlan D, DevSolve S, int phase,
             double den = akx[i] + fabs(b[i]);
             if (den <= 1000.0 * D.N * u64 * (D.rowsum[i] * xmax + fabs(b[i]))) den = akx[i] + xmax * D.rowsum[i];
             const double c = den > 0 ? fabs(rr[i]) / den : (rr[i] == 0 ? 0.0 : INFINITY);
-            cm = fmax(cm, c);
+            cm = nmax(cm, c);
         }
     __syncthreads();
     red[3][threadIdx.x] = cm;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + w]);
+        if (threadIdx.x < w) red[3][threadIdx.x] = nmax(red[3][threadIdx.x], red[3][threadIdx.x + w]);
         __syncthreads();
     }
     const double cw = red[3][0];
@@ -2758,7 +2813,7 @@ __device__ inline double block_max256(double v, double* red) {
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        if (threadIdx.x < w) red[threadIdx.x] = nmax(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
     const double m = red[0];
@@ -2772,7 +2827,7 @@ __global__ __launch_bounds__(256) void k_berr_cw(DevPlan D, DevSolve S, int phas
     if (phase == 1 && !S.active[r]) return;
     const double* px = S.part + (int64_t)r * 3 * S.nblk + S.nblk;  // per-block max |x|
     double m = 0.0;
-    for (int j = threadIdx.x; j < S.nblk; j += 256) m = fmax(m, px[j]);
+    for (int j = threadIdx.x; j < S.nblk; j += 256) m = nmax(m, px[j]);
     const double xmax = block_max256(m, red);
     const double u64 = 1.1102230246251565e-16;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -2797,10 +2852,10 @@ __global__ __launch_bounds__(256) void k_berr_fin(DevPlan D, DevSolve S, int pha
     const double* pc = S.part + (int64_t)3 * S.nblk * S.nrhs + (int64_t)r * S.nblk;
     double mr = 0.0, mx = 0.0, mb = 0.0, mc = 0.0;
     for (int j = threadIdx.x; j < S.nblk; j += 256) {
-        mr = fmax(mr, pr[j]);
-        mx = fmax(mx, pr[S.nblk + j]);
-        mb = fmax(mb, pr[2 * S.nblk + j]);
-        mc = fmax(mc, pc[j]);
+        mr = nmax(mr, pr[j]);
+        mx = nmax(mx, pr[S.nblk + j]);
+        mb = nmax(mb, pr[2 * S.nblk + j]);
+        mc = nmax(mc, pc[j]);
     }
     const double rmax = block_max256(mr, red), xmax = block_max256(mx, red);
     const double bmax = block_max256(mb, red), cw = block_max256(mc, red);
@@ -2821,10 +2876,10 @@ __global__ __launch_bounds__(256) void k_berr_fin(DevPlan D, DevSolve S, int pha
 
 // out = K_static v, from A, Theta, rho, delta (AS) or from the K values (NE).
 __global__ __launch_bounds__(256) void k_matvec(DevPlan D, const double* vin, double* out, int nrhs,
-                                                const double* lsum) {
+                                                const double* lsum, const int32_t* act) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= D.N || r >= nrhs) return;
+    if (i >= D.N || r >= nrhs || (act && !act[r])) return;
     const double* v = vin + (int64_t)r * D.N;
     const int sys = D.sys_old[i];
     const double rho = D.rho_sys[sys], delta = D.delta_sys[sys];
@@ -2859,42 +2914,62 @@ __global__ __launch_bounds__(256) void k_matvec(DevPlan D, const double* vin, do
 }
 
 // out[j * nrhs + r] = <V_j(:, r), w(:, r)> for j < nv.
-__global__ __launch_bounds__(256) void k_dots(const double* V, int nv, const double* w, double* out, int64_t N,
-                                              int nrhs) {
+// Krylov vectors are N x nrhs blocks (original numbering); the refinement unit u = r * nsys + q
+// is right-hand side r of system q, whose entries are the index ranges [a0, a1) and [b0, b1)
+// of sys_rng.  Per unit, dots: out[j * U + u] = V_j(:, r) . w(:, r) over the unit's entries
+// (U = nrhs * nsys), fixed-order tree; units with act[u] == 0 are skipped (act may be NULL).
+__global__ __launch_bounds__(256) void k_dots(DevPlan D, const double* V, int nv, const double* w, double* out,
+                                              int nrhs, const int32_t* act) {
     __shared__ double red[256];
-    const int j = blockIdx.x, r = blockIdx.y;
+    const int j = blockIdx.x, u = blockIdx.y;
+    if (act && !act[u]) return;
+    const int r = u / D.nsys, q = u % D.nsys;
+    const int64_t N = D.N;
     const double* a = V + ((int64_t)j * nrhs + r) * N;
     const double* b = w + (int64_t)r * N;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += 256) acc += a[i] * b[i];
+    for (int h = 0; h < 2; ++h) {
+        const int64_t i0 = D.sys_rng[4 * q + 2 * h], i1 = D.sys_rng[4 * q + 2 * h + 1];
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) acc += a[i] * b[i];
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[j * nrhs + r] = red[0];
+    if (threadIdx.x == 0) out[(int64_t)j * nrhs * D.nsys + u] = red[0];
 }
 
-// w(:, r) -= sum_{j < nv} h[j * nrhs + r] V_j(:, r)   (sign = -1), or
-// w(:, r)  = sum_{j < nv} h[j * nrhs + r] V_j(:, r)   (sign = 0).
-__global__ void k_vcombine(const double* V, int nv, const double* h, double* w, int64_t N, int nrhs, int sign) {
+// w(:, r) -= sum_{j < nv} h[j * U + u] V_j(:, r)   (sign = 1), or
+// w(:, r)  = sum_{j < nv} h[j * U + u] V_j(:, r)   (sign = 0), entry i taking the unit u of its
+// own system; units with act[u] == 0 are left alone (act may be NULL), and nvr (may be NULL)
+// caps nv per unit.
+__global__ void k_vcombine(DevPlan D, const double* V, int nv, const double* h, double* w, int nrhs, int sign,
+                           const int32_t* act, const int32_t* nvr) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= N) return;
+    if (i >= D.N) return;
+    const int u = r * D.nsys + D.sys_old[i];
+    if (act && !act[u]) return;
+    const int64_t U = (int64_t)nrhs * D.nsys;
+    const int nj = nvr ? min(nv, nvr[u]) : nv;
     double acc = 0.0;
-    for (int j = 0; j < nv; ++j) acc += h[j * nrhs + r] * V[((int64_t)j * nrhs + r) * N + i];
-    double* wi = w + (int64_t)r * N + i;
+    for (int j = 0; j < nj; ++j) acc += h[j * U + u] * V[((int64_t)j * nrhs + r) * D.N + i];
+    double* wi = w + (int64_t)r * D.N + i;
     *wi = sign ? *wi - acc : acc;
 }
 
-// dst(:, r) = src(:, r) / sqrt(nrm2[r])  (0 where the norm is 0).
-__global__ void k_vscale(const double* src, const double* nrm2, double* dst, int64_t N, int nrhs) {
+// dst(:, r) = src(:, r) / sqrt(nrm2[u]) per unit (0 where the norm is 0 or not finite).
+__global__ void k_vscale(DevPlan D, const double* src, const double* nrm2, double* dst, int nrhs,
+                         const int32_t* act) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= N) return;
-    const double nn = sqrt(nrm2[r]);
-    dst[(int64_t)r * N + i] = nn > 0.0 ? src[(int64_t)r * N + i] / nn : 0.0;
+    if (i >= D.N) return;
+    const int u = r * D.nsys + D.sys_old[i];
+    if (act && !act[u]) return;
+    const double nn = sqrt(nrm2[u]);
+    dst[(int64_t)r * D.N + i] = (nn > 0.0 && nn < INFINITY) ? src[(int64_t)r * D.N + i] / nn : 0.0;
 }
 
 // Per rhs: whether any system still refines (the solve kernels' gate in a batch).
@@ -2935,6 +3010,87 @@ __global__ void k_recover(DevPlan D, DevSolve S, const double* r7, double* dx, d
             for (int64_t e = D.acp[t]; e < D.acp[t + 1]; ++e) s += D.aval[e] * x[D.ari[e]];
             dx[t + (int64_t)r * D.n] = D.dinv[t] * (s - (r7 ? r7[t + (int64_t)r * D.n] : 0.0));
         }
+    }
+}
+
+// GMRES on K_static M (right preconditioning by the factor, M = (L D L^T)^{-1}) for the
+// correction of one refinement step, one Krylov process per refinement unit u (right-hand
+// side x system: the systems of a batch are independent, so each gets its own coefficients),
+// the Hessenberg matrix reduced by Givens rotations as the Arnoldi process goes, all on the
+// device with one thread per unit.  State per unit (strides GM_M + 1 or GM_M): beta =
+// ||r_u||_2, the rotated right-hand side g, the rotations (c, s), the triangular factor R
+// (GM_M x GM_M, column j written at step j), the number of Krylov vectors taken kr, and act = 1
+// while the unit takes more steps; ract per rhs: some unit of it does.
+__global__ void k_gm_start(DevGmres G, const int32_t* gate, int nu) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nu) return;
+    const double beta = sqrt(G.nrm[u]);
+    const int on = gate[u] && beta > 0.0 && beta < INFINITY;
+    G.act[u] = on;
+    G.kr[u] = 0;
+    G.beta[u] = beta;
+    for (int i = 0; i <= GM_M; ++i) G.g[u * (GM_M + 1) + i] = i == 0 ? beta : 0.0;
+}
+
+// Step j: the new Hessenberg column h (both Gram-Schmidt passes' coefficients summed, and
+// ||w||_2 below), the earlier rotations applied to it, a new rotation that zeroes h[j + 1],
+// and the estimate |g[j + 1]| of the residual norm; the unit stops at tol * beta, at a
+// breakdown (h[j + 1] = 0: the Krylov space holds the solution) or on a non-finite value.
+__global__ void k_gm_rotate(DevGmres G, int j, int nu, double tol) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nu || !G.act[u]) return;
+    double col[GM_M + 1];
+    for (int i = 0; i <= j; ++i) col[i] = G.h1[(int64_t)i * nu + u] + G.h2[(int64_t)i * nu + u];
+    col[j + 1] = sqrt(G.nrm[u]);
+    double* cs = G.cs + (int64_t)u * GM_M;
+    double* sn = G.sn + (int64_t)u * GM_M;
+    for (int i = 0; i < j; ++i) {
+        const double a = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = a;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = hypot(a, b);
+    const double c = den > 0.0 ? a / den : 1.0, sg = den > 0.0 ? b / den : 0.0;
+    cs[j] = c;
+    sn[j] = sg;
+    col[j] = den;
+    for (int i = 0; i <= j; ++i) G.R[((int64_t)u * GM_M + j) * GM_M + i] = col[i];
+    double* g = G.g + (int64_t)u * (GM_M + 1);
+    const double gj = g[j];
+    g[j] = c * gj;
+    g[j + 1] = -sg * gj;
+    const bool finite = den < INFINITY && fabs(g[j + 1]) < INFINITY;
+    G.kr[u] = finite ? j + 1 : j;  // a non-finite step is not used
+    if (!finite || fabs(g[j + 1]) <= tol * G.beta[u] || b == 0.0) G.act[u] = 0;
+}
+
+// Per rhs: whether some unit of it takes more Krylov steps (the gate of the solve kernels).
+__global__ void k_gm_any(DevGmres G, int nsys) {
+    const int r = blockIdx.x;
+    int any = 0;
+    for (int q = threadIdx.x; q < nsys; q += blockDim.x) any |= G.act[r * nsys + q];
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) G.ract[r] = any;
+}
+
+// y = R^{-1} g over the kr Krylov vectors taken (back substitution; a zero pivot from a
+// breakdown contributes nothing), zero beyond; y[i * U + u] as the combination expects.
+__global__ void k_gm_solve(DevGmres G, int nu) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nu) return;
+    const int k = G.kr[u];
+    double y[GM_M];
+    for (int i = GM_M - 1; i >= 0; --i) {
+        double v = 0.0;
+        if (i < k) {
+            v = G.g[(int64_t)u * (GM_M + 1) + i];
+            for (int jj = i + 1; jj < k; ++jj) v -= G.R[((int64_t)u * GM_M + jj) * GM_M + i] * y[jj];
+            const double d = G.R[((int64_t)u * GM_M + i) * GM_M + i];
+            v = d != 0.0 ? v / d : 0.0;
+        }
+        y[i] = v;
+        G.y[(int64_t)i * nu + u] = v;
     }
 }
 
@@ -3019,25 +3175,56 @@ void launch_factor_stats(const DevPlan& D, const PivotParams& pp, double* part, 
     if (D.nsys > 1) hipLaunchKernelGGL(k_sys_inertia, dim3(D.nsys), dim3(256), 0, s, D);
 }
 
-void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, double* lsum, hipStream_t s) {
+void launch_mixed_check(const DevPlan& D, int64_t max_piv, hipStream_t s) {
+    const int64_t n = (int64_t)D.nsys + 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D.redo, n, 0);
+    if (max_piv > 0)
+        hipLaunchKernelGGL(k_mixed_check, dim3((unsigned)((max_piv + MC_CHUNK - 1) / MC_CHUNK), (unsigned)D.nsys),
+                           dim3(256), 0, s, D);
+    hipLaunchKernelGGL(k_mixed_count, dim3(1), dim3(256), 0, s, D);
+}
+
+void launch_matvec(const DevPlan& D, const double* v, double* out, int nrhs, double* lsum, const int32_t* act,
+                   hipStream_t s) {
     if (D.mode == 1 && D.nlong > 0)
-        hipLaunchKernelGGL(k_long_cols, dim3(D.nlong, nrhs), dim3(256), 0, s, D, v, lsum);
+        hipLaunchKernelGGL(k_long_cols, dim3(D.nlong, nrhs), dim3(256), 0, s, D, v, lsum, act);
     hipLaunchKernelGGL(k_matvec, dim3(nblocks(D.N, 256), nrhs), dim3(256), 0, s, D, v, out, nrhs,
-                       (const double*)lsum);
+                       (const double*)lsum, act);
 }
 
-void launch_dots(const double* V, int nv, const double* w, double* out, int64_t N, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_dots, dim3(nv, nrhs), dim3(256), 0, s, V, nv, w, out, N, nrhs);
+void launch_dots(const DevPlan& D, const double* V, int nv, const double* w, double* out, int nrhs,
+                 const int32_t* act, hipStream_t s) {
+    hipLaunchKernelGGL(k_dots, dim3(nv, nrhs * D.nsys), dim3(256), 0, s, D, V, nv, w, out, nrhs, act);
 }
 
-void launch_vcombine(const double* V, int nv, const double* h, double* w, int64_t N, int nrhs, bool subtract,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_vcombine, dim3(nblocks(N, 256), nrhs), dim3(256), 0, s, V, nv, h, w, N, nrhs,
-                       subtract ? 1 : 0);
+void launch_vcombine(const DevPlan& D, const double* V, int nv, const double* h, double* w, int nrhs, bool subtract,
+                     const int32_t* act, const int32_t* nvr, hipStream_t s) {
+    hipLaunchKernelGGL(k_vcombine, dim3(nblocks(D.N, 256), nrhs), dim3(256), 0, s, D, V, nv, h, w, nrhs,
+                       subtract ? 1 : 0, act, nvr);
 }
 
-void launch_vscale(const double* src, const double* nrm2, double* dst, int64_t N, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_vscale, dim3(nblocks(N, 256), nrhs), dim3(256), 0, s, src, nrm2, dst, N, nrhs);
+void launch_vscale(const DevPlan& D, const double* src, const double* nrm2, double* dst, int nrhs,
+                   const int32_t* act, hipStream_t s) {
+    hipLaunchKernelGGL(k_vscale, dim3(nblocks(D.N, 256), nrhs), dim3(256), 0, s, D, src, nrm2, dst, nrhs, act);
+}
+
+// ---- the Krylov correction's small dense part, one thread per refinement unit
+void launch_gm_start(const DevGmres& G, const int32_t* gate, int nu, hipStream_t s) {
+    hipLaunchKernelGGL(k_gm_start, dim3(nblocks(nu, 256)), dim3(256), 0, s, G, gate, nu);
+}
+
+void launch_gm_rotate(const DevGmres& G, int j, int nrhs, int nsys, double tol, hipStream_t s) {
+    const int nu = nrhs * nsys;
+    hipLaunchKernelGGL(k_gm_rotate, dim3(nblocks(nu, 256)), dim3(256), 0, s, G, j, nu, tol);
+    hipLaunchKernelGGL(k_gm_any, dim3(nrhs), dim3(256), 0, s, G, nsys);
+}
+
+void launch_gm_gate(const DevGmres& G, int nrhs, int nsys, hipStream_t s) {
+    hipLaunchKernelGGL(k_gm_any, dim3(nrhs), dim3(256), 0, s, G, nsys);
+}
+
+void launch_gm_solve(const DevGmres& G, int nu, hipStream_t s) {
+    hipLaunchKernelGGL(k_gm_solve, dim3(nblocks(nu, 256)), dim3(256), 0, s, G, nu);
 }
 
 void launch_zero(double* p, int64_t n, hipStream_t s) {
@@ -3118,7 +3305,7 @@ void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L,
 
 void launch_residual(const DevPlan& D, const DevSolve& S, const double* x, hipStream_t s) {
     if (D.mode == 1 && D.nlong > 0)
-        hipLaunchKernelGGL(k_long_cols, dim3(D.nlong, S.nrhs), dim3(256), 0, s, D, x, S.lsum);
+        hipLaunchKernelGGL(k_long_cols, dim3(D.nlong, S.nrhs), dim3(256), 0, s, D, x, S.lsum, (const int32_t*)nullptr);
     hipLaunchKernelGGL(k_residual, dim3(S.nblk, S.nrhs), dim3(256), 0, s, D, S, x);
 }
 

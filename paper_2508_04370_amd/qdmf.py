@@ -86,7 +86,7 @@ class qdmf_factor_info(C.Structure):
     _fields_ = [("nneg", C.c_int64), ("npos", C.c_int64), ("nzero", C.c_int64),
                 ("n2x2", C.c_int64), ("nlift", C.c_int64), ("nprop3", C.c_int64),
                 ("nsign", C.c_int64), ("nzskip", C.c_int64), ("max_edyn", C.c_double),
-                ("knorm", C.c_double), ("status", C.c_int32)]
+                ("knorm", C.c_double), ("status", C.c_int32), ("nredo_fp64", C.c_int32)]
 
 
 class qdmf_solve_info(C.Structure):
