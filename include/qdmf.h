@@ -34,6 +34,7 @@ typedef struct qdmf_ctx* qdmf_handle;
 
 enum { QDMF_NE = 0, QDMF_AS = 1 };              /* system form (Section 3)           */
 enum { QDMF_FP64 = 0, QDMF_MIXED = 1 };         /* precision of the Schur updates    */
+#define QDMF_NOALLOC_SCRATCH_BYTES 67108864      /* qdmf_solve_noalloc work space per GPU (64 MiB) */
 enum { QDMF_ORDER_AMD = 0, QDMF_ORDER_USER = 1, QDMF_ORDER_GRID_ND = 2, QDMF_ORDER_ND = 3, QDMF_ORDER_AUTO = 4 };
 /* kernel kinds for qdmf_profile_kind */
 enum {
@@ -204,7 +205,7 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
  * (Section 4.5).  All vectors are device memory, column-major: r7 and dx n x nrhs, r1 and
  * dy m x nrhs; r7 may be NULL (zero).  Outputs must not alias inputs.  A correction of
  * the FP64 path is d = (L D L^T)^{-1} r; of the mixed path, GMRES on K_static (L D L^T)^{-1}
- * with at most 3 Krylov steps, its small dense part and stop flags on the device.  Between
+ * with at most 8 Krylov steps, its small dense part and stop flags on the device.  Between
  * refinement steps (and between Krylov steps) the call waits for the stream to read the
  * device's stop flags and launches no further step once every right-hand side is done;
  * under graph capture (qdmf_graph_capture) it waits for nothing and enqueues every step,
@@ -213,6 +214,22 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
  * Errors: QDMF_ERR_NOT_FACTORISED, QDMF_ERR_INVALID_ARG. */
 int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev,
                double* dx_dev, double* dy_dev);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): qdmf_solve with the same arguments, result and
+ * statistics, whose work space (QDMF_NOALLOC_SCRATCH_BYTES of device memory per GPU, a
+ * fixed array that each GPU the library runs on holds until the process ends) is not
+ * allocated: it calls no hipMalloc, hipFree or allocating library routine and never reads
+ * the device's flags from the host (it enqueues every refinement step, as under graph
+ * capture).  The factorisation must exist (qdmf_factorise: the handle's own memory).  Every
+ * call on one GPU shares that GPU's array and leaves the last call's contents in it, so calls
+ * that overlap on one GPU (other streams, other threads, other handles) race; calls ordered
+ * on one stream do not.  Errors: as qdmf_solve; QDMF_ERR_OOM (nothing launched) when the
+ * work space of nrhs right-hand sides (the solve vectors and, after a mixed factorisation,
+ * the Krylov basis) exceeds QDMF_NOALLOC_SCRATCH_BYTES; QDMF_ERR_HIP when the array's
+ * address could not be found on this device. */
+int qdmf_solve_noalloc(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev,
+                       double* dx_dev, double* dy_dev);
 
 /* ---- batches of independent systems ---------------------------------------------------
  * A batch of count independent LPs of one mode is analysed as one block-diagonal pattern:

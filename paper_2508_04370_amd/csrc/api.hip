@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,10 @@ struct qdmf_ctx {
     std::vector<int64_t> batch_col_off, batch_row_off;  // system offsets of a batch
     int32_t last_nrhs = 0;
     bool solved = false;
+    // refinement state of the last solve (the handle's work space or qdmf_solve_noalloc's)
+    const double* stat_berr = nullptr;
+    const int32_t* stat_steps = nullptr;
+    bool nopoll = false;  // qdmf_solve_noalloc: enqueue as for a graph (no host reads)
 
     // graph
     hipGraph_t graph = nullptr;
@@ -296,6 +301,65 @@ int upload_plan(qdmf_ctx* h) {
     return 0;
 }
 
+// Device work space of the solves.  One layout serves the allocated work space of qdmf_solve
+// and the fixed array of qdmf_solve_noalloc: a first pass with base == nullptr sizes it, a
+// second assigns the arrays (each on a 256-byte boundary).
+struct Carve {
+    char* base = nullptr;
+    int64_t off = 0;
+    template <class T>
+    T* take(int64_t n) {
+        off = (off + 255) & ~(int64_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += (int64_t)sizeof(T) * std::max<int64_t>(n, 1);
+        return p;
+    }
+};
+
+void layout_solve(const qdmf_ctx* h, int32_t nrhs, Carve& c, DevSolve& S) {
+    const int64_t N = h->P.N;
+    S.nrhs = nrhs;
+    S.nblk = (int32_t)((N + 255) / 256);
+    S.b = c.take<double>(N * nrhs);
+    S.x = c.take<double>(N * nrhs);
+    S.xbak = c.take<double>(N * nrhs);
+    S.r = c.take<double>(N * nrhs);
+    S.d = c.take<double>(N * nrhs);
+    S.xw = c.take<double>(N * nrhs);
+    S.ub = c.take<double>(std::max<int64_t>(1, h->P.ub_total) * nrhs);
+    S.part = c.take<double>((int64_t)4 * S.nblk * nrhs);
+    const int64_t units = (int64_t)nrhs * h->P.nsys;
+    S.berr = c.take<double>(4 * units);
+    S.active = c.take<int32_t>(units);
+    S.steps = c.take<int32_t>(units);
+    S.ract = c.take<int32_t>(nrhs);
+    S.ytot = h->P.ytotal;
+    S.Y = c.take<double>(std::max<int64_t>(1, h->P.ytotal) * nrhs);
+    S.P = c.take<double>(std::max<int64_t>(1, h->P.ppart_max) * SOLVE_BLOCK * nrhs);
+    S.lsum = c.take<double>(std::max<int64_t>(1, (int64_t)h->P.long_col.size()) * 2 * nrhs);
+}
+
+// Krylov work space for cap right-hand sides (mixed-precision refinement).
+void layout_gmres(const qdmf_ctx* h, int32_t cap, Carve& c, double*& V, double*& Z, double*& W, DevGmres& G) {
+    const int64_t N = h->P.N;
+    const int64_t nu = (int64_t)cap * h->P.nsys;  // refinement units
+    V = c.take<double>((int64_t)(GM_M + 1) * N * cap);
+    Z = c.take<double>((int64_t)GM_M * N * cap);
+    W = c.take<double>(N * cap);
+    G.h1 = c.take<double>((GM_M + 1) * nu);
+    G.h2 = c.take<double>((GM_M + 1) * nu);
+    G.nrm = c.take<double>(nu);
+    G.beta = c.take<double>(nu);
+    G.g = c.take<double>((GM_M + 1) * nu);
+    G.cs = c.take<double>(GM_M * nu);
+    G.sn = c.take<double>(GM_M * nu);
+    G.R = c.take<double>((int64_t)GM_M * GM_M * nu);
+    G.y = c.take<double>(GM_M * nu);
+    G.kr = c.take<int32_t>(nu);
+    G.act = c.take<int32_t>(nu);
+    G.ract = c.take<int32_t>(cap);
+}
+
 int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     if (nrhs <= h->solve_cap) {
         h->S.nrhs = nrhs;
@@ -307,28 +371,13 @@ int ensure_solve(qdmf_ctx* h, int32_t nrhs) {
     h->gm = DevGmres{};
     h->gm_cap = 0;
     DevSolve& S = h->S;
-    const int64_t N = h->P.N;
-    S.nblk = (int32_t)((N + 255) / 256);
+    Carve c;
+    layout_solve(h, nrhs, c, S);
     int rc = 0;
-    if ((rc = dalloc(h, h->solve_allocs, &S.b, N * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.x, N * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.xbak, N * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.r, N * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.d, N * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.xw, N * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.ub, std::max<int64_t>(1, h->P.ub_total) * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.part, (int64_t)4 * S.nblk * nrhs))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &c.base, c.off))) return rc;
+    c.off = 0;
+    layout_solve(h, nrhs, c, S);
     const int64_t units = (int64_t)nrhs * h->P.nsys;
-    if ((rc = dalloc(h, h->solve_allocs, &S.berr, 4 * units))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.active, units))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.steps, units))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.ract, nrhs))) return rc;
-    S.ytot = h->P.ytotal;
-    if ((rc = dalloc(h, h->solve_allocs, &S.Y, std::max<int64_t>(1, h->P.ytotal) * nrhs))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.P, std::max<int64_t>(1, h->P.ppart_max) * SOLVE_BLOCK * nrhs)))
-        return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &S.lsum, std::max<int64_t>(1, (int64_t)h->P.long_col.size()) * 2 * nrhs)))
-        return rc;
     if (h->act_host) (void)hipHostFree(h->act_host);
     h->act_host = nullptr;
     if (hipHostMalloc((void**)&h->act_host, sizeof(int32_t) * units, hipHostMallocDefault) != hipSuccess) {
@@ -432,26 +481,13 @@ constexpr double GM_TOL = 1e-6;  // reduction of ||r - K d||_2 that ends a corre
 int ensure_gmres(qdmf_ctx* h) {
     const int32_t nr = h->S.nrhs;
     if (h->gm_V && h->gm_cap >= nr) return 0;
-    const int64_t N = h->P.N;
     const int32_t cap = std::max(nr, h->solve_cap);
-    const int64_t nu = (int64_t)cap * h->P.nsys;  // refinement units
+    Carve c;
+    layout_gmres(h, cap, c, h->gm_V, h->gm_Z, h->gm_W, h->gm);
     int rc = 0;
-    DevGmres& G = h->gm;
-    if ((rc = dalloc(h, h->solve_allocs, &h->gm_V, (int64_t)(GM_M + 1) * N * cap))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &h->gm_Z, (int64_t)GM_M * N * cap))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &h->gm_W, N * cap))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.h1, (GM_M + 1) * nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.h2, (GM_M + 1) * nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.nrm, nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.beta, nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.g, (GM_M + 1) * nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.cs, GM_M * nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.sn, GM_M * nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.R, (int64_t)GM_M * GM_M * nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.y, GM_M * nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.kr, nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.act, nu))) return rc;
-    if ((rc = dalloc(h, h->solve_allocs, &G.ract, (int64_t)cap))) return rc;
+    if ((rc = dalloc(h, h->solve_allocs, &c.base, c.off))) return rc;
+    c.off = 0;
+    layout_gmres(h, cap, c, h->gm_V, h->gm_Z, h->gm_W, h->gm);
     if (h->gm_act_host) (void)hipHostFree(h->gm_act_host);
     h->gm_act_host = nullptr;
     if (hipHostMalloc((void**)&h->gm_act_host, sizeof(int32_t) * cap, hipHostMallocDefault) != hipSuccess) {
@@ -479,7 +515,7 @@ int enqueue_gmres_correction(qdmf_ctx* h) {
     launch_gm_gate(G, nr, ns, st);  // per rhs: some unit takes the first step
     launch_vscale(D, S.r, G.nrm, Vb(0), nr, G.act, st);
     for (int j = 0; j < GM_M; ++j) {
-        if (!h->capturing && j > 0) {
+        if (!h->capturing && !h->nopoll && j > 0) {
             if (hipMemcpyAsync(h->gm_act_host, G.ract, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, st) !=
                     hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
@@ -510,16 +546,16 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
     const double target = mixed ? h->opt.target_berr_mixed : h->opt.target_berr;
     const int max_steps = mixed ? h->opt.max_refine_mixed : h->opt.max_refine;
     hipStream_t st = h->stream;
-    if (mixed && max_steps > 0 && !h->capturing && ensure_gmres(h)) return;  // no work space: no refinement
+    if (mixed && max_steps > 0 && !h->capturing && !h->nopoll && ensure_gmres(h)) return;  // no work space: no refinement
     launch_rhs(D, S, r7, r1, st);
     enqueue_ldlt_solve(h, S.b, S.x, nullptr);
     launch_residual(D, S, S.x, st);
     launch_berr_steps(D, S, 0, target, max_steps, st);
     for (int it = 0; it < max_steps; ++it) {
         // Eager solves look at the refinement flags and stop launching once every
-        // right-hand side has met the target; a captured graph keeps all passes and the
-        // kernels of a finished right-hand side return at once.
-        if (!h->capturing) {
+        // right-hand side has met the target; a captured graph (and qdmf_solve_noalloc)
+        // keeps all passes and the kernels of a finished right-hand side return at once.
+        if (!h->capturing && !h->nopoll) {
             const int64_t units = (int64_t)S.nrhs * h->P.nsys;
             if (hipMemcpyAsync(h->act_host, S.active, sizeof(int32_t) * units, hipMemcpyDeviceToHost, st) !=
                     hipSuccess ||
@@ -540,6 +576,36 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
         launch_berr_steps(D, S, 1, target, max_steps, st);
     }
     launch_recover(D, S, r7, dx, dy, st);
+    h->stat_berr = S.berr;
+    h->stat_steps = S.steps;
+}
+
+// Work space of qdmf_solve_noalloc: a fixed array in device memory, one copy per GPU, held
+// until the process ends.  Host code never passes its name to a kernel or a copy: it uses the
+// address that hipGetSymbolAddress returns with the GPU current (scratch_addr).
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[QDMF_NOALLOC_SCRATCH_BYTES];
+std::mutex scratch_mu;
+void* scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Looks up (once per device, that device current) the device address of this GPU's copy.
+int scratch_lookup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return QDMF_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_ptr[device]) return 0;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return QDMF_ERR_HIP;
+    }
+    scratch_ptr[device] = p;
+    return 0;
+}
+
+void* scratch_addr(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    return scratch_ptr[device];
 }
 
 }  // namespace
@@ -593,6 +659,8 @@ int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_optio
             delete h;
             return QDMF_ERR_HIP;
         }
+        // the allocation-free solve's work space on this GPU (a failure only disables that call)
+        (void)scratch_lookup(device);
     }
     *out = h;
     return 0;
@@ -853,11 +921,11 @@ int qdmf_batch_stats(qdmf_handle h, int64_t* inertia, double* berr_nw, int32_t* 
         if (!h->solved) return QDMF_ERR_NOT_FACTORISED;
         const size_t units = ns * (size_t)h->last_nrhs;
         std::vector<double> bu(4 * units);
-        if (hipMemcpy(bu.data(), h->S.berr, sizeof(double) * bu.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpy(bu.data(), h->stat_berr, sizeof(double) * bu.size(), hipMemcpyDeviceToHost) != hipSuccess)
             return QDMF_ERR_HIP;
         if (berr_nw)
             for (size_t u = 0; u < units; ++u) berr_nw[u] = bu[4 * u];
-        if (steps && hipMemcpy(steps, h->S.steps, sizeof(int32_t) * units, hipMemcpyDeviceToHost) != hipSuccess)
+        if (steps && hipMemcpy(steps, h->stat_steps, sizeof(int32_t) * units, hipMemcpyDeviceToHost) != hipSuccess)
             return QDMF_ERR_HIP;
     }
     return 0;
@@ -878,6 +946,67 @@ int qdmf_solve(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* 
     }
     if ((rc = ensure_solve(h, nrhs))) return rc;
     enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
+    if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
+    h->last_nrhs = nrhs;
+    h->solved = true;
+    return 0;
+}
+
+int qdmf_solve_noalloc(qdmf_handle h, int32_t nrhs, const double* r7_dev, const double* r1_dev, double* dx_dev,
+                       double* dy_dev) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->factorised) return QDMF_ERR_NOT_FACTORISED;
+    if (nrhs <= 0 || (!r1_dev && h->P.m > 0) || (!dx_dev && h->P.n > 0) || (!dy_dev && h->P.m > 0))
+        return QDMF_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    if (h->P.N == 0) {
+        h->last_nrhs = nrhs;
+        h->solved = true;
+        return 0;
+    }
+    void* base = scratch_addr(h->device);
+    if (!base) {
+        h->msg = "qdmf_solve_noalloc: no work space on this device";
+        return QDMF_ERR_HIP;
+    }
+    const bool krylov = h->last_prec == QDMF_MIXED && h->opt.max_refine_mixed > 0;
+    DevSolve S{};
+    DevGmres G{};
+    double *V = nullptr, *Z = nullptr, *W = nullptr;
+    Carve c;
+    layout_solve(h, nrhs, c, S);
+    if (krylov) layout_gmres(h, nrhs, c, V, Z, W, G);
+    if (c.off > (int64_t)QDMF_NOALLOC_SCRATCH_BYTES) {
+        h->msg = "qdmf_solve_noalloc: the work space needs " + std::to_string(c.off) + " bytes, above the " +
+                 std::to_string((int64_t)QDMF_NOALLOC_SCRATCH_BYTES) + " of QDMF_NOALLOC_SCRATCH_BYTES";
+        return QDMF_ERR_OOM;
+    }
+    c.base = (char*)base;
+    c.off = 0;
+    layout_solve(h, nrhs, c, S);
+    if (krylov) layout_gmres(h, nrhs, c, V, Z, W, G);
+    // the enqueue works on the handle's work space members: point them at the fixed array for
+    // this call and give the handle's own back afterwards
+    const DevSolve S0 = h->S;
+    const DevGmres G0 = h->gm;
+    double *V0 = h->gm_V, *Z0 = h->gm_Z, *W0 = h->gm_W;
+    const int32_t cap0 = h->gm_cap;
+    h->S = S;
+    h->gm = G;
+    h->gm_V = V;
+    h->gm_Z = Z;
+    h->gm_W = W;
+    h->gm_cap = krylov ? nrhs : 0;
+    h->nopoll = true;
+    enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
+    h->nopoll = false;
+    h->S = S0;
+    h->gm = G0;
+    h->gm_V = V0;
+    h->gm_Z = Z0;
+    h->gm_W = W0;
+    h->gm_cap = cap0;
     if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
     h->last_nrhs = nrhs;
     h->solved = true;
@@ -938,9 +1067,9 @@ int qdmf_solve_stats(qdmf_handle h, qdmf_solve_info* out, double* berr_nw_per_rh
     const int32_t nr = h->last_nrhs, ns = h->P.nsys;
     std::vector<double> bu(4 * (size_t)nr * ns), be(4 * (size_t)nr, 0.0);
     std::vector<int32_t> su((size_t)nr * ns), steps(nr, 0);
-    if (hipMemcpy(bu.data(), h->S.berr, sizeof(double) * bu.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(bu.data(), h->stat_berr, sizeof(double) * bu.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return QDMF_ERR_HIP;
-    if (hipMemcpy(su.data(), h->S.steps, sizeof(int32_t) * su.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(su.data(), h->stat_steps, sizeof(int32_t) * su.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return QDMF_ERR_HIP;
     for (int32_t r = 0; r < nr; ++r)  // worst system per rhs
         for (int32_t q = 0; q < ns; ++q) {
@@ -1075,6 +1204,8 @@ int qdmf_graph_launch(qdmf_handle h) {
     h->factorised = true;
     h->last_nrhs = h->graph_nrhs;
     h->solved = h->graph_nsolves > 0;
+    h->stat_berr = h->S.berr;
+    h->stat_steps = h->S.steps;
     return 0;
 }
 

@@ -31,7 +31,7 @@ QDMF_WARN_NOT_CONVERGED = 3
 QDMF_WARN_LARGE_REG = 4
 
 EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_analyse",
-            "qdmf_symbolic", "qdmf_set_matrix", "qdmf_factorise", "qdmf_solve",
+            "qdmf_symbolic", "qdmf_set_matrix", "qdmf_factorise", "qdmf_solve", "qdmf_solve_noalloc",
             "qdmf_factor_stats", "qdmf_solve_stats", "qdmf_export_d", "qdmf_export_front",
             "qdmf_graph_capture", "qdmf_graph_launch", "qdmf_destroy", "qdmf_status_string",
             "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read", "qdmf_batch_analyse",
@@ -124,6 +124,7 @@ def lib():
         L.qdmf_set_matrix.argtypes = [P, P, I32]
         L.qdmf_factorise.argtypes = [P, P, D, D, I32]
         L.qdmf_solve.argtypes = [P, I32, P, P, P, P]
+        L.qdmf_solve_noalloc.argtypes = [P, I32, P, P, P, P]
         L.qdmf_factor_stats.argtypes = [P, C.POINTER(qdmf_factor_info)]
         L.qdmf_solve_stats.argtypes = [P, C.POINTER(qdmf_solve_info), P, P]
         L.qdmf_export_d.argtypes = [P, P, P, P, P, P]
@@ -282,6 +283,14 @@ def qdmf_factorise(h, theta_dev, rho, delta, prec=QDMF_FP64):
 def qdmf_solve(h, nrhs, r7_dev, r1_dev, dx_dev, dy_dev):
     return _check(lib().qdmf_solve(h, int(nrhs), _dev(r7_dev), _dev(r1_dev), _dev(dx_dev),
                                    _dev(dy_dev)), "qdmf_solve", h)
+
+
+def qdmf_solve_noalloc(h, nrhs, r7_dev, r1_dev, dx_dev, dy_dev):
+    return _check(lib().qdmf_solve_noalloc(h, int(nrhs), _dev(r7_dev), _dev(r1_dev), _dev(dx_dev),
+                                           _dev(dy_dev)), "qdmf_solve_noalloc", h)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def qdmf_factor_stats(h):
@@ -455,6 +464,12 @@ class Solver:
         if dy_dev is None:
             dy_dev = torch.empty((nrhs, self.lp["m"]), dtype=torch.float64, device=dev).T
         qdmf_solve(self.h, nrhs, r7_dev, r1_dev, dx_dev, dy_dev)
+        return dx_dev, dy_dev
+
+    def solve_noalloc(self, r7_dev, r1_dev, dx_dev, dy_dev):
+        """qdmf_solve_noalloc: the outputs are the caller's (nothing is allocated)."""
+        nrhs = r1_dev.shape[1] if r1_dev.dim() == 2 else 1
+        qdmf_solve_noalloc(self.h, nrhs, r7_dev, r1_dev, dx_dev, dy_dev)
         return dx_dev, dy_dev
 
     def factor_stats(self):
