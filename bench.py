@@ -76,41 +76,14 @@ def copy_calibration(nbytes):
 
 
 def make_workload(name):
-    if name == "as_staircase":
-        return W.as_staircase(), dict()
-    if name == "ne_random":
-        return W.ne_random(), dict()
-    if name == "ne_grid":
-        lp = W.ne_grid(nrhs=8)
-        return lp, dict(ordering=2, grid=lp["grid"])
-    if name == "ne_grid_small":
-        lp = W.ne_grid(24, 24, 20, nrhs=8)
-        return lp, dict(ordering=2, grid=lp["grid"])
-    if name.startswith("ne_dense_front"):  # ne_dense_front or ne_dense_front_<f>
-        f = int(name.split("_")[-1]) if name[-1].isdigit() else 4096
-        return W.ne_dense_front(f), dict(ordering=0)
-    if name in ("as_batch", "as_batch_small"):
-        lps = W.as_batch(512 if name == "as_batch" else 32)
-        cat = W.concat_systems(lps)
-        cat["systems"] = lps
-        return cat, dict(systems=lps, ordering=0)
-    if name == "as_dense_cols":
-        lp = W.as_dense_cols()
-        return lp, dict(ordering=2, grid=lp["grid"])
-    if name == "as_staircase_qp":  # the staircase with a Hessian on half of its columns
-        return W.with_hessian(W.as_staircase(), seed=1, frac=0.5, per_row=3, window=50), dict()
-    raise SystemExit(f"unknown workload {name}")
+    try:
+        return W.named_workload(name)
+    except ValueError as e:
+        raise SystemExit(str(e))
 
 
 def thetas(lp, k, seed):
-    if "systems" in lp:  # batch: system s, iteration k draws from seed [4, s, k]
-        return np.concatenate([W.as_batch_theta(q, s, k) for s, q in enumerate(lp["systems"])])
-    if lp["name"].startswith("ne_dense_front"):
-        return W.log_uniform(W.rng(seed, 1000 + k), 1e-2, 1e2, lp["n"])
-    g = W.rng(seed, 1000 + k)
-    lo, hi = (1e-10, 1e10) if lp["mode"] == W.AS else (1e-6, 1e6)
-    return W.log_uniform(g, lo, hi, lp["n"])
-
+    return W.iteration_theta(lp, k, seed)
 
 
 PRECS = {"fp64": 0, "mixed": 1}

@@ -95,6 +95,10 @@ typedef struct {
     int32_t syrk_tile_front;  /* full trailing updates (after a window, or after a group's last
                                  window) of trailing matrices of at least this many rows run
                                  in 128 x 128 tiles instead of 64 x 64 (0: never); 0        */
+    int32_t mixed_check;      /* MIXED: which systems are factorised again in FP64: 0 none,
+                                 1 those with a pivot that is not finite, 2 also those with
+                                 some |E_dyn| > tau_big ||K||_1, 3 also those with any
+                                 Proposition 3 or sign-rule pivot; 2                         */
 } qdmf_options;
 
 typedef struct {
@@ -190,10 +194,12 @@ int qdmf_set_matrix(qdmf_handle h, const double* a_val, int32_t on_device);
  * until the stream reaches this call's end.  rho, delta >= 0 are the static
  * regularisations.  prec: QDMF_FP64 or QDMF_MIXED (FP32 MFMA Schur updates on fronts of
  * order >= opt.f_mix; everything else FP64).  In mixed precision a system whose factor
- * then holds a pivot that is not finite, or one that needed Proposition 3 or the sign rule
- * (the FP32 rounding of the updates changed a pivot's sign), is factorised again in FP64,
+ * then shows a breakdown of the FP32 updates (opt.mixed_check: by default a pivot that is
+ * not finite or a dynamic regularisation above tau_big ||K||_1) is factorised again in FP64,
  * and only that system; qdmf_factor_info.nredo_fp64 counts them.  Executed eagerly, this
- * call then waits for the stream to read that count.  L, D are owned by the handle.
+ * call then waits for the stream to read that count.  When no front of order >= f_mix has a
+ * trailing update, a mixed factorisation is the FP64 one: no check, and its solves refine by
+ * plain FP64 corrections (to the mixed target).  L, D are owned by the handle.
  * Returns < 0 only for argument errors; numerical outcomes come from qdmf_factor_stats.
  * An empty system (m + n == 0) launches nothing and reports zero pivots. */
 int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double delta,

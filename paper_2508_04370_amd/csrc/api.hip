@@ -40,6 +40,7 @@ struct qdmf_ctx {
     std::vector<int32_t> maxf_lvl, maxp_lvl;  // per level: largest front order and pivot count
     int64_t knnz = 0;
     int64_t max_sys_piv = 0;  // largest pivot count of one system
+    bool fp32_fronts = false; // some trailing update belongs to a front of order >= f_mix
     int64_t device_bytes = 0;
 
     // solve work space
@@ -243,6 +244,11 @@ int upload_plan(qdmf_ctx* h) {
         h->max_sys_piv = 0;
         for (int32_t q = 0; q < P.nsys; ++q)
             h->max_sys_piv = std::max<int64_t>(h->max_sys_piv, P.sys_piv_ptr[q + 1] - P.sys_piv_ptr[q]);
+        h->fp32_fronts = false;
+        for (const Launch& L : P.launches)
+            if (L.kind == L_SYRK || L.kind == L_SYRK128)
+                for (int64_t t = L.task0; t < L.task0 + L.ntask; ++t)
+                    h->fp32_fronts = h->fp32_fronts || P.sn_f[P.tasks[t].s] >= h->opt.f_mix;
     }
     D.nlong = (int32_t)P.long_col.size();
     D.nsys = P.nsys;
@@ -395,8 +401,10 @@ PivotParams pivot_params(const qdmf_ctx* h, int32_t prec) {
     pp.eps_lift = h->opt.eps_lift;
     pp.tau_big = h->opt.tau_big;
     pp.presort = h->opt.presort;
-    pp.mixed = prec == QDMF_MIXED;
+    // a mixed factorisation without any front of order >= f_mix computes what FP64 does
+    pp.mixed = prec == QDMF_MIXED && h->fp32_fronts;
     pp.f_mix = h->opt.f_mix;
+    pp.mixed_check = h->opt.mixed_check;
     return pp;
 }
 
@@ -413,11 +421,11 @@ void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delt
     }
     launch_inv(h->D, h->inv_tasks_dev, (int64_t)h->P.inv_tasks.size(), h->stream);
     launch_factor_stats(h->D, pp, h->stats_part, h->stream);
-    if (!pp.mixed) return;
+    if (!pp.mixed || pp.mixed_check == 0) return;
     // Mixed precision: the systems whose FP32 updates broke down are factorised again in FP64
     // (the same launches, gated to those systems' supernodes).  Eager execution reads the count
     // and skips the second pass when it is zero; a captured graph always holds it.
-    launch_mixed_check(h->D, h->max_sys_piv, h->stream);
+    launch_mixed_check(h->D, pp, h->max_sys_piv, h->stream);
     if (!h->capturing) {
         int32_t nredo = 0;
         if (hipMemcpyAsync(&nredo, h->D.redo + h->P.nsys, sizeof(nredo), hipMemcpyDeviceToHost, h->stream) !=
@@ -539,14 +547,21 @@ int enqueue_gmres_correction(qdmf_ctx* h) {
     return 0;
 }
 
+// The refinement of a mixed factorisation takes Krylov corrections when its factor holds FP32
+// products; without any front of order >= f_mix the factor is FP64's, and so is the correction.
+bool krylov_refine(const qdmf_ctx* h) {
+    return h->last_prec == QDMF_MIXED && h->fp32_fronts && h->opt.max_refine_mixed > 0;
+}
+
 void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, double* dy) {
     const DevPlan& D = h->D;
     const DevSolve& S = h->S;
     const bool mixed = h->last_prec == QDMF_MIXED;
+    const bool krylov = krylov_refine(h);
     const double target = mixed ? h->opt.target_berr_mixed : h->opt.target_berr;
     const int max_steps = mixed ? h->opt.max_refine_mixed : h->opt.max_refine;
     hipStream_t st = h->stream;
-    if (mixed && max_steps > 0 && !h->capturing && !h->nopoll && ensure_gmres(h)) return;  // no work space: no refinement
+    if (krylov && !h->capturing && !h->nopoll && ensure_gmres(h)) return;  // no work space: no refinement
     launch_rhs(D, S, r7, r1, st);
     enqueue_ldlt_solve(h, S.b, S.x, nullptr);
     launch_residual(D, S, S.x, st);
@@ -566,7 +581,7 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
             if (!any) break;
         }
         launch_refine_begin(D, S, st);
-        if (mixed) {
+        if (krylov) {
             if (enqueue_gmres_correction(h)) break;
         } else {
             enqueue_ldlt_solve(h, S.r, S.d, S.active);
@@ -633,6 +648,7 @@ void qdmf_default_options(qdmf_options* o) {
     o->syrk_group_front = 1024;
     o->syrk_group = 4;
     o->syrk_tile_front = 0;
+    o->mixed_check = 2;
 }
 
 int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_options* opt) {
@@ -643,7 +659,7 @@ int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_optio
     else qdmf_default_options(&h->opt);
     if (h->opt.nb != 64 || h->opt.small_front < 1 || h->opt.small_front > 64 || h->opt.split_solve_front < 1 ||
         h->opt.syrk_group_front < 0 || h->opt.syrk_group < 1 || h->opt.syrk_group > SYRK_GROUP_MAX ||
-        h->opt.syrk_tile_front < 0 ||
+        h->opt.syrk_tile_front < 0 || h->opt.mixed_check < 0 || h->opt.mixed_check > 3 ||
         h->opt.max_refine < 0 ||
         h->opt.max_refine_mixed < 0 || h->opt.ordering < QDMF_ORDER_AMD || h->opt.ordering > QDMF_ORDER_AUTO) {
         delete h;
@@ -970,7 +986,7 @@ int qdmf_solve_noalloc(qdmf_handle h, int32_t nrhs, const double* r7_dev, const 
         h->msg = "qdmf_solve_noalloc: no work space on this device";
         return QDMF_ERR_HIP;
     }
-    const bool krylov = h->last_prec == QDMF_MIXED && h->opt.max_refine_mixed > 0;
+    const bool krylov = krylov_refine(h);
     DevSolve S{};
     DevGmres G{};
     double *V = nullptr, *Z = nullptr, *W = nullptr;
@@ -1164,7 +1180,7 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     int rc = ensure_solve(h, nrhs);
     if (rc) return rc;
     // every buffer the captured work uses exists before the capture starts
-    if (prec == QDMF_MIXED && h->opt.max_refine_mixed > 0 && (rc = ensure_gmres(h))) return rc;
+    if (prec == QDMF_MIXED && h->fp32_fronts && h->opt.max_refine_mixed > 0 && (rc = ensure_gmres(h))) return rc;
     destroy_graph(h);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return QDMF_ERR_HIP;

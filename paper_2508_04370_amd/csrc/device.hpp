@@ -31,6 +31,7 @@ struct PivotParams {
     int32_t presort;
     int32_t mixed;  // 1: FP32 Schur updates on fronts with f >= f_mix
     int32_t f_mix;
+    int32_t mixed_check;  // which broken-down mixed factors are redone in FP64 (qdmf_options)
 };
 
 struct DevPlan {
@@ -141,7 +142,7 @@ int factor_stats_blocks(int64_t N);
 void launch_factor_stats(const DevPlan& D, const PivotParams& pp, double* part, hipStream_t s);
 // Marks in D.redo the systems whose mixed-precision factor broke down and counts them in
 // D.redo[nsys]; max_piv is the largest pivot count of one system.
-void launch_mixed_check(const DevPlan& D, int64_t max_piv, hipStream_t s);
+void launch_mixed_check(const DevPlan& D, const PivotParams& pp, int64_t max_piv, hipStream_t s);
 void launch_matrix_norms(const DevPlan& D, hipStream_t s);
 void launch_hessian_norms(const DevPlan& D, hipStream_t s);
 

@@ -1581,21 +1581,25 @@ __global__ __launch_bounds__(256) void k_sys_inertia(DevPlan D) {
     if (threadIdx.x < 3) D.inertia_sys[3 * q + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Mixed precision: marks the systems whose factor broke down, i.e. that hold a pivot that is
-// not finite or one that took Proposition 3 or the sign rule.  An exact quasi-definite matrix
-// needs neither rule, so on such a system the FP32 rounding of the Schur updates has changed a
-// pivot's sign (the cancellation in the updates exceeds FP32's precision).  Block (c, q)
-// scans chunk c of system q's pivot positions; redo is zero when the launch starts.
+// Mixed precision: marks the systems whose factor broke down.  Level 1: a pivot that is not
+// finite; 2: also a dynamic regularisation above tau_big ||K||_1 (a pivot whose computed
+// value had to be replaced wholesale); 3: also any pivot that took Proposition 3 or the sign
+// rule (an exact quasi-definite matrix needs neither, so the FP32 rounding of the Schur
+// updates has changed that pivot's sign).  Block (c, q) scans chunk c of system q's pivot
+// positions; redo is zero when the launch starts.
 constexpr int MC_CHUNK = 4096;
 
-__global__ __launch_bounds__(256) void k_mixed_check(DevPlan D) {
+__global__ __launch_bounds__(256) void k_mixed_check(DevPlan D, PivotParams pp) {
     const int q = blockIdx.y;
     const int64_t a = D.sys_piv_ptr[q] + (int64_t)blockIdx.x * MC_CHUNK;
     const int64_t b = min(D.sys_piv_ptr[q + 1], a + MC_CHUNK);
+    const double big = pp.tau_big * D.knorm_sys[q];
     int bad = 0;
     for (int64_t t = a + threadIdx.x; t < b; t += 256) {
         const int k = D.sys_piv[t];
-        bad |= !isfinite(D.dval[k]) || !isfinite(D.doff[k]) || (D.pflag[k] & (PF_PROP3 | PF_SIGN)) != 0;
+        bad |= !isfinite(D.dval[k]) || !isfinite(D.doff[k]) || !isfinite(D.edyn[k]);
+        if (pp.mixed_check >= 2) bad |= fabs(D.edyn[k]) > big;
+        if (pp.mixed_check >= 3) bad |= (D.pflag[k] & (PF_PROP3 | PF_SIGN)) != 0;
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(D.redo + q, 1);
 }
@@ -3175,12 +3179,12 @@ void launch_factor_stats(const DevPlan& D, const PivotParams& pp, double* part, 
     if (D.nsys > 1) hipLaunchKernelGGL(k_sys_inertia, dim3(D.nsys), dim3(256), 0, s, D);
 }
 
-void launch_mixed_check(const DevPlan& D, int64_t max_piv, hipStream_t s) {
+void launch_mixed_check(const DevPlan& D, const PivotParams& pp, int64_t max_piv, hipStream_t s) {
     const int64_t n = (int64_t)D.nsys + 1;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D.redo, n, 0);
     if (max_piv > 0)
         hipLaunchKernelGGL(k_mixed_check, dim3((unsigned)((max_piv + MC_CHUNK - 1) / MC_CHUNK), (unsigned)D.nsys),
-                           dim3(256), 0, s, D);
+                           dim3(256), 0, s, D, pp);
     hipLaunchKernelGGL(k_mixed_count, dim3(1), dim3(256), 0, s, D);
 }
 

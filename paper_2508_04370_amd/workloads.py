@@ -536,3 +536,45 @@ def small_config():
 def main_config():
     """The 20000 x 40000 staircase LP, augmented system, FP64."""
     return as_staircase()
+
+
+# ------------------------------------------------------------------ measured workloads
+
+def named_workload(name):
+    """The measured workloads by name: (system, analyse options).  Batches carry their systems
+    under "systems"."""
+    if name == "as_staircase":
+        return as_staircase(), dict()
+    if name == "ne_random":
+        return ne_random(), dict()
+    if name == "ne_grid":
+        lp = ne_grid(nrhs=8)
+        return lp, dict(ordering=2, grid=lp["grid"])
+    if name == "ne_grid_small":
+        lp = ne_grid(24, 24, 20, nrhs=8)
+        return lp, dict(ordering=2, grid=lp["grid"])
+    if name.startswith("ne_dense_front"):  # ne_dense_front or ne_dense_front_<f>
+        f = int(name.split("_")[-1]) if name[-1].isdigit() else 4096
+        return ne_dense_front(f), dict(ordering=0)
+    if name in ("as_batch", "as_batch_small"):
+        lps = as_batch(512 if name == "as_batch" else 32)
+        cat = concat_systems(lps)
+        cat["systems"] = lps
+        return cat, dict(systems=lps, ordering=0)
+    if name == "as_dense_cols":
+        lp = as_dense_cols()
+        return lp, dict(ordering=2, grid=lp["grid"])
+    if name == "as_staircase_qp":  # the staircase with a Hessian on half of its columns
+        return with_hessian(as_staircase(), seed=1, frac=0.5, per_row=3, window=50), dict()
+    raise ValueError(f"unknown workload {name}")
+
+
+def iteration_theta(lp, k, seed):
+    """Theta of iteration k of a measured workload (batches: system s draws from seed [4, s, k])."""
+    if "systems" in lp:  # batch: system s, iteration k draws from seed [4, s, k]
+        return np.concatenate([as_batch_theta(q, s, k) for s, q in enumerate(lp["systems"])])
+    if lp["name"].startswith("ne_dense_front"):
+        return log_uniform(rng(seed, 1000 + k), 1e-2, 1e2, lp["n"])
+    g = rng(seed, 1000 + k)
+    lo, hi = (1e-10, 1e10) if lp["mode"] == AS else (1e-6, 1e6)
+    return log_uniform(g, lo, hi, lp["n"])

@@ -43,7 +43,7 @@ def test_options_struct_layout_matches_defaults():
     assert o.split_solve_front == 1024 and o.syrk_group_front == 1024 and o.syrk_group == 4
     assert o.target_berr == 1e-12 and o.target_berr_mixed == 1e-10 and o.tau_big == 1e-8
     assert o.f_mix == 1024 and o.small_front == 64 and o.amalgamate == 1 and o.mem_cap_bytes == 0
-    assert o.syrk_tile_front == 0
+    assert o.syrk_tile_front == 0 and o.mixed_check == 2
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -185,6 +185,11 @@ def test_memory_cap_gives_oom():
     h = Q.qdmf_create(-1, None, o)
     _expect(Q.QDMF_ERR_OOM, lambda: Q.qdmf_analyse(h, lp["m"], lp["n"], lp["colptr"], lp["rowidx"], lp["mode"]))
     Q.qdmf_destroy(h)
+
+
+def test_bad_options_rejected():
+    for bad in (dict(mixed_check=4), dict(mixed_check=-1), dict(syrk_group=5), dict(small_front=65)):
+        _expect(Q.QDMF_ERR_INVALID_ARG, lambda: Q.qdmf_create(-1, None, Q.qdmf_default_options(**bad)))
 
 
 def test_host_only_handle_refuses_numeric_calls():
