@@ -99,6 +99,21 @@ typedef struct {
                                  1 those with a pivot that is not finite, 2 also those with
                                  some |E_dyn| > tau_big ||K||_1, 3 also those with any
                                  Proposition 3 or sign-rule pivot; 2                         */
+    int32_t lookahead_front;  /* fronts of order >= this (0: none) overlap their trailing
+                                 updates with the next pivot windows (Section 4.4's blocked
+                                 factorisation): the tiles of a full update beyond the next
+                                 group's pivot columns run on a second stream the library
+                                 owns, joined back into the caller's stream before any work
+                                 that reads them and before the factorisation ends; the
+                                 factor is bitwise the same as with 0.  Measured no faster
+                                 here: the update tiles and the window kernel cannot share
+                                 a compute unit's registers, so each slows the other; 0     */
+    int32_t graph_poll;       /* 1: a captured graph is cut at the refinement decisions, and
+                                 qdmf_graph_launch reads their flags on the host between the
+                                 parts, as eager solves do, launching only the refinement and
+                                 Krylov steps some right-hand side still needs; 0: one graph
+                                 holding every step (finished steps return at once), launched
+                                 without any host read; 1                                  */
 } qdmf_options;
 
 typedef struct {
@@ -305,8 +320,15 @@ int qdmf_export_front(qdmf_handle h, int32_t s, double* panel, int32_t* rows);
  * nothing and leaves the handle's factorisation and solve state as they were; a launch makes
  * it the graph's (the stats and export calls then report the replayed factorisation and
  * solves).  The result of a replay equals that of the same calls made eagerly.
+ * With the option graph_poll (default) the capture is cut into parts at the points where an
+ * eager solve reads its refinement flags (each refinement pass, each Krylov step after the
+ * first, the FP64 redo of a mixed factorisation that broke down); qdmf_graph_launch then
+ * launches the parts in order and, before a conditional part, copies its flags to pinned
+ * host memory and waits for the stream, skipping the part (and the rest of its loop) when
+ * no unit needs it.  With graph_poll = 0 the capture is one graph that holds every step and
+ * qdmf_graph_launch only enqueues it.
  * Errors: QDMF_ERR_HIP, QDMF_ERR_NOT_ANALYSED, QDMF_ERR_INVALID_ARG (also for an empty
- * system, which has nothing to capture). */
+ * system, which has nothing to capture), QDMF_ERR_OOM (the pinned flag buffer). */
 int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, double delta,
                        int32_t prec, int32_t nsolves, int32_t nrhs, const double* r7_dev,
                        const double* r1_dev, double* dx_dev, double* dy_dev);

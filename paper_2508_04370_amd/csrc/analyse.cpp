@@ -1166,8 +1166,22 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                 const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
                 return w == last && opt.syrk_tile_front > 0 && P.sn_f[t] - k1 >= opt.syrk_tile_front;
             };
-            t0 = (int64_t)P.tasks.size();
-            int64_t nmix = 0;
+            // Lookahead (fronts of order >= lookahead_front): a full update is split by columns.
+            // Its tiles over the next group's pivot columns stay on the main stream (the next
+            // windows need them); the tiles beyond them go to the second stream and run while
+            // the next group's windows and narrow updates run, which touch only their own
+            // columns.  The next full update of that front overlaps those columns, so the
+            // launch that holds it waits for the second stream first.
+            auto split_cols = [&](int32_t t, int32_t T) {  // tile columns kept on the main stream
+                if (opt.lookahead_front <= 0 || P.sn_f[t] < opt.lookahead_front) return INT32_MAX;
+                const int32_t Gn = (opt.syrk_group_front > 0 && P.sn_f[t] >= opt.syrk_group_front) ? opt.syrk_group : 1;
+                const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
+                const int32_t next_cols = std::min(P.sn_p[t], k1 + Gn * NB) - k1;
+                return (next_cols + T - 1) / T;
+            };
+            std::vector<Task> ta[2], tb[2];  // [main, second stream] x [128, 64 tiles]
+            int64_t nmix[2] = {0, 0};
+            bool full_la = false;  // the main-stream part holds a full update of a lookahead front
             for (int pass = 0; pass < 2; ++pass)  // fronts of order >= f_mix first
             for (int32_t t : large)
                 if (w < P.sn_nwin[t] && (P.sn_f[t] >= opt.f_mix) == (pass == 0)) {
@@ -1177,14 +1191,15 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                     const int32_t k1 = std::min(P.sn_p[t], (w + 1) * NB);
                     const int32_t R = (P.sn_f[t] - k1 + 127) / 128;
                     const int32_t code = g * NB | (w - g) << SYRK_COUNT_SHIFT;
+                    const int32_t nA = split_cols(t, 128);
                     for (int32_t bj = 0; bj < R; ++bj)
-                        for (int32_t bi = bj; bi < R; ++bi) P.tasks.push_back(Task{t, code, bi, bj});
-                    if (pass == 0) nmix += (int64_t)R * (R + 1) / 2;
+                        for (int32_t bi = bj; bi < R; ++bi) {
+                            const int st = bj < nA ? 0 : 1;
+                            ta[st].push_back(Task{t, code, bi, bj});
+                            if (pass == 0) ++nmix[st];
+                            if (st == 0 && nA != INT32_MAX) full_la = true;
+                        }
                 }
-            add_launch(L_SYRK128, l, t0, 0, mf);
-            if (!P.launches.empty() && P.launches.back().kind == L_SYRK128 && P.launches.back().task0 == t0)
-                P.launches.back().nmix = nmix;
-            t0 = (int64_t)P.tasks.size();
             for (int32_t t : large)
                 if (w < P.sn_nwin[t]) {
                     int32_t g, last;
@@ -1194,13 +1209,40 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
                     const int32_t R = (P.sn_f[t] - k1 + 63) / 64;
                     const int32_t code = g * NB | (w - g) << SYRK_COUNT_SHIFT;
                     if (w < last) {  // window w + 1 is whole or partial, its columns start at k1
-                        for (int32_t bi = 0; bi < R; ++bi) P.tasks.push_back(Task{t, code | SYRK_NARROW, bi, 0});
+                        for (int32_t bi = 0; bi < R; ++bi) tb[0].push_back(Task{t, code | SYRK_NARROW, bi, 0});
                     } else {
+                        const int32_t nA = split_cols(t, 64);
                         for (int32_t bj = 0; bj < R; ++bj)
-                            for (int32_t bi = bj; bi < R; ++bi) P.tasks.push_back(Task{t, code, bi, bj});
+                            for (int32_t bi = bj; bi < R; ++bi) {
+                                const int st = bj < nA ? 0 : 1;
+                                tb[st].push_back(Task{t, code, bi, bj});
+                                if (st == 0 && nA != INT32_MAX) full_la = true;
+                            }
                     }
                 }
-            add_launch(L_SYRK, l, t0, 0, mf);
+            for (int st = 0; st < 2; ++st) {
+                t0 = (int64_t)P.tasks.size();
+                P.tasks.insert(P.tasks.end(), ta[st].begin(), ta[st].end());
+                add_launch(L_SYRK128, l, t0, 0, mf);
+                if (!P.launches.empty() && P.launches.back().kind == L_SYRK128 && P.launches.back().task0 == t0) {
+                    P.launches.back().nmix = nmix[st];
+                    P.launches.back().stream = (int8_t)st;
+                    P.launches.back().wait = (int8_t)(st == 0 && full_la);
+                }
+                t0 = (int64_t)P.tasks.size();
+                P.tasks.insert(P.tasks.end(), tb[st].begin(), tb[st].end());
+                add_launch(L_SYRK, l, t0, 0, mf);
+                if (!P.launches.empty() && P.launches.back().kind == L_SYRK && P.launches.back().task0 == t0) {
+                    P.launches.back().stream = (int8_t)st;
+                    P.launches.back().wait = (int8_t)(st == 0 && full_la);
+                }
+            }
+        }
+        // The level's last update may sit on the second stream; nothing of this level follows
+        // it, so it moves to the main stream behind a join (and can take the finalize tasks).
+        if (!P.launches.empty() && P.launches.back().level == l && P.launches.back().stream == 1) {
+            P.launches.back().stream = 0;
+            P.launches.back().wait = 1;
         }
         t0 = (int64_t)P.tasks.size();
         for (int32_t t : large)

@@ -21,6 +21,10 @@ struct qdmf_ctx {
     int device = 0;
     bool host_only = false;
     hipStream_t stream = nullptr;
+    // lookahead: the second stream of the factorisation and the two events that order it
+    // against the first (created at the first factorisation whose plan uses it)
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_win = nullptr, ev_s2 = nullptr;
     qdmf_options opt{};
     std::string msg;
 
@@ -68,10 +72,25 @@ struct qdmf_ctx {
     const int32_t* stat_steps = nullptr;
     bool nopoll = false;  // qdmf_solve_noalloc: enqueue as for a graph (no host reads)
 
-    // graph
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // graph: the captured sequence in segments.  Without cuts (option graph_poll = 0) it is
+    // one segment; with them, a segment starts at each decision point the eager code reads
+    // on the host and runs only when its flags say that some unit still needs it.
+    struct GraphSeg {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;  // null: nothing was captured in it
+        const int32_t* flag = nullptr;  // run when some of flag[0 .. nflag) is nonzero (null: always)
+        int32_t nflag = 0;
+        size_t skip_to = 0;  // next segment when the flags are all zero
+    };
+    std::vector<GraphSeg> segs;
     bool capturing = false;
+    bool cut_capture = false;  // capturing with cuts at the decision points
+    bool capture_failed = false;
+    const int32_t* cur_flag = nullptr;  // condition of the segment being captured
+    int32_t cur_nflag = 0;
+    std::vector<std::pair<int64_t, int64_t>> skip_pending;  // (segment, its skip target)
+    int32_t* poll_host = nullptr;  // pinned flags read between segments
+    int32_t poll_cap = 0;
     // what a launch of the captured graph leaves behind (set by qdmf_graph_launch)
     int32_t graph_prec = 0, graph_nrhs = 0, graph_nsolves = 0;
 
@@ -127,7 +146,9 @@ struct ProfScope {
     qdmf_ctx* h;
     bool on;
     hipEvent_t e1 = nullptr;
-    ProfScope(qdmf_ctx* h_, int32_t kind, double flops, double bytes) : h(h_), on(false) {
+    hipStream_t st;
+    ProfScope(qdmf_ctx* h_, int32_t kind, double flops, double bytes, hipStream_t s = nullptr)
+        : h(h_), on(false), st(s ? s : h_->stream) {
         if (h->capturing || h->prof_kind != kind) return;
         if (h->ev_used + 2 > h->ev_pool.size()) {
             for (int q = 0; q < 256; ++q) {
@@ -139,21 +160,65 @@ struct ProfScope {
         hipEvent_t e0 = h->ev_pool[h->ev_used];
         e1 = h->ev_pool[h->ev_used + 1];
         h->ev_used += 2;
-        (void)hipEventRecord(e0, h->stream);
+        (void)hipEventRecord(e0, st);
         h->prof_flops += flops;
         h->prof_bytes += bytes;
         on = true;
     }
     ~ProfScope() {
-        if (on) (void)hipEventRecord(e1, h->stream);
+        if (on) (void)hipEventRecord(e1, st);
     }
 };
 
 void destroy_graph(qdmf_ctx* h) {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
-    h->gexec = nullptr;
-    h->graph = nullptr;
+    for (auto& g : h->segs) {
+        if (g.x) (void)hipGraphExecDestroy(g.x);
+        if (g.g) (void)hipGraphDestroy(g.g);
+    }
+    h->segs.clear();
+}
+
+// Graph capture in segments.  seg_close ends the capture of the current segment and keeps
+// it; seg_open starts the next one, run only when some of flag[0 .. n) is nonzero (flag null:
+// always), and returns its index (or -1 when the capture is not cut).
+void seg_close(qdmf_ctx* h) {
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(h->stream, &g) != hipSuccess || !g) {
+        (void)hipGetLastError();
+        h->capture_failed = true;
+        if (g) (void)hipGraphDestroy(g);
+        g = nullptr;
+    }
+    qdmf_ctx::GraphSeg sg;
+    sg.g = g;
+    sg.flag = h->cur_flag;
+    sg.nflag = h->cur_nflag;
+    size_t nn = 0;
+    if (g && hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) h->capture_failed = true;
+    if (g && nn > 0 && hipGraphInstantiate(&sg.x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        sg.x = nullptr;
+        h->capture_failed = true;
+    }
+    h->segs.push_back(sg);
+}
+
+int64_t seg_open(qdmf_ctx* h, const int32_t* flag, int32_t n) {
+    if (!h->capturing || !h->cut_capture) return -1;
+    seg_close(h);
+    h->cur_flag = flag;
+    h->cur_nflag = n;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        h->capture_failed = true;
+    }
+    return (int64_t)h->segs.size();
+}
+
+// Segments q in heads that find their flags all zero continue at segment `to`.
+void seg_skip(qdmf_ctx* h, const std::vector<int64_t>& heads, int64_t to) {
+    for (int64_t q : heads)
+        if (q >= 0) h->skip_pending.push_back({q, to});
 }
 
 int set_device(qdmf_ctx* h) {
@@ -408,6 +473,54 @@ PivotParams pivot_params(const qdmf_ctx* h, int32_t prec) {
     return pp;
 }
 
+// The plan's factorisation launches in order.  Launches marked for the second stream start
+// after the last pivot window enqueued before them; a launch marked to wait, and every
+// assembly, small-front or finalize step, first waits for the second stream's work so far;
+// the second stream is joined back before returning, so the caller's stream (and a graph
+// captured on it) holds everything.
+void enqueue_launches(qdmf_ctx* h, const DevPlan& D, const PivotParams& pp, bool count_work) {
+    bool pending = false;  // second-stream work not yet joined
+    for (const Launch& L : h->P.launches) {
+        hipStream_t st = h->stream;
+        if (L.stream == 1) {
+            st = h->stream2;
+            (void)hipStreamWaitEvent(st, h->ev_win, 0);
+        } else if (pending && (L.wait || L.kind == L_SMALL || L.kind == L_ASSEMBLE || L.kind == L_FINALIZE ||
+                               L.nfin > 0)) {
+            (void)hipStreamWaitEvent(h->stream, h->ev_s2, 0);
+            pending = false;
+        }
+        {
+            ProfScope ps(h, L.kind, count_work ? L.flops : 0.0, count_work ? L.bytes : 0.0, st);
+            launch_factor_step(D, L, h->tasks_dev, pp, st);
+        }
+        if (L.stream == 1) {
+            (void)hipEventRecord(h->ev_s2, st);
+            pending = true;
+        } else if (L.kind == L_WINDOW && h->stream2) {
+            (void)hipEventRecord(h->ev_win, h->stream);
+        }
+    }
+    if (pending) (void)hipStreamWaitEvent(h->stream, h->ev_s2, 0);
+}
+
+// The second stream and its events, when the plan has launches for it.
+int ensure_stream2(qdmf_ctx* h) {
+    if (h->stream2) return 0;
+    bool any = false;
+    for (const Launch& L : h->P.launches) any = any || L.stream == 1;
+    if (!any) return 0;
+    const hipError_t e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        h->stream2 = nullptr;
+        return QDMF_ERR_HIP;
+    }
+    if (hipEventCreateWithFlags(&h->ev_win, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_s2, hipEventDisableTiming) != hipSuccess)
+        return QDMF_ERR_HIP;
+    return 0;
+}
+
 // shifts_dev: per-system [rho(nsys), delta(nsys)] on the device, or NULL (rho, delta for all)
 void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delta, const double* shifts_dev,
                        int32_t prec) {
@@ -415,10 +528,7 @@ void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delt
     launch_theta(h->D, theta, rho, delta, shifts_dev, shifts_dev ? shifts_dev + h->P.nsys : nullptr, h->stream);
     launch_values_n(h->D, h->knnz, h->stream);
     launch_knorm(h->D, h->stream);
-    for (const Launch& L : h->P.launches) {
-        ProfScope ps(h, L.kind, L.flops, L.bytes);
-        launch_factor_step(h->D, L, h->tasks_dev, pp, h->stream);
-    }
+    enqueue_launches(h, h->D, pp, true);
     launch_inv(h->D, h->inv_tasks_dev, (int64_t)h->P.inv_tasks.size(), h->stream);
     launch_factor_stats(h->D, pp, h->stats_part, h->stream);
     if (!pp.mixed || pp.mixed_check == 0) return;
@@ -426,6 +536,7 @@ void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delt
     // (the same launches, gated to those systems' supernodes).  Eager execution reads the count
     // and skips the second pass when it is zero; a captured graph always holds it.
     launch_mixed_check(h->D, pp, h->max_sys_piv, h->stream);
+    const int64_t redo_seg = seg_open(h, h->D.redo + h->P.nsys, 1);
     if (!h->capturing) {
         int32_t nredo = 0;
         if (hipMemcpyAsync(&nredo, h->D.redo + h->P.nsys, sizeof(nredo), hipMemcpyDeviceToHost, h->stream) !=
@@ -437,12 +548,10 @@ void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delt
     DevPlan G = h->D;
     G.gate = h->D.redo;
     const PivotParams p64 = pivot_params(h, QDMF_FP64);
-    for (const Launch& L : h->P.launches) {
-        ProfScope ps(h, L.kind, 0.0, 0.0);
-        launch_factor_step(G, L, h->tasks_dev, p64, h->stream);
-    }
+    enqueue_launches(h, G, p64, false);
     launch_inv(G, h->inv_tasks_dev, (int64_t)h->P.inv_tasks.size(), h->stream);
     launch_factor_stats(h->D, p64, h->stats_part, h->stream);
+    if (redo_seg >= 0) seg_skip(h, {redo_seg}, seg_open(h, nullptr, 0));
 }
 
 // (L D L^T)^{-1} src -> dst, level by level (forward leaves first, backward roots first).
@@ -522,7 +631,9 @@ int enqueue_gmres_correction(qdmf_ctx* h) {
     launch_gm_start(G, S.active, nu, st);  // per unit: the refinement continues and r != 0
     launch_gm_gate(G, nr, ns, st);  // per rhs: some unit takes the first step
     launch_vscale(D, S.r, G.nrm, Vb(0), nr, G.act, st);
+    std::vector<int64_t> steps;  // cut capture: the segments of Krylov steps 1 ..
     for (int j = 0; j < GM_M; ++j) {
+        if (j > 0) steps.push_back(seg_open(h, G.ract, nr));
         if (!h->capturing && !h->nopoll && j > 0) {
             if (hipMemcpyAsync(h->gm_act_host, G.ract, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, st) !=
                     hipSuccess ||
@@ -542,6 +653,7 @@ int enqueue_gmres_correction(qdmf_ctx* h) {
         launch_vscale(D, h->gm_W, G.nrm, Vb(j + 1), nr, G.act, st);
         launch_gm_rotate(G, j, nr, ns, GM_TOL, st);
     }
+    if (h->capturing && h->cut_capture) seg_skip(h, steps, seg_open(h, nullptr, 0));
     launch_gm_solve(G, nu, st);
     launch_vcombine(D, h->gm_Z, GM_M, G.y, S.d, nr, false, nullptr, G.kr, st);  // d = Z y per unit
     return 0;
@@ -566,7 +678,9 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
     enqueue_ldlt_solve(h, S.b, S.x, nullptr);
     launch_residual(D, S, S.x, st);
     launch_berr_steps(D, S, 0, target, max_steps, st);
+    std::vector<int64_t> passes;  // cut capture: the segments of the refinement passes
     for (int it = 0; it < max_steps; ++it) {
+        passes.push_back(seg_open(h, S.active, (int32_t)((int64_t)S.nrhs * h->P.nsys)));
         // Eager solves look at the refinement flags and stop launching once every
         // right-hand side has met the target; a captured graph (and qdmf_solve_noalloc)
         // keeps all passes and the kernels of a finished right-hand side return at once.
@@ -590,6 +704,7 @@ void enqueue_solve(qdmf_ctx* h, const double* r7, const double* r1, double* dx, 
         launch_residual(D, S, S.x, st);
         launch_berr_steps(D, S, 1, target, max_steps, st);
     }
+    if (h->capturing && h->cut_capture) seg_skip(h, passes, seg_open(h, nullptr, 0));
     launch_recover(D, S, r7, dx, dy, st);
     h->stat_berr = S.berr;
     h->stat_steps = S.steps;
@@ -649,6 +764,8 @@ void qdmf_default_options(qdmf_options* o) {
     o->syrk_group = 4;
     o->syrk_tile_front = 0;
     o->mixed_check = 2;
+    o->lookahead_front = 0;
+    o->graph_poll = 1;
 }
 
 int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_options* opt) {
@@ -660,6 +777,7 @@ int qdmf_create(qdmf_handle* out, int device, void* hip_stream, const qdmf_optio
     if (h->opt.nb != 64 || h->opt.small_front < 1 || h->opt.small_front > 64 || h->opt.split_solve_front < 1 ||
         h->opt.syrk_group_front < 0 || h->opt.syrk_group < 1 || h->opt.syrk_group > SYRK_GROUP_MAX ||
         h->opt.syrk_tile_front < 0 || h->opt.mixed_check < 0 || h->opt.mixed_check > 3 ||
+        h->opt.lookahead_front < 0 ||
         h->opt.max_refine < 0 ||
         h->opt.max_refine_mixed < 0 || h->opt.ordering < QDMF_ORDER_AMD || h->opt.ordering > QDMF_ORDER_AUTO) {
         delete h;
@@ -715,6 +833,7 @@ int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     ao.syrk_group_front = h->opt.syrk_group_front;
     ao.syrk_group = h->opt.syrk_group;
     ao.syrk_tile_front = h->opt.syrk_tile_front;
+    ao.lookahead_front = h->opt.lookahead_front;
     ao.f_mix = h->opt.f_mix;
     ao.user_perm = user_perm;
     ao.nsys = nsys;
@@ -733,6 +852,7 @@ int analyse_impl(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr, con
     h->h_front = h->P.sn_f;
     if (!h->host_only) {
         rc = upload_plan(h);
+        if (!rc) rc = ensure_stream2(h);
         if (rc) {
             free_list(h->plan_allocs);
             return rc;
@@ -1182,8 +1302,25 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     // every buffer the captured work uses exists before the capture starts
     if (prec == QDMF_MIXED && h->fp32_fronts && h->opt.max_refine_mixed > 0 && (rc = ensure_gmres(h))) return rc;
     destroy_graph(h);
+    const int32_t units = nrhs * h->P.nsys;
+    if (h->opt.graph_poll && h->poll_cap < units) {
+        if (h->poll_host) (void)hipHostFree(h->poll_host);
+        h->poll_host = nullptr;
+        h->poll_cap = 0;
+        if (hipHostMalloc((void**)&h->poll_host, sizeof(int32_t) * std::max(units, 1), hipHostMallocDefault) !=
+            hipSuccess) {
+            h->poll_host = nullptr;
+            return QDMF_ERR_OOM;
+        }
+        h->poll_cap = std::max(units, 1);
+    }
     if (hipStreamSynchronize(h->stream) != hipSuccess) return QDMF_ERR_HIP;
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return QDMF_ERR_HIP;
+    h->cut_capture = h->opt.graph_poll != 0;
+    h->capture_failed = false;
+    h->cur_flag = nullptr;
+    h->cur_nflag = 0;
+    h->skip_pending.clear();
     // the enqueue code reads the precision of the factorisation it follows; nothing has run
     // yet, so the handle's own state is restored after the capture
     const int32_t prec_before = h->last_prec;
@@ -1191,17 +1328,14 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     h->capturing = true;
     enqueue_factorise(h, theta_dev, rho, delta, nullptr, prec);
     for (int32_t q = 0; q < nsolves; ++q) enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
+    seg_close(h);
     h->capturing = false;
+    h->cut_capture = false;
     h->last_prec = prec_before;
-    hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(h->stream, &g) != hipSuccess || !g) {
-        (void)hipGetLastError();
-        if (g) (void)hipGraphDestroy(g);
-        return QDMF_ERR_HIP;
-    }
-    h->graph = g;
-    if (hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGetLastError();
+    for (size_t q = 0; q < h->segs.size(); ++q) h->segs[q].skip_to = q + 1;
+    for (const auto& sk : h->skip_pending) h->segs[(size_t)sk.first].skip_to = (size_t)sk.second;
+    h->skip_pending.clear();
+    if (h->capture_failed) {
         destroy_graph(h);
         return QDMF_ERR_HIP;
     }
@@ -1212,9 +1346,26 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
 }
 
 int qdmf_graph_launch(qdmf_handle h) {
-    if (!h || !h->gexec) return QDMF_ERR_INVALID_ARG;
+    if (!h || h->segs.empty()) return QDMF_ERR_INVALID_ARG;
     if (set_device(h)) return QDMF_ERR_HIP;
-    if (hipGraphLaunch(h->gexec, h->stream) != hipSuccess) return QDMF_ERR_HIP;
+    for (size_t q = 0; q < h->segs.size();) {
+        const qdmf_ctx::GraphSeg& g = h->segs[q];
+        if (g.flag) {  // a decision point: read its flags, as an eager solve does
+            if (g.nflag > h->poll_cap ||
+                hipMemcpyAsync(h->poll_host, g.flag, sizeof(int32_t) * g.nflag, hipMemcpyDeviceToHost, h->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(h->stream) != hipSuccess)
+                return QDMF_ERR_HIP;
+            bool any = false;
+            for (int32_t u = 0; u < g.nflag; ++u) any = any || h->poll_host[u] != 0;
+            if (!any) {
+                q = g.skip_to;
+                continue;
+            }
+        }
+        if (g.x && hipGraphLaunch(g.x, h->stream) != hipSuccess) return QDMF_ERR_HIP;
+        ++q;
+    }
     // the handle now holds the graph's factorisation and, with solves, their statistics
     h->last_prec = h->graph_prec;
     h->factorised = true;
@@ -1440,6 +1591,7 @@ int qdmf_choose_mode(qdmf_handle h, int32_t m, int32_t n, const int64_t* colptr,
     ao.syrk_group_front = h->opt.syrk_group_front;
     ao.syrk_group = h->opt.syrk_group;
     ao.syrk_tile_front = h->opt.syrk_tile_front;
+    ao.lookahead_front = h->opt.lookahead_front;
     ao.f_mix = h->opt.f_mix;
     {  // the augmented system first
         Plan Pa;
@@ -1478,9 +1630,13 @@ void qdmf_destroy(qdmf_handle h) {
         (void)hipStreamSynchronize(h->stream);
     }
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->ev_win) (void)hipEventDestroy(h->ev_win);
+    if (h->ev_s2) (void)hipEventDestroy(h->ev_s2);
+    if (h->stream2) (void)hipStreamDestroy(h->stream2);
     if (h->act_host) (void)hipHostFree(h->act_host);
     if (h->gm_act_host) (void)hipHostFree(h->gm_act_host);
     if (h->shift_host) (void)hipHostFree(h->shift_host);
+    if (h->poll_host) (void)hipHostFree(h->poll_host);
     destroy_graph(h);
     free_list(h->solve_allocs);
     free_list(h->plan_allocs);

@@ -2155,38 +2155,37 @@ __global__ __launch_bounds__(256) void k_sfdiag(DevPlan D, DevSolve S, const Tas
     }
 }
 
-// rows below block J: y_i -= sum_k L(i, k0 + k) y_{k0 + k} over the block's 256 columns, 64 at
-// a time with that part of the row in registers; the block's y values pass through LDS sixteen
-// right-hand sides at a time; one row per thread, 256 rows per workgroup
+// rows below block J: y_i -= sum_k L(i, k0 + k) y_{k0 + k} over the block's 256 columns.  One
+// workgroup takes 64 rows of the task's 256-row chunk (blockIdx.y); wave q sums the block's
+// columns 64q .. 64q+63 with that part of its row in registers (lane = row), and wave 0 adds
+// the four partial sums in column order.  The block's y values pass through LDS sixteen
+// right-hand sides at a time.
 __global__ __launch_bounds__(256) void k_sfupd(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
                                                const int32_t* active) {
     __shared__ double Yb[SB * 16];
+    __shared__ double part[4 * 16 * 64];
     if (big_inactive(S, active)) return;
     const Task t = tasks[t0 + blockIdx.x];
     const int s = t.s, k0 = SB * t.k0;
     const int f = D.sn_f[s], p = D.sn_p[s], ld = D.sn_ld[s];
     const int k1 = min(k0 + SB, p), nbJ = k1 - k0;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, q = tid >> 6, lane = tid & 63;
     double* Ys = S.Y + D.yoff[s];
-    const int i = k1 + 256 * t.a + tid;
-    const double* Li = D.front + D.sn_off[s] + min(i, f - 1) + (int64_t)k0 * ld;
+    const int i = k1 + 256 * t.a + 64 * (int)blockIdx.y + lane;
+    const int nb = min(64, nbJ - 64 * q);  // columns of this wave's sub-block (<= 0: none)
+    const double* Li = D.front + D.sn_off[s] + min(i, f - 1) + (int64_t)(k0 + 64 * q) * ld;
+    double l[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) l[k] = (k < nb && i < f) ? Li[(int64_t)k * ld] : 0.0;
     for (int rg = 0; rg < S.nrhs; rg += 16) {
         const int nr = min(16, S.nrhs - rg);
-        __syncthreads();  // the previous group is done with Yb
+        __syncthreads();  // the previous group is done with Yb and part
         for (int idx = tid; idx < SB * 16; idx += 256) {
             const int k = idx & (SB - 1), rr = idx / SB;
             Yb[idx] = (k < nbJ && rr < nr) ? Ys[k0 + k + (int64_t)(rg + rr) * S.ytot] : 0.0;
         }
         __syncthreads();
-        if (i >= f) continue;
-        double acc[16];
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) acc[rr] = 0.0;
-        for (int q = 0; 64 * q < nbJ; ++q) {
-            const int nb = min(64, nbJ - 64 * q);
-            double l[64];
-#pragma unroll
-            for (int k = 0; k < 64; ++k) l[k] = k < nb ? Li[(int64_t)(64 * q + k) * ld] : 0.0;
+        if (nb > 0) {
 #pragma unroll
             for (int rr = 0; rr < 16; ++rr) {
                 if (rr >= nr) break;
@@ -2197,13 +2196,17 @@ __global__ __launch_bounds__(256) void k_sfupd(DevPlan D, DevSolve S, const Task
                     a0 += l[k] * yb[k];
                     a1 += l[k + 1] * yb[k + 1];
                 }
-                acc[rr] += a0 + a1;
+                part[(q * 16 + rr) * 64 + lane] = a0 + a1;
             }
         }
-        for (int rr = 0; rr < nr; ++rr) {
-            if (active && !active[rg + rr]) continue;
-            Ys[i + (int64_t)(rg + rr) * S.ytot] -= acc[rr];
-        }
+        __syncthreads();
+        if (q == 0 && i < f)
+            for (int rr = 0; rr < nr; ++rr) {
+                if (active && !active[rg + rr]) continue;
+                double acc = 0.0 + part[rr * 64 + lane];  // as a sum started at zero
+                for (int w = 1; 64 * w < nbJ; ++w) acc += part[(w * 16 + rr) * 64 + lane];
+                Ys[i + (int64_t)(rg + rr) * S.ytot] -= acc;
+            }
     }
 }
 
@@ -2248,9 +2251,9 @@ __global__ __launch_bounds__(256) void k_sbload(DevPlan D, DevSolve S, const Tas
 }
 
 // partial sums over one 256-row chunk below block J: P[(b * SB + k) * nrhs + r] =
-// sum_i L(i, k0 + k) y_i[r] for the block's 256 columns, 64 columns at a time; the rows are
-// taken in 64-row tiles loaded coalesced (lane = row) and summed through LDS (lane = column),
-// right-hand sides eight at a time
+// sum_i L(i, k0 + k) y_i[r] for 64 of the block's columns (sub-block blockIdx.y); the rows
+// are taken in 64-row tiles loaded coalesced (lane = row) and summed through LDS (lane =
+// column), right-hand sides eight at a time
 __global__ __launch_bounds__(256) void k_sbpart(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
                                                 const int32_t* active) {
     __shared__ double Lt[64 * 65];
@@ -2265,7 +2268,9 @@ __global__ __launch_bounds__(256) void k_sbpart(DevPlan D, DevSolve S, const Tas
     const double* F = D.front + D.sn_off[s];
     const double* Ys = S.Y + D.yoff[s];
     const int r0 = k1 + 256 * t.a, r1 = min(f, r0 + 256);
-    for (int a = 0; 64 * a < nbJ; ++a) {
+    {
+        const int a = (int)blockIdx.y;  // the block's 64-column sub-block
+        if (64 * a >= nbJ) return;
         const int k0 = kJ + 64 * a, nb = min(64, nbJ - 64 * a);
         for (int rg = 0; rg < S.nrhs; rg += 8) {
             const int nr = min(8, S.nrhs - rg);
@@ -3297,10 +3302,10 @@ void launch_big_solve(const DevPlan& D, const DevSolve& S, const SolveLaunch& L,
     switch (L.kind) {
         case S_GATHER: hipLaunchKernelGGL(k_sgather, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
         case S_FDIAG: hipLaunchKernelGGL(k_sfdiag, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
-        case S_FUPD: hipLaunchKernelGGL(k_sfupd, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_FUPD: hipLaunchKernelGGL(k_sfupd, dim3(g, 4), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
         case S_FFIN: hipLaunchKernelGGL(k_sffin, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
         case S_BLOAD: hipLaunchKernelGGL(k_sbload, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
-        case S_BPART: hipLaunchKernelGGL(k_sbpart, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
+        case S_BPART: hipLaunchKernelGGL(k_sbpart, dim3(g, SB / 64), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
         case S_BDIAG: hipLaunchKernelGGL(k_sbdiag, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
         case S_BSTORE: hipLaunchKernelGGL(k_sbstore, dim3(g), dim3(256), 0, s, D, S, stasks, L.task0, active); break;
         default: break;

@@ -49,6 +49,9 @@ struct Launch {
     int64_t fin0 = 0, nfin = 0;  // trailing update: the level's finalize tasks run in the same launch
     int64_t nmix = 0;      // 128-tile trailing update: its first nmix tasks belong to fronts of
                            // order >= f_mix (FP32 products in mixed precision)
+    int8_t stream = 0;     // 0: the library's stream; 1: the second (lookahead) stream, after
+                           // the last pivot window enqueued before it on the first
+    int8_t wait = 0;       // on the first stream: wait for the second stream's work so far
     double flops = 0;      // algorithmic work of the launch
     double bytes = 0;
 };
@@ -172,6 +175,8 @@ struct AnalyseOptions {
     int syrk_group_front = 1024;   // fronts at least this big: grouped trailing updates (0: none)
     int syrk_group = 4;            // windows per group
     int syrk_tile_front = 0;       // full trailing updates of at least this many rows: 128 x 128 tiles (0: never)
+    int lookahead_front = 0;       // fronts at least this big: full updates past the next group's
+                                   // columns on the second stream (0: none)
     int f_mix = 1024;              // mixed precision: fronts of at least this order take FP32 products
     const int32_t* user_perm = nullptr;
     // batch: nsys systems, system s owns columns [col_off[s], col_off[s+1]) and rows

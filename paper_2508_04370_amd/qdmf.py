@@ -52,7 +52,8 @@ class qdmf_options(C.Structure):
                 ("amalgamate", C.c_int32), ("f_mix", C.c_int32), ("small_front", C.c_int32),
                 ("mem_cap_bytes", C.c_int64), ("split_solve_front", C.c_int32),
                 ("syrk_group_front", C.c_int32), ("syrk_group", C.c_int32),
-                ("syrk_tile_front", C.c_int32), ("mixed_check", C.c_int32)]
+                ("syrk_tile_front", C.c_int32), ("mixed_check", C.c_int32),
+                ("lookahead_front", C.c_int32), ("graph_poll", C.c_int32)]
 
 
 class qdmf_mode_choice(C.Structure):

@@ -417,18 +417,25 @@ def test_mixed_precision_hard_case_is_safe(torch_dev, seed):
     assert (ss["status"] == Q.QDMF_WARN_NOT_CONVERGED) == (ss["berr_nw"] > 1e-10)
 
 
-@pytest.mark.parametrize("case", ["small", "grouped"])
+@pytest.mark.parametrize("case", ["small", "one_graph", "grouped", "lookahead"])
 def test_graph_replay_matches_eager(torch_dev, case):
     """factorise + 2 solves captured once; replays read refreshed Theta and rhs in place
     and must reproduce the eager results bitwise, every replay.  "grouped": fronts of up to
-    ~300 rows with their trailing updates grouped three windows at a time."""
+    ~300 rows with their trailing updates grouped three windows at a time; "lookahead": the
+    same with the updates past the next group on the second stream, which the capture forks
+    and joins; "one_graph": the capture is not cut at the refinement decisions (graph_poll =
+    0), so every pass is in the graph and finished ones return at once."""
     torch, dev = torch_dev
     from paper_2508_04370_amd import qdmf as Q
-    if case == "small":
+    if case in ("small", "one_graph"):
         lp, opts = W.as_staircase(periods=4, rows=50, cols=100, link_cols=10), {}
+        if case == "one_graph":
+            opts["graph_poll"] = 0
     else:
         lp = W.as_staircase(periods=4, rows=300, cols=600, link_cols=60, seed=24)
         opts = dict(syrk_group_front=64, syrk_group=3)
+        if case == "lookahead":
+            opts["lookahead_front"] = 64
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         s = Q.Solver(lp, device=0, stream=stream.cuda_stream, **opts)
