@@ -8,6 +8,8 @@ Theta (already resident in HBM), the numeric factorisation, and the predictor an
 corrector solve (Section 4.7: 1 + k directions with k >= 1), each refined in FP64 to its
 backward-error target (1e-12 FP64 path, 1e-10 mixed path).  Prints one JSON line: value = the
 FP64 path's algorithmic GFLOP/s, with the mixed path's time, accuracy and speedup beside it.
+The mixed path runs with the workload's tuned options; when those leave no front with FP32
+products, `mixed_fp32_products` also times the mixed path with them on (f_mix = 1024).
 
 The roofline object describes the kernel kind that takes the most time in an FP64 step: its
 launches inside the timed region are bracketed with HIP events on the library's stream and its
@@ -379,6 +381,8 @@ def main():
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuner's file for the workload")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-line", action="store_true",
+                    help="skip the extra mixed run with FP32 products when the tuned mixed path has none")
     ap.add_argument("--c0", action="store_true",
                     help="instead: the dense-front sweep (one JSON line per front order and pivot count)")
     ap.add_argument("--c0-sizes", default="1024,2048,4096,8192")
@@ -488,6 +492,21 @@ def main():
         f64, mx = out["fp64"], out["mixed"]
         out["mixed_vs_fp64"] = {"speedup": round(f64["ms_per_step"] / mx["ms_per_step"], 4),
                                 "both_within_1e-10": bool(f64["berr_nw_max"] <= 1e-10 and mx["berr_nw_max"] <= 1e-10)}
+    if "fp64" in res and "mixed" in res and opts.get("f_mix", 1024) > sym["max_front"] and not args.no_fp32_line:
+        # the tuned mixed configuration takes no FP32 products on this workload (they did not
+        # pay): time the mixed path with them on (the default f_mix) as well, same steps
+        print("[bench] mixed with FP32 products (f_mix 1024)", file=sys.stderr, flush=True)
+        o32 = dict(opts, f_mix=1024)
+        r32, _, _ = run_gpu(lp, o32, ["mixed"], args.steps, args.warmup, args.nsolves, False)
+        r = r32["mixed"]
+        mms = r["wall"] * 1e3 / args.steps
+        out["mixed_fp32_products"] = {
+            "f_mix": 1024, "ms_per_step": round(mms, 4), "gflops": round(work / (mms * 1e-3) / 1e9, 3),
+            "berr_nw_max": max(r["berr"]), "target_met": bool(max(r["berr"]) <= 1e-10),
+            "refine_steps_mean": float(np.mean(r["steps"])),
+            "speedup_vs_fp64": round(out["fp64"]["ms_per_step"] / mms, 4),
+            "kernel_ms_per_step_by_kind": {Q.KERNEL_KIND_NAMES[k]: round(v["total_ms"], 3)
+                                           for k, v in r["per_kind"].items()}}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

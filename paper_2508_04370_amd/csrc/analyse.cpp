@@ -1001,24 +1001,28 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
         P.bwd_ptr[l + 1] = (int64_t)P.bwd_plan.size();
     }
 
-    // ----- inverses of the diagonal blocks for the levels solved by the one-workgroup kernels
-    // with blocks of more than 8 pivots (levels whose fronts are all at most 64 rows use one
-    // wavefront per supernode instead, and blocks of up to 8 pivots a short serial sweep)
+    // ----- inverses of the 64-pivot diagonal blocks: for the levels solved by the
+    // one-workgroup kernels with blocks of more than 8 pivots (levels whose fronts are all at
+    // most 64 rows use one wavefront per supernode instead, and blocks of up to 8 pivots a
+    // short serial sweep), and for every supernode of the multi-workgroup solves
     P.inv_off.assign(ns, -1);
     P.inv_total = 0;
+    auto add_inv = [&](int32_t t) {
+        const int32_t p = P.sn_p[t], nblk = (p + 63) / 64, nbl = p - 64 * (nblk - 1);
+        if (p <= 0) return;
+        P.inv_off[t] = P.inv_total;
+        P.inv_total += 4096 * (int64_t)(nblk - 1) + (int64_t)nbl * nbl;
+        for (int32_t j = 0; j < nblk; ++j) P.inv_tasks.push_back(Task{t, j, 0, 0});
+    };
     for (int32_t l = 0; l < P.nlevels; ++l) {
         int32_t mf = 0, mp = 0;
         for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) {
             mf = std::max(mf, P.sn_f[P.lvl_sn[q]]);
             mp = std::max(mp, P.sn_p[P.lvl_sn[q]]);
         }
-        if (mf <= 64 || mp <= 8) continue;
-        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) {
-            const int32_t t = P.lvl_sn[q], p = P.sn_p[t], nblk = (p + 63) / 64, nbl = p - 64 * (nblk - 1);
-            P.inv_off[t] = P.inv_total;
-            P.inv_total += 4096 * (int64_t)(nblk - 1) + (int64_t)nbl * nbl;
-            for (int32_t j = 0; j < nblk; ++j) P.inv_tasks.push_back(Task{t, j, 0, 0});
-        }
+        if (mf > 64 && mp > 8)
+            for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) add_inv(P.lvl_sn[q]);
+        for (int64_t q = P.lvl_ptr[l] + P.lvl_small[l]; q < P.lvl_ptr[l + 1]; ++q) add_inv(P.lvl_sn[q]);
     }
 
     // ----- solve work per level (one pass, one rhs): L panel read once, vectors in and out

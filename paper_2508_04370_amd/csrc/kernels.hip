@@ -413,7 +413,21 @@ __global__ __launch_bounds__(256) void k_assemble(DevPlan D, const Task* tasks, 
         const int cp = D.sn_p[ch], cb = D.sn_f[ch] - cp, cld = D.sn_ld[ch];
         const int32_t* rel = D.rel + D.rel_ptr[ch];
         const double* col = D.front + D.sn_off[ch] + (int64_t)(cp + lo) * cld + cp;
-        for (int a = lo + tid; a < cb; a += 256) buf[rel[a] - j] += col[a];
+        // four entries' loads in flight per thread; the rows are distinct, so the order of the
+        // additions into buf is that of the children alone
+        for (int a = lo + tid; a < cb; a += 1024) {
+            double v[4];
+            int r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = a + 256 * u;
+                v[u] = x < cb ? col[x] : 0.0;
+                r[u] = x < cb ? rel[x] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (r[u] >= 0) buf[r[u] - j] += v[u];
+        }
         __syncthreads();
     }
     double* out = D.front + D.sn_off[s] + (int64_t)j * ld + j;
@@ -2096,11 +2110,14 @@ __global__ __launch_bounds__(256) void k_sgather(DevPlan D, DevSolve S, const Ta
 constexpr int SB = SOLVE_BLOCK;
 static_assert(SB == 256, "one row per thread of a 256-thread workgroup within a block");
 
-// forward: y_J <- L_JJ^{-1} y_J for the block J of 256 pivots, right-hand sides eight at a time
+// forward: y_J <- L_JJ^{-1} y_J for the block J of 256 pivots, right-hand sides eight at a
+// time: per 64-pivot sub-block, its precomputed inverse applied by all 256 threads, then the
+// update of the block's later rows
 __global__ __launch_bounds__(256) void k_sfdiag(DevPlan D, DevSolve S, const Task* tasks, int64_t t0,
                                                 const int32_t* active) {
     __shared__ double Lb[64 * 65];
     __shared__ double yb[SB * 8];
+    __shared__ double part[256];
     if (big_inactive(S, active)) return;
     const Task t = tasks[t0 + blockIdx.x];
     const int s = t.s, k0 = SB * t.k0;
@@ -2118,13 +2135,15 @@ __global__ __launch_bounds__(256) void k_sfdiag(DevPlan D, DevSolve S, const Tas
         for (int a = 0; 64 * a < nbJ; ++a) {
             const int nb = min(64, nbJ - 64 * a);
             __syncthreads();  // yb written; the previous sub-block's update is done with Lb
-            stage_block<64>(Lb, F, ld, k0 + 64 * a, nb, tid);
+            {
+                BlockRegs<64> b;
+                load_inv<64>(b, D.linv + D.inv_off[s] + 4096 * (int64_t)(4 * t.k0 + a), nb, tid);
+                store_block<64>(Lb, b, tid);
+            }
             __syncthreads();
-            for (int rr = wv; rr < nr; rr += 4) {
+            for (int rr = 0; rr < nr; ++rr) {  // rr and active[] are the same for the workgroup
                 if (active && !active[rg + rr]) continue;
-                double* y = yb + SB * rr + 64 * a;
-                const double v = trsv_fwd_wave<64>(Lb, lane < nb ? y[lane] : 0.0, lane);
-                if (lane < nb) y[lane] = v;
+                block_inv_apply<64, false>(Lb, yb + SB * rr + 64 * a, nb, part, tid);
             }
             __syncthreads();
             // the rest of the block: rows 64 (a + 1) .. nbJ, columns of sub-block a
@@ -2370,13 +2389,15 @@ __global__ __launch_bounds__(256) void k_sbdiag(DevPlan D, DevSolve S, const Tas
                                                          part[(2 * 64 + lane) * 8 + rr]) + part[(3 * 64 + lane) * 8 + rr];
             }
             __syncthreads();
-            stage_block<64>(Lb, F, ld, kJ + 64 * a, nb, tid);
+            {
+                BlockRegs<64> bl;
+                load_inv<64>(bl, D.linv + D.inv_off[s] + 4096 * (int64_t)(4 * t.k0 + a), nb, tid);
+                store_block<64>(Lb, bl, tid);
+            }
             __syncthreads();
-            for (int rr = wv; rr < nr; rr += 4) {
+            for (int rr = 0; rr < nr; ++rr) {  // rr and active[] are the same for the workgroup
                 if (active && !active[rg + rr]) continue;
-                double* y = yb + SB * rr + 64 * a;
-                const double vv = trsv_bwd_wave<64>(Lb, lane < nb ? y[lane] : 0.0, lane);
-                if (lane < nb) y[lane] = vv;
+                block_inv_apply<64, true>(Lb, yb + SB * rr + 64 * a, nb, part, tid);
             }
         }
         __syncthreads();
