@@ -389,6 +389,13 @@ __global__ __launch_bounds__(64) void k_small(DevPlan D, const Task* tasks, int6
     store_pivots(S, D, c0, 0, p, lane);
 }
 
+// readlane of a wave-uniform lane's 64-bit integer
+__device__ inline int64_t readlane_i64(int64_t v, int l) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // Large fronts: one workgroup per front column.  The column is summed in LDS from the
 // original entries and, children in ascending order, the children's contribution-block
 // columns that map onto it (the parent pulls; no atomics), then written once.  The list of
@@ -408,11 +415,25 @@ __global__ __launch_bounds__(256) void k_assemble(DevPlan D, const Task* tasks, 
         for (int64_t e = D.kcol_ptr[c0 + j] + tid; e < e1; e += 256) buf[D.kloc[e] - j] = D.kval[e];
     }
     __syncthreads();
-    for (int q = t.a; q < t.a + t.b; ++q) {
-        const int ch = D.asm_child[q], lo = D.asm_col[q];
-        const int cp = D.sn_p[ch], cb = D.sn_f[ch] - cp, cld = D.sn_ld[ch];
-        const int32_t* rel = D.rel + D.rel_ptr[ch];
-        const double* col = D.front + D.sn_off[ch] + (int64_t)(cp + lo) * cld + cp;
+    // the children's descriptions, 64 at a time (every wave loads the same: lane i those of
+    // child q0 + i) and read by readlane, so a child costs one load latency, not three
+    const int lane = tid & 63;
+    for (int q0 = t.a; q0 < t.a + t.b; q0 += 64) {
+    const int nq = min(64, t.a + t.b - q0);
+    int m_lo = 0, m_cb = 0;
+    int64_t m_rel = 0, m_col = 0;
+    if (lane < nq) {
+        const int ch = D.asm_child[q0 + lane];
+        const int cp = D.sn_p[ch];
+        m_lo = D.asm_col[q0 + lane];
+        m_cb = D.sn_f[ch] - cp;
+        m_rel = D.rel_ptr[ch];
+        m_col = D.sn_off[ch] + (int64_t)(cp + m_lo) * D.sn_ld[ch] + cp;
+    }
+    for (int k = 0; k < nq; ++k) {
+        const int lo = __builtin_amdgcn_readlane(m_lo, k), cb = __builtin_amdgcn_readlane(m_cb, k);
+        const int32_t* rel = D.rel + readlane_i64(m_rel, k);
+        const double* col = D.front + readlane_i64(m_col, k);
         // four entries' loads in flight per thread; the rows are distinct, so the order of the
         // additions into buf is that of the children alone
         for (int a = lo + tid; a < cb; a += 1024) {
@@ -429,6 +450,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevPlan D, const Task* tasks, 
                 if (r[u] >= 0) buf[r[u] - j] += v[u];
         }
         __syncthreads();
+    }
     }
     double* out = D.front + D.sn_off[s] + (int64_t)j * ld + j;
     for (int i = tid; i < nr; i += 256) out[i] = buf[i];
@@ -456,11 +478,25 @@ __global__ __launch_bounds__(256) void k_assemble_w(DevPlan D, const Task* tasks
         for (int64_t e = D.kcol_ptr[c0 + j] + lane; e < e1; e += 64) buf[D.kloc[e] - j] = D.kval[e];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    for (int q = t.a; q < t.a + t.b; ++q) {
-        const int ch = D.asm_child[q], lo = D.asm_col[q];
-        const int cp = D.sn_p[ch], cb = D.sn_f[ch] - cp, cld = D.sn_ld[ch];
-        const int32_t* rel = D.rel + D.rel_ptr[ch];
-        const double* col = D.front + D.sn_off[ch] + (int64_t)(cp + lo) * cld + cp;
+    // the children's descriptions, 64 at a time: lane i loads those of child q0 + i, and the
+    // loop below reads them with readlane, so a child costs one load latency (its rows and
+    // values), not three dependent ones
+    for (int q0 = t.a; q0 < t.a + t.b; q0 += 64) {
+    const int nq = min(64, t.a + t.b - q0);
+    int m_lo = 0, m_cb = 0;
+    int64_t m_rel = 0, m_col = 0;
+    if (lane < nq) {
+        const int ch = D.asm_child[q0 + lane];
+        const int cp = D.sn_p[ch];
+        m_lo = D.asm_col[q0 + lane];
+        m_cb = D.sn_f[ch] - cp;
+        m_rel = D.rel_ptr[ch];
+        m_col = D.sn_off[ch] + (int64_t)(cp + m_lo) * D.sn_ld[ch] + cp;
+    }
+    for (int k = 0; k < nq; ++k) {
+        const int lo = __builtin_amdgcn_readlane(m_lo, k), cb = __builtin_amdgcn_readlane(m_cb, k);
+        const int32_t* rel = D.rel + readlane_i64(m_rel, k);
+        const double* col = D.front + readlane_i64(m_col, k);
         for (int a0 = lo; a0 < cb; a0 += 256) {  // four rows per lane and trip, loads in flight together
             int ra[4];
             double va[4];
@@ -475,6 +511,7 @@ __global__ __launch_bounds__(256) void k_assemble_w(DevPlan D, const Task* tasks
                 if (ra[u] >= 0) buf[ra[u]] += va[u];
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
     }
     double* out = D.front + D.sn_off[s] + (int64_t)j * ld + j;
     for (int i = lane; i < nr; i += 64) out[i] = buf[i];
