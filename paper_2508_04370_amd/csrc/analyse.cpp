@@ -903,6 +903,7 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
     for (int32_t l = 0; l < P.nlevels; ++l) P.lvl_ptr[l + 1] += P.lvl_ptr[l];
     P.lvl_sn.resize(ns);
     P.lvl_small.assign(P.nlevels, 0);
+    P.lvl_wave.assign(P.nlevels, 0);
     {
         // a level that holds a front of at least split_solve_front pays the multi-workgroup
         // launches anyway (one diagonal solve and one update launch per SOLVE_BLOCK-pivot block
@@ -918,13 +919,17 @@ int build_plan(int32_t m, int32_t n, const int64_t* colptr, const int32_t* rowid
             return nb > 0 && P.sn_f[t] >= std::min(SPLIT_JOIN_FRONT, opt.split_solve_front) &&
                    (P.sn_p[t] + SOLVE_BLOCK - 1) / SOLVE_BLOCK <= nb;
         };
+        // per level: fronts of at most 64 rows (one wavefront each), the other one-workgroup
+        // supernodes, then the big ones
         std::vector<int64_t> fl(P.lvl_ptr.begin(), P.lvl_ptr.end() - 1);
-        for (int pass = 0; pass < 2; ++pass)
-            for (int32_t t = 0; t < ns; ++t)
-                if (split(t) == (pass == 1)) {
-                    P.lvl_sn[fl[P.sn_level[t]]++] = t;
-                    if (pass == 0) P.lvl_small[P.sn_level[t]]++;
-                }
+        for (int pass = 0; pass < 3; ++pass)
+            for (int32_t t = 0; t < ns; ++t) {
+                const int cls = split(t) ? 2 : (P.sn_f[t] <= 64 ? 0 : 1);
+                if (cls != pass) continue;
+                P.lvl_sn[fl[P.sn_level[t]]++] = t;
+                if (pass < 2) P.lvl_small[P.sn_level[t]]++;
+                if (pass == 0) P.lvl_wave[P.sn_level[t]]++;
+            }
     }
     // big supernodes: work-space rows and the launch sequence of each level
     P.yoff.assign(ns, -1);

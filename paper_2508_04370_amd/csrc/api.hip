@@ -42,6 +42,8 @@ struct qdmf_ctx {
     Task* stasks_dev = nullptr;               // tasks of the big-supernode solve launches
     Task* inv_tasks_dev = nullptr;            // diagonal blocks whose inverse the solves use
     std::vector<int32_t> maxf_lvl, maxp_lvl;  // per level: largest front order and pivot count
+                                              // of the one-workgroup solves
+    std::vector<int32_t> maxp_wave;           // per level: largest pivot count of the one-wavefront solves
     int64_t knnz = 0;
     int64_t max_sys_piv = 0;  // largest pivot count of one system
     bool fp32_fronts = false; // some trailing update belongs to a front of order >= f_mix
@@ -363,11 +365,15 @@ int upload_plan(qdmf_ctx* h) {
     // variant) per level, over the supernodes those kernels solve
     h->maxf_lvl.assign(P.nlevels, 1);
     h->maxp_lvl.assign(P.nlevels, 1);
-    for (int32_t l = 0; l < P.nlevels; ++l)
-        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) {
+    h->maxp_wave.assign(P.nlevels, 1);
+    for (int32_t l = 0; l < P.nlevels; ++l) {
+        for (int64_t q = P.lvl_ptr[l]; q < P.lvl_ptr[l] + P.lvl_wave[l]; ++q)
+            h->maxp_wave[l] = std::max(h->maxp_wave[l], P.sn_p[P.lvl_sn[q]]);
+        for (int64_t q = P.lvl_ptr[l] + P.lvl_wave[l]; q < P.lvl_ptr[l] + P.lvl_small[l]; ++q) {
             h->maxf_lvl[l] = std::max(h->maxf_lvl[l], P.sn_f[P.lvl_sn[q]]);
             h->maxp_lvl[l] = std::max(h->maxp_lvl[l], P.sn_p[P.lvl_sn[q]]);
         }
+    }
     if (hipDeviceSynchronize() != hipSuccess) return QDMF_ERR_HIP;
     return 0;
 }
@@ -563,18 +569,24 @@ void enqueue_ldlt_solve(qdmf_ctx* h, const double* src, double* dst, const int32
     hipStream_t st = h->stream;
     if (P.nsys > 1 && active && !per_rhs) active = S.ract;
     launch_permute(h->D, S, src, active, st);
-    // per level: the supernodes solved one per workgroup, then the steps of the big ones
+    // per level: the supernodes of fronts up to 64 rows one per wavefront, the other small ones
+    // one per workgroup, then the steps of the big ones
+    auto level = [&](bool fwd, int32_t l) {
+        const int64_t b = P.lvl_ptr[l];
+        const int32_t nw = P.lvl_wave[l];
+        launch_solve_level(fwd, h->D, S, h->lvl_sn_dev, b, (unsigned)nw, 64, h->maxp_wave[l], active, st);
+        launch_solve_level(fwd, h->D, S, h->lvl_sn_dev, b + nw, (unsigned)(P.lvl_small[l] - nw), h->maxf_lvl[l],
+                           h->maxp_lvl[l], active, st);
+    };
     for (int32_t l = 0; l < P.nlevels; ++l) {
         ProfScope ps(h, QDMF_K_FWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
-        launch_solve_level(true, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)P.lvl_small[l], h->maxf_lvl[l],
-                           h->maxp_lvl[l], active, st);
+        level(true, l);
         for (int64_t q = P.fwd_ptr[l]; q < P.fwd_ptr[l + 1]; ++q)
             launch_big_solve(h->D, S, P.fwd_plan[q], h->stasks_dev, active, st);
     }
     for (int32_t l = P.nlevels - 1; l >= 0; --l) {
         ProfScope ps(h, QDMF_K_BWD, P.lvl_solve_flops[l] * S.nrhs, P.lvl_solve_bytes[l] * S.nrhs);
-        launch_solve_level(false, h->D, S, h->lvl_sn_dev, P.lvl_ptr[l], (unsigned)P.lvl_small[l], h->maxf_lvl[l],
-                           h->maxp_lvl[l], active, st);
+        level(false, l);
         for (int64_t q = P.bwd_ptr[l]; q < P.bwd_ptr[l + 1]; ++q)
             launch_big_solve(h->D, S, P.bwd_plan[q], h->stasks_dev, active, st);
     }

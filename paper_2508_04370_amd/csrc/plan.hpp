@@ -146,6 +146,8 @@ struct Plan {
     std::vector<int32_t> lvl_sn;
     std::vector<double> lvl_solve_flops, lvl_solve_bytes;  // per level, one pass, one rhs
     std::vector<int32_t> lvl_small;     // per level: supernodes of lvl_sn solved one per workgroup (first)
+    std::vector<int32_t> lvl_wave;      // per level: of those, the first ones, whose fronts have at
+                                        // most 64 rows, are solved one per wavefront
     std::vector<Task> stasks;           // tasks of the big-supernode solve launches
     std::vector<int64_t> fwd_ptr, bwd_ptr;  // per level: its range of fwd_plan / bwd_plan
     std::vector<SolveLaunch> fwd_plan, bwd_plan;
