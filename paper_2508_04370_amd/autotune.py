@@ -4,8 +4,9 @@ Coordinate descent over the options that only decide how the same arithmetic is 
 launches, starting from the defaults: which fronts take grouped trailing updates
 (syrk_group_front) and how many windows a group holds (syrk_group), which trailing matrices
 take 128 x 128 tiles (syrk_tile_front), which supernodes take the many-workgroup solves
-(split_solve_front), which fronts are factorised whole in LDS (small_front), and, for the
-mixed path, which fronts take FP32 products (f_mix).  The block size nb, the amalgamation
+(split_solve_front), which fronts are factorised whole in LDS (small_front), which fronts
+overlap their trailing updates with the next windows on a second stream (lookahead_front),
+and, for the mixed path, which fronts take FP32 products (f_mix).  The block size nb, the amalgamation
 rule and the pivoting parameters are never touched: they change the factor itself.
 
 A candidate is timed over a few steps (factorise + the workload's solves, refined as in the
@@ -33,6 +34,7 @@ SPACE = [
     ("syrk_tile_front", [0, 1024, 2048, 4096]),
     ("split_solve_front", [1024, 512, 2048, 4096]),
     ("small_front", [64, 32, 16]),
+    ("lookahead_front", [0, 1024]),
 ]
 MIXED_SPACE = [("f_mix", [1024, 2048, 4096, 1 << 30])]
 TARGET = {0: 1e-12, 1: 1e-10}
