@@ -22,7 +22,7 @@ struct qdmf_ctx {
     bool host_only = false;
     hipStream_t stream = nullptr;
     // lookahead: the second stream of the factorisation and the two events that order it
-    // against the first (created at the first factorisation whose plan uses it)
+    // against the first (created by the analyse of a plan that uses them)
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_win = nullptr, ev_s2 = nullptr;
     qdmf_options opt{};
@@ -503,27 +503,31 @@ void enqueue_launches(qdmf_ctx* h, const DevPlan& D, const PivotParams& pp, bool
         if (L.stream == 1) {
             (void)hipEventRecord(h->ev_s2, st);
             pending = true;
-        } else if (L.kind == L_WINDOW && h->stream2) {
+        } else if (L.kind == L_WINDOW && h->ev_win) {
             (void)hipEventRecord(h->ev_win, h->stream);
         }
     }
     if (pending) (void)hipStreamWaitEvent(h->stream, h->ev_s2, 0);
 }
 
-// The second stream and its events, when the plan has launches for it.
+// The second stream and its events, when the plan has launches for it (each object is
+// created once and kept until the handle is destroyed).
 int ensure_stream2(qdmf_ctx* h) {
-    if (h->stream2) return 0;
     bool any = false;
     for (const Launch& L : h->P.launches) any = any || L.stream == 1;
     if (!any) return 0;
-    const hipError_t e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
-    if (e != hipSuccess) {
+    if (!h->stream2 && hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking) != hipSuccess) {
         h->stream2 = nullptr;
         return QDMF_ERR_HIP;
     }
-    if (hipEventCreateWithFlags(&h->ev_win, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_s2, hipEventDisableTiming) != hipSuccess)
+    if (!h->ev_win && hipEventCreateWithFlags(&h->ev_win, hipEventDisableTiming) != hipSuccess) {
+        h->ev_win = nullptr;
         return QDMF_ERR_HIP;
+    }
+    if (!h->ev_s2 && hipEventCreateWithFlags(&h->ev_s2, hipEventDisableTiming) != hipSuccess) {
+        h->ev_s2 = nullptr;
+        return QDMF_ERR_HIP;
+    }
     return 0;
 }
 
