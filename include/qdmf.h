@@ -276,9 +276,18 @@ int qdmf_batch_offsets(qdmf_handle h, int64_t* row_off, int64_t* col_off);
 
 /* As qdmf_factorise with rho[q], delta[q] (host, count entries, >= 0) for system q.  The
  * call waits for the stream before it stages the shifts (graph capture is not supported for
- * this call; qdmf_graph_capture takes one rho, delta for all systems). */
+ * this call: qdmf_batch_factorise_dev and qdmf_batch_graph_capture take the shifts from device
+ * memory). */
 int qdmf_batch_factorise(qdmf_handle h, const double* theta_dev, const double* rho,
                          const double* delta, int32_t prec);
+
+/* As qdmf_batch_factorise with rho_dev[q], delta_dev[q] (device, count doubles each, read when
+ * the factorisation runs; the caller keeps them until then): nothing is staged on the host
+ * and the call does not wait for the stream, so a graph may capture it.  A negative or
+ * non-finite shift is found on the device and reported as invalid input by
+ * qdmf_factor_stats, as an invalid Theta is.  Errors: as qdmf_batch_factorise. */
+int qdmf_batch_factorise_dev(qdmf_handle h, const double* theta_dev, const double* rho_dev,
+                             const double* delta_dev, int32_t prec);
 
 /* Synchronises; any pointer may be NULL.  inertia: 3 x count (negative, positive, zero
  * pivots of system q at 3q..3q+2); berr_nw, steps: count x nrhs of the last solve, entry
@@ -333,6 +342,15 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
                        int32_t prec, int32_t nsolves, int32_t nrhs, const double* r7_dev,
                        const double* r1_dev, double* dx_dev, double* dy_dev);
 int qdmf_graph_launch(qdmf_handle h);
+
+/* qdmf_graph_capture for a batch with per-system shifts: rho_dev[q], delta_dev[q] (device,
+ * count doubles each) are read by every replay, so the caller refreshes them in place as it
+ * does Theta (Section 4.6's regularisation may then change per system and iteration).
+ * Errors: as qdmf_graph_capture. */
+int qdmf_batch_graph_capture(qdmf_handle h, const double* theta_dev, const double* rho_dev,
+                             const double* delta_dev, int32_t prec, int32_t nsolves,
+                             int32_t nrhs, const double* r7_dev, const double* r1_dev,
+                             double* dx_dev, double* dy_dev);
 
 /* Measurement hook: while kind >= 0, every later eager launch of that kernel kind (above)
  * is bracketed by a pair of HIP events recorded on the handle's stream; kind = -1 stops.

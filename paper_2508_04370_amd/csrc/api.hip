@@ -531,11 +531,11 @@ int ensure_stream2(qdmf_ctx* h) {
     return 0;
 }
 
-// shifts_dev: per-system [rho(nsys), delta(nsys)] on the device, or NULL (rho, delta for all)
-void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delta, const double* shifts_dev,
-                       int32_t prec) {
+// rho_dev, delta_dev: per-system shifts on the device (nsys each), or NULL (rho, delta for all)
+void enqueue_factorise(qdmf_ctx* h, const double* theta, double rho, double delta, const double* rho_dev,
+                       const double* delta_dev, int32_t prec) {
     const PivotParams pp = pivot_params(h, prec);
-    launch_theta(h->D, theta, rho, delta, shifts_dev, shifts_dev ? shifts_dev + h->P.nsys : nullptr, h->stream);
+    launch_theta(h->D, theta, rho, delta, rho_dev, delta_dev, h->stream);
     launch_values_n(h->D, h->knnz, h->stream);
     launch_knorm(h->D, h->stream);
     enqueue_launches(h, h->D, pp, true);
@@ -1014,7 +1014,7 @@ int qdmf_factorise(qdmf_handle h, const double* theta_dev, double rho, double de
         return QDMF_ERR_INVALID_ARG;
     int rc = set_device(h);
     if (rc) return rc;
-    if (h->P.N > 0) enqueue_factorise(h, theta_dev, rho, delta, nullptr, prec);  // an empty system: nothing to do
+    if (h->P.N > 0) enqueue_factorise(h, theta_dev, rho, delta, nullptr, nullptr, prec);  // an empty system: nothing to do
     if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
     h->last_prec = prec;
     h->factorised = true;
@@ -1053,7 +1053,25 @@ int qdmf_batch_factorise(qdmf_handle h, const double* theta_dev, const double* r
     if (hipMemcpyAsync(h->shift_dev, h->shift_host, sizeof(double) * 2 * ns, hipMemcpyHostToDevice, h->stream) !=
         hipSuccess)
         return QDMF_ERR_HIP;
-    if (h->P.N > 0) enqueue_factorise(h, theta_dev, rho[0], delta[0], h->shift_dev, prec);
+    if (h->P.N > 0) enqueue_factorise(h, theta_dev, rho[0], delta[0], h->shift_dev, h->shift_dev + ns, prec);
+    if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
+    h->last_prec = prec;
+    h->factorised = true;
+    h->solved = false;
+    return 0;
+}
+
+int qdmf_batch_factorise_dev(qdmf_handle h, const double* theta_dev, const double* rho_dev,
+                             const double* delta_dev, int32_t prec) {
+    if (!h) return QDMF_ERR_INVALID_ARG;
+    if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
+    if (!h->have_matrix || (h->P.has_q && !h->have_hessian)) return QDMF_ERR_NO_MATRIX;
+    if (h->host_only || (!theta_dev && h->P.n > 0) || !rho_dev || !delta_dev ||
+        (prec != QDMF_FP64 && prec != QDMF_MIXED))
+        return QDMF_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    if (h->P.N > 0) enqueue_factorise(h, theta_dev, 0.0, 0.0, rho_dev, delta_dev, prec);
     if (hipGetLastError() != hipSuccess) return QDMF_ERR_HIP;
     h->last_prec = prec;
     h->factorised = true;
@@ -1303,9 +1321,11 @@ int qdmf_export_front(qdmf_handle h, int32_t s, double* panel, int32_t* rows) {
     return 0;
 }
 
-int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, double delta, int32_t prec,
-                       int32_t nsolves, int32_t nrhs, const double* r7_dev, const double* r1_dev, double* dx_dev,
-                       double* dy_dev) {
+namespace {
+
+int graph_capture_impl(qdmf_handle h, const double* theta_dev, double rho, double delta, const double* rho_dev,
+                       const double* delta_dev, int32_t prec, int32_t nsolves, int32_t nrhs, const double* r7_dev,
+                       const double* r1_dev, double* dx_dev, double* dy_dev) {
     if (!h) return QDMF_ERR_INVALID_ARG;
     if (!h->analysed) return QDMF_ERR_NOT_ANALYSED;
     if (!h->have_matrix || (h->P.has_q && !h->have_hessian)) return QDMF_ERR_NO_MATRIX;
@@ -1342,7 +1362,7 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     const int32_t prec_before = h->last_prec;
     h->last_prec = prec;
     h->capturing = true;
-    enqueue_factorise(h, theta_dev, rho, delta, nullptr, prec);
+    enqueue_factorise(h, theta_dev, rho, delta, rho_dev, delta_dev, prec);
     for (int32_t q = 0; q < nsolves; ++q) enqueue_solve(h, r7_dev, r1_dev, dx_dev, dy_dev);
     seg_close(h);
     h->capturing = false;
@@ -1359,6 +1379,23 @@ int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, doubl
     h->graph_nrhs = nrhs;
     h->graph_nsolves = nsolves;
     return 0;
+}
+
+}  // namespace
+
+int qdmf_graph_capture(qdmf_handle h, const double* theta_dev, double rho, double delta, int32_t prec,
+                       int32_t nsolves, int32_t nrhs, const double* r7_dev, const double* r1_dev, double* dx_dev,
+                       double* dy_dev) {
+    return graph_capture_impl(h, theta_dev, rho, delta, nullptr, nullptr, prec, nsolves, nrhs, r7_dev, r1_dev, dx_dev,
+                              dy_dev);
+}
+
+int qdmf_batch_graph_capture(qdmf_handle h, const double* theta_dev, const double* rho_dev,
+                             const double* delta_dev, int32_t prec, int32_t nsolves, int32_t nrhs,
+                             const double* r7_dev, const double* r1_dev, double* dx_dev, double* dy_dev) {
+    if (!rho_dev || !delta_dev) return QDMF_ERR_INVALID_ARG;
+    return graph_capture_impl(h, theta_dev, 0.0, 0.0, rho_dev, delta_dev, prec, nsolves, nrhs, r7_dev, r1_dev, dx_dev,
+                              dy_dev);
 }
 
 int qdmf_graph_launch(qdmf_handle h) {

@@ -1400,6 +1400,15 @@ __global__ void k_init_scalars(DevPlan D, double rho, double delta, const double
     }
 }
 
+// Per-system shifts read from device arrays: a negative or non-finite rho or delta is reported
+// as invalid input, as a Theta that is not positive and finite is.
+__global__ void k_check_shifts(DevPlan D) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= D.nsys) return;
+    const double r = D.rho_sys[q], d = D.delta_sys[q];
+    if (!(r >= 0.0) || !(d >= 0.0) || !isfinite(r) || !isfinite(d)) atomicOr(&D.sc->bad_theta, 1);
+}
+
 // AS: dinv = 1/Theta (diagonal -(Theta^{-1}) of equation (augsys));
 // NE: dinv = theta~ = 1/(1/Theta + rho) (equation (regul_matrix)).
 __global__ void k_theta(DevPlan D, const double* theta) {
@@ -3171,6 +3180,7 @@ void launch_theta(const DevPlan& D, const double* theta, double rho, double delt
                   const double* delta_sys, hipStream_t s) {
     hipLaunchKernelGGL(k_init_scalars, dim3(nblocks(D.nsys, 256)), dim3(256), 0, s, D, rho, delta, rho_sys,
                        delta_sys);
+    if (rho_sys || delta_sys) hipLaunchKernelGGL(k_check_shifts, dim3(nblocks(D.nsys, 256)), dim3(256), 0, s, D);
     if (D.n > 0) hipLaunchKernelGGL(k_theta, dim3(nblocks(D.n, 256)), dim3(256), 0, s, D, theta);
 }
 

@@ -37,7 +37,7 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read", "qdmf_batch_analyse",
             "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats", "qdmf_choose_mode",
             "qdmf_ipm_default_options", "qdmf_ipm_solve", "qdmf_analyse_qp", "qdmf_set_hessian",
-            "qdmf_export_flags"]
+            "qdmf_export_flags", "qdmf_batch_factorise_dev", "qdmf_batch_graph_capture"]
 QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD, \
     QDMF_K_SYRK128 = range(8)
 KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
@@ -144,6 +144,8 @@ def lib():
         L.qdmf_batch_analyse.argtypes = [P, I32, P, P, P, P, I32]
         L.qdmf_batch_offsets.argtypes = [P, P, P]
         L.qdmf_batch_factorise.argtypes = [P, P, P, P, I32]
+        L.qdmf_batch_factorise_dev.argtypes = [P, P, P, P, I32]
+        L.qdmf_batch_graph_capture.argtypes = [P, P, P, P, I32, I32, I32, P, P, P, P]
         L.qdmf_batch_stats.argtypes = [P, P, P, P]
         for name in EXPORTED:
             getattr(L, name)
@@ -387,6 +389,18 @@ def qdmf_batch_factorise(h, theta_dev, rho, delta, prec=QDMF_FP64):
     d = np.ascontiguousarray(delta, np.float64)
     return _check(lib().qdmf_batch_factorise(h, _dev(theta_dev), _np(r), _np(d), int(prec)),
                   "qdmf_batch_factorise", h)
+
+
+def qdmf_batch_factorise_dev(h, theta_dev, rho_dev, delta_dev, prec=QDMF_FP64):
+    return _check(lib().qdmf_batch_factorise_dev(h, _dev(theta_dev), _dev(rho_dev), _dev(delta_dev), int(prec)),
+                  "qdmf_batch_factorise_dev", h)
+
+
+def qdmf_batch_graph_capture(h, theta_dev, rho_dev, delta_dev, prec, nsolves, nrhs, r7_dev, r1_dev, dx_dev,
+                             dy_dev):
+    return _check(lib().qdmf_batch_graph_capture(h, _dev(theta_dev), _dev(rho_dev), _dev(delta_dev), int(prec),
+                                                 int(nsolves), int(nrhs), _dev(r7_dev), _dev(r1_dev),
+                                                 _dev(dx_dev), _dev(dy_dev)), "qdmf_batch_graph_capture", h)
 
 
 def qdmf_batch_stats(h, count, nrhs=0):
