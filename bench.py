@@ -444,6 +444,20 @@ def main():
             rr["kernel"] = "+".join(Q.KERNEL_KIND_NAMES[k] for k in kinds)
             rr["ms_per_step"] = round(tot["total_ms"], 3)
             roofs[name] = rr
+    # the same fractions against peaks measured on this device (matrix instructions, vector
+    # FMAs, a streaming copy), beside the datasheet ones
+    try:
+        measured = Q.qdmf_peak_probe(0, None)
+    except Exception as exc:  # a failed probe leaves the datasheet fractions only
+        print(f"[bench] peak probe failed: {exc}", file=sys.stderr, flush=True)
+        measured = None
+    if measured:
+        for r in [roof] + list(roofs.values()):
+            mp = {"mfma": measured["mfma_f32_tflops"] if (r["bound"] == "mfma" and pr0 == 1)
+                  else measured["mfma_f64_tflops"], "hbm": measured["hbm_gbs"],
+                  "alu": measured["valu_f64_tflops"]}[r["bound"]]
+            r["peak_measured"] = round(mp, 3)
+            r["frac_measured"] = round(r["achieved"] / mp, 6) if mp > 0 else None
     out = {
         "metric": "factorise+solve GFLOP/s & ms/IPM-iter, mixed vs FP64 at backward err <=1e-10",
         "value": round(value, 3),
@@ -466,6 +480,7 @@ def main():
         "roofline": roof,
         "rooflines": roofs,
         "kernel_ms_per_step_by_kind": {Q.KERNEL_KIND_NAMES[k]: round(v["total_ms"], 3) for k, v in pk.items()},
+        "measured_peaks": measured,
     }
     for pname in precs:
         r = res[pname]

@@ -364,6 +364,15 @@ int qdmf_profile_kind(qdmf_handle h, int32_t kind);
 int qdmf_profile_read(qdmf_handle h, int64_t* launches, double* total_ms, double* flops,
                       double* bytes);
 
+/* Measurement: the peaks the roofline fractions are also reported against, measured on
+ * `device` with events on `hip_stream`: FP64 and FP32 16x16x4 matrix instructions (the trailing
+ * update's) in TFLOP/s, independent FP64 vector FMAs in TFLOP/s, and a streaming device copy of
+ * 1 GiB (2 GiB moved) in GB/s; best of a few runs each.  Allocates and frees 2 GiB + 2 MiB of
+ * device memory and synchronises the stream.  Any pointer may be NULL.
+ * Errors: QDMF_ERR_HIP, QDMF_ERR_OOM. */
+int qdmf_peak_probe(int device, void* hip_stream, double* mfma_f64_tflops, double* mfma_f32_tflops,
+                    double* valu_f64_tflops, double* hbm_gbs);
+
 /* Choice between the normal equations and the augmented system for the pattern of A
  * (Section 4.2: both can be analysed and the better taken, the augmented system first, and
  * the normal equations given up as soon as forming their pattern would hold more entries than

@@ -17,7 +17,7 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,
               "-I", "/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
 
-HIP_SOURCES = ["kernels.hip", "api.hip", "ipm.hip"]
+HIP_SOURCES = ["kernels.hip", "api.hip", "ipm.hip", "peak.hip"]
 HOST_SOURCES = ["analyse.cpp", "amd.cpp", "grid_nd.cpp", "nd.cpp"]
 
 

@@ -37,7 +37,7 @@ EXPORTED = ["qdmf_default_options", "qdmf_create", "qdmf_set_stream", "qdmf_anal
             "qdmf_last_message", "qdmf_profile_kind", "qdmf_profile_read", "qdmf_batch_analyse",
             "qdmf_batch_offsets", "qdmf_batch_factorise", "qdmf_batch_stats", "qdmf_choose_mode",
             "qdmf_ipm_default_options", "qdmf_ipm_solve", "qdmf_analyse_qp", "qdmf_set_hessian",
-            "qdmf_export_flags", "qdmf_batch_factorise_dev", "qdmf_batch_graph_capture"]
+            "qdmf_export_flags", "qdmf_batch_factorise_dev", "qdmf_batch_graph_capture", "qdmf_peak_probe"]
 QDMF_K_SMALL, QDMF_K_ASSEMBLE, QDMF_K_WINDOW, QDMF_K_SYRK, QDMF_K_FINALIZE, QDMF_K_FWD, QDMF_K_BWD, \
     QDMF_K_SYRK128 = range(8)
 KERNEL_KIND_NAMES = {0: "k_small", 1: "k_assemble", 2: "k_window", 3: "k_syrk", 4: "k_finalize", 5: "k_fwd",
@@ -145,6 +145,7 @@ def lib():
         L.qdmf_batch_offsets.argtypes = [P, P, P]
         L.qdmf_batch_factorise.argtypes = [P, P, P, P, I32]
         L.qdmf_batch_factorise_dev.argtypes = [P, P, P, P, I32]
+        L.qdmf_peak_probe.argtypes = [C.c_int, P, P, P, P, P]
         L.qdmf_batch_graph_capture.argtypes = [P, P, P, P, I32, I32, I32, P, P, P, P]
         L.qdmf_batch_stats.argtypes = [P, P, P, P]
         for name in EXPORTED:
@@ -401,6 +402,13 @@ def qdmf_batch_graph_capture(h, theta_dev, rho_dev, delta_dev, prec, nsolves, nr
     return _check(lib().qdmf_batch_graph_capture(h, _dev(theta_dev), _dev(rho_dev), _dev(delta_dev), int(prec),
                                                  int(nsolves), int(nrhs), _dev(r7_dev), _dev(r1_dev),
                                                  _dev(dx_dev), _dev(dy_dev)), "qdmf_batch_graph_capture", h)
+
+
+def qdmf_peak_probe(device=0, stream=None):
+    v = [C.c_double() for _ in range(4)]
+    _check(lib().qdmf_peak_probe(int(device), stream, *[C.byref(x) for x in v]), "qdmf_peak_probe")
+    return dict(mfma_f64_tflops=v[0].value, mfma_f32_tflops=v[1].value, valu_f64_tflops=v[2].value,
+                hbm_gbs=v[3].value)
 
 
 def qdmf_batch_stats(h, count, nrhs=0):
